@@ -1,0 +1,325 @@
+"""Python face of the FP64 CPU oracle (test infrastructure only).
+
+Only tests, the smoke check and the benchmark's CPU-baseline leg use this
+module.  It wraps `ncl_oracle.c` (assembly of both KKT forms, minimum-degree
+ordering, up-looking LDL^T with static pivoting, solves, symmetric products)
+and adds, in plain numpy, the iterative refinement loop, the backward error and
+the adjoint gradient.  It never imports or calls the GPU library.
+
+Paper references (MadNCL, arXiv 2510.05885):
+  condensed K1 = W + Sigma + rho J^T J ............ Sec. 3.3, eq. K1
+  stabilized K2r = [[W+Sigma, J^T], [J, -I/rho]] .. Sec. 3.2, eq. K2r
+  static pivoting with block-dependent sign ....... Sec. 3.1 ("Sparse LDL^T")
+  pivot epsilon, Richardson refinement ............ Sec. 4.3
+  inertia (n,0,0) / (n,m,0) ....................... Sec. 3.4, Prop. "inertia"
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "ncl_oracle.c")
+_LIB = os.path.join(_HERE, "libncl_oracle.so")
+_lib = None
+
+CONDENSED, STABILIZED = 0, 1
+# Proposed pivot-epsilon defaults: the paper fixes 1e-10 for the stabilized
+# form (Sec. 4.3) and leaves the condensed value unstated.
+DEFAULT_EPS = {CONDENSED: 1e-12, STABILIZED: 1e-10}
+
+_i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+_f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+_i8p = np.ctypeslib.ndpointer(np.int8, flags="C_CONTIGUOUS")
+_i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+
+
+def build(force: bool = False) -> str:
+    """Compile ncl_oracle.c into a shared library next to it."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _L():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = C.CDLL(_LIB)
+        asm_args = [C.c_int, C.c_int, _i32p, _i32p, _f64p, _f64p, _i32p, _i32p, _f64p, C.c_double,
+                    _i32p, C.c_void_p, C.c_void_p]
+        for name in ("or_condensed_assemble", "or_stabilized_assemble"):
+            f = getattr(lib, name)
+            f.argtypes = asm_args
+            f.restype = C.c_int64
+        lib.or_symv.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.c_int, _f64p, C.c_int, _f64p, C.c_int]
+        lib.or_symv.restype = None
+        lib.or_norms.argtypes = [C.c_int, _i32p, _i32p, _f64p, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+        lib.or_norms.restype = None
+        lib.or_mindeg.argtypes = [C.c_int, _i32p, _i32p, _i32p]
+        lib.or_mindeg.restype = C.c_int
+        lib.or_factor.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i8p, C.c_double, C.POINTER(C.c_int)]
+        lib.or_factor.restype = C.c_void_p
+        lib.or_free.argtypes = [C.c_void_p]
+        lib.or_free.restype = None
+        lib.or_nnz_L.argtypes = [C.c_void_p]
+        lib.or_nnz_L.restype = C.c_int64
+        lib.or_inertia.argtypes = [C.c_void_p, _i64p]
+        lib.or_inertia.restype = None
+        lib.or_get_factor.argtypes = [C.c_void_p, _i32p, _i32p, _f64p, _f64p, _i32p]
+        lib.or_get_factor.restype = None
+        lib.or_solve.argtypes = [C.c_void_p, C.c_int, _f64p, C.c_int, _f64p, C.c_int]
+        lib.or_solve.restype = None
+        _lib = lib
+    return _lib
+
+
+# ---------------------------------------------------------------------------
+# Assembly
+# ---------------------------------------------------------------------------
+
+@dataclass
+class LowerCSC:
+    """Symmetric matrix stored as its lower triangle in CSC."""
+    N: int
+    p: np.ndarray
+    i: np.ndarray
+    x: np.ndarray
+
+    def to_scipy_full(self) -> sp.csc_matrix:
+        A = sp.csc_matrix((self.x, self.i, self.p), shape=(self.N, self.N))
+        return (A + sp.tril(A, -1).T).tocsc()
+
+    def dense(self) -> np.ndarray:
+        return self.to_scipy_full().toarray()
+
+
+def assemble(inp, form: int = CONDENSED) -> LowerCSC:
+    """K1 (form 0) or K2r (form 1) of `inp`, lower CSC, FP64 (Sec. 3.3 / 3.2)."""
+    lib = _L()
+    n, m = inp.n, inp.m
+    N = n if form == CONDENSED else n + m
+    f = lib.or_condensed_assemble if form == CONDENSED else lib.or_stabilized_assemble
+    args = (n, m, np.ascontiguousarray(inp.W_colptr, np.int32), np.ascontiguousarray(inp.W_rowidx, np.int32),
+            np.ascontiguousarray(inp.W_val, np.float64), np.ascontiguousarray(inp.Sigma, np.float64),
+            np.ascontiguousarray(inp.J_rowptr, np.int32), np.ascontiguousarray(inp.J_colidx, np.int32),
+            np.ascontiguousarray(inp.J_val, np.float64), float(inp.rho))
+    Kp = np.zeros(N + 1, np.int32)
+    nnz = f(*args, Kp, None, None)
+    if nnz < 0:
+        raise MemoryError("oracle assembly failed")
+    Ki = np.zeros(max(nnz, 1), np.int32)
+    Kx = np.zeros(max(nnz, 1), np.float64)
+    f(*args, Kp, Ki.ctypes.data_as(C.c_void_p), Kx.ctypes.data_as(C.c_void_p))
+    return LowerCSC(N, Kp, Ki[:nnz], Kx[:nnz])
+
+
+def symv(K: LowerCSC, X: np.ndarray) -> np.ndarray:
+    """K X for symmetric K (lower CSC), X of shape (N,) or (N, k)."""
+    X2 = np.asarray(X, np.float64).reshape(K.N, -1)
+    Xc = np.ascontiguousarray(X2.T)          # each column contiguous
+    Y = np.zeros_like(Xc)
+    _L().or_symv(K.N, K.p, K.i, K.x, Xc.shape[0], Xc, K.N, Y, K.N)
+    Y = Y.T
+    return Y.reshape(np.shape(X))
+
+
+def norms(K: LowerCSC):
+    """(max_ij |K_ij|, ||K||_inf) of the symmetric matrix."""
+    a, b = C.c_double(), C.c_double()
+    _L().or_norms(K.N, K.p, K.i, K.x, C.byref(a), C.byref(b))
+    return a.value, b.value
+
+
+def block_signs(n: int, m: int, form: int) -> np.ndarray:
+    """+1 for primal rows, -1 for dual rows, in the unpermuted ordering."""
+    s = np.ones(n if form == CONDENSED else n + m, np.int8)
+    if form == STABILIZED:
+        s[n:] = -1
+    return s
+
+
+# ---------------------------------------------------------------------------
+# Ordering and factorization
+# ---------------------------------------------------------------------------
+
+def mindeg(K: LowerCSC) -> np.ndarray:
+    perm = np.zeros(K.N, np.int32)
+    rc = _L().or_mindeg(K.N, K.p, K.i, perm)
+    if rc != 0:
+        raise MemoryError("oracle ordering failed")
+    return perm
+
+
+class OracleError(RuntimeError):
+    pass
+
+
+class LDL:
+    """P K P^T = L D L^T with static pivoting (Sec. 3.1), K lower CSC."""
+
+    def __init__(self, K: LowerCSC, perm=None, signs=None, pivot_thr: float = 0.0):
+        lib = _L()
+        self.N = K.N
+        self.perm = np.ascontiguousarray(mindeg(K) if perm is None else perm, np.int32)
+        sg = np.ones(K.N, np.int8) if signs is None else np.ascontiguousarray(signs, np.int8)
+        st = C.c_int(0)
+        h = lib.or_factor(K.N, K.p, K.i, K.x, self.perm, sg, float(pivot_thr), C.byref(st))
+        self.status = st.value
+        if not h:
+            raise OracleError(f"oracle factorization failed (status {st.value})")
+        self._h = h
+
+    def __del__(self):
+        h = getattr(self, "_h", None)
+        if h:
+            _L().or_free(h)
+            self._h = None
+
+    def inertia(self):
+        out = np.zeros(4, np.int64)
+        _L().or_inertia(self._h, out)
+        return tuple(int(v) for v in out)      # (npos, nneg, nzero, nperturbed)
+
+    def factor(self):
+        """(L as scipy CSC unit lower incl. diagonal, D, perm) in the permuted ordering."""
+        lib = _L()
+        nnz = lib.or_nnz_L(self._h)
+        Lp = np.zeros(self.N + 1, np.int32); Li = np.zeros(max(nnz, 1), np.int32)
+        Lx = np.zeros(max(nnz, 1)); D = np.zeros(self.N); perm = np.zeros(self.N, np.int32)
+        lib.or_get_factor(self._h, Lp, Li, Lx, D, perm)
+        L = sp.csc_matrix((Lx[:nnz], Li[:nnz], Lp), shape=(self.N, self.N)) + sp.eye(self.N, format="csc")
+        return L.tocsc(), D, perm
+
+    def nnz_L(self) -> int:
+        return int(_L().or_nnz_L(self._h))
+
+    def solve(self, B: np.ndarray) -> np.ndarray:
+        B2 = np.asarray(B, np.float64).reshape(self.N, -1)
+        Bc = np.ascontiguousarray(B2.T)
+        Xc = np.zeros_like(Bc)
+        _L().or_solve(self._h, Bc.shape[0], Bc, self.N, Xc, self.N)
+        return Xc.T.reshape(np.shape(B))
+
+
+# ---------------------------------------------------------------------------
+# Refinement, backward error, full solve
+# ---------------------------------------------------------------------------
+
+def backward_error(K: LowerCSC, X, B, Kinf=None) -> np.ndarray:
+    """Normwise backward error per column: ||b - Kx||_inf / (||K||_inf ||x||_inf + ||b||_inf)."""
+    X2 = np.asarray(X).reshape(K.N, -1); B2 = np.asarray(B).reshape(K.N, -1)
+    if Kinf is None:
+        Kinf = norms(K)[1]
+    R = B2 - symv(K, X2)
+    den = Kinf * np.abs(X2).max(axis=0) + np.abs(B2).max(axis=0)
+    return np.abs(R).max(axis=0) / np.where(den > 0, den, 1.0)
+
+
+@dataclass
+class SolveInfo:
+    inertia: tuple = ()
+    ir_steps: int = 0
+    omega_history: list = field(default_factory=list)
+    backward_error: float = np.inf
+    inertia_ok: bool = False
+    nnz_L: int = 0
+
+
+def expected_inertia(n: int, m: int, form: int):
+    """Inertia of a correctly regularized system (Sec. 3.4): (n,0,0) or (n,m,0)."""
+    return (n, 0, 0) if form == CONDENSED else (n, m, 0)
+
+
+def refine(K: LowerCSC, F: LDL, B, ir_max: int = 10, ir_tol: float = 1e-12, ir_stall: float = 0.5,
+           Kinf=None):
+    """Richardson refinement x <- x + F^-1 (b - K x) against the unperturbed K
+    (Sec. 3.1 and 4.3).  Stops when the backward error reaches ir_tol, after
+    ir_max corrections, or when one correction fails to halve it; the best
+    iterate is returned.  Returns (X, omega history, corrections applied)."""
+    B2 = np.asarray(B, np.float64).reshape(K.N, -1)
+    if Kinf is None:
+        Kinf = norms(K)[1]
+    X = F.solve(B2)
+    om = float(backward_error(K, X, B2, Kinf).max())
+    hist = [om]
+    best_X, best = X, om
+    steps = 0
+    while om > ir_tol and steps < ir_max:
+        R = B2 - symv(K, X)
+        Xn = X + F.solve(R)
+        omn = float(backward_error(K, Xn, B2, Kinf).max())
+        steps += 1
+        hist.append(omn)
+        if omn < best:
+            best_X, best = Xn, omn
+        if omn > ir_stall * om:
+            break
+        X, om = Xn, omn
+    return best_X.reshape(np.shape(B)), hist, steps
+
+
+def solve(inp, form: int, B, eps=None, ir_max: int = 10, ir_tol: float = 1e-12, ir_stall: float = 0.5,
+          perm=None, K: LowerCSC | None = None):
+    """Assemble, order, factor with static pivoting and refine: the whole path
+    in FP64 on the CPU.  eps is relative to max_ij |K_ij| (pivot rule
+    |d| < eps*||K||_max -> d = sign*eps*||K||_max).  Refinement runs only when
+    the inertia is the expected one (Sec. 4.3)."""
+    if K is None:
+        K = assemble(inp, form)
+    if eps is None:
+        eps = DEFAULT_EPS[form]
+    kmax, kinf = norms(K)
+    F = LDL(K, perm=perm, signs=block_signs(inp.n, inp.m, form), pivot_thr=eps * kmax)
+    if F.status not in (0,):
+        raise OracleError(f"factorization status {F.status}")
+    info = SolveInfo(inertia=F.inertia(), nnz_L=F.nnz_L())
+    info.inertia_ok = info.inertia[:3] == expected_inertia(inp.n, inp.m, form)
+    if info.inertia_ok:
+        X, hist, steps = refine(K, F, B, ir_max, ir_tol, ir_stall, kinf)
+    else:
+        X = F.solve(B)
+        hist, steps = [float(backward_error(K, X, B, kinf).max())], 0
+    info.omega_history, info.ir_steps, info.backward_error = hist, steps, hist[-1] if steps == 0 else min(hist)
+    return X, info, F, K
+
+
+# ---------------------------------------------------------------------------
+# Adjoint of x = K^-1 b (condensed form)
+# ---------------------------------------------------------------------------
+
+def adjoint_condensed(inp, F: LDL, X, Xbar):
+    """Gradients of a loss with dL/dX = Xbar through X = K^-1 B, K = W + Sigma + rho J^T J.
+
+    lambda = K^-1 Xbar (K symmetric, so the transpose solve is a solve);
+    dL/dB = lambda;  dL/dK = -lambda X^T summed over columns, which on the
+    symmetric storage gives, for a stored lower W entry (i,j), i != j,
+    -(lambda_i x_j + lambda_j x_i) and on the diagonal -lambda_i x_i;
+    dL/dSigma_i = -lambda_i x_i;
+    dL/dJ_ri = -rho [lambda_i (J x)_r + x_i (J lambda)_r];
+    dL/drho = -(J lambda) . (J x).  All sums run over right-hand-side columns.
+    Returns (gB, gW (per stored W entry), gSigma, gJ (per stored J entry), grho)."""
+    X2 = np.asarray(X).reshape(inp.n, -1)
+    Lam = F.solve(np.asarray(Xbar).reshape(inp.n, -1))
+    Wrows = inp.W_rowidx.astype(np.int64)
+    Wcols = np.repeat(np.arange(inp.n), np.diff(inp.W_colptr))
+    off = Wrows != Wcols
+    gW = -np.einsum("ec,ec->e", Lam[Wrows], X2[Wcols])
+    gW = gW - off * np.einsum("ec,ec->e", Lam[Wcols], X2[Wrows])
+    gS = -np.einsum("ic,ic->i", Lam, X2)
+    J = sp.csr_matrix((inp.J_val, inp.J_colidx, inp.J_rowptr), shape=(inp.m, inp.n))
+    JX = J @ X2
+    JL = J @ Lam
+    Jrows = np.repeat(np.arange(inp.m), np.diff(inp.J_rowptr))
+    Jcols = inp.J_colidx.astype(np.int64)
+    gJ = -inp.rho * (np.einsum("ec,ec->e", Lam[Jcols], JX[Jrows]) + np.einsum("ec,ec->e", X2[Jcols], JL[Jrows]))
+    grho = -float(np.sum(JL * JX))
+    return Lam.reshape(np.shape(Xbar)), gW, gS, gJ, grho
