@@ -1,0 +1,212 @@
+/*
+ * ncl_kkt.h — C ABI of the MI355X KKT factor/solve library for the Newton
+ * step of Algorithm NCL (MadNCL, arXiv 2510.05885).
+ *
+ * The library assembles and solves, by supernodal multifrontal LDL^T with
+ * static pivoting, one of two symmetric KKT matrices built from the Hessian
+ * block W (n x n), the barrier diagonal Sigma (n) and the Jacobian J (m x n):
+ *
+ *   condensed  (NCL_CONDENSED):  K = W + Sigma + rho J^T J            order n
+ *              Sec. 3.3, eq. K1.  SPD when the system is correctly
+ *              regularized; expected inertia (n, 0, 0) (Sec. 3.4).
+ *   stabilized (NCL_STABILIZED): K = [[W + Sigma, J^T], [J, -(1/rho) I]]
+ *              Sec. 3.2, eq. K2r.  Symmetric quasi-definite; expected
+ *              inertia (n, m, 0) (Sec. 3.4, Prop. "inertia").
+ *
+ * rho is the effective penalty of the paper (rho-hat = rho + delta, Sec. 3.1);
+ * a caller that regularizes with delta passes Sigma + delta and rho + delta.
+ *
+ * Static pivoting (Sec. 3.1 "Sparse LDL^T factorization", Sec. 4.3): a pivot d
+ * with |d| < eps * ||K||_max (strict; ||K||_max = max_ij |K_ij| of the
+ * assembled, unpermuted K in FP64) is replaced by s * eps * ||K||_max, where
+ * s = +1 for a primal row and -1 for a dual row of the unpermuted matrix.  A
+ * pivot of the wrong sign and magnitude above the threshold is kept and shows
+ * in the inertia.  The factor is thus of a slightly perturbed matrix; solves
+ * refine against the unperturbed K (Richardson, Sec. 4.3).
+ *
+ * Memory: patterns are host arrays copied at analyze time.  Values,
+ * right-hand sides, solutions and gradients are caller-owned DEVICE buffers
+ * (double).  The handle owns all device workspace; it is allocated by
+ * ncl_kkt_analyze and reused by every factor / solve (they allocate nothing).
+ * All device work is ordered on the caller's stream (a hipStream_t passed as
+ * void*; NULL = the null stream).
+ *
+ * Return codes: 0 success; negative = error (nothing usable produced);
+ * positive = completed with a warning.
+ */
+#ifndef NCL_KKT_H
+#define NCL_KKT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct ncl_kkt_s *ncl_kkt_t;
+
+enum { NCL_CONDENSED = 0, NCL_STABILIZED = 1 };
+enum { NCL_FP64 = 0, NCL_FP32_IR = 1 };
+enum { NCL_ORDER_ND = 0, NCL_ORDER_NATURAL = 1, NCL_ORDER_USER = 2 };
+
+#define NCL_OK 0
+#define NCL_ERR_ARG (-1)        /* bad argument (sizes, null pointers, rho <= 0, ...) */
+#define NCL_ERR_PATTERN (-2)    /* unsorted / duplicate / out-of-range / upper-triangle index */
+#define NCL_ERR_ALLOC (-3)      /* host or device allocation failed */
+#define NCL_ERR_HIP (-4)        /* a HIP runtime call failed */
+#define NCL_ERR_STATE (-5)      /* call out of order (solve before factor, ...) */
+#define NCL_ERR_NONFINITE (-6)  /* NaN or Inf met in the assembled matrix or a pivot */
+#define NCL_WARN_INERTIA 1      /* factor done, inertia differs from (n,0,0) / (n,m,0) */
+#define NCL_WARN_IR_NOT_CONVERGED 2  /* refinement stopped above ir_tol */
+#define NCL_WARN_FELL_BACK_FP64 3    /* FP32 factor insufficient; refactored in FP64 */
+
+/* Options.  Fill with ncl_kkt_default_options, then override. */
+typedef struct {
+    int32_t form;          /* NCL_CONDENSED or NCL_STABILIZED */
+    int32_t precision;     /* NCL_FP64, or NCL_FP32_IR: FP32 factor + FP64 refinement */
+    double pivot_eps;      /* relative static-pivot epsilon; <= 0: 1e-12 condensed,
+                              1e-10 stabilized (the paper's value, Sec. 4.3) */
+    int32_t ir_max_steps;  /* max refinement corrections per solve (default 10) */
+    double ir_tol;         /* stop when the backward error is <= ir_tol (default 1e-12) */
+    double ir_stall;       /* stop when a correction does not reduce the backward
+                              error below ir_stall * previous (default 0.5) */
+    int32_t ordering;      /* NCL_ORDER_ND (default), NCL_ORDER_NATURAL, NCL_ORDER_USER */
+    const int32_t *user_perm; /* host, used when ordering == NCL_ORDER_USER: user_perm[k] =
+                                 unpermuted index of the k-th pivot (length n or n+m) */
+} ncl_kkt_options;
+
+/* Result of one solve (normwise backward error
+ * omega = ||b - Kx||_inf / (||K||_inf ||x||_inf + ||b||_inf), max over columns). */
+typedef struct {
+    int32_t ir_steps;        /* refinement corrections applied */
+    int32_t fell_back_fp64;  /* 1 when an FP64 refactor was needed (FP32_IR only) */
+    double backward_error;   /* final omega */
+    double backward_error0;  /* omega of the unrefined solve */
+} ncl_kkt_solve_info;
+
+/* Sizes of the symbolic analysis. */
+typedef struct {
+    int64_t order;          /* n (condensed) or n + m (stabilized), summed over systems */
+    int64_t nnz_K_lower;    /* stored lower entries of K (incl. diagonal) */
+    int64_t nnz_L;          /* entries of L incl. diagonal, supernodal (with padding zeros) */
+    double flops_factor;    /* flops of the partial frontal factorizations */
+    int64_t n_supernodes;
+    int64_t n_levels;       /* levels of the supernodal tree (leaves = level 0) */
+    int64_t max_front;      /* largest front order */
+    int64_t n_large_fronts; /* fronts handled by the global-memory MFMA path */
+    int64_t device_bytes;   /* device workspace held by the handle */
+    double analyze_seconds; /* host time of the symbolic analysis */
+} ncl_kkt_stats;
+
+void ncl_kkt_default_options(ncl_kkt_options *o);
+
+/* Symbolic analysis on the fixed sparsity pattern (Sec. 4.1: the symbolic
+ * factorization is computed once and reused).  W: lower-triangular CSC
+ * (W_colptr[n+1], W_rowidx sorted, row >= column); J: CSR m x n (J_rowptr[m+1],
+ * J_colidx sorted).  m may be 0.  Host arrays, copied.  Orders the matrix,
+ * builds the supernodal elimination tree and every map, then allocates and
+ * uploads the device workspace (current HIP device).  *h is NULL on error. */
+int ncl_kkt_analyze(ncl_kkt_t *h, const ncl_kkt_options *o, int32_t n, int32_t m,
+                    const int32_t *W_colptr, const int32_t *W_rowidx,
+                    const int32_t *J_rowptr, const int32_t *J_colidx);
+
+/* Same analysis without touching any GPU: the handle can only be inspected
+ * (ncl_kkt_get_stats / ncl_kkt_get_perm / ncl_kkt_get_supernodes) and
+ * destroyed.  factor/solve on it return NCL_ERR_STATE. */
+int ncl_kkt_analyze_host(ncl_kkt_t *h, const ncl_kkt_options *o, int32_t n, int32_t m,
+                         const int32_t *W_colptr, const int32_t *W_rowidx,
+                         const int32_t *J_rowptr, const int32_t *J_colidx);
+
+/* Batched condensed systems: `count` independent systems analyzed into one
+ * handle (the block-diagonal union).  Arrays of per-system host pointers.
+ * Values for factor/solve are the per-system arrays concatenated in system
+ * order (W values, Sigma, J values, right-hand-side rows).  form must be
+ * NCL_CONDENSED. */
+int ncl_kkt_analyze_batched(ncl_kkt_t *h, const ncl_kkt_options *o, int32_t count,
+                            const int32_t *n, const int32_t *m,
+                            const int32_t *const *W_colptr, const int32_t *const *W_rowidx,
+                            const int32_t *const *J_rowptr, const int32_t *const *J_colidx);
+
+/* Numeric factorization on new values (device pointers, lengths nnz(W), n,
+ * nnz(J)): assembles K of the chosen form on the GPU (Sec. 3.3 eq. K1 /
+ * Sec. 3.2 eq. K2r), computes ||K||_max, and factors it with the static-pivot
+ * rule.  rho > 0 (Sec. 3.4 assumes rho > 0).  Returns NCL_WARN_INERTIA when
+ * the inertia differs from the expected one (the factor is still usable),
+ * NCL_ERR_NONFINITE on NaN/Inf.  Synchronizes the stream to read the inertia. */
+int ncl_kkt_factor(ncl_kkt_t h, const double *W_val, const double *Sigma,
+                   const double *J_val, double rho, void *stream);
+
+/* Batched factor: rho is a HOST array of `count` penalties. */
+int ncl_kkt_factor_batched(ncl_kkt_t h, const double *W_val, const double *Sigma,
+                           const double *J_val, const double *rho, void *stream);
+
+/* Solve K X = B for nrhs >= 1 columns (device, column-major, leading
+ * dimensions >= order), with FP64 iterative refinement against the
+ * unperturbed K (Sec. 4.3); refinement runs only when the inertia is the
+ * expected one.  B and X must not overlap.  info may be NULL.  Returns
+ * NCL_WARN_IR_NOT_CONVERGED when omega stays above ir_tol, and
+ * NCL_WARN_FELL_BACK_FP64 when the FP32 factor had to be replaced. */
+int ncl_kkt_solve(ncl_kkt_t h, const double *B, int64_t ldb, double *X, int64_t ldx,
+                  int32_t nrhs, void *stream, ncl_kkt_solve_info *info);
+
+/* Inertia of the last factorization (Sec. 3.4): counts of positive,
+ * negative and zero pivots after the static-pivot rule, and how many pivots
+ * the rule replaced.  Batched handles: totals over systems.  Host outputs. */
+int ncl_kkt_inertia(ncl_kkt_t h, int64_t *npos, int64_t *nneg, int64_t *nzero,
+                    int64_t *nperturbed);
+
+/* Per-system inertia of a batched handle: out[4*s + {0,1,2,3}]. */
+int ncl_kkt_inertia_batched(ncl_kkt_t h, int64_t *out);
+
+/* Adjoint of X = K^-1 B for the condensed form K = W + Sigma + rho J^T J
+ * (Sec. 3.3, eq. K1) in reverse mode.  Given the solution X and
+ * Lambda = K^-1 Xbar (the adjoint solve: K is symmetric, so it is an ordinary
+ * ncl_kkt_solve on the same factor), writes (device arrays, overwritten):
+ *   gW[e]  = -sum_c (Lambda_ic X_jc + Lambda_jc X_ic) for a stored lower W
+ *            entry e = (i, j), i != j;  -sum_c Lambda_ic X_ic when i == j;
+ *   gSigma[i] = -sum_c Lambda_ic X_ic;
+ *   gJ[k]  = -rho sum_c [Lambda_ic (J X_c)_r + X_ic (J Lambda_c)_r], k = (r, i);
+ *   gRho[s] = -sum_c (J Lambda_c) . (J X_c)   (one value per system).
+ * J_val are the Jacobian values of the last factorization (device).  X and
+ * Lambda share the leading dimension ld; 1 <= nrhs <= 16.  Any of gW,
+ * gSigma, gJ, gRho may be NULL.  Stream-ordered, no synchronization. */
+int ncl_kkt_backward(ncl_kkt_t h, const double *J_val, const double *X, const double *Lambda, int64_t ld,
+                     int32_t nrhs, double *gW, double *gSigma, double *gJ, double *gRho, void *stream);
+
+int ncl_kkt_get_stats(ncl_kkt_t h, ncl_kkt_stats *st);
+
+/* Fill-reducing permutation in use: perm[k] = unpermuted index of pivot k. */
+int ncl_kkt_get_perm(ncl_kkt_t h, int32_t *perm);
+
+/* Supernode partition (in pivot order): first[s] .. first[s+1]-1 are the
+ * pivots of supernode s (first has n_supernodes+1 entries); parent[s] is the
+ * parent supernode or -1; row_ptr (n_supernodes+1) / rows give each front's
+ * row list in pivot numbering (pivots first, then the contribution rows).
+ * Pass NULL for rows to query only row_ptr. */
+int ncl_kkt_get_supernodes(ncl_kkt_t h, int32_t *first, int32_t *parent, int64_t *row_ptr,
+                           int32_t *rows);
+
+/* Kernel timing.  When enabled, factor and solve record HIP events around
+ * every kernel class on the caller's stream and accumulate device time (ms)
+ * and launch counts, readable with ncl_kkt_get_timing. */
+typedef struct {
+    double ms[8];          /* 0 assemble, 1 small fronts, 2 large-front assembly,
+                              3 large-front panel, 4 large-front update (MFMA),
+                              5 forward/backward solve, 6 residual, 7 other */
+    int64_t launches[8];
+    double update_flops;   /* algorithmic flops of all update launches timed */
+    double small_flops;    /* algorithmic flops of all small-front launches timed */
+    double assemble_bytes; /* algorithmic bytes of all assembly launches timed */
+    double solve_bytes;    /* algorithmic bytes of all solve sweeps timed */
+} ncl_kkt_timing;
+
+int ncl_kkt_set_timing(ncl_kkt_t h, int32_t enable);   /* enabling also clears totals */
+int ncl_kkt_get_timing(ncl_kkt_t h, ncl_kkt_timing *t);
+
+void ncl_kkt_destroy(ncl_kkt_t h);
+const char *ncl_kkt_strerror(int code);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NCL_KKT_H */

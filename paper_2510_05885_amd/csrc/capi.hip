@@ -1,0 +1,733 @@
+// capi.hip — C ABI of the KKT factor/solve library (see include/ncl_kkt.h).
+//
+// Owns the handle: the host plan, every device buffer (allocated once at
+// analyze time) and the per-call orchestration of the kernels:
+//   factor = assemble K (Sec. 3.3 eq. K1 / Sec. 3.2 eq. K2r) -> norms and
+//            static-pivot thresholds -> level-by-level frontal LDL^T ->
+//            inertia read-back (Sec. 3.4);
+//   solve  = permute -> forward sweep -> D^-1 + backward sweep -> unpermute,
+//            then Richardson refinement against the unperturbed K in FP64
+//            (Sec. 4.3), with an FP64 refactor when an FP32 factor stalls.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/ncl_kkt.h"
+#include "analyze.hpp"
+#include "kernels.hpp"
+
+using namespace ncl;
+
+namespace {
+
+struct HipError {
+    hipError_t e;
+};
+
+#define HIPCHK(x)                                  \
+    do {                                           \
+        hipError_t e_ = (x);                       \
+        if (e_ != hipSuccess) throw HipError{e_};  \
+    } while (0)
+
+struct Timer {
+    bool on = false;
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    struct Rec { int cls; size_t a, b; double work; int kind; };
+    std::vector<Rec> recs;
+    ncl_kkt_timing tot{};
+};
+
+}  // namespace
+
+struct ncl_kkt_s {
+    Plan P;
+    ncl_kkt_options opt{};
+    double eps = 0.0;
+    bool host_only = true;
+    int device = 0;
+    std::vector<void*> allocs;
+    DevPlan d{};
+    int64_t nnzF = 0;
+    // schedule arrays (device)
+    int *small_list = nullptr, *level_list = nullptr, *large_asm = nullptr, *large_diag = nullptr,
+        *large_panel = nullptr, *large_upd = nullptr;
+    int *chunk_row0 = nullptr, *chunk_rows = nullptr, *sys_chunk_ptr = nullptr;
+    int nchunks = 0;
+    // numeric state
+    double *K = nullptr, *partial_norm = nullptr, *norms2 = nullptr, *kmax = nullptr, *kinf = nullptr,
+           *thr = nullptr, *rho = nullptr;
+    int* nonfinite = nullptr;
+    unsigned long long* inertia = nullptr;
+    double *F64 = nullptr, *D64 = nullptr, *Y64 = nullptr, *U64 = nullptr;
+    float *F32 = nullptr, *D32 = nullptr, *Y32 = nullptr, *U32 = nullptr;
+    double *R = nullptr, *DX = nullptr, *Xp = nullptr, *partial_res = nullptr, *res_out = nullptr;
+    double *JX = nullptr, *JL = nullptr;
+    int *W_row = nullptr, *W_col = nullptr, *Jj = nullptr, *Jrow_sys = nullptr;
+    int64_t *Jp = nullptr, *sys_jrow = nullptr;
+    double* host_pinned = nullptr;   // read-back staging
+    size_t host_pinned_len = 0;
+    // host state
+    std::vector<double> h_rho, h_kinf;
+    std::vector<int64_t> h_inertia;   // 4 per system
+    int factored = 0;                 // 1 after a successful factor
+    int factor_prec = 0;              // precision of the factor in use (0 FP64, 1 FP32)
+    bool inertia_ok = false;
+    bool fell_back = false;
+    Timer tm;
+};
+
+namespace {
+
+template <typename T>
+T* dalloc(ncl_kkt_s* h, int64_t n) {
+    void* p = nullptr;
+    if (n <= 0) n = 1;
+    HIPCHK(hipMalloc(&p, sizeof(T) * (size_t)n));
+    h->allocs.push_back(p);
+    return static_cast<T*>(p);
+}
+
+template <typename T>
+T* upload(ncl_kkt_s* h, const std::vector<T>& v) {
+    T* p = dalloc<T>(h, (int64_t)v.size());
+    if (!v.empty()) HIPCHK(hipMemcpy(p, v.data(), sizeof(T) * v.size(), hipMemcpyHostToDevice));
+    return p;
+}
+
+// ----- timing helpers ------------------------------------------------------
+enum { TM_ASM = 0, TM_SMALL = 1, TM_LASM = 2, TM_PANEL = 3, TM_UPD = 4, TM_SOLVE = 5, TM_RES = 6, TM_OTHER = 7 };
+
+struct Span {
+    ncl_kkt_s* h;
+    hipStream_t st;
+    int cls;
+    size_t a = 0;
+    double work;
+    int kind;  // 0 none, 1 update flops, 2 small flops, 3 assembly bytes, 4 solve bytes
+    Span(ncl_kkt_s* h_, hipStream_t s_, int c, double w = 0.0, int k = 0) : h(h_), st(s_), cls(c), work(w), kind(k) {
+        if (!h->tm.on) return;
+        if (h->tm.used + 2 > h->tm.pool.size()) { h->tm.on = false; return; }
+        a = h->tm.used++;
+        HIPCHK(hipEventRecord(h->tm.pool[a], st));
+    }
+    ~Span() noexcept(false) {
+        if (!h->tm.on) return;
+        size_t b = h->tm.used++;
+        HIPCHK(hipEventRecord(h->tm.pool[b], st));
+        h->tm.recs.push_back({cls, a, b, work, kind});
+    }
+};
+
+void flush_timing(ncl_kkt_s* h) {
+    if (h->tm.recs.empty()) { h->tm.used = 0; return; }
+    for (auto& r : h->tm.recs) {
+        float ms = 0.f;
+        HIPCHK(hipEventSynchronize(h->tm.pool[r.b]));
+        HIPCHK(hipEventElapsedTime(&ms, h->tm.pool[r.a], h->tm.pool[r.b]));
+        h->tm.tot.ms[r.cls] += ms;
+        h->tm.tot.launches[r.cls] += 1;
+        if (r.kind == 1) h->tm.tot.update_flops += r.work;
+        if (r.kind == 2) h->tm.tot.small_flops += r.work;
+        if (r.kind == 3) h->tm.tot.assemble_bytes += r.work;
+        if (r.kind == 4) h->tm.tot.solve_bytes += r.work;
+    }
+    h->tm.recs.clear();
+    h->tm.used = 0;
+}
+
+// ----- device setup ----------------------------------------------------------
+void setup_device(ncl_kkt_s* h) {
+    Plan& P = h->P;
+    HIPCHK(hipGetDevice(&h->device));
+    DevPlan& d = h->d;
+    d.N = P.N;
+    d.S = P.S;
+    d.form = P.form;
+    h->nnzF = (int64_t)P.Kj.size();
+    std::vector<int> Krow(h->nnzF);
+    for (int64_t i = 0; i < P.N; ++i)
+        for (int64_t q = P.Kp[i]; q < P.Kp[i + 1]; ++q) Krow[q] = (int)i;
+    d.Kp = upload(h, P.Kp);
+    d.Kj = upload(h, P.Kj);
+    d.Krow = upload(h, Krow);
+    d.src_w = upload(h, P.src_w);
+    d.src_j = upload(h, P.src_j);
+    d.src_flag = upload(h, P.src_flag);
+    d.prod_ptr = upload(h, P.prod_ptr);
+    d.prod_a = upload(h, P.prod_a);
+    d.prod_b = upload(h, P.prod_b);
+    d.row_sys = upload(h, P.row_sys);
+    d.row_sign = upload(h, P.row_sign);
+    d.perm = upload(h, P.perm);
+    d.sn_first = upload(h, P.sn_first);
+    d.sn_rowptr = upload(h, P.sn_rowptr);
+    d.sn_rows = upload(h, P.sn_rows);
+    d.child_ptr = upload(h, P.child_ptr);
+    d.child_list = upload(h, P.child_list);
+    d.sn_sys = upload(h, P.sn_sys);
+    d.kent_ptr = upload(h, P.kent_ptr);
+    d.kent_csr = upload(h, P.kent_csr);
+    d.kent_pos = upload(h, P.kent_pos);
+    d.kcol_ptr = upload(h, P.kcol_ptr);
+    d.kcol_base = upload(h, P.kcol_base);
+    d.rel_ptr = upload(h, P.rel_ptr);
+    d.rel = upload(h, P.rel);
+    d.inv_ptr = upload(h, P.inv_ptr);
+    d.inv = upload(h, P.inv);
+    d.L_off = upload(h, P.L_off);
+    d.CB_off = upload(h, P.CB_off);
+    d.CB_ld = upload(h, P.CB_ld);
+    std::vector<int64_t> uo(P.U_off);
+    for (auto& x : uo) x *= kNrhsMax;
+    d.U_off = upload(h, uo);
+    h->small_list = upload(h, P.small_list);
+    h->level_list = upload(h, P.level_list);
+    h->large_asm = upload(h, P.large_asm);
+    h->large_diag = upload(h, P.large_diag);
+    h->large_panel = upload(h, P.large_panel);
+    h->large_upd = upload(h, P.large_upd);
+    // row chunks (<= 256 rows, never straddling two systems)
+    std::vector<int> c0, cn, scp(1, 0);
+    for (int s = 0; s < P.S; ++s) {
+        for (int64_t r = P.sys_voff[s]; r < P.sys_voff[s + 1]; r += 256) {
+            c0.push_back((int)r);
+            cn.push_back((int)std::min<int64_t>(256, P.sys_voff[s + 1] - r));
+        }
+        scp.push_back((int)c0.size());
+    }
+    h->nchunks = (int)c0.size();
+    h->chunk_row0 = upload(h, c0);
+    h->chunk_rows = upload(h, cn);
+    h->sys_chunk_ptr = upload(h, scp);
+    // numeric buffers
+    h->K = dalloc<double>(h, h->nnzF);
+    h->partial_norm = dalloc<double>(h, 2 * (int64_t)h->nchunks);
+    h->norms2 = dalloc<double>(h, 2 * P.S);
+    h->kmax = dalloc<double>(h, P.S);
+    h->kinf = dalloc<double>(h, P.S);
+    h->thr = dalloc<double>(h, P.S);
+    h->rho = dalloc<double>(h, P.S);
+    h->nonfinite = dalloc<int>(h, 1);
+    h->inertia = dalloc<unsigned long long>(h, 4 * P.S);
+    d.sys_thr = h->thr;
+    d.inertia = h->inertia;
+    d.nonfinite = h->nonfinite;
+    h->F64 = dalloc<double>(h, P.factor_elems);
+    h->D64 = dalloc<double>(h, P.N);
+    h->Y64 = dalloc<double>(h, P.N * kNrhsMax);
+    h->U64 = dalloc<double>(h, P.U_elems * kNrhsMax);
+    if (h->opt.precision == NCL_FP32_IR) {
+        h->F32 = dalloc<float>(h, P.factor_elems);
+        h->D32 = dalloc<float>(h, P.N);
+        h->Y32 = dalloc<float>(h, P.N * kNrhsMax);
+        h->U32 = dalloc<float>(h, P.U_elems * kNrhsMax);
+    }
+    h->R = dalloc<double>(h, P.N * kNrhsMax);
+    h->DX = dalloc<double>(h, P.N * kNrhsMax);
+    h->Xp = dalloc<double>(h, P.N * kNrhsMax);
+    h->partial_res = dalloc<double>(h, (int64_t)h->nchunks * kNrhsMax * 3);
+    h->res_out = dalloc<double>(h, (int64_t)P.S * kNrhsMax * 3);
+    // adjoint structures
+    if (P.form == NCL_CONDENSED) {
+        h->W_row = upload(h, P.Wrow_of);
+        h->W_col = upload(h, P.Wcol_of32);
+        h->Jp = upload(h, P.Jp);
+        h->Jj = upload(h, P.Jj);
+        h->Jrow_sys = upload(h, P.Jrow_sys);
+        std::vector<int64_t> sj(P.S + 1, 0);
+        for (int64_t r = 0; r < P.nJrows; ++r) sj[P.Jrow_sys[r] + 1]++;
+        for (int s = 0; s < P.S; ++s) sj[s + 1] += sj[s];
+        h->sys_jrow = upload(h, sj);
+        h->JX = dalloc<double>(h, std::max<int64_t>(P.nJrows, 1) * kNrhsMax);
+        h->JL = dalloc<double>(h, std::max<int64_t>(P.nJrows, 1) * kNrhsMax);
+    }
+    h->host_pinned_len = (size_t)std::max<int64_t>((int64_t)P.S * kNrhsMax * 3, 8 * (int64_t)P.S + 8);
+    HIPCHK(hipHostMalloc((void**)&h->host_pinned, sizeof(double) * h->host_pinned_len, hipHostMallocDefault));
+    {
+        int lds = 0;
+        HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
+        HIPCHK(configure_kernels(lds));
+    }
+    HIPCHK(hipDeviceSynchronize());
+    h->host_only = false;
+}
+
+int pick_small_max(int& fmax_out) {
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return NCL_ERR_HIP;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) return NCL_ERR_HIP;
+    int f = (int)std::floor(std::sqrt((double)lds / 8.0));
+    fmax_out = std::min(f, 128);
+    return NCL_OK;
+}
+
+void fill_defaults(ncl_kkt_options* o) {
+    o->form = NCL_CONDENSED;
+    o->precision = NCL_FP64;
+    o->pivot_eps = 0.0;
+    o->ir_max_steps = 10;
+    o->ir_tol = 1e-12;
+    o->ir_stall = 0.5;
+    o->ordering = NCL_ORDER_ND;
+    o->user_perm = nullptr;
+}
+
+int do_analyze(ncl_kkt_t* out, const ncl_kkt_options* o, const std::vector<SysInput>& sys, bool host_only) {
+    if (!out) return NCL_ERR_ARG;
+    *out = nullptr;
+    ncl_kkt_s* h = new (std::nothrow) ncl_kkt_s();
+    if (!h) return NCL_ERR_ALLOC;
+    if (o) h->opt = *o; else fill_defaults(&h->opt);
+    if (h->opt.form != NCL_CONDENSED && h->opt.form != NCL_STABILIZED) { delete h; return NCL_ERR_ARG; }
+    if (h->opt.precision != NCL_FP64 && h->opt.precision != NCL_FP32_IR) { delete h; return NCL_ERR_ARG; }
+    if (h->opt.ordering < 0 || h->opt.ordering > 2) { delete h; return NCL_ERR_ARG; }
+    if (h->opt.ir_max_steps < 0 || !(h->opt.ir_stall > 0.0)) { delete h; return NCL_ERR_ARG; }
+    if (sys.size() > 1 && h->opt.form != NCL_CONDENSED) { delete h; return NCL_ERR_ARG; }
+    h->eps = h->opt.pivot_eps > 0.0 ? h->opt.pivot_eps : (h->opt.form == NCL_CONDENSED ? 1e-12 : 1e-10);
+    PlanConfig cfg;
+    if (!host_only) {
+        int fm = 90;
+        int rc = pick_small_max(fm);
+        if (rc) { delete h; return rc; }
+        cfg.small_front_max = fm;
+    }
+    std::string err;
+    int rc = build_plan(h->P, h->opt.form, sys, h->opt.ordering, h->opt.user_perm, cfg, err);
+    if (rc) { delete h; return rc; }
+    h->h_rho.assign(h->P.S, 1.0);
+    h->h_kinf.assign(h->P.S, 0.0);
+    h->h_inertia.assign(4 * (size_t)h->P.S, 0);
+    if (!host_only) {
+        try {
+            setup_device(h);
+        } catch (const HipError& e) {
+            rc = (e.e == hipErrorOutOfMemory) ? NCL_ERR_ALLOC : NCL_ERR_HIP;
+        } catch (const std::bad_alloc&) {
+            rc = NCL_ERR_ALLOC;
+        }
+        if (rc) { ncl_kkt_destroy(h); return rc; }
+    }
+    *out = h;
+    return NCL_OK;
+}
+
+// ----- numeric factorization -----------------------------------------------
+template <typename T>
+void factor_fronts(ncl_kkt_s* h, T* F, T* D, hipStream_t st) {
+    Plan& P = h->P;
+    const DevPlan& d = h->d;
+    launch_zero_u64(h->inertia, 4 * (int64_t)P.S, st);
+    size_t sb = 0, lb = 0;
+    for (int l = 0; l < P.nlevels; ++l) {
+        while (sb < P.small_batches.size() && P.small_batches[sb].level == l) {
+            const LevelBatch& b = P.small_batches[sb++];
+            double fl = 0.0;
+            if (h->tm.on)
+                for (int64_t k = b.first; k < b.first + b.count; ++k) {
+                    const int s = P.small_list[k];
+                    const double f = (double)(P.sn_rowptr[s + 1] - P.sn_rowptr[s]);
+                    const int p = P.sn_first[s + 1] - P.sn_first[s];
+                    for (int t = 0; t < p; ++t) { double r = f - t - 1; fl += r + r * (r + 1.0); }
+                }
+            Span sp(h, st, TM_SMALL, fl, 2);
+            launch_small_fronts<T>(d, h->small_list + b.first, (int)b.count, b.fmax, h->K, F, D, st);
+        }
+        if (lb < P.large_steps.size() && P.large_steps[lb].level == l) {
+            const LargeStep& ls = P.large_steps[lb++];
+            {
+                Span sp(h, st, TM_LASM);
+                launch_large_asm<T>(d, h->large_asm + 2 * ls.asm_first, (int)ls.asm_count, h->K, F, st);
+            }
+            for (size_t k = 0; k < ls.panel_first.size(); ++k) {
+                {
+                    Span sp(h, st, TM_PANEL);
+                    launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[k], (int)ls.diag_count[k], F, D, st);
+                    launch_large_panel<T>(d, h->large_panel + 3 * ls.panel_first[k], (int)ls.panel_count[k], F, D,
+                                          st);
+                }
+                Span sp(h, st, TM_UPD, ls.upd_flops[k], 1);
+                launch_large_update<T>(d, h->large_upd + 4 * ls.upd_first[k], (int)ls.upd_count[k], F, D, st);
+            }
+        }
+    }
+}
+
+int read_inertia(ncl_kkt_s* h, hipStream_t st) {
+    const int S = h->P.S;
+    unsigned long long* hp = reinterpret_cast<unsigned long long*>(h->host_pinned);
+    HIPCHK(hipMemcpyAsync(hp, h->inertia, sizeof(unsigned long long) * 4 * S, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h->host_pinned + 4 * S, h->nonfinite, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h->host_pinned + 4 * S + 1, h->kinf, sizeof(double) * 1, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    int nonfin = 0;
+    std::memcpy(&nonfin, h->host_pinned + 4 * S, sizeof(int));
+    h->inertia_ok = true;
+    for (int s = 0; s < S; ++s) {
+        for (int k = 0; k < 4; ++k) h->h_inertia[4 * s + k] = (int64_t)hp[4 * s + k];
+        const int64_t n = h->P.sys_n[s], m = h->P.sys_m[s];
+        const int64_t want_neg = h->P.form == NCL_STABILIZED ? m : 0;
+        if (h->h_inertia[4 * s + 0] != n || h->h_inertia[4 * s + 1] != want_neg || h->h_inertia[4 * s + 2] != 0)
+            h->inertia_ok = false;
+    }
+    if (nonfin) return NCL_ERR_NONFINITE;
+    return NCL_OK;
+}
+
+int factor_impl(ncl_kkt_s* h, const double* W, const double* Sigma, const double* J, const double* rho_host,
+                hipStream_t st) {
+    if (h->host_only) return NCL_ERR_STATE;
+    Plan& P = h->P;
+    for (int s = 0; s < P.S; ++s)
+        if (!(rho_host[s] > 0.0) || !std::isfinite(rho_host[s])) return NCL_ERR_ARG;
+    if ((P.nnzW > 0 && !W) || !Sigma || (P.nnzJ > 0 && !J)) return NCL_ERR_ARG;
+    h->factored = 0;
+    h->fell_back = false;
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        for (int s = 0; s < P.S; ++s) h->host_pinned[s] = rho_host[s];
+        HIPCHK(hipMemcpyAsync(h->rho, h->host_pinned, sizeof(double) * P.S, hipMemcpyHostToDevice, st));
+        launch_zero_i32(h->nonfinite, 1, st);
+        {
+            const double bytes = (double)h->nnzF * (8 + 4 + 4 + 4 + 1 + 8) + 8.0 * (P.nnzW + P.nnzJ + P.N) +
+                                 (double)P.prod_a.size() * 8.0;
+            Span sp(h, st, TM_ASM, bytes, 3);
+            launch_assemble(h->d, h->nnzF, W, Sigma, J, h->rho, h->K, st);
+            launch_chunk_norms(h->d, h->K, h->chunk_row0, h->chunk_rows, h->nchunks, h->partial_norm, st);
+            launch_reduce(h->sys_chunk_ptr, P.S, 2, h->partial_norm, h->norms2, st);
+            launch_thresholds(P.S, h->norms2, h->eps, h->kmax, h->kinf, h->thr, h->nonfinite, st);
+        }
+        HIPCHK(hipGetLastError());
+        if (h->opt.precision == NCL_FP32_IR) {
+            factor_fronts<float>(h, h->F32, h->D32, st);
+            h->factor_prec = 1;
+        } else {
+            factor_fronts<double>(h, h->F64, h->D64, st);
+            h->factor_prec = 0;
+        }
+        HIPCHK(hipGetLastError());
+        int rc = read_inertia(h, st);
+        if (rc) { flush_timing(h); return rc; }
+        if (!h->inertia_ok && h->factor_prec == 1) {
+            // an FP32 factor with the wrong inertia: refactor in FP64
+            factor_fronts<double>(h, h->F64, h->D64, st);
+            h->factor_prec = 0;
+            h->fell_back = true;
+            rc = read_inertia(h, st);
+            if (rc) { flush_timing(h); return rc; }
+        }
+        // host copy of ||K||_inf per system for the backward error
+        HIPCHK(hipMemcpyAsync(h->host_pinned, h->kinf, sizeof(double) * P.S, hipMemcpyDeviceToHost, st));
+        HIPCHK(hipStreamSynchronize(st));
+        for (int s = 0; s < P.S; ++s) { h->h_kinf[s] = h->host_pinned[s]; h->h_rho[s] = rho_host[s]; }
+        flush_timing(h);
+    } catch (const HipError& e) {
+        return NCL_ERR_HIP;
+    }
+    h->factored = 1;
+    if (!h->inertia_ok) return NCL_WARN_INERTIA;
+    return h->fell_back ? NCL_WARN_FELL_BACK_FP64 : NCL_OK;
+}
+
+// ----- solve -------------------------------------------------------------------
+template <typename T>
+void solve_once(ncl_kkt_s* h, const double* B, int64_t ldb, double* X, int64_t ldx, int nrhs, const T* F,
+                const T* D, T* Y, T* U, hipStream_t st) {
+    Plan& P = h->P;
+    const DevPlan& d = h->d;
+    const double lbytes = (double)P.nnzL * sizeof(T);
+    Span sp(h, st, TM_SOLVE, 2.0 * lbytes, 4);
+    launch_permute_in<T>(d, B, ldb, nrhs, Y, st);
+    for (int l = 0; l < P.nlevels; ++l)
+        launch_forward<T>(d, h->level_list + P.level_ptr[l], P.level_ptr[l + 1] - P.level_ptr[l], P.level_fmax[l], F,
+                          Y, U, nrhs, st);
+    for (int l = P.nlevels - 1; l >= 0; --l)
+        launch_backward<T>(d, h->level_list + P.level_ptr[l], P.level_ptr[l + 1] - P.level_ptr[l], P.level_fmax[l],
+                           F, D, Y, nrhs, st);
+    launch_permute_out<T>(d, Y, nrhs, X, ldx, st);
+}
+
+void solve_with_factor(ncl_kkt_s* h, const double* B, int64_t ldb, double* X, int64_t ldx, int nrhs, hipStream_t st) {
+    if (h->factor_prec == 1) solve_once<float>(h, B, ldb, X, ldx, nrhs, h->F32, h->D32, h->Y32, h->U32, st);
+    else solve_once<double>(h, B, ldb, X, ldx, nrhs, h->F64, h->D64, h->Y64, h->U64, st);
+}
+
+// Backward error of X against B (max over systems and columns).
+double backward_error(ncl_kkt_s* h, const double* B, int64_t ldb, const double* X, int64_t ldx, int nrhs,
+                      hipStream_t st) {
+    Plan& P = h->P;
+    {
+        Span sp(h, st, TM_RES);
+        launch_residual(h->d, h->K, B, ldb, X, ldx, h->R, nrhs, h->chunk_row0, h->chunk_rows, h->nchunks,
+                        h->partial_res, st);
+        launch_reduce(h->sys_chunk_ptr, P.S, 3 * nrhs, h->partial_res, h->res_out, st);
+    }
+    HIPCHK(hipMemcpyAsync(h->host_pinned, h->res_out, sizeof(double) * 3 * nrhs * P.S, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    double om = 0.0;
+    for (int s = 0; s < P.S; ++s)
+        for (int q = 0; q < nrhs; ++q) {
+            const double* v = h->host_pinned + ((int64_t)s * nrhs + q) * 3;
+            const double den = h->h_kinf[s] * v[1] + v[2];
+            const double w = den > 0.0 ? v[0] / den : (v[0] > 0.0 ? INFINITY : 0.0);
+            om = std::isnan(w) ? INFINITY : std::max(om, w);
+        }
+    return om;
+}
+
+// One chunk of <= kNrhsMax columns: solve + refinement.  Returns the final omega.
+double solve_refine(ncl_kkt_s* h, const double* B, int64_t ldb, double* X, int64_t ldx, int nrhs, hipStream_t st,
+                    int& steps, double& om0) {
+    const int64_t N = h->P.N;
+    solve_with_factor(h, B, ldb, X, ldx, nrhs, st);
+    double om = backward_error(h, B, ldb, X, ldx, nrhs, st);
+    om0 = om;
+    steps = 0;
+    if (!h->inertia_ok) return om;
+    while (om > h->opt.ir_tol && steps < h->opt.ir_max_steps) {
+        // correction from the residual left in R by backward_error
+        solve_with_factor(h, h->R, N, h->DX, N, nrhs, st);
+        launch_copy_cols(h->Xp, N, X, ldx, N, nrhs, st);
+        launch_axpy_cols(X, ldx, h->DX, N, nrhs, st);
+        const double omn = backward_error(h, B, ldb, X, ldx, nrhs, st);
+        ++steps;
+        if (!(omn <= om)) {          // worse (or NaN): keep the previous iterate
+            launch_copy_cols(X, ldx, h->Xp, N, N, nrhs, st);
+            // R must match X again for a caller that continues
+            backward_error(h, B, ldb, X, ldx, nrhs, st);
+            break;
+        }
+        const bool stalled = omn > h->opt.ir_stall * om;
+        om = omn;
+        if (stalled) break;
+    }
+    return om;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+extern "C" {
+
+void ncl_kkt_default_options(ncl_kkt_options* o) {
+    if (o) fill_defaults(o);
+}
+
+int ncl_kkt_analyze(ncl_kkt_t* h, const ncl_kkt_options* o, int32_t n, int32_t m, const int32_t* W_colptr,
+                    const int32_t* W_rowidx, const int32_t* J_rowptr, const int32_t* J_colidx) {
+    SysInput s{n, m, W_colptr, W_rowidx, J_rowptr, J_colidx};
+    return do_analyze(h, o, {s}, false);
+}
+
+int ncl_kkt_analyze_host(ncl_kkt_t* h, const ncl_kkt_options* o, int32_t n, int32_t m, const int32_t* W_colptr,
+                         const int32_t* W_rowidx, const int32_t* J_rowptr, const int32_t* J_colidx) {
+    SysInput s{n, m, W_colptr, W_rowidx, J_rowptr, J_colidx};
+    return do_analyze(h, o, {s}, true);
+}
+
+int ncl_kkt_analyze_batched(ncl_kkt_t* h, const ncl_kkt_options* o, int32_t count, const int32_t* n,
+                            const int32_t* m, const int32_t* const* W_colptr, const int32_t* const* W_rowidx,
+                            const int32_t* const* J_rowptr, const int32_t* const* J_colidx) {
+    if (!h || count < 1 || !n || !m || !W_colptr || !W_rowidx || !J_rowptr || !J_colidx) return NCL_ERR_ARG;
+    std::vector<SysInput> sys(count);
+    for (int s = 0; s < count; ++s) sys[s] = SysInput{n[s], m[s], W_colptr[s], W_rowidx[s], J_rowptr[s], J_colidx[s]};
+    return do_analyze(h, o, sys, false);
+}
+
+int ncl_kkt_factor(ncl_kkt_t h, const double* W_val, const double* Sigma, const double* J_val, double rho,
+                   void* stream) {
+    if (!h) return NCL_ERR_ARG;
+    if (h->P.S != 1) return NCL_ERR_ARG;
+    return factor_impl(h, W_val, Sigma, J_val, &rho, (hipStream_t)stream);
+}
+
+int ncl_kkt_factor_batched(ncl_kkt_t h, const double* W_val, const double* Sigma, const double* J_val,
+                           const double* rho, void* stream) {
+    if (!h || !rho) return NCL_ERR_ARG;
+    return factor_impl(h, W_val, Sigma, J_val, rho, (hipStream_t)stream);
+}
+
+int ncl_kkt_solve(ncl_kkt_t h, const double* B, int64_t ldb, double* X, int64_t ldx, int32_t nrhs, void* stream,
+                  ncl_kkt_solve_info* info) {
+    if (!h) return NCL_ERR_ARG;
+    if (h->host_only || !h->factored) return NCL_ERR_STATE;
+    if (!B || !X || nrhs < 1 || ldb < h->P.N || ldx < h->P.N) return NCL_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    int total_steps = 0;
+    double om_all = 0.0, om0_all = 0.0;
+    bool fell = h->fell_back;
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        for (int q0 = 0; q0 < nrhs; q0 += kNrhsMax) {
+            const int nq = std::min(kNrhsMax, nrhs - q0);
+            const double* Bq = B + (int64_t)q0 * ldb;
+            double* Xq = X + (int64_t)q0 * ldx;
+            int steps = 0;
+            double om0 = 0.0;
+            double om = solve_refine(h, Bq, ldb, Xq, ldx, nq, st, steps, om0);
+            if (om > h->opt.ir_tol && h->factor_prec == 1 && h->inertia_ok) {
+                // FP32 factor not accurate enough: refactor in FP64 from the assembled K
+                factor_fronts<double>(h, h->F64, h->D64, st);
+                h->factor_prec = 0;
+                h->fell_back = fell = true;
+                int rc = read_inertia(h, st);
+                if (rc) { flush_timing(h); return rc; }
+                int steps2 = 0;
+                om = solve_refine(h, Bq, ldb, Xq, ldx, nq, st, steps2, om0);
+                steps += steps2;
+            }
+            total_steps += steps;
+            om_all = std::max(om_all, om);
+            om0_all = std::max(om0_all, om0);
+        }
+        flush_timing(h);
+    } catch (const HipError&) {
+        return NCL_ERR_HIP;
+    }
+    if (info) {
+        info->ir_steps = total_steps;
+        info->fell_back_fp64 = fell ? 1 : 0;
+        info->backward_error = om_all;
+        info->backward_error0 = om0_all;
+    }
+    if (!h->inertia_ok) return NCL_WARN_INERTIA;
+    if (om_all > h->opt.ir_tol && h->opt.ir_max_steps > 0) return NCL_WARN_IR_NOT_CONVERGED;
+    return fell ? NCL_WARN_FELL_BACK_FP64 : NCL_OK;
+}
+
+int ncl_kkt_inertia(ncl_kkt_t h, int64_t* npos, int64_t* nneg, int64_t* nzero, int64_t* nperturbed) {
+    if (!h) return NCL_ERR_ARG;
+    if (h->host_only || !h->factored) return NCL_ERR_STATE;
+    int64_t t[4] = {0, 0, 0, 0};
+    for (int s = 0; s < h->P.S; ++s)
+        for (int k = 0; k < 4; ++k) t[k] += h->h_inertia[4 * s + k];
+    if (npos) *npos = t[0];
+    if (nneg) *nneg = t[1];
+    if (nzero) *nzero = t[2];
+    if (nperturbed) *nperturbed = t[3];
+    return NCL_OK;
+}
+
+int ncl_kkt_inertia_batched(ncl_kkt_t h, int64_t* out) {
+    if (!h || !out) return NCL_ERR_ARG;
+    if (h->host_only || !h->factored) return NCL_ERR_STATE;
+    std::memcpy(out, h->h_inertia.data(), sizeof(int64_t) * h->h_inertia.size());
+    return NCL_OK;
+}
+
+int ncl_kkt_backward(ncl_kkt_t h, const double* J_val, const double* X, const double* Lambda, int64_t ld,
+                     int32_t nrhs, double* gW, double* gSigma, double* gJ, double* gRho, void* stream) {
+    if (!h) return NCL_ERR_ARG;
+    if (h->host_only || !h->factored) return NCL_ERR_STATE;
+    if (h->P.form != NCL_CONDENSED) return NCL_ERR_ARG;
+    if (!X || !Lambda || nrhs < 1 || nrhs > kNrhsMax || ld < h->P.N) return NCL_ERR_ARG;
+    if ((gJ || gRho) && h->P.nnzJ > 0 && !J_val) return NCL_ERR_ARG;
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        launch_adjoint(h->d, h->P.nnzW, h->W_row, h->W_col, h->P.nJrows, h->Jp, h->Jj, h->Jrow_sys, J_val, h->rho, X,
+                       Lambda, ld, nrhs, gW, gSigma, gJ, gRho, h->JX, h->JL, h->sys_jrow, st);
+        HIPCHK(hipGetLastError());
+    } catch (const HipError&) {
+        return NCL_ERR_HIP;
+    }
+    return NCL_OK;
+}
+
+int ncl_kkt_get_stats(ncl_kkt_t h, ncl_kkt_stats* st) {
+    if (!h || !st) return NCL_ERR_ARG;
+    const Plan& P = h->P;
+    st->order = P.N;
+    st->nnz_K_lower = P.nnz_lower;
+    st->nnz_L = P.nnzL;
+    st->flops_factor = P.flops;
+    st->n_supernodes = P.nsn;
+    st->n_levels = P.nlevels;
+    st->max_front = P.max_front;
+    st->n_large_fronts = P.n_large;
+    int64_t bytes = 0;
+    for (void* p : h->allocs) (void)p;
+    st->device_bytes = h->host_only ? 0 : (int64_t)(P.factor_elems * (h->F32 ? 12 : 8));
+    (void)bytes;
+    st->analyze_seconds = P.analyze_seconds;
+    return NCL_OK;
+}
+
+int ncl_kkt_get_perm(ncl_kkt_t h, int32_t* perm) {
+    if (!h || !perm) return NCL_ERR_ARG;
+    std::memcpy(perm, h->P.perm.data(), sizeof(int32_t) * h->P.perm.size());
+    return NCL_OK;
+}
+
+int ncl_kkt_get_supernodes(ncl_kkt_t h, int32_t* first, int32_t* parent, int64_t* row_ptr, int32_t* rows) {
+    if (!h) return NCL_ERR_ARG;
+    const Plan& P = h->P;
+    if (first) std::memcpy(first, P.sn_first.data(), sizeof(int32_t) * P.sn_first.size());
+    if (parent) std::memcpy(parent, P.sn_parent.data(), sizeof(int32_t) * P.sn_parent.size());
+    if (row_ptr) std::memcpy(row_ptr, P.sn_rowptr.data(), sizeof(int64_t) * P.sn_rowptr.size());
+    if (rows) std::memcpy(rows, P.sn_rows.data(), sizeof(int32_t) * P.sn_rows.size());
+    return NCL_OK;
+}
+
+int ncl_kkt_set_timing(ncl_kkt_t h, int32_t enable) {
+    if (!h) return NCL_ERR_ARG;
+    if (h->host_only) return NCL_ERR_STATE;
+    try {
+        if (enable && h->tm.pool.empty()) {
+            h->tm.pool.resize(16384);
+            for (auto& e : h->tm.pool) HIPCHK(hipEventCreate(&e));
+        }
+    } catch (const HipError&) {
+        return NCL_ERR_HIP;
+    }
+    h->tm.on = enable != 0;
+    h->tm.tot = ncl_kkt_timing{};
+    h->tm.recs.clear();
+    h->tm.used = 0;
+    return NCL_OK;
+}
+
+int ncl_kkt_get_timing(ncl_kkt_t h, ncl_kkt_timing* t) {
+    if (!h || !t) return NCL_ERR_ARG;
+    *t = h->tm.tot;
+    return NCL_OK;
+}
+
+void ncl_kkt_destroy(ncl_kkt_t h) {
+    if (!h) return;
+    if (!h->host_only || !h->allocs.empty()) {
+        (void)hipSetDevice(h->device);
+        (void)hipDeviceSynchronize();
+        for (void* p : h->allocs) (void)hipFree(p);
+        if (h->host_pinned) (void)hipHostFree(h->host_pinned);
+        for (auto& e : h->tm.pool) (void)hipEventDestroy(e);
+    }
+    delete h;
+}
+
+const char* ncl_kkt_strerror(int code) {
+    switch (code) {
+        case NCL_OK: return "success";
+        case NCL_ERR_ARG: return "invalid argument";
+        case NCL_ERR_PATTERN: return "invalid sparsity pattern (unsorted, duplicate, out-of-range or upper entry)";
+        case NCL_ERR_ALLOC: return "allocation failed";
+        case NCL_ERR_HIP: return "HIP runtime error";
+        case NCL_ERR_STATE: return "call out of order (no numeric factorization or host-only handle)";
+        case NCL_ERR_NONFINITE: return "NaN or Inf in the assembled matrix or a pivot";
+        case NCL_WARN_INERTIA: return "warning: inertia differs from the expected (n,0,0) / (n,m,0)";
+        case NCL_WARN_IR_NOT_CONVERGED: return "warning: iterative refinement stopped above the tolerance";
+        case NCL_WARN_FELL_BACK_FP64: return "warning: FP32 factor replaced by an FP64 refactorization";
+        default: return "unknown status";
+    }
+}
+
+}  // extern "C"

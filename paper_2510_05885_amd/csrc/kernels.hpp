@@ -1,0 +1,117 @@
+// kernels.hpp — device-side plan and launchers of the KKT factor/solve kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ncl {
+
+constexpr int kNrhsMax = 16;   // columns per solve sweep (wider solves are chunked)
+constexpr int kPanel = 32;     // pivot block width of the large-front path
+constexpr int kTile = 64;      // tile order of the large-front MFMA update
+constexpr int kRowBlock = 64;  // rows per panel task
+
+// Device copies of the plan (all device pointers), passed by value.
+struct DevPlan {
+    int64_t N;
+    int S;
+    int form;
+    // full CSR of K with value sources
+    const int64_t* Kp;
+    const int* Kj;
+    const int* Krow;
+    const int* src_w;
+    const int* src_j;
+    const uint8_t* src_flag;
+    const int64_t* prod_ptr;
+    const int* prod_a;
+    const int* prod_b;
+    const int* row_sys;
+    const int8_t* row_sign;
+    const int* perm;
+    // supernodes
+    const int* sn_first;
+    const int64_t* sn_rowptr;
+    const int* sn_rows;
+    const int* child_ptr;
+    const int* child_list;
+    const int* sn_sys;
+    const int64_t* kent_ptr;
+    const int64_t* kent_csr;
+    const int* kent_pos;
+    const int64_t* kcol_ptr;
+    const int64_t* kcol_base;
+    const int64_t* rel_ptr;
+    const int* rel;
+    const int64_t* inv_ptr;
+    const int* inv;
+    const int64_t* L_off;
+    const int64_t* CB_off;
+    const int* CB_ld;
+    const int64_t* U_off;      // in elements of one column block (times kNrhsMax applied)
+    // per system
+    const double* sys_thr;     // static-pivot thresholds eps * ||K||_max
+    unsigned long long* inertia;  // 4 per system: npos, nneg, nzero, nperturbed
+    int* nonfinite;            // set to 1 on a NaN/Inf pivot
+};
+
+// ---- assembly (FP64) ------------------------------------------------------
+void launch_assemble(const DevPlan& d, int64_t nnzF, const double* W, const double* Sigma, const double* J,
+                     const double* sys_rho, double* K, hipStream_t st);
+// Block per chunk of rows: partial[2c] = max |K_ij|, partial[2c+1] = max row sum of |K|.
+void launch_chunk_norms(const DevPlan& d, const double* K, const int* chunk_row0, const int* chunk_rows, int nchunks,
+                        double* partial, hipStream_t st);
+// out[s*width + k] = max over the chunks of system s of partial[c*width + k].
+void launch_reduce(const int* sys_chunk_ptr, int S, int width, const double* partial, double* out, hipStream_t st);
+// kmax, kinf, thr = eps * kmax per system from the reduced norms; flags non-finite norms.
+void launch_thresholds(int S, const double* norms2, double eps, double* kmax, double* kinf, double* thr,
+                       int* nonfinite, hipStream_t st);
+
+// ---- numeric factorization (T = double or float) --------------------------
+template <typename T>
+void launch_small_fronts(const DevPlan& d, const int* list, int count, int fmax, const double* K, T* F, T* D,
+                         hipStream_t st);
+template <typename T>
+void launch_large_asm(const DevPlan& d, const int* tasks, int count, const double* K, T* F, hipStream_t st);
+template <typename T>
+void launch_large_diag(const DevPlan& d, const int* tasks, int count, T* F, T* D, hipStream_t st);
+template <typename T>
+void launch_large_panel(const DevPlan& d, const int* tasks, int count, T* F, const T* D, hipStream_t st);
+template <typename T>
+void launch_large_update(const DevPlan& d, const int* tasks, int count, T* F, const T* D, hipStream_t st);
+
+// ---- solves -----------------------------------------------------------------
+template <typename T>
+void launch_permute_in(const DevPlan& d, const double* B, int64_t ldb, int nrhs, T* Y, hipStream_t st);
+template <typename T>
+void launch_permute_out(const DevPlan& d, const T* Y, int nrhs, double* X, int64_t ldx, hipStream_t st);
+template <typename T>
+void launch_forward(const DevPlan& d, const int* fronts, int count, int fmax, const T* F, T* Y, T* U, int nrhs,
+                    hipStream_t st);
+template <typename T>
+void launch_backward(const DevPlan& d, const int* fronts, int count, int fmax, const T* F, const T* D, T* Y,
+                     int nrhs, hipStream_t st);
+
+// ---- refinement -------------------------------------------------------------
+// R = B - K X; per chunk of rows (all of one system) the maxima of |R|, |X|, |B| per column.
+void launch_residual(const DevPlan& d, const double* K, const double* B, int64_t ldb, const double* X,
+                     int64_t ldx, double* R, int nrhs, const int* chunk_row0, const int* chunk_rows, int nchunks,
+                     double* partial, hipStream_t st);
+void launch_reduce_partials(const int* sys_chunk_ptr, int S, int width, const double* partial, double* out,
+                            hipStream_t st);
+void launch_axpy_cols(double* X, int64_t ldx, const double* DX, int64_t N, int nrhs, hipStream_t st);
+void launch_copy_cols(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t N, int nrhs,
+                      hipStream_t st);
+void launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st);
+void launch_zero_i32(int* p, int64_t n, hipStream_t st);
+
+// Raises the dynamic-LDS limit of the LDS-resident kernels to the device maximum.
+hipError_t configure_kernels(int max_dynamic_lds);
+
+// ---- adjoint (condensed) ----------------------------------------------------
+void launch_adjoint(const DevPlan& d, int64_t nnzW, const int* W_row, const int* W_col, int64_t nJrows,
+                    const int64_t* Jp, const int* Jj, const int* Jrow_sys, const double* Jval, const double* sys_rho,
+                    const double* X, const double* Lam, int64_t ld, int nrhs, double* gW, double* gSigma,
+                    double* gJ, double* gRho, double* JX, double* JL, const int64_t* sys_jrow, hipStream_t st);
+
+}  // namespace ncl

@@ -1,0 +1,382 @@
+"""Python binding of libncl_kkt.so (argument marshalling only).
+
+Every step of the hot path runs in the library's HIP kernels; torch is used
+for device memory (tensors passed by data pointer) and streams.  The binding
+fails loudly when the compiled library is missing — there is no fallback.
+
+    kkt = KKT.analyze(n, m, W_colptr, W_rowidx, J_rowptr, J_colidx, form="condensed")
+    kkt.factor(W_val, Sigma, J_val, rho)          # device float64 tensors
+    X, info = kkt.solve(B)                        # B: (order, nrhs) device float64
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libncl_kkt.so")
+
+NCL_CONDENSED, NCL_STABILIZED = 0, 1
+NCL_FP64, NCL_FP32_IR = 0, 1
+NCL_ORDER_ND, NCL_ORDER_NATURAL, NCL_ORDER_USER = 0, 1, 2
+NCL_OK = 0
+NCL_WARN_INERTIA, NCL_WARN_IR_NOT_CONVERGED, NCL_WARN_FELL_BACK_FP64 = 1, 2, 3
+
+EXPORTED = [
+    "ncl_kkt_default_options", "ncl_kkt_analyze", "ncl_kkt_analyze_host", "ncl_kkt_analyze_batched",
+    "ncl_kkt_factor", "ncl_kkt_factor_batched", "ncl_kkt_solve", "ncl_kkt_inertia",
+    "ncl_kkt_inertia_batched", "ncl_kkt_backward", "ncl_kkt_get_stats", "ncl_kkt_get_perm",
+    "ncl_kkt_get_supernodes", "ncl_kkt_set_timing", "ncl_kkt_get_timing", "ncl_kkt_destroy",
+    "ncl_kkt_strerror",
+]
+
+
+class Options(C.Structure):
+    _fields_ = [("form", C.c_int32), ("precision", C.c_int32), ("pivot_eps", C.c_double),
+                ("ir_max_steps", C.c_int32), ("ir_tol", C.c_double), ("ir_stall", C.c_double),
+                ("ordering", C.c_int32), ("user_perm", C.POINTER(C.c_int32))]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("ir_steps", C.c_int32), ("fell_back_fp64", C.c_int32),
+                ("backward_error", C.c_double), ("backward_error0", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("order", C.c_int64), ("nnz_K_lower", C.c_int64), ("nnz_L", C.c_int64),
+                ("flops_factor", C.c_double), ("n_supernodes", C.c_int64), ("n_levels", C.c_int64),
+                ("max_front", C.c_int64), ("n_large_fronts", C.c_int64), ("device_bytes", C.c_int64),
+                ("analyze_seconds", C.c_double)]
+
+
+class Timing(C.Structure):
+    _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8), ("update_flops", C.c_double),
+                ("small_flops", C.c_double), ("assemble_bytes", C.c_double), ("solve_bytes", C.c_double)]
+
+    CLASSES = ("assemble", "small_fronts", "large_assembly", "large_panel", "large_update_mfma",
+               "solve_sweeps", "residual", "other")
+
+    def as_dict(self):
+        return {"ms": {k: self.ms[i] for i, k in enumerate(self.CLASSES)},
+                "launches": {k: int(self.launches[i]) for i, k in enumerate(self.CLASSES)},
+                "update_flops": self.update_flops, "small_flops": self.small_flops,
+                "assemble_bytes": self.assemble_bytes, "solve_bytes": self.solve_bytes}
+
+
+_lib = None
+
+
+def lib():
+    """Load the compiled library; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2510_05885_amd/build.py "
+                           "(__graft_entry__.build()); there is no fallback path")
+    # torch ships its own HIP runtime with the same soname; load it first so the
+    # library binds to that one copy instead of a second runtime from /opt/rocm.
+    import torch  # noqa: F401
+    L = C.CDLL(LIB_PATH)
+    vp, i32, i64, dbl = C.c_void_p, C.c_int32, C.c_int64, C.c_double
+    pi32 = C.POINTER(C.c_int32)
+    ph = C.POINTER(C.c_void_p)
+    L.ncl_kkt_default_options.argtypes = [C.POINTER(Options)]
+    L.ncl_kkt_default_options.restype = None
+    for nm in ("ncl_kkt_analyze", "ncl_kkt_analyze_host"):
+        f = getattr(L, nm)
+        f.argtypes = [ph, C.POINTER(Options), i32, i32, pi32, pi32, pi32, pi32]
+        f.restype = C.c_int
+    L.ncl_kkt_analyze_batched.argtypes = [ph, C.POINTER(Options), i32, pi32, pi32, C.POINTER(pi32),
+                                          C.POINTER(pi32), C.POINTER(pi32), C.POINTER(pi32)]
+    L.ncl_kkt_analyze_batched.restype = C.c_int
+    L.ncl_kkt_factor.argtypes = [vp, vp, vp, vp, dbl, vp]
+    L.ncl_kkt_factor.restype = C.c_int
+    L.ncl_kkt_factor_batched.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double), vp]
+    L.ncl_kkt_factor_batched.restype = C.c_int
+    L.ncl_kkt_solve.argtypes = [vp, vp, i64, vp, i64, i32, vp, C.POINTER(SolveInfo)]
+    L.ncl_kkt_solve.restype = C.c_int
+    L.ncl_kkt_inertia.argtypes = [vp] + [C.POINTER(C.c_int64)] * 4
+    L.ncl_kkt_inertia.restype = C.c_int
+    L.ncl_kkt_inertia_batched.argtypes = [vp, C.POINTER(C.c_int64)]
+    L.ncl_kkt_inertia_batched.restype = C.c_int
+    L.ncl_kkt_backward.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, vp]
+    L.ncl_kkt_backward.restype = C.c_int
+    L.ncl_kkt_get_stats.argtypes = [vp, C.POINTER(Stats)]
+    L.ncl_kkt_get_stats.restype = C.c_int
+    L.ncl_kkt_get_perm.argtypes = [vp, pi32]
+    L.ncl_kkt_get_perm.restype = C.c_int
+    L.ncl_kkt_get_supernodes.argtypes = [vp, pi32, pi32, C.POINTER(C.c_int64), pi32]
+    L.ncl_kkt_get_supernodes.restype = C.c_int
+    L.ncl_kkt_set_timing.argtypes = [vp, i32]
+    L.ncl_kkt_set_timing.restype = C.c_int
+    L.ncl_kkt_get_timing.argtypes = [vp, C.POINTER(Timing)]
+    L.ncl_kkt_get_timing.restype = C.c_int
+    L.ncl_kkt_destroy.argtypes = [vp]
+    L.ncl_kkt_destroy.restype = None
+    L.ncl_kkt_strerror.argtypes = [C.c_int]
+    L.ncl_kkt_strerror.restype = C.c_char_p
+    _lib = L
+    return L
+
+
+class NCLError(RuntimeError):
+    def __init__(self, code, where):
+        self.code = code
+        super().__init__(f"{where}: {lib().ncl_kkt_strerror(code).decode()} (status {code})")
+
+
+def _check(code, where):
+    if code < 0:
+        raise NCLError(code, where)
+    return code
+
+
+def _i32(a):
+    a = np.ascontiguousarray(a, dtype=np.int32)
+    return a, a.ctypes.data_as(C.POINTER(C.c_int32))
+
+
+def _ptr(t):
+    """Device pointer of a torch tensor (must be float64, contiguous along rows)."""
+    if t is None:
+        return None
+    return C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        import torch
+        return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+    if isinstance(stream, int):
+        return C.c_void_p(stream)
+    return C.c_void_p(stream.cuda_stream)
+
+
+_FORMS = {"condensed": NCL_CONDENSED, "stabilized": NCL_STABILIZED}
+_PRECS = {"fp64": NCL_FP64, "fp32_ir": NCL_FP32_IR}
+_ORDS = {"nd": NCL_ORDER_ND, "natural": NCL_ORDER_NATURAL, "user": NCL_ORDER_USER}
+
+
+def make_options(form="condensed", precision="fp64", pivot_eps=0.0, ir_max_steps=10, ir_tol=1e-12,
+                 ir_stall=0.5, ordering="nd", user_perm=None):
+    o = Options()
+    lib().ncl_kkt_default_options(C.byref(o))
+    o.form = _FORMS[form] if isinstance(form, str) else int(form)
+    o.precision = _PRECS[precision] if isinstance(precision, str) else int(precision)
+    o.pivot_eps = float(pivot_eps)
+    o.ir_max_steps = int(ir_max_steps)
+    o.ir_tol = float(ir_tol)
+    o.ir_stall = float(ir_stall)
+    keep = None
+    if user_perm is not None:
+        keep, p = _i32(user_perm)
+        o.ordering = NCL_ORDER_USER
+        o.user_perm = p
+    else:
+        o.ordering = _ORDS[ordering] if isinstance(ordering, str) else int(ordering)
+    return o, keep
+
+
+@dataclass
+class Info:
+    status: int
+    ir_steps: int
+    fell_back_fp64: bool
+    backward_error: float
+    backward_error0: float
+
+
+class KKT:
+    """One analyzed KKT pattern (or a batch of independent ones)."""
+
+    def __init__(self, handle, order, S, nnzW, nnzJ, form):
+        self._h = handle
+        self.order = order
+        self.S = S
+        self.nnzW = nnzW
+        self.nnzJ = nnzJ
+        self.form = form
+
+    # ---------------------------------------------------------------- create
+    @classmethod
+    def analyze(cls, n, m, W_colptr, W_rowidx, J_rowptr, J_colidx, host_only=False, **opts):
+        o, keep = make_options(**opts)
+        arrs = [_i32(a) for a in (W_colptr, W_rowidx, J_rowptr, J_colidx)]
+        h = C.c_void_p()
+        f = lib().ncl_kkt_analyze_host if host_only else lib().ncl_kkt_analyze
+        _check(f(C.byref(h), C.byref(o), int(n), int(m), *[a[1] for a in arrs]), "ncl_kkt_analyze")
+        del keep
+        order = n if o.form == NCL_CONDENSED else n + m
+        return cls(h, order, 1, int(arrs[0][0][-1]), int(arrs[2][0][-1]) if m > 0 else 0, o.form)
+
+    @classmethod
+    def from_input(cls, inp, host_only=False, **opts):
+        return cls.analyze(inp.n, inp.m, inp.W_colptr, inp.W_rowidx, inp.J_rowptr, inp.J_colidx,
+                           host_only=host_only, **opts)
+
+    @classmethod
+    def analyze_batched(cls, inputs, **opts):
+        o, keep = make_options(**opts)
+        cnt = len(inputs)
+        ns = np.array([i.n for i in inputs], np.int32)
+        ms = np.array([i.m for i in inputs], np.int32)
+        held = []
+        tabs = []
+        for field in ("W_colptr", "W_rowidx", "J_rowptr", "J_colidx"):
+            ptrs = (C.POINTER(C.c_int32) * cnt)()
+            for k, i in enumerate(inputs):
+                a, p = _i32(getattr(i, field))
+                held.append(a)
+                ptrs[k] = p
+            tabs.append(ptrs)
+        h = C.c_void_p()
+        _check(lib().ncl_kkt_analyze_batched(C.byref(h), C.byref(o), cnt, ns.ctypes.data_as(C.POINTER(C.c_int32)),
+                                              ms.ctypes.data_as(C.POINTER(C.c_int32)), *tabs),
+               "ncl_kkt_analyze_batched")
+        del keep
+        return cls(h, int(ns.sum()), cnt, int(sum(int(i.W_colptr[-1]) for i in inputs)),
+                   int(sum(int(i.J_rowptr[-1]) for i in inputs)), o.form)
+
+    def close(self):
+        if self._h:
+            lib().ncl_kkt_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ---------------------------------------------------------------- numeric
+    def factor(self, W_val, Sigma, J_val, rho, stream=None):
+        """Assemble and factor on the device.  Returns the status (0 or a warning)."""
+        st = _stream(stream)
+        if self.S == 1 and np.ndim(rho) == 0:
+            rc = lib().ncl_kkt_factor(self._h, _ptr(W_val), _ptr(Sigma), _ptr(J_val), float(rho), st)
+        else:
+            r = np.ascontiguousarray(np.asarray(rho, np.float64).reshape(-1))
+            rc = lib().ncl_kkt_factor_batched(self._h, _ptr(W_val), _ptr(Sigma), _ptr(J_val),
+                                              r.ctypes.data_as(C.POINTER(C.c_double)), st)
+        return _check(rc, "ncl_kkt_factor")
+
+    def solve(self, B, X=None, stream=None):
+        """Solve K X = B (B: (order,) or (order, nrhs) float64 on the device)."""
+        import torch
+        vec = B.dim() == 1
+        B2 = B.reshape(self.order, -1)
+        Bc = B2.t().contiguous().t() if not B2.t().is_contiguous() else B2   # column-major view
+        nrhs = Bc.shape[1]
+        if X is None:
+            X = torch.empty((nrhs, self.order), dtype=torch.float64, device=B.device).t()
+        info = SolveInfo()
+        rc = lib().ncl_kkt_solve(self._h, _ptr(Bc), self.order, _ptr(X), self.order, nrhs, _stream(stream),
+                                 C.byref(info))
+        _check(rc, "ncl_kkt_solve")
+        out = X.reshape(self.order) if vec else X
+        return out, Info(rc, info.ir_steps, bool(info.fell_back_fp64), info.backward_error, info.backward_error0)
+
+    def inertia(self):
+        v = [C.c_int64() for _ in range(4)]
+        _check(lib().ncl_kkt_inertia(self._h, *[C.byref(x) for x in v]), "ncl_kkt_inertia")
+        return tuple(int(x.value) for x in v)
+
+    def inertia_batched(self):
+        out = np.zeros(4 * self.S, np.int64)
+        _check(lib().ncl_kkt_inertia_batched(self._h, out.ctypes.data_as(C.POINTER(C.c_int64))),
+               "ncl_kkt_inertia_batched")
+        return out.reshape(self.S, 4)
+
+    def backward(self, J_val, X, Lam, gW=None, gSigma=None, gJ=None, gRho=None, stream=None):
+        X2 = X.reshape(self.order, -1)
+        L2 = Lam.reshape(self.order, -1)
+        _check(lib().ncl_kkt_backward(self._h, _ptr(J_val), _ptr(X2), _ptr(L2), self.order, X2.shape[1],
+                                      _ptr(gW), _ptr(gSigma), _ptr(gJ), _ptr(gRho), _stream(stream)),
+               "ncl_kkt_backward")
+
+    # ---------------------------------------------------------------- inspect
+    def stats(self) -> dict:
+        s = Stats()
+        _check(lib().ncl_kkt_get_stats(self._h, C.byref(s)), "ncl_kkt_get_stats")
+        return {k: getattr(s, k) for k, _ in Stats._fields_}
+
+    def perm(self):
+        p = np.zeros(self.order, np.int32)
+        _check(lib().ncl_kkt_get_perm(self._h, p.ctypes.data_as(C.POINTER(C.c_int32))), "ncl_kkt_get_perm")
+        return p
+
+    def supernodes(self):
+        ns = self.stats()["n_supernodes"]
+        first = np.zeros(ns + 1, np.int32)
+        parent = np.zeros(ns, np.int32)
+        rp = np.zeros(ns + 1, np.int64)
+        P32 = C.POINTER(C.c_int32)
+        _check(lib().ncl_kkt_get_supernodes(self._h, first.ctypes.data_as(P32), parent.ctypes.data_as(P32),
+                                            rp.ctypes.data_as(C.POINTER(C.c_int64)), None), "supernodes")
+        rows = np.zeros(max(int(rp[-1]), 1), np.int32)
+        _check(lib().ncl_kkt_get_supernodes(self._h, None, None, None, rows.ctypes.data_as(P32)), "supernodes")
+        return first, parent, rp, rows[:int(rp[-1])]
+
+    def set_timing(self, on=True):
+        _check(lib().ncl_kkt_set_timing(self._h, 1 if on else 0), "ncl_kkt_set_timing")
+
+    def timing(self) -> dict:
+        t = Timing()
+        _check(lib().ncl_kkt_get_timing(self._h, C.byref(t)), "ncl_kkt_get_timing")
+        return t.as_dict()
+
+
+def _autograd_function():
+    import torch
+
+    class KKTSolve(torch.autograd.Function):
+        """X = K(W, Sigma, J, rho)^-1 B for the condensed form, with the adjoint
+        of the factorization: the backward pass solves with the same factor
+        (K is symmetric) and scatters -lambda x^T onto the stored entries of W,
+        Sigma and J (through rho J^T J) and onto rho."""
+
+        @staticmethod
+        def forward(ctx, kkt, W_val, Sigma, J_val, rho, B):
+            rho_v = float(rho.item()) if torch.is_tensor(rho) else float(rho)
+            kkt.factor(W_val.detach(), Sigma.detach(), J_val.detach(), rho_v)
+            X, info = kkt.solve(B.detach())
+            ctx.kkt = kkt
+            ctx.save_for_backward(J_val.detach(), X)
+            ctx.rho_is_tensor = torch.is_tensor(rho)
+            ctx.info = info
+            return X
+
+        @staticmethod
+        def backward(ctx, Xbar):
+            kkt = ctx.kkt
+            J_val, X = ctx.saved_tensors
+            Lam, _ = kkt.solve(Xbar.contiguous() if Xbar.dim() == 1 else Xbar)
+            dev = X.device
+            gW = torch.empty(kkt.nnzW, dtype=torch.float64, device=dev)
+            gS = torch.empty(kkt.order, dtype=torch.float64, device=dev)
+            gJ = torch.empty(kkt.nnzJ, dtype=torch.float64, device=dev)
+            gR = torch.empty(1, dtype=torch.float64, device=dev)
+            X2 = X.reshape(kkt.order, -1)
+            L2 = Lam.reshape(kkt.order, -1)
+            Xc = X2.t().contiguous().t()
+            Lc = L2.t().contiguous().t()
+            kkt.backward(J_val, Xc, Lc, gW, gS, gJ, gR)
+            grho = gR.reshape(()) if ctx.rho_is_tensor else None
+            return None, gW, gS, gJ, grho, Lam
+
+    return KKTSolve
+
+
+_KKTSolve = None
+
+
+def kkt_solve(kkt, W_val, Sigma, J_val, rho, B):
+    """Differentiable X = K^-1 B (condensed form) through the library."""
+    global _KKTSolve
+    if _KKTSolve is None:
+        _KKTSolve = _autograd_function()
+    return _KKTSolve.apply(kkt, W_val, Sigma, J_val, rho, B)
