@@ -662,6 +662,15 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
             uoff = align(uoff + (f - p));
         }
         P.U_elems = std::max<int64_t>(uoff, 32);
+        P.M_off.assign(nsn, 0);
+        int64_t moff = 0;
+        for (int s = 0; s < nsn; ++s) {
+            if (!P.sn_large[s]) continue;
+            const int64_t p = P.sn_first[s + 1] - P.sn_first[s];
+            P.M_off[s] = moff;
+            moff += ((p + cfg.panel - 1) / cfg.panel) * (int64_t)cfg.panel * cfg.panel;
+        }
+        P.M_elems = std::max<int64_t>(moff, 32);
 
         // ---------------- schedule ------------------------------------------
         const int nb = cfg.panel, T = cfg.tile;
@@ -702,10 +711,12 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                 for (int j = 0; j < f; ++j) { P.large_asm.push_back(s); P.large_asm.push_back(j); }
             }
             st.asm_count = (int64_t)P.large_asm.size() / 2 - st.asm_first;
+            st.d0_first = (int64_t)P.large_diag0.size();
+            for (int s : large) P.large_diag0.push_back(s);
+            st.d0_count = (int64_t)large.size();
             int maxp = 0;
             for (int s : large) maxp = std::max(maxp, P.sn_first[s + 1] - P.sn_first[s]);
             for (int k0 = 0; k0 < maxp; k0 += nb) {
-                st.diag_first.push_back((int64_t)P.large_diag.size() / 2);
                 st.panel_first.push_back((int64_t)P.large_panel.size() / 3);
                 st.upd_first.push_back((int64_t)P.large_upd.size() / 4);
                 double fl = 0.0;
@@ -714,10 +725,11 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                     const int p = P.sn_first[s + 1] - P.sn_first[s];
                     if (k0 >= p) continue;
                     const int k1 = std::min(k0 + nb, p);
-                    P.large_diag.push_back(s); P.large_diag.push_back(k0);
-                    for (int r0 = k1; r0 < f; r0 += 64) {
+                    for (int r0 = k1; r0 < f; r0 += 256) {
                         P.large_panel.push_back(s); P.large_panel.push_back(k0); P.large_panel.push_back(r0);
                     }
+                    P.large_upd.push_back(s); P.large_upd.push_back(k0);
+                    P.large_upd.push_back(-1); P.large_upd.push_back(-1);
                     for (int j0 = k1; j0 < f; j0 += T)
                         for (int i0 = j0; i0 < f; i0 += T) {
                             P.large_upd.push_back(s); P.large_upd.push_back(k0);
@@ -727,12 +739,54 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                             fl += 2.0 * ent * (k1 - k0);
                         }
                 }
-                st.diag_count.push_back((int64_t)P.large_diag.size() / 2 - st.diag_first.back());
                 st.panel_count.push_back((int64_t)P.large_panel.size() / 3 - st.panel_first.back());
                 st.upd_count.push_back((int64_t)P.large_upd.size() / 4 - st.upd_first.back());
                 st.upd_flops.push_back(fl);
             }
             P.large_steps.push_back(std::move(st));
+        }
+        // ---------------- solve schedule -----------------------------------
+        {
+            const int PW = cfg.solve_panel, FUSE = cfg.solve_fuse_rows, GR = cfg.solve_chunk_rows;
+            for (int l = 0; l < P.nlevels; ++l) {
+                int maxj = 0;
+                for (int k = P.level_ptr[l]; k < P.level_ptr[l + 1]; ++k) {
+                    int s = P.level_list[k];
+                    int p = P.sn_first[s + 1] - P.sn_first[s];
+                    maxj = std::max(maxj, (p + PW - 1) / PW);
+                }
+                for (int j = 0; j < maxj; ++j) {
+                    SolveStep st;
+                    st.level = l; st.j = j;
+                    st.t_first = (int64_t)P.solve_t.size() / 5;
+                    st.g_first = (int64_t)P.solve_g.size() / 5;
+                    int slot = 0;
+                    for (int k = P.level_ptr[l]; k < P.level_ptr[l + 1]; ++k) {
+                        int s = P.level_list[k];
+                        const int p = P.sn_first[s + 1] - P.sn_first[s];
+                        const int f = (int)(P.sn_rowptr[s + 1] - P.sn_rowptr[s]);
+                        const int c0 = j * PW;
+                        if (c0 >= p) continue;
+                        const int w = std::min(PW, p - c0);
+                        const int below = f - c0 - w;
+                        const bool fused = below <= FUSE;
+                        const int gfirst = slot;
+                        if (!fused) {
+                            for (int r0 = c0 + w; r0 < f; r0 += GR) {
+                                P.solve_g.push_back(s); P.solve_g.push_back(c0); P.solve_g.push_back(r0);
+                                P.solve_g.push_back(std::min(f, r0 + GR)); P.solve_g.push_back(slot++);
+                            }
+                        }
+                        P.solve_t.push_back(s); P.solve_t.push_back(c0); P.solve_t.push_back(fused ? 1 : 0);
+                        P.solve_t.push_back(gfirst); P.solve_t.push_back(slot - gfirst);
+                        st.fwd_bytes += 8.0 * ((double)w * (w + 1) / 2.0 + (double)below * w);
+                    }
+                    st.t_count = (int64_t)P.solve_t.size() / 5 - st.t_first;
+                    st.g_count = (int64_t)P.solve_g.size() / 5 - st.g_first;
+                    P.solve_max_slots = std::max<int64_t>(P.solve_max_slots, slot);
+                    P.solve_steps.push_back(st);
+                }
+            }
         }
     } catch (const AnalyzeError& e) {
         err = e.what();

@@ -54,11 +54,12 @@ struct ncl_kkt_s {
     bool host_only = true;
     int device = 0;
     std::vector<void*> allocs;
+    int64_t dev_bytes = 0;
     DevPlan d{};
     int64_t nnzF = 0;
     // schedule arrays (device)
-    int *small_list = nullptr, *level_list = nullptr, *large_asm = nullptr, *large_diag = nullptr,
-        *large_panel = nullptr, *large_upd = nullptr;
+    int *small_list = nullptr, *level_list = nullptr, *large_asm = nullptr, *large_panel = nullptr,
+        *large_upd = nullptr, *large_diag0 = nullptr, *solve_t = nullptr, *solve_g = nullptr;
     int *chunk_row0 = nullptr, *chunk_rows = nullptr, *sys_chunk_ptr = nullptr;
     int nchunks = 0;
     // numeric state
@@ -66,8 +67,8 @@ struct ncl_kkt_s {
            *thr = nullptr, *rho = nullptr;
     int* nonfinite = nullptr;
     unsigned long long* inertia = nullptr;
-    double *F64 = nullptr, *D64 = nullptr, *Y64 = nullptr, *U64 = nullptr;
-    float *F32 = nullptr, *D32 = nullptr, *Y32 = nullptr, *U32 = nullptr;
+    double *F64 = nullptr, *D64 = nullptr, *Y64 = nullptr, *U64 = nullptr, *P64 = nullptr, *M64 = nullptr;
+    float *F32 = nullptr, *D32 = nullptr, *Y32 = nullptr, *U32 = nullptr, *P32 = nullptr, *M32 = nullptr;
     double *R = nullptr, *DX = nullptr, *Xp = nullptr, *partial_res = nullptr, *res_out = nullptr;
     double *JX = nullptr, *JL = nullptr;
     int *W_row = nullptr, *W_col = nullptr, *Jj = nullptr, *Jrow_sys = nullptr;
@@ -92,6 +93,7 @@ T* dalloc(ncl_kkt_s* h, int64_t n) {
     if (n <= 0) n = 1;
     HIPCHK(hipMalloc(&p, sizeof(T) * (size_t)n));
     h->allocs.push_back(p);
+    h->dev_bytes += (int64_t)(sizeof(T) * (size_t)n);
     return static_cast<T*>(p);
 }
 
@@ -188,10 +190,13 @@ void setup_device(ncl_kkt_s* h) {
     std::vector<int64_t> uo(P.U_off);
     for (auto& x : uo) x *= kNrhsMax;
     d.U_off = upload(h, uo);
+    d.M_off = upload(h, P.M_off);
     h->small_list = upload(h, P.small_list);
     h->level_list = upload(h, P.level_list);
     h->large_asm = upload(h, P.large_asm);
-    h->large_diag = upload(h, P.large_diag);
+    h->large_diag0 = upload(h, P.large_diag0);
+    h->solve_t = upload(h, P.solve_t);
+    h->solve_g = upload(h, P.solve_g);
     h->large_panel = upload(h, P.large_panel);
     h->large_upd = upload(h, P.large_upd);
     // row chunks (<= 256 rows, never straddling two systems)
@@ -222,13 +227,17 @@ void setup_device(ncl_kkt_s* h) {
     d.nonfinite = h->nonfinite;
     h->F64 = dalloc<double>(h, P.factor_elems);
     h->D64 = dalloc<double>(h, P.N);
+    h->M64 = dalloc<double>(h, P.M_elems);
     h->Y64 = dalloc<double>(h, P.N * kNrhsMax);
     h->U64 = dalloc<double>(h, P.U_elems * kNrhsMax);
+    h->P64 = dalloc<double>(h, std::max<int64_t>(P.solve_max_slots, 1) * kSolvePanel * kNrhsMax);
     if (h->opt.precision == NCL_FP32_IR) {
         h->F32 = dalloc<float>(h, P.factor_elems);
         h->D32 = dalloc<float>(h, P.N);
+        h->M32 = dalloc<float>(h, P.M_elems);
         h->Y32 = dalloc<float>(h, P.N * kNrhsMax);
         h->U32 = dalloc<float>(h, P.U_elems * kNrhsMax);
+        h->P32 = dalloc<float>(h, std::max<int64_t>(P.solve_max_slots, 1) * kSolvePanel * kNrhsMax);
     }
     h->R = dalloc<double>(h, P.N * kNrhsMax);
     h->DX = dalloc<double>(h, P.N * kNrhsMax);
@@ -321,7 +330,7 @@ int do_analyze(ncl_kkt_t* out, const ncl_kkt_options* o, const std::vector<SysIn
 
 // ----- numeric factorization -----------------------------------------------
 template <typename T>
-void factor_fronts(ncl_kkt_s* h, T* F, T* D, hipStream_t st) {
+void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
     Plan& P = h->P;
     const DevPlan& d = h->d;
     launch_zero_u64(h->inertia, 4 * (int64_t)P.S, st);
@@ -346,15 +355,18 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, hipStream_t st) {
                 Span sp(h, st, TM_LASM);
                 launch_large_asm<T>(d, h->large_asm + 2 * ls.asm_first, (int)ls.asm_count, h->K, F, st);
             }
+            {
+                Span sp(h, st, TM_PANEL);
+                launch_large_diag0<T>(d, h->large_diag0 + ls.d0_first, (int)ls.d0_count, F, D, Mb, st);
+            }
             for (size_t k = 0; k < ls.panel_first.size(); ++k) {
                 {
                     Span sp(h, st, TM_PANEL);
-                    launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[k], (int)ls.diag_count[k], F, D, st);
                     launch_large_panel<T>(d, h->large_panel + 3 * ls.panel_first[k], (int)ls.panel_count[k], F, D,
-                                          st);
+                                          Mb, st);
                 }
                 Span sp(h, st, TM_UPD, ls.upd_flops[k], 1);
-                launch_large_update<T>(d, h->large_upd + 4 * ls.upd_first[k], (int)ls.upd_count[k], F, D, st);
+                launch_large_update<T>(d, h->large_upd + 4 * ls.upd_first[k], (int)ls.upd_count[k], F, D, Mb, st);
             }
         }
     }
@@ -406,10 +418,10 @@ int factor_impl(ncl_kkt_s* h, const double* W, const double* Sigma, const double
         }
         HIPCHK(hipGetLastError());
         if (h->opt.precision == NCL_FP32_IR) {
-            factor_fronts<float>(h, h->F32, h->D32, st);
+            factor_fronts<float>(h, h->F32, h->D32, h->M32, st);
             h->factor_prec = 1;
         } else {
-            factor_fronts<double>(h, h->F64, h->D64, st);
+            factor_fronts<double>(h, h->F64, h->D64, h->M64, st);
             h->factor_prec = 0;
         }
         HIPCHK(hipGetLastError());
@@ -417,7 +429,7 @@ int factor_impl(ncl_kkt_s* h, const double* W, const double* Sigma, const double
         if (rc) { flush_timing(h); return rc; }
         if (!h->inertia_ok && h->factor_prec == 1) {
             // an FP32 factor with the wrong inertia: refactor in FP64
-            factor_fronts<double>(h, h->F64, h->D64, st);
+            factor_fronts<double>(h, h->F64, h->D64, h->M64, st);
             h->factor_prec = 0;
             h->fell_back = true;
             rc = read_inertia(h, st);
@@ -439,24 +451,29 @@ int factor_impl(ncl_kkt_s* h, const double* W, const double* Sigma, const double
 // ----- solve -------------------------------------------------------------------
 template <typename T>
 void solve_once(ncl_kkt_s* h, const double* B, int64_t ldb, double* X, int64_t ldx, int nrhs, const T* F,
-                const T* D, T* Y, T* U, hipStream_t st) {
+                const T* D, T* Y, T* U, T* partial, hipStream_t st) {
     Plan& P = h->P;
     const DevPlan& d = h->d;
-    const double lbytes = (double)P.nnzL * sizeof(T);
-    Span sp(h, st, TM_SOLVE, 2.0 * lbytes, 4);
     launch_permute_in<T>(d, B, ldb, nrhs, Y, st);
-    for (int l = 0; l < P.nlevels; ++l)
-        launch_forward<T>(d, h->level_list + P.level_ptr[l], P.level_ptr[l + 1] - P.level_ptr[l], P.level_fmax[l], F,
-                          Y, U, nrhs, st);
-    for (int l = P.nlevels - 1; l >= 0; --l)
-        launch_backward<T>(d, h->level_list + P.level_ptr[l], P.level_ptr[l + 1] - P.level_ptr[l], P.level_fmax[l],
-                           F, D, Y, nrhs, st);
+    for (const SolveStep& ss : P.solve_steps) {
+        Span sp(h, st, TM_SOLVE, ss.fwd_bytes * sizeof(T) / 8.0, 4);
+        launch_fwd_T<T>(d, h->solve_t + 5 * ss.t_first, (int)ss.t_count, F, Y, U, nrhs, st);
+        launch_fwd_G<T>(d, h->solve_g + 5 * ss.g_first, (int)ss.g_count, F, Y, U, nrhs, st);
+    }
+    for (auto it = P.solve_steps.rbegin(); it != P.solve_steps.rend(); ++it) {
+        const SolveStep& ss = *it;
+        Span sp(h, st, TM_SOLVE, ss.fwd_bytes * sizeof(T) / 8.0, 4);
+        launch_bwd_G<T>(d, h->solve_g + 5 * ss.g_first, (int)ss.g_count, F, Y, partial, nrhs, st);
+        launch_bwd_T<T>(d, h->solve_t + 5 * ss.t_first, (int)ss.t_count, F, D, Y, partial, nrhs, st);
+    }
     launch_permute_out<T>(d, Y, nrhs, X, ldx, st);
 }
 
 void solve_with_factor(ncl_kkt_s* h, const double* B, int64_t ldb, double* X, int64_t ldx, int nrhs, hipStream_t st) {
-    if (h->factor_prec == 1) solve_once<float>(h, B, ldb, X, ldx, nrhs, h->F32, h->D32, h->Y32, h->U32, st);
-    else solve_once<double>(h, B, ldb, X, ldx, nrhs, h->F64, h->D64, h->Y64, h->U64, st);
+    if (h->factor_prec == 1)
+        solve_once<float>(h, B, ldb, X, ldx, nrhs, h->F32, h->D32, h->Y32, h->U32, h->P32, st);
+    else
+        solve_once<double>(h, B, ldb, X, ldx, nrhs, h->F64, h->D64, h->Y64, h->U64, h->P64, st);
 }
 
 // Backward error of X against B (max over systems and columns).
@@ -576,7 +593,7 @@ int ncl_kkt_solve(ncl_kkt_t h, const double* B, int64_t ldb, double* X, int64_t 
             double om = solve_refine(h, Bq, ldb, Xq, ldx, nq, st, steps, om0);
             if (om > h->opt.ir_tol && h->factor_prec == 1 && h->inertia_ok) {
                 // FP32 factor not accurate enough: refactor in FP64 from the assembled K
-                factor_fronts<double>(h, h->F64, h->D64, st);
+                factor_fronts<double>(h, h->F64, h->D64, h->M64, st);
                 h->factor_prec = 0;
                 h->fell_back = fell = true;
                 int rc = read_inertia(h, st);
@@ -654,10 +671,8 @@ int ncl_kkt_get_stats(ncl_kkt_t h, ncl_kkt_stats* st) {
     st->n_levels = P.nlevels;
     st->max_front = P.max_front;
     st->n_large_fronts = P.n_large;
-    int64_t bytes = 0;
-    for (void* p : h->allocs) (void)p;
-    st->device_bytes = h->host_only ? 0 : (int64_t)(P.factor_elems * (h->F32 ? 12 : 8));
-    (void)bytes;
+    // host-only handles report the factor buffer they would need in FP64
+    st->device_bytes = h->host_only ? P.factor_elems * 8 : h->dev_bytes;
     st->analyze_seconds = P.analyze_seconds;
     return NCL_OK;
 }

@@ -73,6 +73,137 @@ template <> struct Mfma<float> {
     static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
 };
 
+// 1/d from the hardware reciprocal refined by two Newton steps (within ~1 ulp
+// of the rounded quotient); shorter dependent latency than a full division.
+__device__ __forceinline__ double fast_rcp(double d) {
+    double r = __builtin_amdgcn_rcp(d);
+    double e = __builtin_fma(-d, r, 1.0);
+    r = __builtin_fma(r, e, r);
+    e = __builtin_fma(-d, r, 1.0);
+    return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float fast_rcp(float d) {
+    float r = __builtin_amdgcn_rcpf(d);
+    const float e = __builtin_fmaf(-d, r, 1.0f);
+    return __builtin_fmaf(r, e, r);
+}
+
+// Value of `v` held by lane `src` (a compile-time / wave-uniform lane index).
+__device__ __forceinline__ double bcast(double v, int src) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), src);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), src);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+__device__ __forceinline__ float bcast(float v, int src) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), src));
+}
+
+// Compiler-level fence: keeps LDS accesses of one wave in program order.
+__device__ __forceinline__ void wave_fence() {
+    __builtin_amdgcn_wave_barrier();
+    __asm__ volatile("" ::: "memory");
+}
+
+// Partial LDL^T of the leading p columns of an f x f lower-triangular matrix
+// held in LDS (column-major, leading dimension lda), with the static-pivot
+// rule of Sec. 3.1.  Blocked by 16 columns: wave 0 factors each 16-column
+// sub-panel over all rows below it (one row per lane, no workgroup barrier),
+// then the four waves apply the rank-16 update to the trailing lower matrix
+// on MFMA.  On return A holds L (unit lower, strictly below the diagonal) in
+// its first p columns, d_k on the diagonal and in dv[k], and the Schur
+// complement in the trailing (f - p) x (f - p) part.  sgn[k] is the block sign
+// of pivot k.  Lane 0 of wave 0 accumulates the pivot counts into cnt[4].
+// kTwoRows: f may exceed 64 + (sub-panel start), so a lane holds two rows.
+// Must be called by all 256 threads; ends with a barrier.
+template <typename T, bool kTwoRows>
+__device__ void lds_partial_ldlt(T* A, int lda, int f, int p, T* dv, const int8_t* sgn, double thr,
+                                 unsigned int* cnt, bool& bad_out) {
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    bool bad_any = false;
+    for (int kb = 0; kb < p; kb += 16) {
+        const int bw = min(16, p - kb);
+        if (wave == 0) {
+            // rows kb + lane and kb + lane + 64 of the sub-panel, in registers
+            const int i0 = kb + lane, i1 = kb + lane + 64;
+            T r0[16], r1[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                r0[t] = (t < bw && i0 < f && t <= lane) ? A[i0 + (kb + t) * lda] : T(0);
+                r1[t] = (kTwoRows && t < bw && i1 < f) ? A[i1 + (kb + t) * lda] : T(0);
+            }
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                if (t >= bw) continue;   // uniform; keeps the loop fully unrolled
+                // column t of the sub-panel rows (lanes t+1..bw-1), before it is scaled
+                T ck[16];
+#pragma unroll
+                for (int u = 0; u < 16; ++u) ck[u] = (u > t && u < bw) ? bcast(r0[t], u) : T(0);
+                bool pert, bad;
+                const T dk = static_pivot(bcast(r0[t], t), thr, sgn[kb + t], pert, bad);
+                const T inv = fast_rcp(dk);
+                if (lane > t) {
+                    const T l = r0[t] * inv;
+#pragma unroll
+                    for (int u = 0; u < 16; ++u)
+                        if (u > t && u < bw && u <= lane) r0[u] -= l * ck[u];
+                    r0[t] = l;
+                } else if (lane == t) {
+                    r0[t] = dk;
+                }
+                if (kTwoRows && i1 < f) {
+                    const T l = r1[t] * inv;
+#pragma unroll
+                    for (int u = 0; u < 16; ++u)
+                        if (u > t && u < bw) r1[u] -= l * ck[u];
+                    r1[t] = l;
+                }
+                if (lane == 0) {
+                    dv[kb + t] = dk;
+                    const double dd = to_d(dk);
+                    if (dd > 0.0) cnt[0]++; else if (dd < 0.0) cnt[1]++; else cnt[2]++;
+                    if (pert) cnt[3]++;
+                    bad_any |= bad;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                if (t < bw && i0 < f && t <= lane) A[i0 + (kb + t) * lda] = r0[t];
+                if (kTwoRows && t < bw && i1 < f) A[i1 + (kb + t) * lda] = r1[t];
+            }
+        }
+        __syncthreads();
+        // trailing update on MFMA: C -= L_panel D L_panel^T for rows/cols >= r0
+        const int r0 = kb + bw;
+        const int nt = (f - r0 + 15) / 16;
+        const int ntiles = nt * (nt + 1) / 2;
+        for (int tix = wave; tix < ntiles; tix += 4) {
+            int tj = 0, rem = tix;
+            while (rem >= nt - tj) { rem -= nt - tj; ++tj; }
+            const int ti = tj + rem;
+            const int i0 = r0 + 16 * ti, j0 = r0 + 16 * tj;
+            typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                const int tt = 4 * st + lk;
+                const bool tv = tt < bw;
+                const int t = kb + tt;
+                const T a = (tv && i0 + lr < f) ? A[(i0 + lr) + t * lda] : T(0);
+                const T b = (tv && j0 + lr < f) ? A[(j0 + lr) + t * lda] * dv[tv ? t : 0] : T(0);
+                acc = Mfma<T>::run(a, b, acc);
+            }
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gi = i0 + Mfma<T>::row(lk, r), gj = j0 + lr;
+                if (gi < f && gj < f && gi >= gj) A[gi + gj * lda] -= acc[r];
+            }
+        }
+        __syncthreads();
+    }
+    bad_out = bad_any;
+}
+
 inline unsigned int blocks_for(int64_t n, int bs) { return (unsigned int)((n + bs - 1) / bs); }
 
 // ---------------------------------------------------------------------------
@@ -167,12 +298,14 @@ __global__ void k_thresholds(int S, const double* norms2, double eps, double* km
 // ---------------------------------------------------------------------------
 // small fronts: one workgroup per front, front in LDS (column-major, ld = f)
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, bool kTwoRows>
 __global__ __launch_bounds__(256) void k_small_fronts(DevPlan d, const int* __restrict__ list,
                                                       const double* __restrict__ K, T* __restrict__ F,
                                                       T* __restrict__ D) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* A = reinterpret_cast<T*>(smem_raw);
+    __shared__ T dv[kSmallMax];
+    __shared__ int8_t sgn[kSmallMax];
     const int s = list[blockIdx.x];
     const int first = d.sn_first[s];
     const int p = d.sn_first[s + 1] - first;
@@ -199,33 +332,20 @@ __global__ __launch_bounds__(256) void k_small_fronts(DevPlan d, const int* __re
         }
         __syncthreads();
     }
-    // partial LDL^T of the p pivot columns (right-looking, one barrier per pivot)
+    // partial LDL^T of the p pivot columns (blocked, MFMA trailing updates)
     const int sys = d.sn_sys[s];
-    const double thr = d.sys_thr[sys];
-    unsigned long long* in4 = d.inertia + 4 * sys;
-    for (int k = 0; k < p; ++k) {
-        bool pert, bad;
-        const int sign = d.row_sign[d.perm[first + k]];
-        const T dk = static_pivot(A[k + k * f], thr, sign, pert, bad);
-        const T inv = T(1) / dk;
-        for (int i0 = k + 1; i0 < f; i0 += 64) {
-            const int i = i0 + ti;
-            if (i < f) {
-                const T lik = A[i + k * f] * inv;
-                for (int j = k + 1 + tj; j <= i; j += 4) A[i + j * f] -= lik * A[j + k * f];
-            }
-        }
-        if (tid == 0) {
-            D[first + k] = dk;
-            count_pivot(in4, to_d(dk), pert);
-            if (bad) d.nonfinite[0] = 1;
-        }
-        __syncthreads();
-        // column k is no longer read by the updates: scale it now
-        for (int i = k + 1 + tid; i < f; i += 256) A[i + k * f] *= inv;
-        if (tid == 0) A[k + k * f] = dk;
-    }
+    for (int k = tid; k < p; k += 256) sgn[k] = d.row_sign[d.perm[first + k]];
     __syncthreads();
+    unsigned int cnt[4] = {0, 0, 0, 0};
+    bool bad = false;
+    lds_partial_ldlt<T, kTwoRows>(A, f, f, p, dv, sgn, d.sys_thr[sys], cnt, bad);
+    if (tid == 0) {
+        unsigned long long* in4 = d.inertia + 4 * sys;
+        for (int k = 0; k < 4; ++k)
+            if (cnt[k]) atomicAdd(&in4[k], (unsigned long long)cnt[k]);
+        if (bad) d.nonfinite[0] = 1;
+    }
+    for (int k = tid; k < p; k += 256) D[first + k] = dv[k];
     // write L (f x p, ld f) and the contribution block (c x c, ld CB_ld)
     T* __restrict__ L = F + d.L_off[s];
     for (int j = tj; j < p; j += 4)
@@ -271,89 +391,108 @@ __global__ __launch_bounds__(256) void k_large_asm(DevPlan d, const int* __restr
     }
 }
 
-// One wave per (front, panel): LDL^T of the diagonal block with the static-pivot rule.
+// Writes the factored diagonal block of a panel (in LDS: L strictly below the
+// diagonal, column-major with leading dimension kPanel + 1; dv = pivots) to
+// its three consumers: D, the block's upper triangle (transposed; copied into
+// place by the next update launch) and Mg = L_kk D row-major, read by the
+// panel solve through uniform loads.
 template <typename T>
-__global__ __launch_bounds__(64) void k_large_diag(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
-                                                   T* __restrict__ D) {
-    const int s = tasks[2 * blockIdx.x], k0 = tasks[2 * blockIdx.x + 1];
+__device__ void publish_diag(T* A, int f, int k0, int w, const T* Bf, const T* dv, T* D, int first, T* Mg) {
+    constexpr int LB = kPanel + 1;
+    const int tid = threadIdx.x;
+    if (tid < w) D[first + k0 + tid] = dv[tid];
+    for (int idx = tid; idx < kPanel * kPanel; idx += 256) {
+        const int a = idx & (kPanel - 1), b = idx / kPanel;
+        if (a < w && b < a) A[(k0 + b) + (int64_t)(k0 + a) * f] = Bf[a + b * LB];
+        const int t = idx / kPanel, u = idx % kPanel;
+        Mg[idx] = (u < t && t < w) ? Bf[t + u * LB] * dv[u] : T(0);
+    }
+}
+
+// One workgroup per large front: factor the diagonal block of the first
+// panel (static-pivot rule, inertia) and publish it.
+template <typename T>
+__global__ __launch_bounds__(256) void k_large_diag0(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
+                                                     T* __restrict__ D, T* __restrict__ Mbuf) {
+    const int s = tasks[blockIdx.x];
     const int first = d.sn_first[s];
     const int p = d.sn_first[s + 1] - first;
     const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
-    const int w = min(kPanel, p - k0);
+    const int w = min(kPanel, p);
     T* __restrict__ A = F + d.L_off[s];
-    __shared__ T B[kPanel][kPanel + 1];
-    const int lane = threadIdx.x;
-    for (int j = 0; j < w; ++j)
-        if (lane >= j && lane < w) B[lane][j] = A[(k0 + lane) + (int64_t)(k0 + j) * f];
+    constexpr int LB = kPanel + 1;
+    __shared__ T Bf[kPanel * LB];
+    __shared__ T dv[kPanel];
+    __shared__ int8_t sgn[kPanel];
+    const int tid = threadIdx.x;
+    for (int idx = tid; idx < kPanel * kPanel; idx += 256) {
+        const int a = idx & (kPanel - 1), b = idx / kPanel;
+        if (a < w && b <= a) Bf[a + b * LB] = A[a + (int64_t)b * f];
+    }
+    if (tid < w) sgn[tid] = d.row_sign[d.perm[first + tid]];
     __syncthreads();
     const int sys = d.sn_sys[s];
-    const double thr = d.sys_thr[sys];
-    unsigned long long* in4 = d.inertia + 4 * sys;
-    for (int k = 0; k < w; ++k) {
-        bool pert, bad;
-        const int sign = d.row_sign[d.perm[first + k0 + k]];
-        const T dk = static_pivot(B[k][k], thr, sign, pert, bad);
-        const T inv = T(1) / dk;
-        if (lane > k && lane < w) {
-            const T lik = B[lane][k] * inv;
-            for (int j = k + 1; j <= lane; ++j) B[lane][j] -= lik * B[j][k];
-        }
-        __syncthreads();
-        if (lane > k && lane < w) B[lane][k] *= inv;
-        if (lane == 0) {
-            B[k][k] = dk;
-            D[first + k0 + k] = dk;
-            count_pivot(in4, to_d(dk), pert);
-            if (bad) d.nonfinite[0] = 1;
-        }
-        __syncthreads();
+    unsigned int cnt[4] = {0, 0, 0, 0};
+    bool bad = false;
+    lds_partial_ldlt<T, false>(Bf, LB, w, w, dv, sgn, d.sys_thr[sys], cnt, bad);
+    if (tid == 0) {
+        unsigned long long* in4 = d.inertia + 4 * sys;
+        for (int k = 0; k < 4; ++k)
+            if (cnt[k]) atomicAdd(&in4[k], (unsigned long long)cnt[k]);
+        if (bad) d.nonfinite[0] = 1;
     }
-    for (int j = 0; j < w; ++j)
-        if (lane >= j && lane < w) A[(k0 + lane) + (int64_t)(k0 + j) * f] = B[lane][j];
+    publish_diag<T>(A, f, 0, w, Bf, dv, D, first, Mbuf + d.M_off[s]);
 }
 
-// One wave per (front, panel, 64-row block below the diagonal block):
-// L[i, k0:k1] = A[i, k0:k1] L_kk^-T D_k^-1, one row per lane.
+// One workgroup per (front, panel, 256-row block): for its rows below the
+// panel's (already factored) diagonal block, L[i, k0:k1] = A[i, k0:k1]
+// L_kk^-T D^-1, one row per thread.  M = L_kk D and the pivots are the same
+// for every lane and are read through uniform loads.
 template <typename T>
-__global__ __launch_bounds__(64) void k_large_panel(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
-                                                    const T* __restrict__ D) {
+__global__ __launch_bounds__(256) void k_large_panel(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
+                                                     const T* __restrict__ D, const T* __restrict__ Mbuf) {
     const int s = tasks[3 * blockIdx.x], k0 = tasks[3 * blockIdx.x + 1], r0 = tasks[3 * blockIdx.x + 2];
     const int first = d.sn_first[s];
     const int p = d.sn_first[s + 1] - first;
     const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
     const int w = min(kPanel, p - k0);
+    const int k1 = k0 + w;
     T* __restrict__ A = F + d.L_off[s];
-    __shared__ T M[kPanel][kPanel + 1];   // M[t][u] = L_kk[t][u] * d_u (u < t)
-    __shared__ T dinv[kPanel];
-    const int lane = threadIdx.x;
-    for (int u = 0; u < w; ++u)
-        if (lane > u && lane < w) M[lane][u] = A[(k0 + lane) + (int64_t)(k0 + u) * f] * D[first + k0 + u];
-    if (lane < w) dinv[lane] = T(1) / D[first + k0 + lane];
-    __syncthreads();
-    const int row = r0 + lane;
-    if (row >= f) return;
+    const T* __restrict__ M = Mbuf + d.M_off[s] + (int64_t)(k0 / kPanel) * (kPanel * kPanel);
+    const T* __restrict__ dk = D + first + k0;
+    const int row = r0 + threadIdx.x;
+    if (row < k1 || row >= f) return;
     T x[kPanel];
 #pragma unroll
     for (int t = 0; t < kPanel; ++t) x[t] = (t < w) ? A[row + (int64_t)(k0 + t) * f] : T(0);
 #pragma unroll
     for (int t = 0; t < kPanel; ++t) {
-        if (t < w) {
-            T v = x[t];
+        // four partial sums shorten the dependent FMA chain
+        T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
 #pragma unroll
-            for (int u = 0; u < t; ++u) v -= M[t][u] * x[u];
-            x[t] = v * dinv[t];
+        for (int u = 0; u + 3 < t; u += 4) {
+            s0 += M[t * kPanel + u] * x[u];
+            s1 += M[t * kPanel + u + 1] * x[u + 1];
+            s2 += M[t * kPanel + u + 2] * x[u + 2];
+            s3 += M[t * kPanel + u + 3] * x[u + 3];
         }
+#pragma unroll
+        for (int u = t & ~3; u < t; ++u) s0 += M[t * kPanel + u] * x[u];
+        const T v = x[t] - ((s0 + s1) + (s2 + s3));
+        x[t] = (t < w) ? v / dk[t < w ? t : 0] : T(0);
     }
 #pragma unroll
     for (int t = 0; t < kPanel; ++t)
         if (t < w) A[row + (int64_t)(k0 + t) * f] = x[t];
 }
 
-// Trailing update of one 64x64 lower tile: C -= L_I D_k L_J^T on MFMA.
-// Four waves, each a 32x32 quadrant as 2x2 blocks of 16x16; K-depth = panel.
+// Trailing update of one 64x64 lower tile: C -= L_I D_k L_J^T on MFMA, with
+// the operands read straight from the front (no LDS).  Four waves, each a
+// 32x32 quadrant as 2x2 blocks of 16x16; depth = panel width.  A task with
+// i0 < 0 instead copies the panel's parked diagonal block into place.
 template <typename T>
 __global__ __launch_bounds__(256) void k_large_update(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
-                                                      const T* __restrict__ D) {
+                                                      T* __restrict__ D, T* __restrict__ Mbuf) {
     const int* tk = tasks + 4 * blockIdx.x;
     const int s = tk[0], k0 = tk[1], i0 = tk[2], j0 = tk[3];
     const int first = d.sn_first[s];
@@ -361,24 +500,32 @@ __global__ __launch_bounds__(256) void k_large_update(DevPlan d, const int* __re
     const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
     const int w = min(kPanel, p - k0);
     T* __restrict__ A = F + d.L_off[s];
-    __shared__ T La[kTile][kPanel + 1];
-    __shared__ T Lb[kTile][kPanel + 1];
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < kTile * kPanel; idx += 256) {
-        const int r = idx & (kTile - 1), t = idx / kTile;
-        T a = T(0), b = T(0);
-        if (t < w) {
-            const int64_t cofs = (int64_t)(k0 + t) * f;
-            if (i0 + r < f) a = A[(i0 + r) + cofs];
-            if (j0 + r < f) b = A[(j0 + r) + cofs] * D[first + k0 + t];
+    if (i0 < 0) {
+        for (int idx = tid; idx < kPanel * kPanel; idx += 256) {
+            const int a = idx & (kPanel - 1), b = idx / kPanel;
+            if (a < w && b < a) A[(k0 + a) + (int64_t)(k0 + b) * f] = A[(k0 + b) + (int64_t)(k0 + a) * f];
         }
-        La[r][t] = a;
-        Lb[r][t] = b;
+        return;
     }
-    __syncthreads();
     const int wave = tid >> 6, lane = tid & 63;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int lr = lane & 15, lk = lane >> 4;
+    constexpr int KS = kPanel / 4;
+    T av[KS][2], bv[KS][2];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int t = 4 * ks + lk;
+        const bool tv = t < w;
+        const int64_t cofs = (int64_t)(k0 + t) * f;
+        const T dt = tv ? D[first + k0 + t] : T(0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int ri = i0 + wr + 16 * h + lr, rj = j0 + wc + 16 * h + lr;
+            av[ks][h] = (tv && ri < f) ? A[ri + cofs] : T(0);
+            bv[ks][h] = (tv && rj < f) ? A[rj + cofs] * dt : T(0);
+        }
+    }
     typedef typename Mfma<T>::acc_t acc_t;
     acc_t acc[2][2];
 #pragma unroll
@@ -386,24 +533,47 @@ __global__ __launch_bounds__(256) void k_large_update(DevPlan d, const int* __re
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = acc_t{0, 0, 0, 0};
 #pragma unroll
-    for (int kk = 0; kk < kPanel; kk += 4) {
-        T a0 = La[wr + lr][kk + lk], a1 = La[wr + 16 + lr][kk + lk];
-        T b0 = Lb[wc + lr][kk + lk], b1 = Lb[wc + 16 + lr][kk + lk];
-        acc[0][0] = Mfma<T>::run(a0, b0, acc[0][0]);
-        acc[0][1] = Mfma<T>::run(a0, b1, acc[0][1]);
-        acc[1][0] = Mfma<T>::run(a1, b0, acc[1][0]);
-        acc[1][1] = Mfma<T>::run(a1, b1, acc[1][1]);
-    }
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = Mfma<T>::run(av[ks][bi], bv[ks][bj], acc[bi][bj]);
+    const int k1 = k0 + w;
+    const bool next_diag = (i0 == k1 && j0 == k1 && k1 < p);
+    constexpr int LB = kPanel + 1;
+    __shared__ T Bf[kPanel * LB];
+    __shared__ T dv[kPanel];
+    __shared__ int8_t sgn[kPanel];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int gi = i0 + wr + bi * 16 + Mfma<T>::row(lk, r);
-                const int gj = j0 + wc + bj * 16 + lr;
-                if (gi < f && gj < f && gi >= gj) A[gi + (int64_t)gj * f] -= acc[bi][bj][r];
+                const int li = wr + bi * 16 + Mfma<T>::row(lk, r), lj = wc + bj * 16 + lr;
+                const int gi = i0 + li, gj = j0 + lj;
+                if (gi < f && gj < f && gi >= gj) {
+                    const T nv = A[gi + (int64_t)gj * f] - acc[bi][bj][r];
+                    A[gi + (int64_t)gj * f] = nv;
+                    if (next_diag) Bf[li + lj * LB] = nv;
+                }
             }
+    if (!next_diag) return;
+    // This tile is the next panel's diagonal block: factor it now and park it.
+    const int w2 = min(kPanel, p - k1);
+    if (tid < w2) sgn[tid] = d.row_sign[d.perm[first + k1 + tid]];
+    __syncthreads();
+    const int sys = d.sn_sys[s];
+    unsigned int cnt[4] = {0, 0, 0, 0};
+    bool bad = false;
+    lds_partial_ldlt<T, false>(Bf, LB, w2, w2, dv, sgn, d.sys_thr[sys], cnt, bad);
+    if (tid == 0) {
+        unsigned long long* in4 = d.inertia + 4 * sys;
+        for (int k = 0; k < 4; ++k)
+            if (cnt[k]) atomicAdd(&in4[k], (unsigned long long)cnt[k]);
+        if (bad) d.nonfinite[0] = 1;
+    }
+    publish_diag<T>(A, f, k1, w2, Bf, dv, D, first, Mbuf + d.M_off[s] + (int64_t)(k1 / kPanel) * (kPanel * kPanel));
 }
 
 // ---------------------------------------------------------------------------
@@ -425,24 +595,33 @@ __global__ void k_permute_out(DevPlan d, const T* __restrict__ Y, int nrhs, doub
     for (int q = 0; q < nrhs; ++q) X[dst + q * ldx] = to_d(Y[k + q * d.N]);
 }
 
-// Forward sweep of one level: y_p = L11^-1 (b_p + children), u = (children) - L21 y_p.
+// ---- panel-based sweeps ----------------------------------------------------
+// Task layouts: T = (front, c0, fused, g_first, g_count), G = (front, c0, r0, r1, slot).
+// Panel = pivot columns [c0, c0 + w), w <= kSolvePanel, of front s; its
+// triangle is solved in 64-column sub-blocks staged in LDS.
+
+// Forward T: (c0 == 0) pull the children's update vectors; solve the panel's
+// triangle; when `fused`, also apply the panel to every row below it.
 template <typename T>
-__global__ __launch_bounds__(256) void k_forward(DevPlan d, const int* __restrict__ fronts, const T* __restrict__ F,
-                                                 T* __restrict__ Y, T* __restrict__ U, int nrhs, int qc) {
+__global__ __launch_bounds__(256) void k_fwd_T(DevPlan d, const int* __restrict__ tasks, const T* __restrict__ F,
+                                               T* __restrict__ Y, T* __restrict__ U, int nrhs) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* v = reinterpret_cast<T*>(smem_raw);
-    const int s = fronts[blockIdx.x];
+    T* Ld = reinterpret_cast<T*>(smem_raw);       // 64 x 65
+    T* v = Ld + 64 * 65;                          // kSolvePanel x nrhs
+    const int* tk = tasks + 5 * blockIdx.x;
+    const int s = tk[0], c0 = tk[1], fused = tk[2];
     const int first = d.sn_first[s];
     const int p = d.sn_first[s + 1] - first;
     const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
     const int c = f - p;
+    const int w = min(kSolvePanel, p - c0);
     const T* __restrict__ L = F + d.L_off[s];
-    const int tid = threadIdx.x;
+    T* __restrict__ Us = U + d.U_off[s];
+    const int tid = threadIdx.x, lane = tid & 63;
     const int64_t N = d.N;
-    for (int q0 = 0; q0 < nrhs; q0 += qc) {
-        const int nq = min(qc, nrhs - q0);
-        for (int q = 0; q < nq; ++q)
-            for (int i = tid; i < f; i += 256) v[i + q * f] = i < p ? Y[first + i + (q0 + q) * N] : T(0);
+    if (c0 == 0) {
+        for (int q = 0; q < nrhs; ++q)
+            for (int i = tid; i < c; i += 256) Us[i + (int64_t)q * c] = T(0);
         __syncthreads();
         for (int k = d.child_ptr[s]; k < d.child_ptr[s + 1]; ++k) {
             const int ch = d.child_list[k];
@@ -450,97 +629,216 @@ __global__ __launch_bounds__(256) void k_forward(DevPlan d, const int* __restric
             const int cc = fc - (d.sn_first[ch + 1] - d.sn_first[ch]);
             const T* __restrict__ Uc = U + d.U_off[ch];
             const int* __restrict__ r = d.rel + d.rel_ptr[ch];
-            for (int q = 0; q < nq; ++q)
-                for (int a = tid; a < cc; a += 256) v[r[a] + q * f] += Uc[a + (int64_t)(q0 + q) * cc];
+            for (int q = 0; q < nrhs; ++q)
+                for (int a = tid; a < cc; a += 256) {
+                    const int t = r[a];
+                    const T val = Uc[a + (int64_t)q * cc];
+                    if (t < p) Y[first + t + q * N] += val;
+                    else Us[(t - p) + (int64_t)q * c] += val;
+                }
             __syncthreads();
         }
-        for (int kb = 0; kb < p; kb += 64) {
-            const int w = min(64, p - kb);
-            if (tid < 64) {
-                for (int q = 0; q < nq; ++q) {
-                    T val = tid < w ? v[kb + tid + q * f] : T(0);
-                    for (int k = 0; k < w; ++k) {
-                        const T yk = __shfl(val, k, 64);
-                        if (tid > k && tid < w) val -= L[(kb + tid) + (int64_t)(kb + k) * f] * yk;
-                    }
-                    if (tid < w) v[kb + tid + q * f] = val;
-                }
-            }
-            __syncthreads();
-            for (int i = kb + w + tid; i < f; i += 256) {
-                for (int q = 0; q < nq; ++q) {
-                    T acc = T(0);
-                    for (int k = 0; k < w; ++k) acc += L[i + (int64_t)(kb + k) * f] * v[kb + k + q * f];
-                    v[i + q * f] -= acc;
-                }
-            }
-            __syncthreads();
+    }
+    for (int q = 0; q < nrhs; ++q)
+        for (int t = tid; t < w; t += 256) v[t + q * kSolvePanel] = Y[first + c0 + t + q * N];
+    __syncthreads();
+    for (int sb = 0; sb < w; sb += 64) {
+        const int ws = min(64, w - sb);
+        for (int idx = tid; idx < 64 * ws; idx += 256) {
+            const int a = idx & 63, b = idx >> 6;
+            if (a < ws && b < a) Ld[a * 65 + b] = L[(c0 + sb + a) + (int64_t)(c0 + sb + b) * f];
         }
-        T* __restrict__ Us = U + d.U_off[s];
-        for (int q = 0; q < nq; ++q)
-            for (int i = tid; i < f; i += 256) {
-                if (i < p) Y[first + i + (q0 + q) * N] = v[i + q * f];
-                else Us[(i - p) + (int64_t)(q0 + q) * c] = v[i + q * f];
-            }
         __syncthreads();
+        if (tid < 64) {
+            T lrow[64];
+#pragma unroll
+            for (int k = 0; k < 64; ++k) lrow[k] = (k < lane && lane < ws) ? Ld[lane * 65 + k] : T(0);
+            for (int q = 0; q < nrhs; ++q) {
+                T val = lane < ws ? v[sb + lane + q * kSolvePanel] : T(0);
+#pragma unroll
+                for (int k = 0; k < 63; ++k) val -= lrow[k] * bcast(val, k);
+                if (lane < ws) v[sb + lane + q * kSolvePanel] = val;
+            }
+        }
+        __syncthreads();
+        for (int t = sb + ws + tid; t < w; t += 256) {
+            for (int q = 0; q < nrhs; ++q) {
+                T acc = T(0);
+                const T* vq = v + sb + q * kSolvePanel;
+#pragma unroll 8
+                for (int k = 0; k < ws; ++k) acc += L[(c0 + t) + (int64_t)(c0 + sb + k) * f] * vq[k];
+                v[t + q * kSolvePanel] -= acc;
+            }
+        }
+        __syncthreads();
+    }
+    for (int q = 0; q < nrhs; ++q)
+        for (int t = tid; t < w; t += 256) Y[first + c0 + t + q * N] = v[t + q * kSolvePanel];
+    if (!fused) return;
+    for (int i = c0 + w + tid; i < f; i += 256) {
+        for (int q = 0; q < nrhs; ++q) {
+            T acc = T(0);
+            const T* vq = v + q * kSolvePanel;
+#pragma unroll 8
+            for (int k = 0; k < w; ++k) acc += L[i + (int64_t)(c0 + k) * f] * vq[k];
+            if (i < p) Y[first + i + q * N] -= acc;
+            else Us[(i - p) + (int64_t)q * c] -= acc;
+        }
     }
 }
 
-// Backward sweep of one level: x_p = L11^-T (D^-1 y_p - L21^T x_c), x_c read from ancestors.
+// Forward G: rows [r0, r1) of front s minus L[rows, panel] y_panel.
 template <typename T>
-__global__ __launch_bounds__(256) void k_backward(DevPlan d, const int* __restrict__ fronts, const T* __restrict__ F,
-                                                  const T* __restrict__ D, T* __restrict__ Y, int nrhs, int qc) {
+__global__ __launch_bounds__(256) void k_fwd_G(DevPlan d, const int* __restrict__ tasks, const T* __restrict__ F,
+                                               T* __restrict__ Y, T* __restrict__ U, int nrhs) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* Lt = reinterpret_cast<T*>(smem_raw);          // 64 x 65 diagonal block
-    T* v = Lt + 64 * 65;
-    const int s = fronts[blockIdx.x];
+    T* y = reinterpret_cast<T*>(smem_raw);        // kSolvePanel x nrhs
+    const int* tk = tasks + 5 * blockIdx.x;
+    const int s = tk[0], c0 = tk[1], r0 = tk[2], r1 = tk[3];
+    const int first = d.sn_first[s];
+    const int p = d.sn_first[s + 1] - first;
+    const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
+    const int c = f - p;
+    const int w = min(kSolvePanel, p - c0);
+    const T* __restrict__ L = F + d.L_off[s];
+    T* __restrict__ Us = U + d.U_off[s];
+    const int tid = threadIdx.x;
+    const int64_t N = d.N;
+    for (int q = 0; q < nrhs; ++q)
+        for (int t = tid; t < w; t += 256) y[t + q * kSolvePanel] = Y[first + c0 + t + q * N];
+    __syncthreads();
+    for (int i = r0 + tid; i < r1; i += 256) {
+        for (int q = 0; q < nrhs; ++q) {
+            T acc = T(0);
+            const T* yq = y + q * kSolvePanel;
+#pragma unroll 8
+            for (int k = 0; k < w; ++k) acc += L[i + (int64_t)(c0 + k) * f] * yq[k];
+            if (i < p) Y[first + i + q * N] -= acc;
+            else Us[(i - p) + (int64_t)q * c] -= acc;
+        }
+    }
+}
+
+// Backward G: partial[slot][t][q] = sum over rows [r0, r1) of L[i, c0 + t] x_i.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_G(DevPlan d, const int* __restrict__ tasks, const T* __restrict__ F,
+                                               const T* __restrict__ Y, T* __restrict__ partial, int nrhs) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* xs = reinterpret_cast<T*>(smem_raw);       // kSolveChunk x nrhs
+    const int* tk = tasks + 5 * blockIdx.x;
+    const int s = tk[0], c0 = tk[1], r0 = tk[2], r1 = tk[3], slot = tk[4];
     const int first = d.sn_first[s];
     const int p = d.sn_first[s + 1] - first;
     const int64_t rb = d.sn_rowptr[s];
     const int f = (int)(d.sn_rowptr[s + 1] - rb);
+    const int w = min(kSolvePanel, p - c0);
     const T* __restrict__ L = F + d.L_off[s];
     const int* __restrict__ rows = d.sn_rows + rb;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int tid = threadIdx.x;
     const int64_t N = d.N;
-    for (int q0 = 0; q0 < nrhs; q0 += qc) {
-        const int nq = min(qc, nrhs - q0);
-        for (int q = 0; q < nq; ++q)
-            for (int i = tid; i < f; i += 256)
-                v[i + q * f] = i < p ? Y[first + i + (q0 + q) * N] / D[first + i] : Y[rows[i] + (q0 + q) * N];
-        __syncthreads();
-        for (int kb = ((p - 1) / 64) * 64; kb >= 0; kb -= 64) {
-            const int w = min(64, p - kb);
-            const int below = kb + w;
-            for (int t = wave; t < w; t += 4) {
-                const T* __restrict__ col = L + (int64_t)(kb + t) * f;
-                for (int q = 0; q < nq; ++q) {
-                    T part = T(0);
-                    for (int i = below + lane; i < f; i += 64) part += col[i] * v[i + q * f];
-                    for (int o = 32; o > 0; o >>= 1) part += __shfl_xor(part, o, 64);
-                    if (lane == 0) v[kb + t + q * f] -= part;
-                }
-            }
-            for (int idx = tid; idx < 64 * w; idx += 256) {
-                const int a = idx & 63, b = idx >> 6;
-                if (a < w) Lt[a * 65 + b] = L[(kb + a) + (int64_t)(kb + b) * f];
-            }
-            __syncthreads();
-            if (tid < 64) {
-                for (int q = 0; q < nq; ++q) {
-                    T val = tid < w ? v[kb + tid + q * f] : T(0);
-                    for (int k = w - 1; k > 0; --k) {
-                        const T xk = __shfl(val, k, 64);
-                        if (tid < k) val -= Lt[k * 65 + tid] * xk;
-                    }
-                    if (tid < w) v[kb + tid + q * f] = val;
-                }
-            }
-            __syncthreads();
+    const int nr = r1 - r0;
+    for (int q = 0; q < nrhs; ++q)
+        for (int i = tid; i < nr; i += 256) {
+            const int gi = r0 + i;
+            xs[i + q * kSolveChunk] = gi < p ? Y[first + gi + q * N] : Y[rows[gi] + q * N];
         }
-        for (int q = 0; q < nq; ++q)
-            for (int i = tid; i < p; i += 256) Y[first + i + (q0 + q) * N] = v[i + q * f];
+    __syncthreads();
+    for (int t = tid; t < w; t += 256) {
+        const T* __restrict__ col = L + (int64_t)(c0 + t) * f + r0;
+        for (int q = 0; q < nrhs; ++q) {
+            T acc = T(0);
+            const T* xq = xs + q * kSolveChunk;
+#pragma unroll 8
+            for (int i = 0; i < nr; ++i) acc += col[i] * xq[i];
+            partial[((int64_t)slot * kSolvePanel + t) * kNrhsMax + q] = acc;
+        }
+    }
+}
+
+// Backward T: v = D^-1 y - (rows below, from G partials or computed here when
+// fused), then the panel's transposed triangle in reverse sub-blocks.
+template <typename T>
+__global__ __launch_bounds__(256) void k_bwd_T(DevPlan d, const int* __restrict__ tasks, const T* __restrict__ F,
+                                               const T* __restrict__ D, T* __restrict__ Y,
+                                               const T* __restrict__ partial, int nrhs) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* Ld = reinterpret_cast<T*>(smem_raw);       // 64 x 65
+    T* v = Ld + 64 * 65;                          // kSolvePanel x nrhs
+    T* xs = v + kSolvePanel * nrhs;               // kSolveChunk x nrhs (fused rows below)
+    const int* tk = tasks + 5 * blockIdx.x;
+    const int s = tk[0], c0 = tk[1], fused = tk[2], gfirst = tk[3], gcount = tk[4];
+    const int first = d.sn_first[s];
+    const int p = d.sn_first[s + 1] - first;
+    const int64_t rb = d.sn_rowptr[s];
+    const int f = (int)(d.sn_rowptr[s + 1] - rb);
+    const int w = min(kSolvePanel, p - c0);
+    const T* __restrict__ L = F + d.L_off[s];
+    const int* __restrict__ rows = d.sn_rows + rb;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int64_t N = d.N;
+    const int below0 = c0 + w;
+    const int nb = f - below0;
+    if (fused && nb > 0) {
+        for (int q = 0; q < nrhs; ++q)
+            for (int i = tid; i < nb; i += 256) {
+                const int gi = below0 + i;
+                xs[i + q * kSolveChunk] = gi < p ? Y[first + gi + q * N] : Y[rows[gi] + q * N];
+            }
         __syncthreads();
     }
+    for (int t = tid; t < w; t += 256) {
+        const T dinv = T(1) / D[first + c0 + t];
+        for (int q = 0; q < nrhs; ++q) {
+            T val = Y[first + c0 + t + q * N] * dinv;
+            if (fused) {
+                const T* __restrict__ col = L + (int64_t)(c0 + t) * f + below0;
+                const T* xq = xs + q * kSolveChunk;
+                T acc = T(0);
+#pragma unroll 8
+                for (int i = 0; i < nb; ++i) acc += col[i] * xq[i];
+                val -= acc;
+            } else {
+                T acc = T(0);
+                for (int g = 0; g < gcount; ++g) acc += partial[((int64_t)(gfirst + g) * kSolvePanel + t) * kNrhsMax + q];
+                val -= acc;
+            }
+            v[t + q * kSolvePanel] = val;
+        }
+    }
+    __syncthreads();
+    for (int sb = ((w - 1) / 64) * 64; sb >= 0; sb -= 64) {
+        const int ws = min(64, w - sb);
+        const int ub = sb + ws;
+        if (tid < ws && ub < w) {
+            const T* __restrict__ col = L + (int64_t)(c0 + sb + tid) * f + c0;
+            for (int q = 0; q < nrhs; ++q) {
+                const T* vq = v + q * kSolvePanel;
+                T acc = T(0);
+#pragma unroll 8
+                for (int u = ub; u < w; ++u) acc += col[u] * vq[u];
+                v[sb + tid + q * kSolvePanel] -= acc;
+            }
+        }
+        for (int idx = tid; idx < 64 * ws; idx += 256) {
+            const int a = idx & 63, b = idx >> 6;
+            if (a < ws && b < a) Ld[a * 65 + b] = L[(c0 + sb + a) + (int64_t)(c0 + sb + b) * f];
+        }
+        __syncthreads();
+        if (tid < 64) {
+            T lcol[64];
+#pragma unroll
+            for (int k = 0; k < 64; ++k) lcol[k] = (lane < k && k < ws) ? Ld[k * 65 + lane] : T(0);
+            for (int q = 0; q < nrhs; ++q) {
+                T val = lane < ws ? v[sb + lane + q * kSolvePanel] : T(0);
+#pragma unroll
+                for (int k = 63; k > 0; --k) val -= lcol[k] * bcast(val, k);
+                if (lane < ws) v[sb + lane + q * kSolvePanel] = val;
+            }
+        }
+        __syncthreads();
+    }
+    for (int q = 0; q < nrhs; ++q)
+        for (int t = tid; t < w; t += 256) Y[first + c0 + t + q * N] = v[t + q * kSolvePanel];
 }
 
 // ---------------------------------------------------------------------------
@@ -716,7 +1014,10 @@ void launch_small_fronts(const DevPlan& d, const int* list, int count, int fmax,
                          hipStream_t st) {
     if (count <= 0) return;
     const size_t lds = (size_t)fmax * fmax * sizeof(T);
-    hipLaunchKernelGGL(k_small_fronts<T>, dim3(count), dim3(256), lds, st, d, list, K, F, D);
+    if (fmax <= 64)
+        hipLaunchKernelGGL((k_small_fronts<T, false>), dim3(count), dim3(256), lds, st, d, list, K, F, D);
+    else
+        hipLaunchKernelGGL((k_small_fronts<T, true>), dim3(count), dim3(256), lds, st, d, list, K, F, D);
 }
 
 template <typename T>
@@ -726,21 +1027,21 @@ void launch_large_asm(const DevPlan& d, const int* tasks, int count, const doubl
 }
 
 template <typename T>
-void launch_large_diag(const DevPlan& d, const int* tasks, int count, T* F, T* D, hipStream_t st) {
+void launch_large_diag0(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_large_diag<T>, dim3(count), dim3(64), 0, st, d, tasks, F, D);
+    hipLaunchKernelGGL(k_large_diag0<T>, dim3(count), dim3(256), 0, st, d, tasks, F, D, M);
 }
 
 template <typename T>
-void launch_large_panel(const DevPlan& d, const int* tasks, int count, T* F, const T* D, hipStream_t st) {
+void launch_large_panel(const DevPlan& d, const int* tasks, int count, T* F, const T* D, const T* M, hipStream_t st) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_large_panel<T>, dim3(count), dim3(64), 0, st, d, tasks, F, D);
+    hipLaunchKernelGGL(k_large_panel<T>, dim3(count), dim3(256), 0, st, d, tasks, F, D, M);
 }
 
 template <typename T>
-void launch_large_update(const DevPlan& d, const int* tasks, int count, T* F, const T* D, hipStream_t st) {
+void launch_large_update(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_large_update<T>, dim3(count), dim3(256), 0, st, d, tasks, F, D);
+    hipLaunchKernelGGL(k_large_update<T>, dim3(count), dim3(256), 0, st, d, tasks, F, D, M);
 }
 
 template <typename T>
@@ -753,29 +1054,34 @@ void launch_permute_out(const DevPlan& d, const T* Y, int nrhs, double* X, int64
     hipLaunchKernelGGL(k_permute_out<T>, dim3(blocks_for(d.N, 256)), dim3(256), 0, st, d, Y, nrhs, X, ldx);
 }
 
-static int solve_chunk(int fmax, int nrhs, size_t elem, size_t budget) {
-    int qc = (int)(budget / elem / (size_t)(fmax > 0 ? fmax : 1));
-    if (qc > nrhs) qc = nrhs;
-    return qc;
+template <typename T>
+void launch_fwd_T(const DevPlan& d, const int* tasks, int count, const T* F, T* Y, T* U, int nrhs, hipStream_t st) {
+    if (count <= 0) return;
+    const size_t lds = (size_t)(64 * 65 + kSolvePanel * nrhs) * sizeof(T);
+    hipLaunchKernelGGL(k_fwd_T<T>, dim3(count), dim3(256), lds, st, d, tasks, F, Y, U, nrhs);
 }
 
 template <typename T>
-void launch_forward(const DevPlan& d, const int* fronts, int count, int fmax, const T* F, T* Y, T* U, int nrhs,
-                    hipStream_t st) {
+void launch_fwd_G(const DevPlan& d, const int* tasks, int count, const T* F, T* Y, T* U, int nrhs, hipStream_t st) {
     if (count <= 0) return;
-    const int qc = solve_chunk(fmax, nrhs, sizeof(T), 64 * 1024);
-    const size_t lds = (size_t)fmax * qc * sizeof(T);
-    hipLaunchKernelGGL(k_forward<T>, dim3(count), dim3(256), lds, st, d, fronts, F, Y, U, nrhs, qc);
+    const size_t lds = (size_t)kSolvePanel * nrhs * sizeof(T);
+    hipLaunchKernelGGL(k_fwd_G<T>, dim3(count), dim3(256), lds, st, d, tasks, F, Y, U, nrhs);
 }
 
 template <typename T>
-void launch_backward(const DevPlan& d, const int* fronts, int count, int fmax, const T* F, const T* D, T* Y,
-                     int nrhs, hipStream_t st) {
+void launch_bwd_G(const DevPlan& d, const int* tasks, int count, const T* F, const T* Y, T* partial, int nrhs,
+                  hipStream_t st) {
     if (count <= 0) return;
-    const size_t diag = 64 * 65 * sizeof(T);
-    const int qc = solve_chunk(fmax, nrhs, sizeof(T), 64 * 1024);
-    const size_t lds = diag + (size_t)fmax * qc * sizeof(T);
-    hipLaunchKernelGGL(k_backward<T>, dim3(count), dim3(256), lds, st, d, fronts, F, D, Y, nrhs, qc);
+    const size_t lds = (size_t)kSolveChunk * nrhs * sizeof(T);
+    hipLaunchKernelGGL(k_bwd_G<T>, dim3(count), dim3(256), lds, st, d, tasks, F, Y, partial, nrhs);
+}
+
+template <typename T>
+void launch_bwd_T(const DevPlan& d, const int* tasks, int count, const T* F, const T* D, T* Y, const T* partial,
+                  int nrhs, hipStream_t st) {
+    if (count <= 0) return;
+    const size_t lds = (size_t)(64 * 65 + kSolvePanel * nrhs + kSolveChunk * nrhs) * sizeof(T);
+    hipLaunchKernelGGL(k_bwd_T<T>, dim3(count), dim3(256), lds, st, d, tasks, F, D, Y, partial, nrhs);
 }
 
 void launch_residual(const DevPlan& d, const double* K, const double* B, int64_t ldb, const double* X, int64_t ldx,
@@ -829,11 +1135,18 @@ void launch_adjoint(const DevPlan& d, int64_t nnzW, const int* W_row, const int*
 // (gfx950 has 160 KiB per workgroup).
 hipError_t configure_kernels(int max_dynamic_lds) {
     hipError_t e = hipSuccess, r;
-    const void* fns[] = {(const void*)k_small_fronts<double>, (const void*)k_small_fronts<float>,
-                         (const void*)k_forward<double>, (const void*)k_forward<float>,
-                         (const void*)k_backward<double>, (const void*)k_backward<float>};
+    const void* fns[] = {(const void*)k_small_fronts<double, true>, (const void*)k_small_fronts<float, true>,
+                         (const void*)k_small_fronts<double, false>, (const void*)k_small_fronts<float, false>,
+                         (const void*)k_fwd_T<double>, (const void*)k_fwd_T<float>,
+                         (const void*)k_fwd_G<double>, (const void*)k_fwd_G<float>,
+                         (const void*)k_bwd_G<double>, (const void*)k_bwd_G<float>,
+                         (const void*)k_bwd_T<double>, (const void*)k_bwd_T<float>};
     for (const void* f : fns) {
-        r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, max_dynamic_lds);
+        hipFuncAttributes at{};
+        r = hipFuncGetAttributes(&at, f);
+        if (r != hipSuccess) { e = r; continue; }
+        const int dyn = max_dynamic_lds - (int)at.sharedSizeBytes;
+        r = hipFuncSetAttribute(f, hipFuncAttributeMaxDynamicSharedMemorySize, dyn);
         if (r != hipSuccess) e = r;
     }
     return e;
@@ -842,13 +1155,15 @@ hipError_t configure_kernels(int max_dynamic_lds) {
 #define NCL_INSTANTIATE(T)                                                                                         \
     template void launch_small_fronts<T>(const DevPlan&, const int*, int, int, const double*, T*, T*, hipStream_t); \
     template void launch_large_asm<T>(const DevPlan&, const int*, int, const double*, T*, hipStream_t);            \
-    template void launch_large_diag<T>(const DevPlan&, const int*, int, T*, T*, hipStream_t);                      \
-    template void launch_large_panel<T>(const DevPlan&, const int*, int, T*, const T*, hipStream_t);               \
-    template void launch_large_update<T>(const DevPlan&, const int*, int, T*, const T*, hipStream_t);              \
+    template void launch_large_diag0<T>(const DevPlan&, const int*, int, T*, T*, T*, hipStream_t);               \
+    template void launch_large_panel<T>(const DevPlan&, const int*, int, T*, const T*, const T*, hipStream_t);     \
+    template void launch_large_update<T>(const DevPlan&, const int*, int, T*, T*, T*, hipStream_t);              \
     template void launch_permute_in<T>(const DevPlan&, const double*, int64_t, int, T*, hipStream_t);              \
     template void launch_permute_out<T>(const DevPlan&, const T*, int, double*, int64_t, hipStream_t);             \
-    template void launch_forward<T>(const DevPlan&, const int*, int, int, const T*, T*, T*, int, hipStream_t);     \
-    template void launch_backward<T>(const DevPlan&, const int*, int, int, const T*, const T*, T*, int, hipStream_t);
+    template void launch_fwd_T<T>(const DevPlan&, const int*, int, const T*, T*, T*, int, hipStream_t);           \
+    template void launch_fwd_G<T>(const DevPlan&, const int*, int, const T*, T*, T*, int, hipStream_t);           \
+    template void launch_bwd_G<T>(const DevPlan&, const int*, int, const T*, const T*, T*, int, hipStream_t);     \
+    template void launch_bwd_T<T>(const DevPlan&, const int*, int, const T*, const T*, T*, const T*, int, hipStream_t);
 
 NCL_INSTANTIATE(double)
 NCL_INSTANTIATE(float)

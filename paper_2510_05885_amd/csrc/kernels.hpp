@@ -7,9 +7,11 @@
 namespace ncl {
 
 constexpr int kNrhsMax = 16;   // columns per solve sweep (wider solves are chunked)
-constexpr int kPanel = 32;     // pivot block width of the large-front path
-constexpr int kTile = 64;      // tile order of the large-front MFMA update
-constexpr int kRowBlock = 64;  // rows per panel task
+constexpr int kPanel = 64;       // pivot block width of the large-front path
+constexpr int kSmallMax = 128;   // largest front order of the LDS-resident path
+constexpr int kTile = 64;        // tile order of the large-front MFMA update
+constexpr int kSolvePanel = 256; // pivot columns per solve panel
+constexpr int kSolveChunk = 256; // rows per solve G task (and fused rows below a panel)
 
 // Device copies of the plan (all device pointers), passed by value.
 struct DevPlan {
@@ -49,6 +51,7 @@ struct DevPlan {
     const int64_t* CB_off;
     const int* CB_ld;
     const int64_t* U_off;      // in elements of one column block (times kNrhsMax applied)
+    const int64_t* M_off;      // large fronts: offset of the per-panel L_kk D blocks (64 x 64 each)
     // per system
     const double* sys_thr;     // static-pivot thresholds eps * ||K||_max
     unsigned long long* inertia;  // 4 per system: npos, nneg, nzero, nperturbed
@@ -74,11 +77,11 @@ void launch_small_fronts(const DevPlan& d, const int* list, int count, int fmax,
 template <typename T>
 void launch_large_asm(const DevPlan& d, const int* tasks, int count, const double* K, T* F, hipStream_t st);
 template <typename T>
-void launch_large_diag(const DevPlan& d, const int* tasks, int count, T* F, T* D, hipStream_t st);
+void launch_large_diag0(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st);
 template <typename T>
-void launch_large_panel(const DevPlan& d, const int* tasks, int count, T* F, const T* D, hipStream_t st);
+void launch_large_panel(const DevPlan& d, const int* tasks, int count, T* F, const T* D, const T* M, hipStream_t st);
 template <typename T>
-void launch_large_update(const DevPlan& d, const int* tasks, int count, T* F, const T* D, hipStream_t st);
+void launch_large_update(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st);
 
 // ---- solves -----------------------------------------------------------------
 template <typename T>
@@ -86,11 +89,15 @@ void launch_permute_in(const DevPlan& d, const double* B, int64_t ldb, int nrhs,
 template <typename T>
 void launch_permute_out(const DevPlan& d, const T* Y, int nrhs, double* X, int64_t ldx, hipStream_t st);
 template <typename T>
-void launch_forward(const DevPlan& d, const int* fronts, int count, int fmax, const T* F, T* Y, T* U, int nrhs,
-                    hipStream_t st);
+void launch_fwd_T(const DevPlan& d, const int* tasks, int count, const T* F, T* Y, T* U, int nrhs, hipStream_t st);
 template <typename T>
-void launch_backward(const DevPlan& d, const int* fronts, int count, int fmax, const T* F, const T* D, T* Y,
-                     int nrhs, hipStream_t st);
+void launch_fwd_G(const DevPlan& d, const int* tasks, int count, const T* F, T* Y, T* U, int nrhs, hipStream_t st);
+template <typename T>
+void launch_bwd_G(const DevPlan& d, const int* tasks, int count, const T* F, const T* Y, T* partial, int nrhs,
+                  hipStream_t st);
+template <typename T>
+void launch_bwd_T(const DevPlan& d, const int* tasks, int count, const T* F, const T* D, T* Y, const T* partial,
+                  int nrhs, hipStream_t st);
 
 // ---- refinement -------------------------------------------------------------
 // R = B - K X; per chunk of rows (all of one system) the maxima of |R|, |X|, |B| per column.

@@ -15,9 +15,12 @@ namespace ncl {
 // device's LDS limit and the element size.
 struct PlanConfig {
     int small_front_max = 90;   // fronts with f <= this run in one workgroup in LDS
-    int panel = 32;             // pivot block width of the large-front path
+    int panel = 64;             // pivot block width of the large-front path
     int tile = 64;              // tile order of the large-front update
     int nd_leaf = 64;           // nested-dissection leaf size (compressed vertices)
+    int solve_panel = 256;      // pivot columns per solve panel
+    int solve_fuse_rows = 256;  // rows below a panel handled inside the panel's workgroup
+    int solve_chunk_rows = 256; // rows per G task otherwise
 };
 
 struct LevelBatch {            // one launch of the small-front kernel
@@ -29,11 +32,22 @@ struct LevelBatch {            // one launch of the small-front kernel
 struct LargeStep {             // launches of the large-front path for one level
     int level = 0;
     int64_t asm_first = 0, asm_count = 0;     // (front, column) tasks in large_asm
-    // per panel step k: diagonal-block, panel and update tasks
-    std::vector<int64_t> diag_first, diag_count;
+    int64_t d0_first = 0, d0_count = 0;       // fronts in large_diag0 (first panel's diagonal block)
+    // per panel step k: panel (TRSM) and update tasks
     std::vector<int64_t> panel_first, panel_count;
     std::vector<int64_t> upd_first, upd_count;
     std::vector<double> upd_flops;            // algorithmic flops of each update launch
+};
+
+// Solve schedule: each front is swept in panels of up to kSolvePanel pivot
+// columns.  A T task solves one panel's triangle in one workgroup; when the
+// rows below the panel are many, G tasks (row chunks) apply the panel to them
+// in parallel.  Per level and panel index j, one T launch and one G launch.
+struct SolveStep {
+    int level = 0, j = 0;
+    int64_t t_first = 0, t_count = 0;   // tasks in Plan::solve_t (5 ints each)
+    int64_t g_first = 0, g_count = 0;   // tasks in Plan::solve_g (5 ints each)
+    double fwd_bytes = 0.0;             // algorithmic bytes of L read by the step
 };
 
 struct Plan {
@@ -100,6 +114,8 @@ struct Plan {
     std::vector<int> CB_ld;
     int64_t factor_elems = 0;        // factor buffer length (elements of T)
     std::vector<int64_t> U_off;      // solve: update vector of each front (c_s * nrhs_max)
+    std::vector<int64_t> M_off;      // large fronts: per-panel L_kk D blocks (panel^2 each)
+    int64_t M_elems = 0;
     int64_t U_elems = 0;
 
     // ---- schedule --------------------------------------------------------
@@ -112,9 +128,15 @@ struct Plan {
     std::vector<LargeStep> large_steps;
     // large-front tasks
     std::vector<int> large_asm;      // pairs (front, column)
-    std::vector<int> large_diag;     // pairs (front, k0)
+    std::vector<int> large_diag0;    // large fronts, by level (first-panel diagonal factorization)
     std::vector<int> large_panel;    // triples (front, k0, row block start >= k0 + panel)
-    std::vector<int> large_upd;      // quads (front, k0, tile row start, tile col start)
+    std::vector<int> large_upd;      // quads (front, k0, tile row start, tile col start);
+                                     // i0 == -1: copy the panel's factored diagonal block back
+    // solve schedule
+    std::vector<SolveStep> solve_steps;
+    std::vector<int> solve_t;        // (front, c0, fused, g_first, g_count)
+    std::vector<int> solve_g;        // (front, c0, r0, r1, slot)
+    int64_t solve_max_slots = 0;     // G tasks in the largest step (partial-sum slots)
 
     // ---- stats ------------------------------------------------------------
     int64_t nnzL = 0;
