@@ -73,6 +73,11 @@ typedef struct {
     int32_t ordering;      /* NCL_ORDER_ND (default), NCL_ORDER_NATURAL, NCL_ORDER_USER */
     const int32_t *user_perm; /* host, used when ordering == NCL_ORDER_USER: user_perm[k] =
                                  unpermuted index of the k-th pivot (length n or n+m) */
+    int32_t use_graphs;    /* 1 (default): replay the fixed launch sequences of the frontal
+                              factorization and of the triangular sweeps as HIP graphs */
+    int32_t small_front_max; /* fronts up to this order are factored in LDS; 0 = device limit */
+    double relax_big_zeros;  /* supernode amalgamation: fraction of explicit zeros allowed in
+                                fronts above 128 rows; < 0 selects the default (0.2) */
 } ncl_kkt_options;
 
 /* Result of one solve (normwise backward error

@@ -376,7 +376,7 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                 double zm = g_z[c] + g_z[P0] + (sm - stor(g_p[c], g_f[c]) - stor(g_p[P0], g_f[P0]));
                 double zf = zm / sm;
                 bool ok = (pm <= 8 && zf <= 0.8) || (pm <= 24 && zf <= 0.35) || (pm <= 64 && zf <= 0.12) ||
-                          zf <= 0.04;
+                          zf <= 0.04 || (fm > cfg.relax_big_front && zf <= cfg.relax_big_zeros);
                 if (fm > 4000) ok = false;
                 if (!ok) continue;
                 grp[c] = P0;
@@ -725,7 +725,7 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                     const int p = P.sn_first[s + 1] - P.sn_first[s];
                     if (k0 >= p) continue;
                     const int k1 = std::min(k0 + nb, p);
-                    for (int r0 = k1; r0 < f; r0 += 256) {
+                    for (int r0 = k1; r0 < f; r0 += 64) {
                         P.large_panel.push_back(s); P.large_panel.push_back(k0); P.large_panel.push_back(r0);
                     }
                     P.large_upd.push_back(s); P.large_upd.push_back(k0);

@@ -13,9 +13,11 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/ncl_kkt.h"
@@ -83,6 +85,10 @@ struct ncl_kkt_s {
     bool inertia_ok = false;
     bool fell_back = false;
     Timer tm;
+    // HIP graphs of the fixed launch sequences (per precision; sweeps per nrhs)
+    hipStream_t cap_stream = nullptr;
+    hipGraphExec_t g_factor[2] = {nullptr, nullptr};
+    hipGraphExec_t g_sweep[2][kNrhsMax + 1] = {};
 };
 
 namespace {
@@ -260,6 +266,7 @@ void setup_device(ncl_kkt_s* h) {
     }
     h->host_pinned_len = (size_t)std::max<int64_t>((int64_t)P.S * kNrhsMax * 3, 8 * (int64_t)P.S + 8);
     HIPCHK(hipHostMalloc((void**)&h->host_pinned, sizeof(double) * h->host_pinned_len, hipHostMallocDefault));
+    HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     {
         int lds = 0;
         HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
@@ -287,6 +294,9 @@ void fill_defaults(ncl_kkt_options* o) {
     o->ir_stall = 0.5;
     o->ordering = NCL_ORDER_ND;
     o->user_perm = nullptr;
+    o->use_graphs = 1;
+    o->small_front_max = 0;
+    o->relax_big_zeros = -1.0;
 }
 
 int do_analyze(ncl_kkt_t* out, const ncl_kkt_options* o, const std::vector<SysInput>& sys, bool host_only) {
@@ -308,6 +318,11 @@ int do_analyze(ncl_kkt_t* out, const ncl_kkt_options* o, const std::vector<SysIn
         if (rc) { delete h; return rc; }
         cfg.small_front_max = fm;
     }
+    if (h->opt.small_front_max > 0) {
+        if (h->opt.small_front_max > cfg.small_front_max && !host_only) { delete h; return NCL_ERR_ARG; }
+        cfg.small_front_max = std::min(h->opt.small_front_max, kSmallMax);
+    }
+    if (h->opt.relax_big_zeros >= 0.0) cfg.relax_big_zeros = h->opt.relax_big_zeros;
     std::string err;
     int rc = build_plan(h->P, h->opt.form, sys, h->opt.ordering, h->opt.user_perm, cfg, err);
     if (rc) { delete h; return rc; }
@@ -372,6 +387,31 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
     }
 }
 
+// Runs the frontal factorization; with graphs enabled (and timing off) the
+// launch sequence is captured once on a private stream and replayed on the
+// caller's stream.  All its pointers are owned by the handle.
+template <typename T>
+void run_factor(ncl_kkt_s* h, hipStream_t st) {
+    const int pr = std::is_same<T, float>::value ? 1 : 0;
+    T* F = pr ? (T*)h->F32 : (T*)h->F64;
+    T* D = pr ? (T*)h->D32 : (T*)h->D64;
+    T* Mb = pr ? (T*)h->M32 : (T*)h->M64;
+    if (!h->opt.use_graphs || h->tm.on) {
+        factor_fronts<T>(h, F, D, Mb, st);
+        return;
+    }
+    if (!h->g_factor[pr]) {
+        hipGraph_t g = nullptr;
+        HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+        factor_fronts<T>(h, F, D, Mb, h->cap_stream);
+        HIPCHK(hipStreamEndCapture(h->cap_stream, &g));
+        hipError_t e = hipGraphInstantiate(&h->g_factor[pr], g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        HIPCHK(e);
+    }
+    HIPCHK(hipGraphLaunch(h->g_factor[pr], st));
+}
+
 int read_inertia(ncl_kkt_s* h, hipStream_t st) {
     const int S = h->P.S;
     unsigned long long* hp = reinterpret_cast<unsigned long long*>(h->host_pinned);
@@ -418,10 +458,10 @@ int factor_impl(ncl_kkt_s* h, const double* W, const double* Sigma, const double
         }
         HIPCHK(hipGetLastError());
         if (h->opt.precision == NCL_FP32_IR) {
-            factor_fronts<float>(h, h->F32, h->D32, h->M32, st);
+            run_factor<float>(h, st);
             h->factor_prec = 1;
         } else {
-            factor_fronts<double>(h, h->F64, h->D64, h->M64, st);
+            run_factor<double>(h, st);
             h->factor_prec = 0;
         }
         HIPCHK(hipGetLastError());
@@ -429,7 +469,7 @@ int factor_impl(ncl_kkt_s* h, const double* W, const double* Sigma, const double
         if (rc) { flush_timing(h); return rc; }
         if (!h->inertia_ok && h->factor_prec == 1) {
             // an FP32 factor with the wrong inertia: refactor in FP64
-            factor_fronts<double>(h, h->F64, h->D64, h->M64, st);
+            run_factor<double>(h, st);
             h->factor_prec = 0;
             h->fell_back = true;
             rc = read_inertia(h, st);
@@ -450,11 +490,9 @@ int factor_impl(ncl_kkt_s* h, const double* W, const double* Sigma, const double
 
 // ----- solve -------------------------------------------------------------------
 template <typename T>
-void solve_once(ncl_kkt_s* h, const double* B, int64_t ldb, double* X, int64_t ldx, int nrhs, const T* F,
-                const T* D, T* Y, T* U, T* partial, hipStream_t st) {
+void sweeps(ncl_kkt_s* h, int nrhs, const T* F, const T* D, T* Y, T* U, T* partial, hipStream_t st) {
     Plan& P = h->P;
     const DevPlan& d = h->d;
-    launch_permute_in<T>(d, B, ldb, nrhs, Y, st);
     for (const SolveStep& ss : P.solve_steps) {
         Span sp(h, st, TM_SOLVE, ss.fwd_bytes * sizeof(T) / 8.0, 4);
         launch_fwd_T<T>(d, h->solve_t + 5 * ss.t_first, (int)ss.t_count, F, Y, U, nrhs, st);
@@ -465,6 +503,29 @@ void solve_once(ncl_kkt_s* h, const double* B, int64_t ldb, double* X, int64_t l
         Span sp(h, st, TM_SOLVE, ss.fwd_bytes * sizeof(T) / 8.0, 4);
         launch_bwd_G<T>(d, h->solve_g + 5 * ss.g_first, (int)ss.g_count, F, Y, partial, nrhs, st);
         launch_bwd_T<T>(d, h->solve_t + 5 * ss.t_first, (int)ss.t_count, F, D, Y, partial, nrhs, st);
+    }
+}
+
+template <typename T>
+void solve_once(ncl_kkt_s* h, const double* B, int64_t ldb, double* X, int64_t ldx, int nrhs, const T* F,
+                const T* D, T* Y, T* U, T* partial, hipStream_t st) {
+    const DevPlan& d = h->d;
+    launch_permute_in<T>(d, B, ldb, nrhs, Y, st);
+    const int pr = std::is_same<T, float>::value ? 1 : 0;
+    if (!h->opt.use_graphs || h->tm.on) {
+        sweeps<T>(h, nrhs, F, D, Y, U, partial, st);
+    } else {
+        hipGraphExec_t& ge = h->g_sweep[pr][nrhs];
+        if (!ge) {
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+            sweeps<T>(h, nrhs, F, D, Y, U, partial, h->cap_stream);
+            HIPCHK(hipStreamEndCapture(h->cap_stream, &g));
+            hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            HIPCHK(e);
+        }
+        HIPCHK(hipGraphLaunch(ge, st));
     }
     launch_permute_out<T>(d, Y, nrhs, X, ldx, st);
 }
@@ -593,7 +654,7 @@ int ncl_kkt_solve(ncl_kkt_t h, const double* B, int64_t ldb, double* X, int64_t 
             double om = solve_refine(h, Bq, ldb, Xq, ldx, nq, st, steps, om0);
             if (om > h->opt.ir_tol && h->factor_prec == 1 && h->inertia_ok) {
                 // FP32 factor not accurate enough: refactor in FP64 from the assembled K
-                factor_fronts<double>(h, h->F64, h->D64, h->M64, st);
+                run_factor<double>(h, st);
                 h->factor_prec = 0;
                 h->fell_back = fell = true;
                 int rc = read_inertia(h, st);
@@ -725,6 +786,10 @@ void ncl_kkt_destroy(ncl_kkt_t h) {
         for (void* p : h->allocs) (void)hipFree(p);
         if (h->host_pinned) (void)hipHostFree(h->host_pinned);
         for (auto& e : h->tm.pool) (void)hipEventDestroy(e);
+        for (auto& g : h->g_factor) if (g) (void)hipGraphExecDestroy(g);
+        for (auto& row : h->g_sweep)
+            for (auto& g : row) if (g) (void)hipGraphExecDestroy(g);
+        if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
     }
     delete h;
 }

@@ -125,7 +125,10 @@ __device__ void lds_partial_ldlt(T* A, int lda, int f, int p, T* dv, const int8_
     for (int kb = 0; kb < p; kb += 16) {
         const int bw = min(16, p - kb);
         if (wave == 0) {
-            // rows kb + lane and kb + lane + 64 of the sub-panel, in registers
+            // Rows kb + lane and kb + lane + 64 of the sub-panel, in registers.
+            // Slots above a row's diagonal are scratch: they take the same
+            // unpredicated updates as the rest, are never read for a later
+            // pivot, and are not written back.
             const int i0 = kb + lane, i1 = kb + lane + 64;
             T r0[16], r1[16];
 #pragma unroll
@@ -133,44 +136,42 @@ __device__ void lds_partial_ldlt(T* A, int lda, int f, int p, T* dv, const int8_
                 r0[t] = (t < bw && i0 < f && t <= lane) ? A[i0 + (kb + t) * lda] : T(0);
                 r1[t] = (kTwoRows && t < bw && i1 < f) ? A[i1 + (kb + t) * lda] : T(0);
             }
+            T mydk = T(0);
+            unsigned int np = 0, nn = 0, nz = 0, npt = 0;
+            bool anybad = false;
 #pragma unroll
             for (int t = 0; t < 16; ++t) {
                 if (t >= bw) continue;   // uniform; keeps the loop fully unrolled
-                // column t of the sub-panel rows (lanes t+1..bw-1), before it is scaled
-                T ck[16];
-#pragma unroll
-                for (int u = 0; u < 16; ++u) ck[u] = (u > t && u < bw) ? bcast(r0[t], u) : T(0);
                 bool pert, bad;
                 const T dk = static_pivot(bcast(r0[t], t), thr, sgn[kb + t], pert, bad);
                 const T inv = fast_rcp(dk);
-                if (lane > t) {
-                    const T l = r0[t] * inv;
+                T ck[16];
 #pragma unroll
-                    for (int u = 0; u < 16; ++u)
-                        if (u > t && u < bw && u <= lane) r0[u] -= l * ck[u];
-                    r0[t] = l;
-                } else if (lane == t) {
-                    r0[t] = dk;
-                }
-                if (kTwoRows && i1 < f) {
-                    const T l = r1[t] * inv;
+                for (int u = t + 1; u < 16; ++u) ck[u] = (u < bw) ? bcast(r0[t], u) : T(0);
+                const T l0 = r0[t] * inv;
 #pragma unroll
-                    for (int u = 0; u < 16; ++u)
-                        if (u > t && u < bw) r1[u] -= l * ck[u];
-                    r1[t] = l;
+                for (int u = t + 1; u < 16; ++u) r0[u] -= l0 * ck[u];
+                r0[t] = (lane == t) ? dk : l0;
+                if (kTwoRows) {
+                    const T l1 = r1[t] * inv;
+#pragma unroll
+                    for (int u = t + 1; u < 16; ++u) r1[u] -= l1 * ck[u];
+                    r1[t] = l1;
                 }
-                if (lane == 0) {
-                    dv[kb + t] = dk;
-                    const double dd = to_d(dk);
-                    if (dd > 0.0) cnt[0]++; else if (dd < 0.0) cnt[1]++; else cnt[2]++;
-                    if (pert) cnt[3]++;
-                    bad_any |= bad;
-                }
+                mydk = (lane == t) ? dk : mydk;
+                const double dd = to_d(dk);
+                np += dd > 0.0; nn += dd < 0.0; nz += dd == 0.0; npt += pert;
+                anybad |= bad;
             }
 #pragma unroll
             for (int t = 0; t < 16; ++t) {
                 if (t < bw && i0 < f && t <= lane) A[i0 + (kb + t) * lda] = r0[t];
                 if (kTwoRows && t < bw && i1 < f) A[i1 + (kb + t) * lda] = r1[t];
+            }
+            if (lane < bw) dv[kb + lane] = mydk;
+            if (lane == 0) {
+                cnt[0] += np; cnt[1] += nn; cnt[2] += nz; cnt[3] += npt;
+                bad_any |= anybad;
             }
         }
         __syncthreads();
@@ -234,27 +235,31 @@ __global__ void k_assemble(DevPlan d, int64_t nnzF, const double* __restrict__ W
 }
 
 // Block per chunk of rows (one system): max |K_ij| and max row sum of |K|.
+// Eight lanes share a row (coalesced reads of the row's entries).
 __global__ __launch_bounds__(256) void k_chunk_norms(DevPlan d, const double* __restrict__ K,
                                                      const int* __restrict__ chunk_row0,
                                                      const int* __restrict__ chunk_rows, double* partial) {
     const int c = blockIdx.x;
-    const int tid = threadIdx.x;
-    double mx = 0.0, rs = 0.0;
-    if (tid < chunk_rows[c]) {
-        const int row = chunk_row0[c] + tid;
-        bool bad = false;
-        for (int64_t e = d.Kp[row]; e < d.Kp[row + 1]; ++e) {
+    const int tid = threadIdx.x, sub = tid & 7, grp = tid >> 3;   // 32 row groups of 8 lanes
+    double mx = 0.0, rsmax = 0.0;
+    bool bad = false;
+    for (int r = grp; r < chunk_rows[c]; r += 32) {
+        const int row = chunk_row0[c] + r;
+        double rs = 0.0;
+        for (int64_t e = d.Kp[row] + sub; e < d.Kp[row + 1]; e += 8) {
             const double v = K[e];
             bad |= !isfinite(v);
             const double a = fabs(v);
             mx = fmax(mx, a);
             rs += a;
         }
-        if (bad) { mx = INFINITY; rs = INFINITY; }
+        for (int o = 4; o > 0; o >>= 1) rs += __shfl_xor(rs, o, 8);
+        rsmax = fmax(rsmax, rs);
     }
+    if (bad) { mx = INFINITY; rsmax = INFINITY; }
     __shared__ double sm[2][256];
     sm[0][tid] = mx;
-    sm[1][tid] = rs;
+    sm[1][tid] = rsmax;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if (tid < o) {
@@ -394,8 +399,8 @@ __global__ __launch_bounds__(256) void k_large_asm(DevPlan d, const int* __restr
 // Writes the factored diagonal block of a panel (in LDS: L strictly below the
 // diagonal, column-major with leading dimension kPanel + 1; dv = pivots) to
 // its three consumers: D, the block's upper triangle (transposed; copied into
-// place by the next update launch) and Mg = L_kk D row-major, read by the
-// panel solve through uniform loads.
+// place by the next update launch) and Mg = L_kk D (strictly lower part,
+// column-major) with 1/d_t on its diagonal, for the panel solve.
 template <typename T>
 __device__ void publish_diag(T* A, int f, int k0, int w, const T* Bf, const T* dv, T* D, int first, T* Mg) {
     constexpr int LB = kPanel + 1;
@@ -404,8 +409,8 @@ __device__ void publish_diag(T* A, int f, int k0, int w, const T* Bf, const T* d
     for (int idx = tid; idx < kPanel * kPanel; idx += 256) {
         const int a = idx & (kPanel - 1), b = idx / kPanel;
         if (a < w && b < a) A[(k0 + b) + (int64_t)(k0 + a) * f] = Bf[a + b * LB];
-        const int t = idx / kPanel, u = idx % kPanel;
-        Mg[idx] = (u < t && t < w) ? Bf[t + u * LB] * dv[u] : T(0);
+        const int t = idx / kPanel, u = idx % kPanel;    // column t, row u
+        Mg[idx] = (u > t && u < w) ? Bf[u + t * LB] * dv[t] : (u == t && t < w) ? T(1) / dv[t] : T(0);
     }
 }
 
@@ -444,10 +449,15 @@ __global__ __launch_bounds__(256) void k_large_diag0(DevPlan d, const int* __res
     publish_diag<T>(A, f, 0, w, Bf, dv, D, first, Mbuf + d.M_off[s]);
 }
 
-// One workgroup per (front, panel, 256-row block): for its rows below the
+// One workgroup per (front, panel, 64-row block): for its rows below the
 // panel's (already factored) diagonal block, L[i, k0:k1] = A[i, k0:k1]
-// L_kk^-T D^-1, one row per thread.  M = L_kk D and the pivots are the same
-// for every lane and are read through uniform loads.
+// L_kk^-T D^-1.  Lanes are rows; wave q owns the panel columns
+// [16q, 16q + 16).  For q0 = 0..3: wave q0 finishes its columns by
+// column-oriented substitution (x_t *= 1/d_t, then x_u -= M[u][t] x_t for the
+// later columns of the quarter), publishes them through LDS, and after the
+// barrier every later wave subtracts their 16 x 16 block of contributions.
+// M = L_kk D (strictly lower, column-major, 1/d on the diagonal) is the same
+// for every lane and is read through uniform loads of at most 16 values.
 template <typename T>
 __global__ __launch_bounds__(256) void k_large_panel(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
                                                      const T* __restrict__ D, const T* __restrict__ Mbuf) {
@@ -458,32 +468,45 @@ __global__ __launch_bounds__(256) void k_large_panel(DevPlan d, const int* __res
     const int w = min(kPanel, p - k0);
     const int k1 = k0 + w;
     T* __restrict__ A = F + d.L_off[s];
-    const T* __restrict__ M = Mbuf + d.M_off[s] + (int64_t)(k0 / kPanel) * (kPanel * kPanel);
-    const T* __restrict__ dk = D + first + k0;
-    const int row = r0 + threadIdx.x;
-    if (row < k1 || row >= f) return;
-    T x[kPanel];
+    const T* __restrict__ Mt = Mbuf + d.M_off[s] + (int64_t)(k0 / kPanel) * (kPanel * kPanel);
+    __shared__ T xs[64][kPanel + 1];
+    const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int row = r0 + lane;
+    const bool active = row >= k1 && row < f;
+    const int c0 = 16 * q;
+    T x[16];
 #pragma unroll
-    for (int t = 0; t < kPanel; ++t) x[t] = (t < w) ? A[row + (int64_t)(k0 + t) * f] : T(0);
+    for (int j = 0; j < 16; ++j) x[j] = (active && c0 + j < w) ? A[row + (int64_t)(k0 + c0 + j) * f] : T(0);
+    for (int q0 = 0; q0 < 4; ++q0) {
+        if (16 * q0 >= w) break;   // uniform
+        if (q == q0) {
 #pragma unroll
-    for (int t = 0; t < kPanel; ++t) {
-        // four partial sums shorten the dependent FMA chain
-        T s0 = T(0), s1 = T(0), s2 = T(0), s3 = T(0);
+            for (int j = 0; j < 16; ++j) {
+                const int t = c0 + j;
+                const T* __restrict__ col = Mt + t * kPanel;
+                x[j] *= col[t];
 #pragma unroll
-        for (int u = 0; u + 3 < t; u += 4) {
-            s0 += M[t * kPanel + u] * x[u];
-            s1 += M[t * kPanel + u + 1] * x[u + 1];
-            s2 += M[t * kPanel + u + 2] * x[u + 2];
-            s3 += M[t * kPanel + u + 3] * x[u + 3];
+                for (int jj = j + 1; jj < 16; ++jj) x[jj] -= col[c0 + jj] * x[j];
+            }
+#pragma unroll
+            for (int j = 0; j < 16; ++j) xs[lane][c0 + j] = x[j];
         }
+        __syncthreads();
+        if (q > q0) {
 #pragma unroll
-        for (int u = t & ~3; u < t; ++u) s0 += M[t * kPanel + u] * x[u];
-        const T v = x[t] - ((s0 + s1) + (s2 + s3));
-        x[t] = (t < w) ? v / dk[t < w ? t : 0] : T(0);
+            for (int jt = 0; jt < 16; ++jt) {
+                const int t = 16 * q0 + jt;
+                const T xv = xs[lane][t];
+                const T* __restrict__ col = Mt + t * kPanel + c0;
+#pragma unroll
+                for (int j = 0; j < 16; ++j) x[j] -= col[j] * xv;
+            }
+        }
     }
+    if (!active) return;
 #pragma unroll
-    for (int t = 0; t < kPanel; ++t)
-        if (t < w) A[row + (int64_t)(k0 + t) * f] = x[t];
+    for (int j = 0; j < 16; ++j)
+        if (c0 + j < w) A[row + (int64_t)(k0 + c0 + j) * f] = x[j];
 }
 
 // Trailing update of one 64x64 lower tile: C -= L_I D_k L_J^T on MFMA, with
@@ -844,31 +867,36 @@ __global__ __launch_bounds__(256) void k_bwd_T(DevPlan d, const int* __restrict_
 // ---------------------------------------------------------------------------
 // refinement
 // ---------------------------------------------------------------------------
+// Block per chunk of rows (one system); eight lanes share a row.  R = B - K X
+// and, per column, the chunk's max |R|, |X|, |B|.
 __global__ __launch_bounds__(256) void k_residual(DevPlan d, const double* __restrict__ K,
                                                   const double* __restrict__ B, int64_t ldb,
                                                   const double* __restrict__ X, int64_t ldx, double* __restrict__ R,
                                                   int nrhs, const int* __restrict__ chunk_row0,
                                                   const int* __restrict__ chunk_rows, double* partial) {
     const int c = blockIdx.x;
-    const int tid = threadIdx.x;
-    const bool valid = tid < chunk_rows[c];
-    const int row = chunk_row0[c] + tid;
+    const int tid = threadIdx.x, sub = tid & 7, grp = tid >> 3;
     __shared__ double sm[3][256];
     for (int q = 0; q < nrhs; ++q) {
-        double r = 0.0, xa = 0.0, ba = 0.0;
-        if (valid) {
-            const double* __restrict__ x = X + q * ldx;
+        const double* __restrict__ x = X + q * ldx;
+        double rm = 0.0, xm = 0.0, bm = 0.0;
+        for (int r = grp; r < chunk_rows[c]; r += 32) {
+            const int row = chunk_row0[c] + r;
             double acc = 0.0;
-            for (int64_t e = d.Kp[row]; e < d.Kp[row + 1]; ++e) acc += K[e] * x[d.Kj[e]];
-            const double b = B[row + q * ldb];
-            r = b - acc;
-            R[row + q * d.N] = r;
-            xa = fabs(x[row]);
-            ba = fabs(b);
+            for (int64_t e = d.Kp[row] + sub; e < d.Kp[row + 1]; e += 8) acc += K[e] * x[d.Kj[e]];
+            for (int o = 4; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 8);
+            if (sub == 0) {
+                const double b = B[row + q * ldb];
+                const double rr = b - acc;
+                R[row + q * d.N] = rr;
+                rm = (rr == rr) ? fmax(rm, fabs(rr)) : INFINITY;   // NaN residual -> infinite
+                xm = fmax(xm, fabs(x[row]));
+                bm = fmax(bm, fabs(b));
+            }
         }
-        sm[0][tid] = fabs(r);
-        sm[1][tid] = xa;
-        sm[2][tid] = ba;
+        sm[0][tid] = rm;
+        sm[1][tid] = xm;
+        sm[2][tid] = bm;
         __syncthreads();
         for (int o = 128; o > 0; o >>= 1) {
             if (tid < o) {

@@ -18,6 +18,8 @@ struct PlanConfig {
     int panel = 64;             // pivot block width of the large-front path
     int tile = 64;              // tile order of the large-front update
     int nd_leaf = 64;           // nested-dissection leaf size (compressed vertices)
+    int relax_big_front = 128;  // fronts above this order (the global-memory path, swept in
+    double relax_big_zeros = 0.2;  // panels anyway) may carry up to this fraction of zeros
     int solve_panel = 256;      // pivot columns per solve panel
     int solve_fuse_rows = 256;  // rows below a panel handled inside the panel's workgroup
     int solve_chunk_rows = 256; // rows per G task otherwise
@@ -129,7 +131,7 @@ struct Plan {
     // large-front tasks
     std::vector<int> large_asm;      // pairs (front, column)
     std::vector<int> large_diag0;    // large fronts, by level (first-panel diagonal factorization)
-    std::vector<int> large_panel;    // triples (front, k0, row block start >= k0 + panel)
+    std::vector<int> large_panel;    // triples (front, k0, 64-row block start >= k0 + panel)
     std::vector<int> large_upd;      // quads (front, k0, tile row start, tile col start);
                                      // i0 == -1: copy the panel's factored diagonal block back
     // solve schedule

@@ -37,7 +37,8 @@ EXPORTED = [
 class Options(C.Structure):
     _fields_ = [("form", C.c_int32), ("precision", C.c_int32), ("pivot_eps", C.c_double),
                 ("ir_max_steps", C.c_int32), ("ir_tol", C.c_double), ("ir_stall", C.c_double),
-                ("ordering", C.c_int32), ("user_perm", C.POINTER(C.c_int32))]
+                ("ordering", C.c_int32), ("user_perm", C.POINTER(C.c_int32)), ("use_graphs", C.c_int32),
+                ("small_front_max", C.c_int32), ("relax_big_zeros", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -162,7 +163,8 @@ _ORDS = {"nd": NCL_ORDER_ND, "natural": NCL_ORDER_NATURAL, "user": NCL_ORDER_USE
 
 
 def make_options(form="condensed", precision="fp64", pivot_eps=0.0, ir_max_steps=10, ir_tol=1e-12,
-                 ir_stall=0.5, ordering="nd", user_perm=None):
+                 ir_stall=0.5, ordering="nd", user_perm=None, use_graphs=True, small_front_max=0,
+                 relax_big_zeros=-1.0):
     o = Options()
     lib().ncl_kkt_default_options(C.byref(o))
     o.form = _FORMS[form] if isinstance(form, str) else int(form)
@@ -171,6 +173,9 @@ def make_options(form="condensed", precision="fp64", pivot_eps=0.0, ir_max_steps
     o.ir_max_steps = int(ir_max_steps)
     o.ir_tol = float(ir_tol)
     o.ir_stall = float(ir_stall)
+    o.use_graphs = 1 if use_graphs else 0
+    o.small_front_max = int(small_front_max)
+    o.relax_big_zeros = float(relax_big_zeros)
     keep = None
     if user_perm is not None:
         keep, p = _i32(user_perm)
