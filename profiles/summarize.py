@@ -1,10 +1,15 @@
-"""Print a per-kernel summary (count, total ms, average us) from a rocprofv3
-results database (rocpd SQLite output of `rocprofv3 --kernel-trace --stats`)."""
+"""Summaries of rocprofv3 result databases (rocpd SQLite output).
+
+  python profiles/summarize.py kernels DB          per-kernel calls / total ms / avg us
+  python profiles/summarize.py pmc DB COUNTER REGEX  per-dispatch counter values of the
+                                                     kernels matching REGEX (mean, sum)
+"""
+import re
 import sqlite3
 import sys
 
 
-def main(db, top=25):
+def kernels(db, top=25):
     con = sqlite3.connect(db)
     rows = con.execute("select name, count(*), sum(end-start)/1e6, avg(end-start)/1e3 from kernels "
                        "group by name order by sum(end-start) desc").fetchall()
@@ -16,5 +21,30 @@ def main(db, top=25):
     print(f"{'TOTAL':70s} {'':7s} {tot:10.3f}")
 
 
+def pmc(db, counter, regex):
+    con = sqlite3.connect(db)
+    cols = [r[1] for r in con.execute("pragma table_info(counters_collection)").fetchall()]
+    q = "select * from counters_collection"
+    rows = con.execute(q).fetchall()
+    idx = {c: i for i, c in enumerate(cols)}
+    name_col = "kernel_name" if "kernel_name" in idx else "name"
+    vals = {}
+    for r in rows:
+        nm = r[idx[name_col]]
+        if not re.search(regex, nm):
+            continue
+        if r[idx["counter_name"]] != counter:
+            continue
+        key = nm.replace("ncl::(anonymous namespace)::", "").split("(")[0]
+        vals.setdefault(key, []).append(float(r[idx["value"]]))
+    for k, v in sorted(vals.items()):
+        print(f"{k:60s} {counter} dispatches={len(v):6d} mean={sum(v)/len(v):14.1f} sum={sum(v):16.1f}")
+
+
 if __name__ == "__main__":
-    main(sys.argv[1])
+    if sys.argv[1] == "kernels":
+        kernels(sys.argv[2])
+    elif sys.argv[1] == "pmc":
+        pmc(sys.argv[2], sys.argv[3], sys.argv[4])
+    else:
+        kernels(sys.argv[1])
