@@ -78,6 +78,12 @@ typedef struct {
     int32_t small_front_max; /* fronts up to this order are factored in LDS; 0 = device limit */
     double relax_big_zeros;  /* supernode amalgamation: fraction of explicit zeros allowed in
                                 fronts above 128 rows; < 0 selects the default (0.2) */
+    int32_t fp32_sticky;     /* NCL_FP32_IR only.  1 (default): once an FP32 factor had to be
+                                replaced by FP64 (wrong inertia, or refinement above ir_tol)
+                                at rho = r, every later factor with max rho >= r is computed
+                                in FP64 directly; a factor with max rho < r tries FP32 again
+                                (rho grows along an NCL outer loop, Algorithm 1).  0: always
+                                try FP32 first. */
 } ncl_kkt_options;
 
 /* Result of one solve (normwise backward error

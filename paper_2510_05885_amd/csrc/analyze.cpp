@@ -662,7 +662,7 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
             uoff = align(uoff + (f - p));
         }
         P.U_elems = std::max<int64_t>(uoff, 32);
-        P.M_off.assign(nsn, 0);
+        P.M_off.assign(nsn, -1);   // -1: small front (no panel inverses)
         int64_t moff = 0;
         for (int s = 0; s < nsn; ++s) {
             if (!P.sn_large[s]) continue;
@@ -711,12 +711,10 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                 for (int j = 0; j < f; ++j) { P.large_asm.push_back(s); P.large_asm.push_back(j); }
             }
             st.asm_count = (int64_t)P.large_asm.size() / 2 - st.asm_first;
-            st.d0_first = (int64_t)P.large_diag0.size();
-            for (int s : large) P.large_diag0.push_back(s);
-            st.d0_count = (int64_t)large.size();
             int maxp = 0;
             for (int s : large) maxp = std::max(maxp, P.sn_first[s + 1] - P.sn_first[s]);
             for (int k0 = 0; k0 < maxp; k0 += nb) {
+                st.diag_first.push_back((int64_t)P.large_diag.size() / 2);
                 st.panel_first.push_back((int64_t)P.large_panel.size() / 3);
                 st.upd_first.push_back((int64_t)P.large_upd.size() / 4);
                 double fl = 0.0;
@@ -725,11 +723,10 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                     const int p = P.sn_first[s + 1] - P.sn_first[s];
                     if (k0 >= p) continue;
                     const int k1 = std::min(k0 + nb, p);
-                    for (int r0 = k1; r0 < f; r0 += 64) {
+                    P.large_diag.push_back(s); P.large_diag.push_back(k0);
+                    for (int r0 = k1; r0 < f; r0 += 32) {
                         P.large_panel.push_back(s); P.large_panel.push_back(k0); P.large_panel.push_back(r0);
                     }
-                    P.large_upd.push_back(s); P.large_upd.push_back(k0);
-                    P.large_upd.push_back(-1); P.large_upd.push_back(-1);
                     for (int j0 = k1; j0 < f; j0 += T)
                         for (int i0 = j0; i0 < f; i0 += T) {
                             P.large_upd.push_back(s); P.large_upd.push_back(k0);
@@ -739,6 +736,7 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                             fl += 2.0 * ent * (k1 - k0);
                         }
                 }
+                st.diag_count.push_back((int64_t)P.large_diag.size() / 2 - st.diag_first.back());
                 st.panel_count.push_back((int64_t)P.large_panel.size() / 3 - st.panel_first.back());
                 st.upd_count.push_back((int64_t)P.large_upd.size() / 4 - st.upd_first.back());
                 st.upd_flops.push_back(fl);

@@ -61,7 +61,7 @@ struct ncl_kkt_s {
     int64_t nnzF = 0;
     // schedule arrays (device)
     int *small_list = nullptr, *level_list = nullptr, *large_asm = nullptr, *large_panel = nullptr,
-        *large_upd = nullptr, *large_diag0 = nullptr, *solve_t = nullptr, *solve_g = nullptr;
+        *large_upd = nullptr, *large_diag = nullptr, *solve_t = nullptr, *solve_g = nullptr;
     int *chunk_row0 = nullptr, *chunk_rows = nullptr, *sys_chunk_ptr = nullptr;
     int nchunks = 0;
     // numeric state
@@ -84,6 +84,9 @@ struct ncl_kkt_s {
     int factor_prec = 0;              // precision of the factor in use (0 FP64, 1 FP32)
     bool inertia_ok = false;
     bool fell_back = false;
+    // FP32_IR: smallest max-rho at which an FP32 factor had to be replaced
+    double fp32_rho_limit = HUGE_VAL;
+    double cur_rho_max = 0.0;
     Timer tm;
     // HIP graphs of the fixed launch sequences (per precision; sweeps per nrhs)
     hipStream_t cap_stream = nullptr;
@@ -200,7 +203,7 @@ void setup_device(ncl_kkt_s* h) {
     h->small_list = upload(h, P.small_list);
     h->level_list = upload(h, P.level_list);
     h->large_asm = upload(h, P.large_asm);
-    h->large_diag0 = upload(h, P.large_diag0);
+    h->large_diag = upload(h, P.large_diag);
     h->solve_t = upload(h, P.solve_t);
     h->solve_g = upload(h, P.solve_g);
     h->large_panel = upload(h, P.large_panel);
@@ -297,6 +300,7 @@ void fill_defaults(ncl_kkt_options* o) {
     o->use_graphs = 1;
     o->small_front_max = 0;
     o->relax_big_zeros = -1.0;
+    o->fp32_sticky = 1;
 }
 
 int do_analyze(ncl_kkt_t* out, const ncl_kkt_options* o, const std::vector<SysInput>& sys, bool host_only) {
@@ -370,11 +374,11 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
                 Span sp(h, st, TM_LASM);
                 launch_large_asm<T>(d, h->large_asm + 2 * ls.asm_first, (int)ls.asm_count, h->K, F, st);
             }
-            {
-                Span sp(h, st, TM_PANEL);
-                launch_large_diag0<T>(d, h->large_diag0 + ls.d0_first, (int)ls.d0_count, F, D, Mb, st);
-            }
             for (size_t k = 0; k < ls.panel_first.size(); ++k) {
+                {
+                    Span sp(h, st, TM_PANEL);
+                    launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[k], (int)ls.diag_count[k], F, D, Mb, st);
+                }
                 {
                     Span sp(h, st, TM_PANEL);
                     launch_large_panel<T>(d, h->large_panel + 3 * ls.panel_first[k], (int)ls.panel_count[k], F, D,
@@ -457,9 +461,18 @@ int factor_impl(ncl_kkt_s* h, const double* W, const double* Sigma, const double
             launch_thresholds(P.S, h->norms2, h->eps, h->kmax, h->kinf, h->thr, h->nonfinite, st);
         }
         HIPCHK(hipGetLastError());
-        if (h->opt.precision == NCL_FP32_IR) {
+        double rho_max = 0.0;
+        for (int s = 0; s < P.S; ++s) rho_max = std::max(rho_max, rho_host[s]);
+        h->cur_rho_max = rho_max;
+        const bool skip32 = h->opt.fp32_sticky && rho_max >= h->fp32_rho_limit;
+        if (h->opt.precision == NCL_FP32_IR && !skip32) {
             run_factor<float>(h, st);
             h->factor_prec = 1;
+        } else if (h->opt.precision == NCL_FP32_IR) {
+            // an FP32 factor failed at a smaller rho of this sequence: FP64 directly
+            run_factor<double>(h, st);
+            h->factor_prec = 0;
+            h->fell_back = true;
         } else {
             run_factor<double>(h, st);
             h->factor_prec = 0;
@@ -472,6 +485,7 @@ int factor_impl(ncl_kkt_s* h, const double* W, const double* Sigma, const double
             run_factor<double>(h, st);
             h->factor_prec = 0;
             h->fell_back = true;
+            h->fp32_rho_limit = std::min(h->fp32_rho_limit, rho_max);
             rc = read_inertia(h, st);
             if (rc) { flush_timing(h); return rc; }
         }
@@ -490,36 +504,36 @@ int factor_impl(ncl_kkt_s* h, const double* W, const double* Sigma, const double
 
 // ----- solve -------------------------------------------------------------------
 template <typename T>
-void sweeps(ncl_kkt_s* h, int nrhs, const T* F, const T* D, T* Y, T* U, T* partial, hipStream_t st) {
+void sweeps(ncl_kkt_s* h, int nrhs, const T* F, const T* Z, const T* D, T* Y, T* U, T* partial, hipStream_t st) {
     Plan& P = h->P;
     const DevPlan& d = h->d;
     for (const SolveStep& ss : P.solve_steps) {
         Span sp(h, st, TM_SOLVE, ss.fwd_bytes * sizeof(T) / 8.0, 4);
-        launch_fwd_T<T>(d, h->solve_t + 5 * ss.t_first, (int)ss.t_count, F, Y, U, nrhs, st);
+        launch_fwd_T<T>(d, h->solve_t + 5 * ss.t_first, (int)ss.t_count, F, Z, Y, U, nrhs, st);
         launch_fwd_G<T>(d, h->solve_g + 5 * ss.g_first, (int)ss.g_count, F, Y, U, nrhs, st);
     }
     for (auto it = P.solve_steps.rbegin(); it != P.solve_steps.rend(); ++it) {
         const SolveStep& ss = *it;
         Span sp(h, st, TM_SOLVE, ss.fwd_bytes * sizeof(T) / 8.0, 4);
         launch_bwd_G<T>(d, h->solve_g + 5 * ss.g_first, (int)ss.g_count, F, Y, partial, nrhs, st);
-        launch_bwd_T<T>(d, h->solve_t + 5 * ss.t_first, (int)ss.t_count, F, D, Y, partial, nrhs, st);
+        launch_bwd_T<T>(d, h->solve_t + 5 * ss.t_first, (int)ss.t_count, F, Z, D, Y, partial, nrhs, st);
     }
 }
 
 template <typename T>
 void solve_once(ncl_kkt_s* h, const double* B, int64_t ldb, double* X, int64_t ldx, int nrhs, const T* F,
-                const T* D, T* Y, T* U, T* partial, hipStream_t st) {
+                const T* Z, const T* D, T* Y, T* U, T* partial, hipStream_t st) {
     const DevPlan& d = h->d;
     launch_permute_in<T>(d, B, ldb, nrhs, Y, st);
     const int pr = std::is_same<T, float>::value ? 1 : 0;
     if (!h->opt.use_graphs || h->tm.on) {
-        sweeps<T>(h, nrhs, F, D, Y, U, partial, st);
+        sweeps<T>(h, nrhs, F, Z, D, Y, U, partial, st);
     } else {
         hipGraphExec_t& ge = h->g_sweep[pr][nrhs];
         if (!ge) {
             hipGraph_t g = nullptr;
             HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
-            sweeps<T>(h, nrhs, F, D, Y, U, partial, h->cap_stream);
+            sweeps<T>(h, nrhs, F, Z, D, Y, U, partial, h->cap_stream);
             HIPCHK(hipStreamEndCapture(h->cap_stream, &g));
             hipError_t e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
@@ -532,9 +546,9 @@ void solve_once(ncl_kkt_s* h, const double* B, int64_t ldb, double* X, int64_t l
 
 void solve_with_factor(ncl_kkt_s* h, const double* B, int64_t ldb, double* X, int64_t ldx, int nrhs, hipStream_t st) {
     if (h->factor_prec == 1)
-        solve_once<float>(h, B, ldb, X, ldx, nrhs, h->F32, h->D32, h->Y32, h->U32, h->P32, st);
+        solve_once<float>(h, B, ldb, X, ldx, nrhs, h->F32, h->M32, h->D32, h->Y32, h->U32, h->P32, st);
     else
-        solve_once<double>(h, B, ldb, X, ldx, nrhs, h->F64, h->D64, h->Y64, h->U64, h->P64, st);
+        solve_once<double>(h, B, ldb, X, ldx, nrhs, h->F64, h->M64, h->D64, h->Y64, h->U64, h->P64, st);
 }
 
 // Backward error of X against B (max over systems and columns).
@@ -657,6 +671,7 @@ int ncl_kkt_solve(ncl_kkt_t h, const double* B, int64_t ldb, double* X, int64_t 
                 run_factor<double>(h, st);
                 h->factor_prec = 0;
                 h->fell_back = fell = true;
+                h->fp32_rho_limit = std::min(h->fp32_rho_limit, h->cur_rho_max);
                 int rc = read_inertia(h, st);
                 if (rc) { flush_timing(h); return rc; }
                 int steps2 = 0;

@@ -205,6 +205,188 @@ __device__ void lds_partial_ldlt(T* A, int lda, int f, int p, T* dv, const int8_
     bad_out = bad_any;
 }
 
+// Value of lane 16 * (lane / 16) + U of each 16-lane row (DPP row_newbcast).
+template <int U>
+__device__ __forceinline__ double rowbcast(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const long long r = __builtin_amdgcn_update_dpp(b, b, 0x150 + U, 0xf, 0xf, true);
+    return __builtin_bit_cast(double, r);
+}
+template <int U>
+__device__ __forceinline__ float rowbcast(float v) {
+    const int b = __builtin_bit_cast(int, v);
+    const int r = __builtin_amdgcn_update_dpp(b, b, 0x150 + U, 0xf, 0xf, true);
+    return __builtin_bit_cast(float, r);
+}
+template <typename T>
+__device__ __forceinline__ T rowbcast_n(T v, int u) {   // u: a compile-time constant after unrolling
+    switch (u) {
+        case 0: return rowbcast<0>(v);   case 1: return rowbcast<1>(v);   case 2: return rowbcast<2>(v);
+        case 3: return rowbcast<3>(v);   case 4: return rowbcast<4>(v);   case 5: return rowbcast<5>(v);
+        case 6: return rowbcast<6>(v);   case 7: return rowbcast<7>(v);   case 8: return rowbcast<8>(v);
+        case 9: return rowbcast<9>(v);   case 10: return rowbcast<10>(v); case 11: return rowbcast<11>(v);
+        case 12: return rowbcast<12>(v); case 13: return rowbcast<13>(v); case 14: return rowbcast<14>(v);
+        default: return rowbcast<15>(v);
+    }
+}
+
+// LDL^T of one kPanel x kPanel diagonal block held in LDS (column-major,
+// leading dimension kPanel + 1, lower triangle), with the static-pivot rule of
+// Sec. 3.1 for its first w pivots.  The caller pads the block beyond w with
+// the identity and zeroes the upper triangle, so every size is a compile-time
+// constant: wave 0 factors each 16-column sub-panel in registers (lane = row,
+// readlane broadcasts), then the four waves apply its rank-16 update to the
+// trailing lower block on MFMA.  Bit c of negmask set = pivot c takes the
+// negative sign.  On return: L strictly below the diagonal, d on the diagonal
+// and in dv; lane 0 of wave 0 has added the counts of the first w pivots to
+// cnt[4].  Called by all 256 threads; ends with a barrier.
+template <typename T>
+__device__ __forceinline__ void diag_ldlt64(T* B, T* dv, unsigned long long negmask, int w, double thr, unsigned int* cnt,
+                            bool& bad_out) {
+    constexpr int LB = kPanel + 1;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    bool bad_any = false;
+#pragma unroll
+    for (int kb = 0; kb < kPanel; kb += 16) {
+        if (wave == 0) {
+            // Row `lane`, columns kb..kb+15.  Entries above a row's diagonal are
+            // scratch: they take the same updates, are never read as a pivot or
+            // a multiplier of a lower row, and are not stored.
+            T r[16];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) r[t] = B[lane + (kb + t) * LB];
+            T mydk = T(0);
+            unsigned int np = 0, nn = 0, nz = 0, npt = 0;
+            bool anybad = false;
+#pragma unroll
+            for (int t = 0; t < 16; ++t) {
+                const int c = kb + t;
+                bool pert, bd;
+                const T dk = static_pivot(bcast(r[t], c), thr, ((negmask >> c) & 1ULL) ? -1 : 1, pert, bd);
+                const T inv = fast_rcp(dk);
+                const T l = r[t] * inv;
+#pragma unroll
+                for (int u = t + 1; u < 16; ++u) r[u] -= l * bcast(r[t], kb + u);
+                r[t] = (lane == c) ? dk : l;
+                mydk = (lane == c) ? dk : mydk;
+                if (c < w) {
+                    const double dd = to_d(dk);
+                    np += dd > 0.0; nn += dd < 0.0; nz += dd == 0.0; npt += pert;
+                    anybad |= bd;
+                }
+            }
+#pragma unroll
+            for (int t = 0; t < 16; ++t)
+                if (lane >= kb + t) B[lane + (kb + t) * LB] = r[t];
+            if (lane >= kb && lane < kb + 16) dv[lane] = mydk;
+            if (lane == 0) {
+                cnt[0] += np; cnt[1] += nn; cnt[2] += nz; cnt[3] += npt;
+                bad_any |= anybad;
+            }
+        }
+        __syncthreads();
+        if (kb + 16 < kPanel) {
+            // trailing lower block of order kPanel - kb - 16, in 16 x 16 tiles
+            const int r0 = kb + 16;
+            const int nt = (kPanel - r0) / 16;
+            const int ntiles = nt * (nt + 1) / 2;
+            for (int tix = wave; tix < ntiles; tix += 4) {
+                int tj = 0, rem = tix;
+                while (rem >= nt - tj) { rem -= nt - tj; ++tj; }
+                const int ti = tj + rem;
+                const int i0 = r0 + 16 * ti, j0 = r0 + 16 * tj;
+                typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    const int t = kb + 4 * st + lk;
+                    acc = Mfma<T>::run(B[(i0 + lr) + t * LB], B[(j0 + lr) + t * LB] * dv[t], acc);
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int gi = i0 + Mfma<T>::row(lk, r), gj = j0 + lr;
+                    if (gi >= gj) B[gi + gj * LB] -= acc[r];
+                }
+            }
+            __syncthreads();
+        }
+    }
+    bad_out = bad_any;
+}
+
+// Inverse Z = L^-1 of the unit lower triangle of a factored kPanel x kPanel
+// block in LDS (L strictly below the diagonal of B, column-major, leading
+// dimension kPanel + 1).  Z is unit lower triangular; its strictly lower part
+// is stored transposed in the strictly upper triangle of B (Z[u][t] at
+// B[t + u * LB], u > t).  By 16 x 16 blocks: Z_qq = L_qq^-1 by substitution
+// (wave q, lane j builds column j), then for distance 1..3 the blocks below,
+// Z_iq = -Z_ii (sum_{k=q}^{i-1} L_ik Z_kq), on MFMA.  Called by all 256
+// threads; ends with a barrier.
+template <typename T>
+__device__ __forceinline__ T zget(const T* B, int u, int t) {   // Z[u][t]
+    constexpr int LB = kPanel + 1;
+    return u > t ? B[t + u * LB] : (u == t ? T(1) : T(0));
+}
+
+template <typename T>
+__device__ __forceinline__ void tri_inv64(T* B) {
+    constexpr int LB = kPanel + 1;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    {
+        // wave q: lane (g, j) builds column j of Z_qq (same in each 16-lane
+        // row) and holds row j of L_qq; L[i][u] comes from lane i of its row.
+        const int o = 16 * wave, j = lr;
+        T lrow[16], z[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            lrow[u] = u < j ? B[(o + j) + (o + u) * LB] : T(0);
+            z[u] = (u == j) ? T(1) : T(0);
+        }
+#pragma unroll
+        for (int i = 1; i < 16; ++i)
+#pragma unroll
+            for (int u = 0; u < i; ++u) z[i] = __builtin_fma(-rowbcast_n(lrow[u], i), z[u], z[i]);
+        if (lane < 16) {
+#pragma unroll
+            for (int i = 1; i < 16; ++i)
+                if (i > j) B[(o + j) + (o + i) * LB] = z[i];
+        }
+    }
+    __syncthreads();
+    typedef typename Mfma<T>::acc_t acc_t;
+#pragma unroll
+    for (int dist = 1; dist < 4; ++dist) {
+        const int q = wave, i = q + dist;
+        if (i < 4) {
+            acc_t S = {0, 0, 0, 0};
+            for (int k = q; k < i; ++k) {
+#pragma unroll
+                for (int st = 0; st < 4; ++st) {
+                    const int kk = Mfma<T>::row(lk, st);
+                    S = Mfma<T>::run(B[(16 * i + lr) + (16 * k + kk) * LB], zget(B, 16 * k + kk, 16 * q + lr), S);
+                }
+            }
+            acc_t R = {0, 0, 0, 0};
+#pragma unroll
+            for (int st = 0; st < 4; ++st)
+                R = Mfma<T>::run(zget(B, 16 * i + lr, 16 * i + Mfma<T>::row(lk, st)), S[st], R);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) B[(16 * q + lr) + (16 * i + Mfma<T>::row(lk, r)) * LB] = -R[r];
+        }
+        __syncthreads();
+    }
+}
+
+// Workgroups are dealt to the 8 XCDs round-robin (workgroup b runs on XCD
+// b mod 8), each XCD with its own L2.  Task index for workgroup b of n such
+// that every XCD takes one contiguous range of tasks: neighbouring tiles of a
+// front share their panel operands, which then stay in one L2.
+__device__ __forceinline__ int xcd_task(int b, int n) {
+    const int x = b & 7, q = n >> 3, r = n & 7;
+    return x * q + min(x, r) + (b >> 3);
+}
+
 inline unsigned int blocks_for(int64_t n, int bs) { return (unsigned int)((n + bs - 1) / bs); }
 
 // ---------------------------------------------------------------------------
@@ -397,126 +579,146 @@ __global__ __launch_bounds__(256) void k_large_asm(DevPlan d, const int* __restr
 }
 
 // Writes the factored diagonal block of a panel (in LDS: L strictly below the
-// diagonal, column-major with leading dimension kPanel + 1; dv = pivots) to
-// its three consumers: D, the block's upper triangle (transposed; copied into
-// place by the next update launch) and Mg = L_kk D (strictly lower part,
-// column-major) with 1/d_t on its diagonal, for the panel solve.
+// diagonal, Z = L^-1 transposed strictly above it, column-major with leading
+// dimension kPanel + 1; dv = pivots) to its consumers: D, the front's L
+// (strictly lower part of the block), and Zg = Z (column-major, kPanel x
+// kPanel, unit diagonal, identity beyond w) for the panel solves.
 template <typename T>
-__device__ void publish_diag(T* A, int f, int k0, int w, const T* Bf, const T* dv, T* D, int first, T* Mg) {
+__device__ void publish_diag(T* A, int f, int k0, int w, const T* Bf, const T* dv, T* D, int first, T* Zg) {
     constexpr int LB = kPanel + 1;
     const int tid = threadIdx.x;
     if (tid < w) D[first + k0 + tid] = dv[tid];
     for (int idx = tid; idx < kPanel * kPanel; idx += 256) {
-        const int a = idx & (kPanel - 1), b = idx / kPanel;
-        if (a < w && b < a) A[(k0 + b) + (int64_t)(k0 + a) * f] = Bf[a + b * LB];
-        const int t = idx / kPanel, u = idx % kPanel;    // column t, row u
-        Mg[idx] = (u > t && u < w) ? Bf[u + t * LB] * dv[t] : (u == t && t < w) ? T(1) / dv[t] : T(0);
+        const int u = idx & (kPanel - 1), t = idx / kPanel;   // row u, column t
+        if (u < w && t < u) A[(k0 + u) + (int64_t)(k0 + t) * f] = Bf[u + t * LB];
+        Zg[idx] = zget(Bf, u, t);
     }
 }
 
-// One workgroup per large front: factor the diagonal block of the first
-// panel (static-pivot rule, inertia) and publish it.
+// Pads the diagonal block beyond its w pivots with the identity and zeroes
+// its upper triangle (entries with u < w and t < w on or below the diagonal
+// are left to the caller).
 template <typename T>
-__global__ __launch_bounds__(256) void k_large_diag0(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
-                                                     T* __restrict__ D, T* __restrict__ Mbuf) {
-    const int s = tasks[blockIdx.x];
+__device__ __forceinline__ void pad_diag(T* Bf, int w) {
+    constexpr int LB = kPanel + 1;
+    for (int idx = threadIdx.x; idx < kPanel * kPanel; idx += 256) {
+        const int u = idx & (kPanel - 1), t = idx / kPanel;
+        if (u < t) Bf[u + t * LB] = T(0);
+        else if (u >= w) Bf[u + t * LB] = (u == t) ? T(1) : T(0);
+    }
+}
+
+__device__ __forceinline__ unsigned long long neg_mask(const DevPlan& d, int first, int k0, int w) {
+    const int lane = threadIdx.x & 63;
+    const bool neg = lane < w && d.row_sign[d.perm[first + k0 + lane]] < 0;
+    return __ballot(neg);
+}
+
+// One workgroup per (large front, panel): factor the panel's diagonal block
+// (already updated by every earlier panel) with the static-pivot rule of
+// Sec. 3.1, count its inertia, invert its unit lower triangle and publish
+// L, D and Z = L_kk^-1.
+template <typename T>
+__global__ __launch_bounds__(256) void k_large_diag(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
+                                                    T* __restrict__ D, T* __restrict__ Zbuf) {
+    const int s = tasks[2 * blockIdx.x], k0 = tasks[2 * blockIdx.x + 1];
     const int first = d.sn_first[s];
     const int p = d.sn_first[s + 1] - first;
     const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
-    const int w = min(kPanel, p);
+    const int w = min(kPanel, p - k0);
     T* __restrict__ A = F + d.L_off[s];
     constexpr int LB = kPanel + 1;
     __shared__ T Bf[kPanel * LB];
     __shared__ T dv[kPanel];
-    __shared__ int8_t sgn[kPanel];
     const int tid = threadIdx.x;
     for (int idx = tid; idx < kPanel * kPanel; idx += 256) {
-        const int a = idx & (kPanel - 1), b = idx / kPanel;
-        if (a < w && b <= a) Bf[a + b * LB] = A[a + (int64_t)b * f];
+        const int u = idx & (kPanel - 1), t = idx / kPanel;
+        if (u < w && t <= u) Bf[u + t * LB] = A[(k0 + u) + (int64_t)(k0 + t) * f];
     }
-    if (tid < w) sgn[tid] = d.row_sign[d.perm[first + tid]];
+    pad_diag<T>(Bf, w);
+    const unsigned long long negmask = neg_mask(d, first, k0, w);
     __syncthreads();
     const int sys = d.sn_sys[s];
     unsigned int cnt[4] = {0, 0, 0, 0};
     bool bad = false;
-    lds_partial_ldlt<T, false>(Bf, LB, w, w, dv, sgn, d.sys_thr[sys], cnt, bad);
+    diag_ldlt64<T>(Bf, dv, negmask, w, d.sys_thr[sys], cnt, bad);
+    tri_inv64<T>(Bf);
     if (tid == 0) {
         unsigned long long* in4 = d.inertia + 4 * sys;
         for (int k = 0; k < 4; ++k)
             if (cnt[k]) atomicAdd(&in4[k], (unsigned long long)cnt[k]);
         if (bad) d.nonfinite[0] = 1;
     }
-    publish_diag<T>(A, f, 0, w, Bf, dv, D, first, Mbuf + d.M_off[s]);
+    publish_diag<T>(A, f, k0, w, Bf, dv, D, first, Zbuf + d.M_off[s] + (int64_t)(k0 / kPanel) * (kPanel * kPanel));
 }
 
-// One workgroup per (front, panel, 64-row block): for its rows below the
-// panel's (already factored) diagonal block, L[i, k0:k1] = A[i, k0:k1]
-// L_kk^-T D^-1.  Lanes are rows; wave q owns the panel columns
-// [16q, 16q + 16).  For q0 = 0..3: wave q0 finishes its columns by
-// column-oriented substitution (x_t *= 1/d_t, then x_u -= M[u][t] x_t for the
-// later columns of the quarter), publishes them through LDS, and after the
-// barrier every later wave subtracts their 16 x 16 block of contributions.
-// M = L_kk D (strictly lower, column-major, 1/d on the diagonal) is the same
-// for every lane and is read through uniform loads of at most 16 values.
+// One workgroup per (front, panel, 32-row block) below the panel's diagonal
+// block: L[i, k0:k1] = A[i, k0:k1] Z^T D^-1 with Z = L_kk^-1 (published by the
+// diagonal-block factorization), on MFMA.  The result is also stored
+// transposed in the front's upper triangle (never used by the factorization)
+// so that the backward solve reads L^T rows contiguously.  Wave w takes rows r0 + 16 (w & 1)
+// and the output column blocks J = w >> 1 and 3 - (w >> 1); Z is lower
+// triangular, so block J contracts over k < 16 (J + 1) only.
 template <typename T>
 __global__ __launch_bounds__(256) void k_large_panel(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
-                                                     const T* __restrict__ D, const T* __restrict__ Mbuf) {
+                                                     const T* __restrict__ D, const T* __restrict__ Zbuf) {
     const int s = tasks[3 * blockIdx.x], k0 = tasks[3 * blockIdx.x + 1], r0 = tasks[3 * blockIdx.x + 2];
     const int first = d.sn_first[s];
     const int p = d.sn_first[s + 1] - first;
     const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
     const int w = min(kPanel, p - k0);
-    const int k1 = k0 + w;
     T* __restrict__ A = F + d.L_off[s];
-    const T* __restrict__ Mt = Mbuf + d.M_off[s] + (int64_t)(k0 / kPanel) * (kPanel * kPanel);
-    __shared__ T xs[64][kPanel + 1];
-    const int q = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int row = r0 + lane;
-    const bool active = row >= k1 && row < f;
-    const int c0 = 16 * q;
-    T x[16];
+    const T* __restrict__ Zt = Zbuf + d.M_off[s] + (int64_t)(k0 / kPanel) * (kPanel * kPanel);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int lr = lane & 15, lk = lane >> 4;
+    const int rb = r0 + 16 * (wave & 1);
+    const int row = rb + lr;
+    const bool rv = row < f;
+    T a[4][4];
 #pragma unroll
-    for (int j = 0; j < 16; ++j) x[j] = (active && c0 + j < w) ? A[row + (int64_t)(k0 + c0 + j) * f] : T(0);
-    for (int q0 = 0; q0 < 4; ++q0) {
-        if (16 * q0 >= w) break;   // uniform
-        if (q == q0) {
+    for (int K = 0; K < 4; ++K)
 #pragma unroll
-            for (int j = 0; j < 16; ++j) {
-                const int t = c0 + j;
-                const T* __restrict__ col = Mt + t * kPanel;
-                x[j] *= col[t];
-#pragma unroll
-                for (int jj = j + 1; jj < 16; ++jj) x[jj] -= col[c0 + jj] * x[j];
-            }
-#pragma unroll
-            for (int j = 0; j < 16; ++j) xs[lane][c0 + j] = x[j];
+        for (int st = 0; st < 4; ++st) {
+            const int kk = 16 * K + Mfma<T>::row(lk, st);
+            a[K][st] = (rv && kk < w) ? A[row + (int64_t)(k0 + kk) * f] : T(0);
         }
-        __syncthreads();
-        if (q > q0) {
+    typedef typename Mfma<T>::acc_t acc_t;
 #pragma unroll
-            for (int jt = 0; jt < 16; ++jt) {
-                const int t = 16 * q0 + jt;
-                const T xv = xs[lane][t];
-                const T* __restrict__ col = Mt + t * kPanel + c0;
+    for (int h = 0; h < 2; ++h) {
+        const int J = h ? 3 - (wave >> 1) : (wave >> 1);
+        acc_t acc = {0, 0, 0, 0};
 #pragma unroll
-                for (int j = 0; j < 16; ++j) x[j] -= col[j] * xv;
+        for (int K = 0; K < 4; ++K) {
+            if (K > J) continue;   // uniform
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                const int kk = 16 * K + Mfma<T>::row(lk, st);
+                acc = Mfma<T>::run(a[K][st], Zt[kk * kPanel + 16 * J + lr], acc);
+            }
+        }
+        const int col = 16 * J + lr;
+        if (col < w) {
+            const T dinv = T(1) / D[first + k0 + col];
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gi = rb + Mfma<T>::row(lk, r);
+                if (gi < f) {
+                    const T x = acc[r] * dinv;
+                    A[gi + (int64_t)(k0 + col) * f] = x;
+                    A[(k0 + col) + (int64_t)gi * f] = x;   // L^T in the unused upper triangle
+                }
             }
         }
     }
-    if (!active) return;
-#pragma unroll
-    for (int j = 0; j < 16; ++j)
-        if (c0 + j < w) A[row + (int64_t)(k0 + c0 + j) * f] = x[j];
 }
 
 // Trailing update of one 64x64 lower tile: C -= L_I D_k L_J^T on MFMA, with
 // the operands read straight from the front (no LDS).  Four waves, each a
-// 32x32 quadrant as 2x2 blocks of 16x16; depth = panel width.  A task with
-// i0 < 0 instead copies the panel's parked diagonal block into place.
+// 32x32 quadrant as 2x2 blocks of 16x16; depth = panel width.
 template <typename T>
 __global__ __launch_bounds__(256) void k_large_update(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
-                                                      T* __restrict__ D, T* __restrict__ Mbuf) {
-    const int* tk = tasks + 4 * blockIdx.x;
+                                                      const T* __restrict__ D) {
+    const int* tk = tasks + 4 * xcd_task(blockIdx.x, gridDim.x);
     const int s = tk[0], k0 = tk[1], i0 = tk[2], j0 = tk[3];
     const int first = d.sn_first[s];
     const int p = d.sn_first[s + 1] - first;
@@ -524,13 +726,6 @@ __global__ __launch_bounds__(256) void k_large_update(DevPlan d, const int* __re
     const int w = min(kPanel, p - k0);
     T* __restrict__ A = F + d.L_off[s];
     const int tid = threadIdx.x;
-    if (i0 < 0) {
-        for (int idx = tid; idx < kPanel * kPanel; idx += 256) {
-            const int a = idx & (kPanel - 1), b = idx / kPanel;
-            if (a < w && b < a) A[(k0 + a) + (int64_t)(k0 + b) * f] = A[(k0 + b) + (int64_t)(k0 + a) * f];
-        }
-        return;
-    }
     const int wave = tid >> 6, lane = tid & 63;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int lr = lane & 15, lk = lane >> 4;
@@ -561,42 +756,15 @@ __global__ __launch_bounds__(256) void k_large_update(DevPlan d, const int* __re
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
             for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = Mfma<T>::run(av[ks][bi], bv[ks][bj], acc[bi][bj]);
-    const int k1 = k0 + w;
-    const bool next_diag = (i0 == k1 && j0 == k1 && k1 < p);
-    constexpr int LB = kPanel + 1;
-    __shared__ T Bf[kPanel * LB];
-    __shared__ T dv[kPanel];
-    __shared__ int8_t sgn[kPanel];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int li = wr + bi * 16 + Mfma<T>::row(lk, r), lj = wc + bj * 16 + lr;
-                const int gi = i0 + li, gj = j0 + lj;
-                if (gi < f && gj < f && gi >= gj) {
-                    const T nv = A[gi + (int64_t)gj * f] - acc[bi][bj][r];
-                    A[gi + (int64_t)gj * f] = nv;
-                    if (next_diag) Bf[li + lj * LB] = nv;
-                }
+                const int gi = i0 + wr + bi * 16 + Mfma<T>::row(lk, r), gj = j0 + wc + bj * 16 + lr;
+                if (gi < f && gj < f && gi >= gj) A[gi + (int64_t)gj * f] -= acc[bi][bj][r];
             }
-    if (!next_diag) return;
-    // This tile is the next panel's diagonal block: factor it now and park it.
-    const int w2 = min(kPanel, p - k1);
-    if (tid < w2) sgn[tid] = d.row_sign[d.perm[first + k1 + tid]];
-    __syncthreads();
-    const int sys = d.sn_sys[s];
-    unsigned int cnt[4] = {0, 0, 0, 0};
-    bool bad = false;
-    lds_partial_ldlt<T, false>(Bf, LB, w2, w2, dv, sgn, d.sys_thr[sys], cnt, bad);
-    if (tid == 0) {
-        unsigned long long* in4 = d.inertia + 4 * sys;
-        for (int k = 0; k < 4; ++k)
-            if (cnt[k]) atomicAdd(&in4[k], (unsigned long long)cnt[k]);
-        if (bad) d.nonfinite[0] = 1;
-    }
-    publish_diag<T>(A, f, k1, w2, Bf, dv, D, first, Mbuf + d.M_off[s] + (int64_t)(k1 / kPanel) * (kPanel * kPanel));
 }
 
 // ---------------------------------------------------------------------------
@@ -620,17 +788,121 @@ __global__ void k_permute_out(DevPlan d, const T* __restrict__ Y, int nrhs, doub
 
 // ---- panel-based sweeps ----------------------------------------------------
 // Task layouts: T = (front, c0, fused, g_first, g_count), G = (front, c0, r0, r1, slot).
-// Panel = pivot columns [c0, c0 + w), w <= kSolvePanel, of front s; its
-// triangle is solved in 64-column sub-blocks staged in LDS.
+// Panel = pivot columns [c0, c0 + w), w <= kSolvePanel, of front s, taken in
+// 64-column sub-blocks.  For a large front the sub-block's triangle is applied
+// through its inverse Z = L_kk^-1 published by the factorization (a GEMV, no
+// dependent chain), and L^T is read from the front's upper triangle; a small
+// front solves the sub-block by substitution (one wave, readlane broadcasts).
+// Dot products load 64 operands per thread at a time (memory-level
+// parallelism); vectors in LDS are zero beyond their length.
+
+// acc[q] += sum_{k < n} M[row + (col0 + k) * f] v[k + q * ldv], q < nrhs,
+// in chunks of kDotChunk operands loaded before use.
+constexpr int kDotChunk = 32;
+template <typename T>
+__device__ __forceinline__ void row_dot(const T* __restrict__ M, int64_t f, int row, int col0, int n, const T* v,
+                                        int ldv, int nrhs, T* acc) {
+    for (int kc = 0; kc < n; kc += kDotChunk) {
+        T lv[kDotChunk];
+#pragma unroll
+        for (int k = 0; k < kDotChunk; ++k) lv[k] = (kc + k < n) ? M[row + (int64_t)(col0 + kc + k) * f] : T(0);
+        const bool tail = kc + kDotChunk > n;
+#pragma unroll
+        for (int q = 0; q < kNrhsMax; ++q) {
+            if (q >= nrhs) continue;   // uniform
+            const T* vq = v + kc + q * ldv;
+            T a0 = T(0), a1 = T(0);
+            if (!tail) {
+#pragma unroll
+                for (int k = 0; k < kDotChunk; k += 2) { a0 += lv[k] * vq[k]; a1 += lv[k + 1] * vq[k + 1]; }
+            } else {
+#pragma unroll
+                for (int k = 0; k < kDotChunk; k += 2) {
+                    a0 += (kc + k < n) ? lv[k] * vq[k] : T(0);
+                    a1 += (kc + k + 1 < n) ? lv[k + 1] * vq[k + 1] : T(0);
+                }
+            }
+            acc[q] += a0 + a1;
+        }
+    }
+}
+
+// Small fronts: the sub-block's unit lower triangle staged in Ld (64 x 65),
+// then one wave substitutes (forward: rows; backward: transposed).
+template <typename T, bool kBackward>
+__device__ __forceinline__ void chain_solve64(const T* __restrict__ L, int f, int c, int ws, T* Ld, T* v, int nrhs) {
+    const int tid = threadIdx.x, lane = tid & 63;
+    for (int idx = tid; idx < 64 * ws; idx += 256) {
+        const int a = idx & 63, b = idx >> 6;
+        if (a < ws && b < a) Ld[a * 65 + b] = L[(c + a) + (int64_t)(c + b) * f];
+    }
+    __syncthreads();
+    if (tid < 64) {
+        T lrow[64];
+        if (!kBackward) {
+#pragma unroll
+            for (int k = 0; k < 64; ++k) lrow[k] = (k < lane && lane < ws) ? Ld[lane * 65 + k] : T(0);
+        } else {
+#pragma unroll
+            for (int k = 0; k < 64; ++k) lrow[k] = (lane < k && k < ws) ? Ld[k * 65 + lane] : T(0);
+        }
+        for (int q = 0; q < nrhs; ++q) {
+            T val = lane < ws ? v[lane + q * kSolvePanel] : T(0);
+            if (!kBackward) {
+#pragma unroll
+                for (int k = 0; k < 63; ++k) val -= lrow[k] * bcast(val, k);
+            } else {
+#pragma unroll
+                for (int k = 63; k > 0; --k) val -= lrow[k] * bcast(val, k);
+            }
+            if (lane < ws) v[lane + q * kSolvePanel] = val;
+        }
+    }
+    __syncthreads();
+}
+
+// Large fronts: v[0:64) <- Z v (forward) or Z^T v (backward) for one 64-block,
+// the 4 waves splitting the contraction; Zs (64 x 65 LDS) stages Z for the
+// transposed product; part holds 4 x 64 x nrhs partial sums.
+template <typename T, bool kBackward>
+__device__ __forceinline__ void zmul64(const T* __restrict__ Zb, int ws, T* Zs, T* part, T* v, int nrhs) {
+    const int tid = threadIdx.x, lane = tid & 63, q4 = tid >> 6;
+    T z[16];
+    if (!kBackward) {
+#pragma unroll
+        for (int j = 0; j < 16; ++j) z[j] = Zb[(16 * q4 + j) * kPanel + lane];   // Z[lane][16 q4 + j]
+    } else {
+        for (int idx = tid; idx < kPanel * kPanel; idx += 256) Zs[(idx & 63) + (idx >> 6) * 65] = Zb[idx];
+        __syncthreads();
+#pragma unroll
+        for (int j = 0; j < 16; ++j) z[j] = Zs[(16 * q4 + j) + lane * 65];        // Z[16 q4 + j][lane]
+    }
+    for (int q = 0; q < nrhs; ++q) {
+        const T* vq = v + 16 * q4 + q * kSolvePanel;
+        T acc = T(0);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc += z[j] * vq[j];
+        part[(q4 * 64 + lane) * nrhs + q] = acc;
+    }
+    __syncthreads();
+    if (tid < ws)
+        for (int q = 0; q < nrhs; ++q) {
+            const T* pp = part + tid * nrhs + q;
+            v[tid + q * kSolvePanel] = (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]);
+        }
+    __syncthreads();
+}
 
 // Forward T: (c0 == 0) pull the children's update vectors; solve the panel's
 // triangle; when `fused`, also apply the panel to every row below it.
 template <typename T>
 __global__ __launch_bounds__(256) void k_fwd_T(DevPlan d, const int* __restrict__ tasks, const T* __restrict__ F,
-                                               T* __restrict__ Y, T* __restrict__ U, int nrhs) {
+                                               const T* __restrict__ Zbuf, T* __restrict__ Y, T* __restrict__ U,
+                                               int nrhs) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* Ld = reinterpret_cast<T*>(smem_raw);       // 64 x 65
-    T* v = Ld + 64 * 65;                          // kSolvePanel x nrhs
+    T* v = reinterpret_cast<T*>(smem_raw);        // kSolvePanel x nrhs
+    T* part = v + kSolvePanel * nrhs;             // 4 x 64 x nrhs
+    T* Ld = part + 256 * nrhs;                    // 64 x 65
     const int* tk = tasks + 5 * blockIdx.x;
     const int s = tk[0], c0 = tk[1], fused = tk[2];
     const int first = d.sn_first[s];
@@ -640,8 +912,9 @@ __global__ __launch_bounds__(256) void k_fwd_T(DevPlan d, const int* __restrict_
     const int w = min(kSolvePanel, p - c0);
     const T* __restrict__ L = F + d.L_off[s];
     T* __restrict__ Us = U + d.U_off[s];
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int tid = threadIdx.x;
     const int64_t N = d.N;
+    const int64_t zoff = d.M_off[s];
     if (c0 == 0) {
         for (int q = 0; q < nrhs; ++q)
             for (int i = tid; i < c; i += 256) Us[i + (int64_t)q * c] = T(0);
@@ -663,35 +936,24 @@ __global__ __launch_bounds__(256) void k_fwd_T(DevPlan d, const int* __restrict_
         }
     }
     for (int q = 0; q < nrhs; ++q)
-        for (int t = tid; t < w; t += 256) v[t + q * kSolvePanel] = Y[first + c0 + t + q * N];
+        for (int t = tid; t < kSolvePanel; t += 256) v[t + q * kSolvePanel] = t < w ? Y[first + c0 + t + q * N] : T(0);
     __syncthreads();
     for (int sb = 0; sb < w; sb += 64) {
         const int ws = min(64, w - sb);
-        for (int idx = tid; idx < 64 * ws; idx += 256) {
-            const int a = idx & 63, b = idx >> 6;
-            if (a < ws && b < a) Ld[a * 65 + b] = L[(c0 + sb + a) + (int64_t)(c0 + sb + b) * f];
-        }
-        __syncthreads();
-        if (tid < 64) {
-            T lrow[64];
+        if (zoff >= 0)
+            zmul64<T, false>(Zbuf + zoff + (int64_t)((c0 + sb) / kPanel) * (kPanel * kPanel), ws, Ld, part, v + sb,
+                             nrhs);
+        else
+            chain_solve64<T, false>(L, f, c0 + sb, ws, Ld, v + sb, nrhs);
+        const int t = sb + ws + tid;
+        if (t < w) {
+            T acc[kNrhsMax];
 #pragma unroll
-            for (int k = 0; k < 64; ++k) lrow[k] = (k < lane && lane < ws) ? Ld[lane * 65 + k] : T(0);
-            for (int q = 0; q < nrhs; ++q) {
-                T val = lane < ws ? v[sb + lane + q * kSolvePanel] : T(0);
+            for (int q = 0; q < kNrhsMax; ++q) acc[q] = T(0);
+            row_dot(L, f, c0 + t, c0 + sb, ws, v + sb, kSolvePanel, nrhs, acc);
 #pragma unroll
-                for (int k = 0; k < 63; ++k) val -= lrow[k] * bcast(val, k);
-                if (lane < ws) v[sb + lane + q * kSolvePanel] = val;
-            }
-        }
-        __syncthreads();
-        for (int t = sb + ws + tid; t < w; t += 256) {
-            for (int q = 0; q < nrhs; ++q) {
-                T acc = T(0);
-                const T* vq = v + sb + q * kSolvePanel;
-#pragma unroll 8
-                for (int k = 0; k < ws; ++k) acc += L[(c0 + t) + (int64_t)(c0 + sb + k) * f] * vq[k];
-                v[t + q * kSolvePanel] -= acc;
-            }
+            for (int q = 0; q < kNrhsMax; ++q)
+                if (q < nrhs) v[t + q * kSolvePanel] -= acc[q];
         }
         __syncthreads();
     }
@@ -699,13 +961,15 @@ __global__ __launch_bounds__(256) void k_fwd_T(DevPlan d, const int* __restrict_
         for (int t = tid; t < w; t += 256) Y[first + c0 + t + q * N] = v[t + q * kSolvePanel];
     if (!fused) return;
     for (int i = c0 + w + tid; i < f; i += 256) {
-        for (int q = 0; q < nrhs; ++q) {
-            T acc = T(0);
-            const T* vq = v + q * kSolvePanel;
-#pragma unroll 8
-            for (int k = 0; k < w; ++k) acc += L[i + (int64_t)(c0 + k) * f] * vq[k];
-            if (i < p) Y[first + i + q * N] -= acc;
-            else Us[(i - p) + (int64_t)q * c] -= acc;
+        T acc[kNrhsMax];
+#pragma unroll
+        for (int q = 0; q < kNrhsMax; ++q) acc[q] = T(0);
+        row_dot(L, f, i, c0, w, v, kSolvePanel, nrhs, acc);
+#pragma unroll
+        for (int q = 0; q < kNrhsMax; ++q) {
+            if (q >= nrhs) continue;
+            if (i < p) Y[first + i + q * N] -= acc[q];
+            else Us[(i - p) + (int64_t)q * c] -= acc[q];
         }
     }
 }
@@ -728,21 +992,25 @@ __global__ __launch_bounds__(256) void k_fwd_G(DevPlan d, const int* __restrict_
     const int tid = threadIdx.x;
     const int64_t N = d.N;
     for (int q = 0; q < nrhs; ++q)
-        for (int t = tid; t < w; t += 256) y[t + q * kSolvePanel] = Y[first + c0 + t + q * N];
+        for (int t = tid; t < kSolvePanel; t += 256) y[t + q * kSolvePanel] = t < w ? Y[first + c0 + t + q * N] : T(0);
     __syncthreads();
     for (int i = r0 + tid; i < r1; i += 256) {
-        for (int q = 0; q < nrhs; ++q) {
-            T acc = T(0);
-            const T* yq = y + q * kSolvePanel;
-#pragma unroll 8
-            for (int k = 0; k < w; ++k) acc += L[i + (int64_t)(c0 + k) * f] * yq[k];
-            if (i < p) Y[first + i + q * N] -= acc;
-            else Us[(i - p) + (int64_t)q * c] -= acc;
+        T acc[kNrhsMax];
+#pragma unroll
+        for (int q = 0; q < kNrhsMax; ++q) acc[q] = T(0);
+        row_dot(L, f, i, c0, w, y, kSolvePanel, nrhs, acc);
+#pragma unroll
+        for (int q = 0; q < kNrhsMax; ++q) {
+            if (q >= nrhs) continue;
+            if (i < p) Y[first + i + q * N] -= acc[q];
+            else Us[(i - p) + (int64_t)q * c] -= acc[q];
         }
     }
 }
 
-// Backward G: partial[slot][t][q] = sum over rows [r0, r1) of L[i, c0 + t] x_i.
+// Backward G (large fronts only: a G task exists only when more than
+// kSolveChunk rows lie below the panel): partial[slot][t][q] = sum over rows
+// [r0, r1) of L[i, c0 + t] x_i, read as rows of L^T (upper triangle).
 template <typename T>
 __global__ __launch_bounds__(256) void k_bwd_G(DevPlan d, const int* __restrict__ tasks, const T* __restrict__ F,
                                                const T* __restrict__ Y, T* __restrict__ partial, int nrhs) {
@@ -761,20 +1029,19 @@ __global__ __launch_bounds__(256) void k_bwd_G(DevPlan d, const int* __restrict_
     const int64_t N = d.N;
     const int nr = r1 - r0;
     for (int q = 0; q < nrhs; ++q)
-        for (int i = tid; i < nr; i += 256) {
+        for (int i = tid; i < kSolveChunk; i += 256) {
             const int gi = r0 + i;
-            xs[i + q * kSolveChunk] = gi < p ? Y[first + gi + q * N] : Y[rows[gi] + q * N];
+            xs[i + q * kSolveChunk] = i >= nr ? T(0) : gi < p ? Y[first + gi + q * N] : Y[rows[gi] + q * N];
         }
     __syncthreads();
     for (int t = tid; t < w; t += 256) {
-        const T* __restrict__ col = L + (int64_t)(c0 + t) * f + r0;
-        for (int q = 0; q < nrhs; ++q) {
-            T acc = T(0);
-            const T* xq = xs + q * kSolveChunk;
-#pragma unroll 8
-            for (int i = 0; i < nr; ++i) acc += col[i] * xq[i];
-            partial[((int64_t)slot * kSolvePanel + t) * kNrhsMax + q] = acc;
-        }
+        T acc[kNrhsMax];
+#pragma unroll
+        for (int q = 0; q < kNrhsMax; ++q) acc[q] = T(0);
+        row_dot(L, f, c0 + t, r0, nr, xs, kSolveChunk, nrhs, acc);
+#pragma unroll
+        for (int q = 0; q < kNrhsMax; ++q)
+            if (q < nrhs) partial[((int64_t)slot * kSolvePanel + t) * kNrhsMax + q] = acc[q];
     }
 }
 
@@ -782,12 +1049,13 @@ __global__ __launch_bounds__(256) void k_bwd_G(DevPlan d, const int* __restrict_
 // fused), then the panel's transposed triangle in reverse sub-blocks.
 template <typename T>
 __global__ __launch_bounds__(256) void k_bwd_T(DevPlan d, const int* __restrict__ tasks, const T* __restrict__ F,
-                                               const T* __restrict__ D, T* __restrict__ Y,
-                                               const T* __restrict__ partial, int nrhs) {
+                                               const T* __restrict__ Zbuf, const T* __restrict__ D,
+                                               T* __restrict__ Y, const T* __restrict__ partial, int nrhs) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* Ld = reinterpret_cast<T*>(smem_raw);       // 64 x 65
-    T* v = Ld + 64 * 65;                          // kSolvePanel x nrhs
-    T* xs = v + kSolvePanel * nrhs;               // kSolveChunk x nrhs (fused rows below)
+    T* v = reinterpret_cast<T*>(smem_raw);        // kSolvePanel x nrhs
+    T* xs = v + kSolvePanel * nrhs;               // kSolveChunk x nrhs: fused rows below, then partial sums
+    T* part = xs;
+    T* Ld = xs + kSolveChunk * nrhs;              // 64 x 65
     const int* tk = tasks + 5 * blockIdx.x;
     const int s = tk[0], c0 = tk[1], fused = tk[2], gfirst = tk[3], gcount = tk[4];
     const int first = d.sn_first[s];
@@ -797,68 +1065,96 @@ __global__ __launch_bounds__(256) void k_bwd_T(DevPlan d, const int* __restrict_
     const int w = min(kSolvePanel, p - c0);
     const T* __restrict__ L = F + d.L_off[s];
     const int* __restrict__ rows = d.sn_rows + rb;
-    const int tid = threadIdx.x, lane = tid & 63;
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int64_t N = d.N;
+    const int64_t zoff = d.M_off[s];
+    const bool large = zoff >= 0;
     const int below0 = c0 + w;
     const int nb = f - below0;
     if (fused && nb > 0) {
         for (int q = 0; q < nrhs; ++q)
-            for (int i = tid; i < nb; i += 256) {
+            for (int i = tid; i < kSolveChunk; i += 256) {
                 const int gi = below0 + i;
-                xs[i + q * kSolveChunk] = gi < p ? Y[first + gi + q * N] : Y[rows[gi] + q * N];
+                xs[i + q * kSolveChunk] = i >= nb ? T(0) : gi < p ? Y[first + gi + q * N] : Y[rows[gi] + q * N];
             }
         __syncthreads();
     }
-    for (int t = tid; t < w; t += 256) {
-        const T dinv = T(1) / D[first + c0 + t];
-        for (int q = 0; q < nrhs; ++q) {
-            T val = Y[first + c0 + t + q * N] * dinv;
-            if (fused) {
-                const T* __restrict__ col = L + (int64_t)(c0 + t) * f + below0;
-                const T* xq = xs + q * kSolveChunk;
-                T acc = T(0);
-#pragma unroll 8
-                for (int i = 0; i < nb; ++i) acc += col[i] * xq[i];
-                val -= acc;
-            } else {
-                T acc = T(0);
-                for (int g = 0; g < gcount; ++g) acc += partial[((int64_t)(gfirst + g) * kSolvePanel + t) * kNrhsMax + q];
-                val -= acc;
-            }
-            v[t + q * kSolvePanel] = val;
+    for (int t = tid; t < kSolvePanel; t += 256) {
+        if (t >= w) {
+            for (int q = 0; q < nrhs; ++q) v[t + q * kSolvePanel] = T(0);
+            continue;
         }
+        const T dinv = T(1) / D[first + c0 + t];
+        T acc[kNrhsMax];
+#pragma unroll
+        for (int q = 0; q < kNrhsMax; ++q) acc[q] = T(0);
+        if (fused && nb > 0) {
+            if (large) {
+                row_dot(L, f, c0 + t, below0, nb, xs, kSolveChunk, nrhs, acc);
+            } else {
+                const T* __restrict__ col = L + (int64_t)(c0 + t) * f + below0;
+#pragma unroll
+                for (int q = 0; q < kNrhsMax; ++q) {
+                    if (q >= nrhs) continue;
+                    const T* xq = xs + q * kSolveChunk;
+                    T a = T(0);
+#pragma unroll 8
+                    for (int i = 0; i < nb; ++i) a += col[i] * xq[i];
+                    acc[q] = a;
+                }
+            }
+        } else if (!fused) {
+#pragma unroll
+            for (int q = 0; q < kNrhsMax; ++q) {
+                if (q >= nrhs) continue;
+                T a = T(0);
+                for (int g = 0; g < gcount; ++g) a += partial[((int64_t)(gfirst + g) * kSolvePanel + t) * kNrhsMax + q];
+                acc[q] = a;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kNrhsMax; ++q)
+            if (q < nrhs) v[t + q * kSolvePanel] = Y[first + c0 + t + q * N] * dinv - acc[q];
     }
     __syncthreads();
     for (int sb = ((w - 1) / 64) * 64; sb >= 0; sb -= 64) {
         const int ws = min(64, w - sb);
         const int ub = sb + ws;
-        if (tid < ws && ub < w) {
-            const T* __restrict__ col = L + (int64_t)(c0 + sb + tid) * f + c0;
-            for (int q = 0; q < nrhs; ++q) {
-                const T* vq = v + q * kSolvePanel;
-                T acc = T(0);
+        if (ub < w) {
+            // v[sb + i] -= sum_{u in [ub, w)} L[c0 + u, c0 + sb + i] x_u
+            if (large) {
+                // wave k takes u in [ub + 64 k, ub + 64 k + 64); lane = i
+                const int u0 = ub + 64 * wave;
+                T acc[kNrhsMax];
+#pragma unroll
+                for (int q = 0; q < kNrhsMax; ++q) acc[q] = T(0);
+                if (u0 < w) row_dot(L, f, c0 + sb + lane, c0 + u0, min(64, w - u0), v + u0, kSolvePanel, nrhs, acc);
+#pragma unroll
+                for (int q = 0; q < kNrhsMax; ++q)
+                    if (q < nrhs) part[(wave * 64 + lane) * nrhs + q] = acc[q];
+                __syncthreads();
+                if (tid < ws)
+                    for (int q = 0; q < nrhs; ++q) {
+                        const T* pp = part + tid * nrhs + q;
+                        v[sb + tid + q * kSolvePanel] -= (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]);
+                    }
+            } else if (tid < ws) {
+                const T* __restrict__ col = L + (int64_t)(c0 + sb + tid) * f + c0;
+                for (int q = 0; q < nrhs; ++q) {
+                    const T* vq = v + q * kSolvePanel;
+                    T acc = T(0);
 #pragma unroll 8
-                for (int u = ub; u < w; ++u) acc += col[u] * vq[u];
-                v[sb + tid + q * kSolvePanel] -= acc;
+                    for (int u = ub; u < w; ++u) acc += col[u] * vq[u];
+                    v[sb + tid + q * kSolvePanel] -= acc;
+                }
             }
+            __syncthreads();
         }
-        for (int idx = tid; idx < 64 * ws; idx += 256) {
-            const int a = idx & 63, b = idx >> 6;
-            if (a < ws && b < a) Ld[a * 65 + b] = L[(c0 + sb + a) + (int64_t)(c0 + sb + b) * f];
-        }
-        __syncthreads();
-        if (tid < 64) {
-            T lcol[64];
-#pragma unroll
-            for (int k = 0; k < 64; ++k) lcol[k] = (lane < k && k < ws) ? Ld[k * 65 + lane] : T(0);
-            for (int q = 0; q < nrhs; ++q) {
-                T val = lane < ws ? v[sb + lane + q * kSolvePanel] : T(0);
-#pragma unroll
-                for (int k = 63; k > 0; --k) val -= lcol[k] * bcast(val, k);
-                if (lane < ws) v[sb + lane + q * kSolvePanel] = val;
-            }
-        }
-        __syncthreads();
+        if (large)
+            zmul64<T, true>(Zbuf + zoff + (int64_t)((c0 + sb) / kPanel) * (kPanel * kPanel), ws, Ld, part, v + sb,
+                            nrhs);
+        else
+            chain_solve64<T, true>(L, f, c0 + sb, ws, Ld, v + sb, nrhs);
     }
     for (int q = 0; q < nrhs; ++q)
         for (int t = tid; t < w; t += 256) Y[first + c0 + t + q * N] = v[t + q * kSolvePanel];
@@ -1055,9 +1351,9 @@ void launch_large_asm(const DevPlan& d, const int* tasks, int count, const doubl
 }
 
 template <typename T>
-void launch_large_diag0(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st) {
+void launch_large_diag(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_large_diag0<T>, dim3(count), dim3(256), 0, st, d, tasks, F, D, M);
+    hipLaunchKernelGGL(k_large_diag<T>, dim3(count), dim3(256), 0, st, d, tasks, F, D, M);
 }
 
 template <typename T>
@@ -1069,7 +1365,8 @@ void launch_large_panel(const DevPlan& d, const int* tasks, int count, T* F, con
 template <typename T>
 void launch_large_update(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_large_update<T>, dim3(count), dim3(256), 0, st, d, tasks, F, D, M);
+    (void)M;
+    hipLaunchKernelGGL(k_large_update<T>, dim3(count), dim3(256), 0, st, d, tasks, F, (const T*)D);
 }
 
 template <typename T>
@@ -1083,10 +1380,11 @@ void launch_permute_out(const DevPlan& d, const T* Y, int nrhs, double* X, int64
 }
 
 template <typename T>
-void launch_fwd_T(const DevPlan& d, const int* tasks, int count, const T* F, T* Y, T* U, int nrhs, hipStream_t st) {
+void launch_fwd_T(const DevPlan& d, const int* tasks, int count, const T* F, const T* Z, T* Y, T* U, int nrhs,
+                  hipStream_t st) {
     if (count <= 0) return;
-    const size_t lds = (size_t)(64 * 65 + kSolvePanel * nrhs) * sizeof(T);
-    hipLaunchKernelGGL(k_fwd_T<T>, dim3(count), dim3(256), lds, st, d, tasks, F, Y, U, nrhs);
+    const size_t lds = (size_t)(kSolvePanel * nrhs + 256 * nrhs + 64 * 65) * sizeof(T);
+    hipLaunchKernelGGL(k_fwd_T<T>, dim3(count), dim3(256), lds, st, d, tasks, F, Z, Y, U, nrhs);
 }
 
 template <typename T>
@@ -1105,11 +1403,11 @@ void launch_bwd_G(const DevPlan& d, const int* tasks, int count, const T* F, con
 }
 
 template <typename T>
-void launch_bwd_T(const DevPlan& d, const int* tasks, int count, const T* F, const T* D, T* Y, const T* partial,
-                  int nrhs, hipStream_t st) {
+void launch_bwd_T(const DevPlan& d, const int* tasks, int count, const T* F, const T* Z, const T* D, T* Y,
+                  const T* partial, int nrhs, hipStream_t st) {
     if (count <= 0) return;
-    const size_t lds = (size_t)(64 * 65 + kSolvePanel * nrhs + kSolveChunk * nrhs) * sizeof(T);
-    hipLaunchKernelGGL(k_bwd_T<T>, dim3(count), dim3(256), lds, st, d, tasks, F, D, Y, partial, nrhs);
+    const size_t lds = (size_t)(kSolvePanel * nrhs + kSolveChunk * nrhs + 64 * 65) * sizeof(T);
+    hipLaunchKernelGGL(k_bwd_T<T>, dim3(count), dim3(256), lds, st, d, tasks, F, Z, D, Y, partial, nrhs);
 }
 
 void launch_residual(const DevPlan& d, const double* K, const double* B, int64_t ldb, const double* X, int64_t ldx,
@@ -1183,15 +1481,16 @@ hipError_t configure_kernels(int max_dynamic_lds) {
 #define NCL_INSTANTIATE(T)                                                                                         \
     template void launch_small_fronts<T>(const DevPlan&, const int*, int, int, const double*, T*, T*, hipStream_t); \
     template void launch_large_asm<T>(const DevPlan&, const int*, int, const double*, T*, hipStream_t);            \
-    template void launch_large_diag0<T>(const DevPlan&, const int*, int, T*, T*, T*, hipStream_t);               \
+    template void launch_large_diag<T>(const DevPlan&, const int*, int, T*, T*, T*, hipStream_t);                \
     template void launch_large_panel<T>(const DevPlan&, const int*, int, T*, const T*, const T*, hipStream_t);     \
     template void launch_large_update<T>(const DevPlan&, const int*, int, T*, T*, T*, hipStream_t);              \
     template void launch_permute_in<T>(const DevPlan&, const double*, int64_t, int, T*, hipStream_t);              \
     template void launch_permute_out<T>(const DevPlan&, const T*, int, double*, int64_t, hipStream_t);             \
-    template void launch_fwd_T<T>(const DevPlan&, const int*, int, const T*, T*, T*, int, hipStream_t);           \
+    template void launch_fwd_T<T>(const DevPlan&, const int*, int, const T*, const T*, T*, T*, int, hipStream_t);           \
     template void launch_fwd_G<T>(const DevPlan&, const int*, int, const T*, T*, T*, int, hipStream_t);           \
     template void launch_bwd_G<T>(const DevPlan&, const int*, int, const T*, const T*, T*, int, hipStream_t);     \
-    template void launch_bwd_T<T>(const DevPlan&, const int*, int, const T*, const T*, T*, const T*, int, hipStream_t);
+    template void launch_bwd_T<T>(const DevPlan&, const int*, int, const T*, const T*, const T*, T*, const T*, int,        \
+                                  hipStream_t);
 
 NCL_INSTANTIATE(double)
 NCL_INSTANTIATE(float)

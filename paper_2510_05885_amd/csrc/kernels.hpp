@@ -51,7 +51,7 @@ struct DevPlan {
     const int64_t* CB_off;
     const int* CB_ld;
     const int64_t* U_off;      // in elements of one column block (times kNrhsMax applied)
-    const int64_t* M_off;      // large fronts: offset of the per-panel L_kk D blocks (64 x 64 each)
+    const int64_t* M_off;      // large fronts: offset of the per-panel inverses L_kk^-1 (64 x 64 each)
     // per system
     const double* sys_thr;     // static-pivot thresholds eps * ||K||_max
     unsigned long long* inertia;  // 4 per system: npos, nneg, nzero, nperturbed
@@ -77,7 +77,7 @@ void launch_small_fronts(const DevPlan& d, const int* list, int count, int fmax,
 template <typename T>
 void launch_large_asm(const DevPlan& d, const int* tasks, int count, const double* K, T* F, hipStream_t st);
 template <typename T>
-void launch_large_diag0(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st);
+void launch_large_diag(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st);
 template <typename T>
 void launch_large_panel(const DevPlan& d, const int* tasks, int count, T* F, const T* D, const T* M, hipStream_t st);
 template <typename T>
@@ -89,15 +89,16 @@ void launch_permute_in(const DevPlan& d, const double* B, int64_t ldb, int nrhs,
 template <typename T>
 void launch_permute_out(const DevPlan& d, const T* Y, int nrhs, double* X, int64_t ldx, hipStream_t st);
 template <typename T>
-void launch_fwd_T(const DevPlan& d, const int* tasks, int count, const T* F, T* Y, T* U, int nrhs, hipStream_t st);
+void launch_fwd_T(const DevPlan& d, const int* tasks, int count, const T* F, const T* Z, T* Y, T* U, int nrhs,
+                  hipStream_t st);
 template <typename T>
 void launch_fwd_G(const DevPlan& d, const int* tasks, int count, const T* F, T* Y, T* U, int nrhs, hipStream_t st);
 template <typename T>
 void launch_bwd_G(const DevPlan& d, const int* tasks, int count, const T* F, const T* Y, T* partial, int nrhs,
                   hipStream_t st);
 template <typename T>
-void launch_bwd_T(const DevPlan& d, const int* tasks, int count, const T* F, const T* D, T* Y, const T* partial,
-                  int nrhs, hipStream_t st);
+void launch_bwd_T(const DevPlan& d, const int* tasks, int count, const T* F, const T* Z, const T* D, T* Y,
+                  const T* partial, int nrhs, hipStream_t st);
 
 // ---- refinement -------------------------------------------------------------
 // R = B - K X; per chunk of rows (all of one system) the maxima of |R|, |X|, |B| per column.

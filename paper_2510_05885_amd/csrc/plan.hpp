@@ -34,8 +34,8 @@ struct LevelBatch {            // one launch of the small-front kernel
 struct LargeStep {             // launches of the large-front path for one level
     int level = 0;
     int64_t asm_first = 0, asm_count = 0;     // (front, column) tasks in large_asm
-    int64_t d0_first = 0, d0_count = 0;       // fronts in large_diag0 (first panel's diagonal block)
-    // per panel step k: panel (TRSM) and update tasks
+    // per panel step k: diagonal-block, panel (TRSM) and update tasks
+    std::vector<int64_t> diag_first, diag_count;
     std::vector<int64_t> panel_first, panel_count;
     std::vector<int64_t> upd_first, upd_count;
     std::vector<double> upd_flops;            // algorithmic flops of each update launch
@@ -116,7 +116,7 @@ struct Plan {
     std::vector<int> CB_ld;
     int64_t factor_elems = 0;        // factor buffer length (elements of T)
     std::vector<int64_t> U_off;      // solve: update vector of each front (c_s * nrhs_max)
-    std::vector<int64_t> M_off;      // large fronts: per-panel L_kk D blocks (panel^2 each)
+    std::vector<int64_t> M_off;      // large fronts: per-panel inverses L_kk^-1 (panel^2 each)
     int64_t M_elems = 0;
     int64_t U_elems = 0;
 
@@ -130,10 +130,9 @@ struct Plan {
     std::vector<LargeStep> large_steps;
     // large-front tasks
     std::vector<int> large_asm;      // pairs (front, column)
-    std::vector<int> large_diag0;    // large fronts, by level (first-panel diagonal factorization)
-    std::vector<int> large_panel;    // triples (front, k0, 64-row block start >= k0 + panel)
-    std::vector<int> large_upd;      // quads (front, k0, tile row start, tile col start);
-                                     // i0 == -1: copy the panel's factored diagonal block back
+    std::vector<int> large_diag;     // pairs (front, k0): diagonal block factorization + inverse
+    std::vector<int> large_panel;    // triples (front, k0, 32-row block start >= k0 + panel)
+    std::vector<int> large_upd;      // quads (front, k0, tile row start, tile col start)
     // solve schedule
     std::vector<SolveStep> solve_steps;
     std::vector<int> solve_t;        // (front, c0, fused, g_first, g_count)

@@ -38,7 +38,7 @@ class Options(C.Structure):
     _fields_ = [("form", C.c_int32), ("precision", C.c_int32), ("pivot_eps", C.c_double),
                 ("ir_max_steps", C.c_int32), ("ir_tol", C.c_double), ("ir_stall", C.c_double),
                 ("ordering", C.c_int32), ("user_perm", C.POINTER(C.c_int32)), ("use_graphs", C.c_int32),
-                ("small_front_max", C.c_int32), ("relax_big_zeros", C.c_double)]
+                ("small_front_max", C.c_int32), ("relax_big_zeros", C.c_double), ("fp32_sticky", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -164,7 +164,7 @@ _ORDS = {"nd": NCL_ORDER_ND, "natural": NCL_ORDER_NATURAL, "user": NCL_ORDER_USE
 
 def make_options(form="condensed", precision="fp64", pivot_eps=0.0, ir_max_steps=10, ir_tol=1e-12,
                  ir_stall=0.5, ordering="nd", user_perm=None, use_graphs=True, small_front_max=0,
-                 relax_big_zeros=-1.0):
+                 relax_big_zeros=-1.0, fp32_sticky=True):
     o = Options()
     lib().ncl_kkt_default_options(C.byref(o))
     o.form = _FORMS[form] if isinstance(form, str) else int(form)
@@ -176,6 +176,7 @@ def make_options(form="condensed", precision="fp64", pivot_eps=0.0, ir_max_steps
     o.use_graphs = 1 if use_graphs else 0
     o.small_front_max = int(small_front_max)
     o.relax_big_zeros = float(relax_big_zeros)
+    o.fp32_sticky = 1 if fp32_sticky else 0
     keep = None
     if user_perm is not None:
         keep, p = _i32(user_perm)

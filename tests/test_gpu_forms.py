@@ -35,6 +35,33 @@ def test_fp32_ir_matches_oracle(rho, nrhs):
         assert info.fell_back_fp64
 
 
+@pytest.mark.parametrize("sticky", [True, False])
+def test_fp32_sticky_policy(sticky):
+    """One handle through an increasing-rho sequence (as in an NCL outer loop):
+    after an FP32 factor had to be replaced at rho = r, later factors with
+    rho >= r go to FP64 directly (one frontal pass instead of two) and a factor
+    at a smaller rho tries FP32 again.  Every solve meets the tolerance."""
+    print(f"[gpu] fp32 sticky={sticky}", flush=True)
+    base = synth.grid_banded(rho=1e2, seed=3)
+    kkt = nk.KKT.from_input(base, precision="fp32_ir", fp32_sticky=sticky)
+    B = synth.rhs(base.n, 1, seed=5)
+    passes = []
+    for rho in (1e2, 1e8, 1e9, 1e3):
+        inp = base.with_values(rho=rho)
+        kkt.set_timing(True)
+        rc, X, info = factor_solve(kkt, inp, B)
+        tm = kkt.timing()
+        kkt.set_timing(False)
+        assert omega_cpu(inp, "condensed", X, B) <= 1e-12, (rho, info)
+        passes.append((info.fell_back_fp64, tm["launches"]["small_fronts"]))
+    one = passes[0][1]                        # launches of one frontal pass (FP32 kept at 1e2)
+    assert not passes[0][0]
+    assert passes[1][0] and passes[1][1] == 2 * one      # FP32 tried, replaced by FP64
+    assert passes[2][0]
+    assert passes[2][1] == (one if sticky else 2 * one)  # sticky: FP64 directly
+    assert not passes[3][0] and passes[3][1] == one       # smaller rho: FP32 again
+
+
 def test_fp32_ir_stabilized():
     print("[gpu] fp32_ir stabilized", flush=True)
     inp = synth.grid_banded(rho=1e3, seed=4)
