@@ -723,7 +723,7 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                     const int p = P.sn_first[s + 1] - P.sn_first[s];
                     if (k0 >= p) continue;
                     const int k1 = std::min(k0 + nb, p);
-                    P.large_diag.push_back(s); P.large_diag.push_back(k0);
+                    if (k0 == 0) { P.large_diag.push_back(s); P.large_diag.push_back(k0); }
                     for (int r0 = k1; r0 < f; r0 += 32) {
                         P.large_panel.push_back(s); P.large_panel.push_back(k0); P.large_panel.push_back(r0);
                     }

@@ -375,7 +375,7 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
                 launch_large_asm<T>(d, h->large_asm + 2 * ls.asm_first, (int)ls.asm_count, h->K, F, st);
             }
             for (size_t k = 0; k < ls.panel_first.size(); ++k) {
-                {
+                if (ls.diag_count[k] > 0) {
                     Span sp(h, st, TM_PANEL);
                     launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[k], (int)ls.diag_count[k], F, D, Mb, st);
                 }

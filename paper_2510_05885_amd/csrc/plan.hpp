@@ -130,7 +130,7 @@ struct Plan {
     std::vector<LargeStep> large_steps;
     // large-front tasks
     std::vector<int> large_asm;      // pairs (front, column)
-    std::vector<int> large_diag;     // pairs (front, k0): diagonal block factorization + inverse
+    std::vector<int> large_diag;     // pairs (front, 0): first panel's diagonal block factorization + inverse
     std::vector<int> large_panel;    // triples (front, k0, 32-row block start >= k0 + panel)
     std::vector<int> large_upd;      // quads (front, k0, tile row start, tile col start)
     // solve schedule
