@@ -758,6 +758,7 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                     st.level = l; st.j = j;
                     st.t_first = (int64_t)P.solve_t.size() / 5;
                     st.g_first = (int64_t)P.solve_g.size() / 5;
+                    st.s_first = (int64_t)P.solve_s.size();
                     int slot = 0;
                     for (int k = P.level_ptr[l]; k < P.level_ptr[l + 1]; ++k) {
                         int s = P.level_list[k];
@@ -767,6 +768,11 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                         if (c0 >= p) continue;
                         const int w = std::min(PW, p - c0);
                         const int below = f - c0 - w;
+                        if (!P.sn_large[s] && p <= 64 && f <= 128) {
+                            P.solve_s.push_back(s);
+                            st.fwd_bytes += 8.0 * ((double)w * (w + 1) / 2.0 + (double)below * w);
+                            continue;
+                        }
                         const bool fused = below <= FUSE;
                         const int gfirst = slot;
                         if (!fused) {
@@ -780,6 +786,7 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                         st.fwd_bytes += 8.0 * ((double)w * (w + 1) / 2.0 + (double)below * w);
                     }
                     st.t_count = (int64_t)P.solve_t.size() / 5 - st.t_first;
+                    st.s_count = (int64_t)P.solve_s.size() - st.s_first;
                     st.g_count = (int64_t)P.solve_g.size() / 5 - st.g_first;
                     P.solve_max_slots = std::max<int64_t>(P.solve_max_slots, slot);
                     P.solve_steps.push_back(st);

@@ -61,7 +61,7 @@ struct ncl_kkt_s {
     int64_t nnzF = 0;
     // schedule arrays (device)
     int *small_list = nullptr, *level_list = nullptr, *large_asm = nullptr, *large_panel = nullptr,
-        *large_upd = nullptr, *large_diag = nullptr, *solve_t = nullptr, *solve_g = nullptr;
+        *large_upd = nullptr, *large_diag = nullptr, *solve_t = nullptr, *solve_g = nullptr, *solve_s = nullptr;
     int *chunk_row0 = nullptr, *chunk_rows = nullptr, *sys_chunk_ptr = nullptr;
     int nchunks = 0;
     // numeric state
@@ -206,6 +206,7 @@ void setup_device(ncl_kkt_s* h) {
     h->large_diag = upload(h, P.large_diag);
     h->solve_t = upload(h, P.solve_t);
     h->solve_g = upload(h, P.solve_g);
+    h->solve_s = upload(h, P.solve_s);
     h->large_panel = upload(h, P.large_panel);
     h->large_upd = upload(h, P.large_upd);
     // row chunks (<= 256 rows, never straddling two systems)
@@ -509,6 +510,7 @@ void sweeps(ncl_kkt_s* h, int nrhs, const T* F, const T* Z, const T* D, T* Y, T*
     const DevPlan& d = h->d;
     for (const SolveStep& ss : P.solve_steps) {
         Span sp(h, st, TM_SOLVE, ss.fwd_bytes * sizeof(T) / 8.0, 4);
+        launch_fwd_S<T>(d, h->solve_s + ss.s_first, (int)ss.s_count, F, Y, U, nrhs, st);
         launch_fwd_T<T>(d, h->solve_t + 5 * ss.t_first, (int)ss.t_count, F, Z, Y, U, nrhs, st);
         launch_fwd_G<T>(d, h->solve_g + 5 * ss.g_first, (int)ss.g_count, F, Y, U, nrhs, st);
     }
@@ -517,6 +519,7 @@ void sweeps(ncl_kkt_s* h, int nrhs, const T* F, const T* Z, const T* D, T* Y, T*
         Span sp(h, st, TM_SOLVE, ss.fwd_bytes * sizeof(T) / 8.0, 4);
         launch_bwd_G<T>(d, h->solve_g + 5 * ss.g_first, (int)ss.g_count, F, Y, partial, nrhs, st);
         launch_bwd_T<T>(d, h->solve_t + 5 * ss.t_first, (int)ss.t_count, F, Z, D, Y, partial, nrhs, st);
+        launch_bwd_S<T>(d, h->solve_s + ss.s_first, (int)ss.s_count, F, D, Y, nrhs, st);
     }
 }
 

@@ -1194,6 +1194,175 @@ __global__ __launch_bounds__(256) void k_bwd_T(DevPlan d, const int* __restrict_
         for (int t = tid; t < w; t += 256) Y[first + c0 + t + q * N] = v[t + q * kSolvePanel];
 }
 
+// ---- small fronts: one wave per front ---------------------------------------
+// Fronts with p <= 64 pivots and f <= kSmallRows rows (L is f x p, ld f).  Each
+// wave keeps its front's right-hand-side rows in LDS (ld kSmallRows) and
+// synchronizes only with itself; a workgroup carries four fronts.
+constexpr int kSmallRows = 128;
+
+// Forward: pull the children's update vectors, substitute the p pivots (lane =
+// pivot row, readlane broadcasts), apply them to the rows below, write back.
+template <typename T>
+__global__ __launch_bounds__(256, 4) void k_fwd_S(DevPlan d, const int* __restrict__ fronts, int count,
+                                               const T* __restrict__ F, T* __restrict__ Y, T* __restrict__ U,
+                                               int nrhs) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int task = blockIdx.x * 4 + wv;
+    if (task >= count) return;   // whole wave; no workgroup barrier below
+    T* ys = reinterpret_cast<T*>(smem_raw) + wv * kSmallRows * nrhs;
+    const int s = fronts[task];
+    const int first = d.sn_first[s];
+    const int p = d.sn_first[s + 1] - first;
+    const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
+    const int c = f - p;
+    const T* __restrict__ L = F + d.L_off[s];
+    T* __restrict__ Us = U + d.U_off[s];
+    const int64_t N = d.N;
+    for (int q = 0; q < nrhs; ++q)
+        for (int i = lane; i < f; i += 64) ys[i + q * kSmallRows] = i < p ? Y[first + i + q * N] : T(0);
+    wave_fence();
+    for (int k = d.child_ptr[s]; k < d.child_ptr[s + 1]; ++k) {
+        const int ch = d.child_list[k];
+        const int cc = (int)(d.sn_rowptr[ch + 1] - d.sn_rowptr[ch]) - (d.sn_first[ch + 1] - d.sn_first[ch]);
+        const T* __restrict__ Uc = U + d.U_off[ch];
+        const int* __restrict__ r = d.rel + d.rel_ptr[ch];
+        for (int q = 0; q < nrhs; ++q)
+            for (int a = lane; a < cc; a += 64) ys[r[a] + q * kSmallRows] += Uc[a + (int64_t)q * cc];
+        wave_fence();
+    }
+    // substitution in two 32-column chunks (most small fronts need one)
+    const int lr = min(lane, f - 1);
+    for (int kc = 0; kc < p; kc += 32) {
+        T lrow[32];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            if (kc + k < p) {
+                const T x = L[lr + (int64_t)(kc + k) * f];
+                lrow[k] = (kc + k < lane && lane < p) ? x : T(0);
+            } else {
+                lrow[k] = T(0);
+            }
+        }
+        for (int q = 0; q < nrhs; ++q) {
+            T val = lane < p ? ys[lane + q * kSmallRows] : T(0);
+#pragma unroll
+            for (int k = 0; k < 32; ++k)
+                if (kc + k + 1 < p) val -= lrow[k] * bcast(val, kc + k);
+            if (lane < p) ys[lane + q * kSmallRows] = val;
+        }
+        wave_fence();
+    }
+    for (int i0 = p; i0 < f; i0 += 64) {
+        const int i = i0 + lane;
+        const int ic = min(i, f - 1);
+        T acc[kNrhsMax];
+#pragma unroll
+        for (int q = 0; q < kNrhsMax; ++q) acc[q] = T(0);
+        for (int kc = 0; kc < p; kc += 32) {
+            T lv[32];
+#pragma unroll
+            for (int k = 0; k < 32; ++k) lv[k] = (kc + k < p) ? L[ic + (int64_t)(kc + k) * f] : T(0);
+#pragma unroll
+            for (int q = 0; q < kNrhsMax; ++q) {
+                if (q >= nrhs) continue;
+                const T* yq = ys + kc + q * kSmallRows;
+                T a = T(0);
+#pragma unroll
+                for (int k = 0; k < 32; ++k)
+                    if (kc + k < p) a += lv[k] * yq[k];
+                acc[q] += a;
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < kNrhsMax; ++q)
+            if (q < nrhs && i < f) ys[i + q * kSmallRows] -= acc[q];
+    }
+    wave_fence();
+    for (int q = 0; q < nrhs; ++q)
+        for (int i = lane; i < f; i += 64) {
+            const T v = ys[i + q * kSmallRows];
+            if (i < p) Y[first + i + q * N] = v;
+            else Us[(i - p) + (int64_t)q * c] = v;
+        }
+}
+
+// Backward: gather x of the rows below, v_t = y_t / d_t - sum_i L[i][t] x_i
+// (lane = pivot column t, its column read contiguously), then the transposed
+// substitution from the last pivot up (readlane broadcasts).
+template <typename T>
+__global__ __launch_bounds__(256, 4) void k_bwd_S(DevPlan d, const int* __restrict__ fronts, int count,
+                                               const T* __restrict__ F, const T* __restrict__ D,
+                                               T* __restrict__ Y, int nrhs) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int task = blockIdx.x * 4 + wv;
+    if (task >= count) return;   // whole wave; no workgroup barrier below
+    T* xs = reinterpret_cast<T*>(smem_raw) + wv * kSmallRows * nrhs;
+    const int s = fronts[task];
+    const int first = d.sn_first[s];
+    const int p = d.sn_first[s + 1] - first;
+    const int64_t rb = d.sn_rowptr[s];
+    const int f = (int)(d.sn_rowptr[s + 1] - rb);
+    const T* __restrict__ L = F + d.L_off[s];
+    const int* __restrict__ rows = d.sn_rows + rb;
+    const int64_t N = d.N;
+    for (int q = 0; q < nrhs; ++q)
+        for (int i = lane; i < f; i += 64)
+            xs[i + q * kSmallRows] = i < p ? Y[first + i + q * N] : Y[rows[i] + q * N];
+    wave_fence();
+    const int t = lane;
+    const bool tv = t < p;
+    const T* __restrict__ col = L + (int64_t)min(t, p - 1) * f;
+    T acc[kNrhsMax];
+#pragma unroll
+    for (int q = 0; q < kNrhsMax; ++q) acc[q] = T(0);
+    for (int i0 = p; i0 < f; i0 += 32) {
+        T lv[32];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) lv[k] = (i0 + k < f) ? col[i0 + k] : T(0);
+#pragma unroll
+        for (int q = 0; q < kNrhsMax; ++q) {
+            if (q >= nrhs) continue;
+            const T* xq = xs + i0 + q * kSmallRows;
+            T a = T(0);
+#pragma unroll
+            for (int k = 0; k < 32; ++k)
+                if (i0 + k < f) a += lv[k] * xq[k];
+            acc[q] += a;
+        }
+    }
+    // v_t into xs[t], then the transposed substitution in 32-row chunks from
+    // the last pivot up (x_k final at lane k when chunk k is reached)
+    const T dinv = T(1) / D[first + min(t, p - 1)];
+#pragma unroll
+    for (int q = 0; q < kNrhsMax; ++q)
+        if (q < nrhs && tv) xs[t + q * kSmallRows] = xs[t + q * kSmallRows] * dinv - acc[q];
+    wave_fence();
+    for (int kc = ((p - 1) / 32) * 32; kc >= 0; kc -= 32) {
+        T lcol[32];
+#pragma unroll
+        for (int k = 0; k < 32; ++k) {
+            if (kc + k < p) {
+                const T x = col[kc + k];
+                lcol[k] = (tv && kc + k > t) ? x : T(0);
+            } else {
+                lcol[k] = T(0);
+            }
+        }
+        for (int q = 0; q < nrhs; ++q) {
+            T val = tv ? xs[t + q * kSmallRows] : T(0);
+#pragma unroll
+            for (int k = 31; k >= 0; --k)
+                if (kc + k < p && kc + k > 0) val -= lcol[k] * bcast(val, kc + k);
+            if (tv) xs[t + q * kSmallRows] = val;
+        }
+        wave_fence();
+    }
+    for (int q = 0; q < nrhs; ++q)
+        if (tv) Y[first + t + q * N] = xs[t + q * kSmallRows];
+}
+
 // ---------------------------------------------------------------------------
 // refinement
 // ---------------------------------------------------------------------------
@@ -1421,6 +1590,21 @@ void launch_fwd_T(const DevPlan& d, const int* tasks, int count, const T* F, con
 }
 
 template <typename T>
+void launch_fwd_S(const DevPlan& d, const int* fronts, int count, const T* F, T* Y, T* U, int nrhs, hipStream_t st) {
+    if (count <= 0) return;
+    const size_t lds = (size_t)4 * kSmallRows * nrhs * sizeof(T);
+    hipLaunchKernelGGL(k_fwd_S<T>, dim3((count + 3) / 4), dim3(256), lds, st, d, fronts, count, F, Y, U, nrhs);
+}
+
+template <typename T>
+void launch_bwd_S(const DevPlan& d, const int* fronts, int count, const T* F, const T* D, T* Y, int nrhs,
+                  hipStream_t st) {
+    if (count <= 0) return;
+    const size_t lds = (size_t)4 * kSmallRows * nrhs * sizeof(T);
+    hipLaunchKernelGGL(k_bwd_S<T>, dim3((count + 3) / 4), dim3(256), lds, st, d, fronts, count, F, D, Y, nrhs);
+}
+
+template <typename T>
 void launch_fwd_G(const DevPlan& d, const int* tasks, int count, const T* F, T* Y, T* U, int nrhs, hipStream_t st) {
     if (count <= 0) return;
     const size_t lds = (size_t)kSolvePanel * nrhs * sizeof(T);
@@ -1499,7 +1683,9 @@ hipError_t configure_kernels(int max_dynamic_lds) {
                          (const void*)k_fwd_T<double>, (const void*)k_fwd_T<float>,
                          (const void*)k_fwd_G<double>, (const void*)k_fwd_G<float>,
                          (const void*)k_bwd_G<double>, (const void*)k_bwd_G<float>,
-                         (const void*)k_bwd_T<double>, (const void*)k_bwd_T<float>};
+                         (const void*)k_bwd_T<double>, (const void*)k_bwd_T<float>,
+                         (const void*)k_fwd_S<double>, (const void*)k_fwd_S<float>,
+                         (const void*)k_bwd_S<double>, (const void*)k_bwd_S<float>};
     for (const void* f : fns) {
         hipFuncAttributes at{};
         r = hipFuncGetAttributes(&at, f);
@@ -1521,6 +1707,8 @@ hipError_t configure_kernels(int max_dynamic_lds) {
     template void launch_permute_out<T>(const DevPlan&, const T*, int, double*, int64_t, hipStream_t);             \
     template void launch_fwd_T<T>(const DevPlan&, const int*, int, const T*, const T*, T*, T*, int, hipStream_t);           \
     template void launch_fwd_G<T>(const DevPlan&, const int*, int, const T*, T*, T*, int, hipStream_t);           \
+    template void launch_fwd_S<T>(const DevPlan&, const int*, int, const T*, T*, T*, int, hipStream_t);           \
+    template void launch_bwd_S<T>(const DevPlan&, const int*, int, const T*, const T*, T*, int, hipStream_t);     \
     template void launch_bwd_G<T>(const DevPlan&, const int*, int, const T*, const T*, T*, int, hipStream_t);     \
     template void launch_bwd_T<T>(const DevPlan&, const int*, int, const T*, const T*, const T*, T*, const T*, int,        \
                                   hipStream_t);

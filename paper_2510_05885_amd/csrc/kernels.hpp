@@ -92,6 +92,11 @@ template <typename T>
 void launch_fwd_T(const DevPlan& d, const int* tasks, int count, const T* F, const T* Z, T* Y, T* U, int nrhs,
                   hipStream_t st);
 template <typename T>
+void launch_fwd_S(const DevPlan& d, const int* fronts, int count, const T* F, T* Y, T* U, int nrhs, hipStream_t st);
+template <typename T>
+void launch_bwd_S(const DevPlan& d, const int* fronts, int count, const T* F, const T* D, T* Y, int nrhs,
+                  hipStream_t st);
+template <typename T>
 void launch_fwd_G(const DevPlan& d, const int* tasks, int count, const T* F, T* Y, T* U, int nrhs, hipStream_t st);
 template <typename T>
 void launch_bwd_G(const DevPlan& d, const int* tasks, int count, const T* F, const T* Y, T* partial, int nrhs,

@@ -49,6 +49,7 @@ struct SolveStep {
     int level = 0, j = 0;
     int64_t t_first = 0, t_count = 0;   // tasks in Plan::solve_t (5 ints each)
     int64_t g_first = 0, g_count = 0;   // tasks in Plan::solve_g (5 ints each)
+    int64_t s_first = 0, s_count = 0;   // small fronts in Plan::solve_s (one wave each)
     double fwd_bytes = 0.0;             // algorithmic bytes of L read by the step
 };
 
@@ -137,6 +138,7 @@ struct Plan {
     std::vector<SolveStep> solve_steps;
     std::vector<int> solve_t;        // (front, c0, fused, g_first, g_count)
     std::vector<int> solve_g;        // (front, c0, r0, r1, slot)
+    std::vector<int> solve_s;        // small fronts (p <= 64, f <= 128) solved by one wave each
     int64_t solve_max_slots = 0;     // G tasks in the largest step (partial-sum slots)
 
     // ---- stats ------------------------------------------------------------
