@@ -708,6 +708,7 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
             st.asm_first = (int64_t)P.large_asm.size() / 2;
             for (int s : large) {
                 const int f = (int)(P.sn_rowptr[s + 1] - P.sn_rowptr[s]);
+                st.asm_fmax = std::max(st.asm_fmax, f);
                 for (int j = 0; j < f; ++j) { P.large_asm.push_back(s); P.large_asm.push_back(j); }
             }
             st.asm_count = (int64_t)P.large_asm.size() / 2 - st.asm_first;

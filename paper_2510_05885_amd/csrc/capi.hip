@@ -90,6 +90,9 @@ struct ncl_kkt_s {
     Timer tm;
     // HIP graphs of the fixed launch sequences (per precision; sweeps per nrhs)
     hipStream_t cap_stream = nullptr;
+    // second stream: a level's small fronts run beside its large-front chain
+    hipStream_t aux_stream = nullptr;
+    std::vector<hipEvent_t> lvl_ev;   // 2 per level: fork, join
     hipGraphExec_t g_factor[2] = {nullptr, nullptr};
     hipGraphExec_t g_sweep[2][kNrhsMax + 1] = {};
 };
@@ -271,6 +274,9 @@ void setup_device(ncl_kkt_s* h) {
     h->host_pinned_len = (size_t)std::max<int64_t>((int64_t)P.S * kNrhsMax * 3, 8 * (int64_t)P.S + 8);
     HIPCHK(hipHostMalloc((void**)&h->host_pinned, sizeof(double) * h->host_pinned_len, hipHostMallocDefault));
     HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&h->aux_stream, hipStreamNonBlocking));
+    h->lvl_ev.assign(2 * (size_t)std::max(P.nlevels, 1), nullptr);
+    for (auto& e : h->lvl_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     {
         int lds = 0;
         HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
@@ -356,6 +362,17 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
     launch_zero_u64(h->inertia, 4 * (int64_t)P.S, st);
     size_t sb = 0, lb = 0;
     for (int l = 0; l < P.nlevels; ++l) {
+        // Fronts of one level are independent: when the level has both kinds,
+        // its small fronts go to the second stream (forked after the previous
+        // level, joined before the next one).
+        const bool has_small = sb < P.small_batches.size() && P.small_batches[sb].level == l;
+        const bool has_large = lb < P.large_steps.size() && P.large_steps[lb].level == l;
+        const bool fork = has_small && has_large;
+        hipStream_t ss = fork ? h->aux_stream : st;
+        if (fork) {
+            HIPCHK(hipEventRecord(h->lvl_ev[2 * l], st));
+            HIPCHK(hipStreamWaitEvent(ss, h->lvl_ev[2 * l], 0));
+        }
         while (sb < P.small_batches.size() && P.small_batches[sb].level == l) {
             const LevelBatch& b = P.small_batches[sb++];
             double fl = 0.0;
@@ -366,14 +383,14 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
                     const int p = P.sn_first[s + 1] - P.sn_first[s];
                     for (int t = 0; t < p; ++t) { double r = f - t - 1; fl += r + r * (r + 1.0); }
                 }
-            Span sp(h, st, TM_SMALL, fl, 2);
-            launch_small_fronts<T>(d, h->small_list + b.first, (int)b.count, b.fmax, h->K, F, D, st);
+            Span sp(h, ss, TM_SMALL, fl, 2);
+            launch_small_fronts<T>(d, h->small_list + b.first, (int)b.count, b.fmax, h->K, F, D, ss);
         }
         if (lb < P.large_steps.size() && P.large_steps[lb].level == l) {
             const LargeStep& ls = P.large_steps[lb++];
             {
                 Span sp(h, st, TM_LASM);
-                launch_large_asm<T>(d, h->large_asm + 2 * ls.asm_first, (int)ls.asm_count, h->K, F, st);
+                launch_large_asm<T>(d, h->large_asm + 2 * ls.asm_first, (int)ls.asm_count, ls.asm_fmax, h->K, F, st);
             }
             for (size_t k = 0; k < ls.panel_first.size(); ++k) {
                 if (ls.diag_count[k] > 0) {
@@ -388,6 +405,10 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
                 Span sp(h, st, TM_UPD, ls.upd_flops[k], 1);
                 launch_large_update<T>(d, h->large_upd + 4 * ls.upd_first[k], (int)ls.upd_count[k], F, D, Mb, st);
             }
+        }
+        if (fork) {
+            HIPCHK(hipEventRecord(h->lvl_ev[2 * l + 1], ss));
+            HIPCHK(hipStreamWaitEvent(st, h->lvl_ev[2 * l + 1], 0));
         }
     }
 }
@@ -508,18 +529,74 @@ template <typename T>
 void sweeps(ncl_kkt_s* h, int nrhs, const T* F, const T* Z, const T* D, T* Y, T* U, T* partial, hipStream_t st) {
     Plan& P = h->P;
     const DevPlan& d = h->d;
-    for (const SolveStep& ss : P.solve_steps) {
-        Span sp(h, st, TM_SOLVE, ss.fwd_bytes * sizeof(T) / 8.0, 4);
-        launch_fwd_S<T>(d, h->solve_s + ss.s_first, (int)ss.s_count, F, Y, U, nrhs, st);
-        launch_fwd_T<T>(d, h->solve_t + 5 * ss.t_first, (int)ss.t_count, F, Z, Y, U, nrhs, st);
-        launch_fwd_G<T>(d, h->solve_g + 5 * ss.g_first, (int)ss.g_count, F, Y, U, nrhs, st);
+    const std::vector<SolveStep>& S = P.solve_steps;
+    // Steps of one level are independent between small fronts (one wave each)
+    // and large fronts (panel chain): when a level has both, the small ones go
+    // to the second stream, forked at the level's first step and joined after
+    // its last.
+    auto level_end = [&](size_t i) {
+        size_t e = i;
+        while (e < S.size() && S[e].level == S[i].level) ++e;
+        return e;
+    };
+    auto has_large = [&](size_t i0, size_t i1) {
+        for (size_t i = i0; i < i1; ++i)
+            if (S[i].t_count > 0 || S[i].g_count > 0) return true;
+        return false;
+    };
+    for (size_t i0 = 0; i0 < S.size();) {
+        const size_t i1 = level_end(i0);
+        const int l = S[i0].level;
+        const bool fork = S[i0].s_count > 0 && has_large(i0, i1);
+        hipStream_t ss = fork ? h->aux_stream : st;
+        if (fork) {
+            HIPCHK(hipEventRecord(h->lvl_ev[2 * l], st));
+            HIPCHK(hipStreamWaitEvent(ss, h->lvl_ev[2 * l], 0));
+        }
+        for (size_t i = i0; i < i1; ++i) {
+            const SolveStep& ss_ = S[i];
+            if (ss_.s_count > 0) {
+                Span sp(h, ss, TM_SOLVE, 0.0, 0);
+                launch_fwd_S<T>(d, h->solve_s + ss_.s_first, (int)ss_.s_count, F, Y, U, nrhs, ss);
+            }
+            Span sp(h, st, TM_SOLVE, ss_.fwd_bytes * sizeof(T) / 8.0, 4);
+            launch_fwd_T<T>(d, h->solve_t + 5 * ss_.t_first, (int)ss_.t_count, F, Z, Y, U, nrhs, st);
+            launch_fwd_G<T>(d, h->solve_g + 5 * ss_.g_first, (int)ss_.g_count, F, Y, U, nrhs, st);
+        }
+        if (fork) {
+            HIPCHK(hipEventRecord(h->lvl_ev[2 * l + 1], ss));
+            HIPCHK(hipStreamWaitEvent(st, h->lvl_ev[2 * l + 1], 0));
+        }
+        i0 = i1;
     }
-    for (auto it = P.solve_steps.rbegin(); it != P.solve_steps.rend(); ++it) {
-        const SolveStep& ss = *it;
-        Span sp(h, st, TM_SOLVE, ss.fwd_bytes * sizeof(T) / 8.0, 4);
-        launch_bwd_G<T>(d, h->solve_g + 5 * ss.g_first, (int)ss.g_count, F, Y, partial, nrhs, st);
-        launch_bwd_T<T>(d, h->solve_t + 5 * ss.t_first, (int)ss.t_count, F, Z, D, Y, partial, nrhs, st);
-        launch_bwd_S<T>(d, h->solve_s + ss.s_first, (int)ss.s_count, F, D, Y, nrhs, st);
+    // backward: levels from the top down, steps of a level in reverse
+    std::vector<size_t> starts;
+    for (size_t i0 = 0; i0 < S.size(); i0 = level_end(i0)) starts.push_back(i0);
+    for (auto it = starts.rbegin(); it != starts.rend(); ++it) {
+        const size_t i0 = *it, i1 = level_end(i0);
+        const int l = S[i0].level;
+        const bool fork = S[i0].s_count > 0 && has_large(i0, i1);
+        hipStream_t ss = fork ? h->aux_stream : st;
+        if (fork) {
+            HIPCHK(hipEventRecord(h->lvl_ev[2 * l], st));
+            HIPCHK(hipStreamWaitEvent(ss, h->lvl_ev[2 * l], 0));
+        }
+        for (size_t i = i1; i-- > i0;) {
+            const SolveStep& ss_ = S[i];
+            {
+                Span sp(h, st, TM_SOLVE, ss_.fwd_bytes * sizeof(T) / 8.0, 4);
+                launch_bwd_G<T>(d, h->solve_g + 5 * ss_.g_first, (int)ss_.g_count, F, Y, partial, nrhs, st);
+                launch_bwd_T<T>(d, h->solve_t + 5 * ss_.t_first, (int)ss_.t_count, F, Z, D, Y, partial, nrhs, st);
+            }
+            if (ss_.s_count > 0) {
+                Span sp(h, ss, TM_SOLVE, 0.0, 0);
+                launch_bwd_S<T>(d, h->solve_s + ss_.s_first, (int)ss_.s_count, F, D, Y, nrhs, ss);
+            }
+        }
+        if (fork) {
+            HIPCHK(hipEventRecord(h->lvl_ev[2 * l + 1], ss));
+            HIPCHK(hipStreamWaitEvent(st, h->lvl_ev[2 * l + 1], 0));
+        }
     }
 }
 
@@ -808,6 +885,8 @@ void ncl_kkt_destroy(ncl_kkt_t h) {
         for (auto& row : h->g_sweep)
             for (auto& g : row) if (g) (void)hipGraphExecDestroy(g);
         if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+        if (h->aux_stream) (void)hipStreamDestroy(h->aux_stream);
+        for (auto& e : h->lvl_ev) if (e) (void)hipEventDestroy(e);
     }
     delete h;
 }

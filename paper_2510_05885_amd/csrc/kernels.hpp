@@ -12,6 +12,7 @@ constexpr int kSmallMax = 128;   // largest front order of the LDS-resident path
 constexpr int kTile = 64;        // tile order of the large-front MFMA update
 constexpr int kSolvePanel = 256; // pivot columns per solve panel
 constexpr int kSolveChunk = 256; // rows per solve G task (and fused rows below a panel)
+constexpr size_t kAsmLdsMax = 96 * 1024;  // large-front column assembly staged in LDS up to this size
 
 // Device copies of the plan (all device pointers), passed by value.
 struct DevPlan {
@@ -75,7 +76,8 @@ template <typename T>
 void launch_small_fronts(const DevPlan& d, const int* list, int count, int fmax, const double* K, T* F, T* D,
                          hipStream_t st);
 template <typename T>
-void launch_large_asm(const DevPlan& d, const int* tasks, int count, const double* K, T* F, hipStream_t st);
+void launch_large_asm(const DevPlan& d, const int* tasks, int count, int fmax, const double* K, T* F,
+                      hipStream_t st);
 template <typename T>
 void launch_large_diag(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st);
 template <typename T>

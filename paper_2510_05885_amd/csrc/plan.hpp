@@ -34,6 +34,7 @@ struct LevelBatch {            // one launch of the small-front kernel
 struct LargeStep {             // launches of the large-front path for one level
     int level = 0;
     int64_t asm_first = 0, asm_count = 0;     // (front, column) tasks in large_asm
+    int asm_fmax = 0;                         // largest front of the level (column buffer size)
     // per panel step k: diagonal-block, panel (TRSM) and update tasks
     std::vector<int64_t> diag_first, diag_count;
     std::vector<int64_t> panel_first, panel_count;
