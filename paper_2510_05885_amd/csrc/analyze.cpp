@@ -724,12 +724,13 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                     const int p = P.sn_first[s + 1] - P.sn_first[s];
                     if (k0 >= p) continue;
                     const int k1 = std::min(k0 + nb, p);
-                    if (k0 == 0) { P.large_diag.push_back(s); P.large_diag.push_back(k0); }
+                    P.large_diag.push_back(s); P.large_diag.push_back(k0);
                     for (int r0 = k1; r0 < f; r0 += 32) {
                         P.large_panel.push_back(s); P.large_panel.push_back(k0); P.large_panel.push_back(r0);
                     }
                     for (int j0 = k1; j0 < f; j0 += T)
                         for (int i0 = j0; i0 < f; i0 += T) {
+                            if (i0 == k1 && j0 == k1 && k1 < p) continue;   // the next diagonal block
                             P.large_upd.push_back(s); P.large_upd.push_back(k0);
                             P.large_upd.push_back(i0); P.large_upd.push_back(j0);
                             double ri = std::min(T, f - i0), rj = std::min(T, f - j0);

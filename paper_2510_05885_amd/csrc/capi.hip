@@ -93,6 +93,9 @@ struct ncl_kkt_s {
     // second stream: a level's small fronts run beside its large-front chain
     hipStream_t aux_stream = nullptr;
     std::vector<hipEvent_t> lvl_ev;   // 2 per level: fork, join
+    // third stream: the next panel's diagonal block beside the current update
+    hipStream_t diag_stream = nullptr;
+    hipEvent_t diag_ev[2] = {nullptr, nullptr};
     hipGraphExec_t g_factor[2] = {nullptr, nullptr};
     hipGraphExec_t g_sweep[2][kNrhsMax + 1] = {};
 };
@@ -275,6 +278,8 @@ void setup_device(ncl_kkt_s* h) {
     HIPCHK(hipHostMalloc((void**)&h->host_pinned, sizeof(double) * h->host_pinned_len, hipHostMallocDefault));
     HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&h->aux_stream, hipStreamNonBlocking));
+    HIPCHK(hipStreamCreateWithFlags(&h->diag_stream, hipStreamNonBlocking));
+    for (auto& e : h->diag_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     h->lvl_ev.assign(2 * (size_t)std::max(P.nlevels, 1), nullptr);
     for (auto& e : h->lvl_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     {
@@ -392,18 +397,36 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
                 Span sp(h, st, TM_LASM);
                 launch_large_asm<T>(d, h->large_asm + 2 * ls.asm_first, (int)ls.asm_count, ls.asm_fmax, h->K, F, st);
             }
-            for (size_t k = 0; k < ls.panel_first.size(); ++k) {
-                if (ls.diag_count[k] > 0) {
-                    Span sp(h, st, TM_PANEL);
-                    launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[k], (int)ls.diag_count[k], F, D, Mb, st);
-                }
+            // Step k: panel TRSM, then the trailing update beside the next
+            // panel's diagonal block (which updates that block itself) on a
+            // third stream; both finish before the next panel.
+            const size_t nsteps = ls.panel_first.size();
+            {
+                Span sp(h, st, TM_PANEL);
+                launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[0], (int)ls.diag_count[0], F, D, Mb, st);
+            }
+            for (size_t k = 0; k < nsteps; ++k) {
                 {
                     Span sp(h, st, TM_PANEL);
                     launch_large_panel<T>(d, h->large_panel + 3 * ls.panel_first[k], (int)ls.panel_count[k], F, D,
                                           Mb, st);
                 }
-                Span sp(h, st, TM_UPD, ls.upd_flops[k], 1);
-                launch_large_update<T>(d, h->large_upd + 4 * ls.upd_first[k], (int)ls.upd_count[k], F, D, Mb, st);
+                const bool next = k + 1 < nsteps && ls.diag_count[k + 1] > 0;
+                if (next) {
+                    HIPCHK(hipEventRecord(h->diag_ev[0], st));
+                    HIPCHK(hipStreamWaitEvent(h->diag_stream, h->diag_ev[0], 0));
+                    {
+                        Span sp(h, h->diag_stream, TM_PANEL);
+                        launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[k + 1], (int)ls.diag_count[k + 1], F,
+                                             D, Mb, h->diag_stream);
+                    }
+                    HIPCHK(hipEventRecord(h->diag_ev[1], h->diag_stream));
+                }
+                {
+                    Span sp(h, st, TM_UPD, ls.upd_flops[k], 1);
+                    launch_large_update<T>(d, h->large_upd + 4 * ls.upd_first[k], (int)ls.upd_count[k], F, D, Mb, st);
+                }
+                if (next) HIPCHK(hipStreamWaitEvent(st, h->diag_ev[1], 0));
             }
         }
         if (fork) {
@@ -886,6 +909,8 @@ void ncl_kkt_destroy(ncl_kkt_t h) {
             for (auto& g : row) if (g) (void)hipGraphExecDestroy(g);
         if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
         if (h->aux_stream) (void)hipStreamDestroy(h->aux_stream);
+        if (h->diag_stream) (void)hipStreamDestroy(h->diag_stream);
+        for (auto& e : h->diag_ev) if (e) (void)hipEventDestroy(e);
         for (auto& e : h->lvl_ev) if (e) (void)hipEventDestroy(e);
     }
     delete h;

@@ -620,10 +620,63 @@ __device__ __forceinline__ unsigned long long neg_mask(const DevPlan& d, int fir
     return __ballot(neg);
 }
 
-// One workgroup per large front: factor the diagonal block of the front's
-// first panel with the static-pivot rule of Sec. 3.1, count its inertia,
-// invert its unit lower triangle and publish L, D and Z = L_kk^-1.  (Later
-// panels' blocks are handled by the update launch that finishes them.)
+// C - L_I D_k L_J^T for the 64x64 tile at rows i0, columns j0 of front A
+// (ld f), with panel k = columns [k0, k0 + w): four waves, each a 32x32
+// quadrant as 2x2 blocks of 16x16 (v_mfma 16x16x4).  The accumulators start
+// from C (prefetched with the operands, clamped addresses) and the B operand
+// is negated, so the result is the updated tile.  acc[bi][bj][r] holds entry
+// (i0 + wr + 16 bi + row(lk, r), j0 + wc + 16 bj + lr).
+template <typename T>
+__device__ __forceinline__ void tile_update(const T* __restrict__ A, int f, int k0, int w, int i0, int j0,
+                                            const T* __restrict__ Dk, typename Mfma<T>::acc_t (&acc)[2][2]) {
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+    const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj) {
+            const int gj = min(j0 + wc + 16 * bj + lr, f - 1);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                const int gi = min(i0 + wr + 16 * bi + Mfma<T>::row(lk, r), f - 1);
+                acc[bi][bj][r] = A[gi + (int64_t)gj * f];
+            }
+        }
+    constexpr int KS = kPanel / 4;
+    T av[KS][2], bv[KS][2];
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks) {
+        const int t = 4 * ks + lk;
+        const bool tv = t < w;
+        const int tc = tv ? t : 0;
+        const int64_t cofs = (int64_t)(k0 + tc) * f;
+        const T dtr = Dk[tc];
+        const T ndt = tv ? -dtr : T(0);
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int ri = i0 + wr + 16 * h + lr, rj = j0 + wc + 16 * h + lr;
+            const T a = A[min(ri, f - 1) + cofs], b = A[min(rj, f - 1) + cofs];
+            av[ks][h] = (tv && ri < f) ? a : T(0);
+            bv[ks][h] = (rj < f) ? b * ndt : T(0);
+        }
+    }
+#pragma unroll
+    for (int ks = 0; ks < KS; ++ks)
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = Mfma<T>::run(av[ks][bi], bv[ks][bj], acc[bi][bj]);
+}
+
+// One workgroup per (large front, panel k0): bring the panel's diagonal block
+// up to date (for k0 > 0 it applies the previous panel's update to the block
+// itself, which the update launch of that panel leaves out, so the two run
+// side by side), factor it with the static-pivot rule of Sec. 3.1, count its
+// inertia, invert its unit lower triangle and publish L, D and Z = L_kk^-1.
+// When the panel is narrower than 64, the block's rows past the last pivot
+// belong to the panel rows below it / the contribution block and are written
+// back to the front.
 template <typename T>
 __global__ __launch_bounds__(256) void k_large_diag(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
                                                     T* __restrict__ D, T* __restrict__ Zbuf) {
@@ -637,9 +690,29 @@ __global__ __launch_bounds__(256) void k_large_diag(DevPlan d, const int* __rest
     __shared__ T Bf[kPanel * LB];
     __shared__ T dv[kPanel];
     const int tid = threadIdx.x;
-    for (int idx = tid; idx < kPanel * kPanel; idx += 256) {
-        const int u = idx & (kPanel - 1), t = idx / kPanel;
-        if (u < w && t <= u) Bf[u + t * LB] = A[(k0 + u) + (int64_t)(k0 + t) * f];
+    if (k0 == 0) {
+        for (int idx = tid; idx < kPanel * kPanel; idx += 256) {
+            const int u = idx & (kPanel - 1), t = idx / kPanel;
+            if (u < w && t <= u) Bf[u + t * LB] = A[(k0 + u) + (int64_t)(k0 + t) * f];
+        }
+    } else {
+        typename Mfma<T>::acc_t acc[2][2];
+        tile_update<T>(A, f, k0 - kPanel, kPanel, k0, k0, D + first + k0 - kPanel, acc);
+        const int wave = tid >> 6, lane = tid & 63;
+        const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+        const int lr = lane & 15, lk = lane >> 4;
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int li = wr + bi * 16 + Mfma<T>::row(lk, r), lj = wc + bj * 16 + lr;
+                    const int gi = k0 + li, gj = k0 + lj;
+                    if (li < lj || gi >= f) continue;
+                    if (li < w) Bf[li + lj * LB] = acc[bi][bj][r];
+                    else A[gi + (int64_t)gj * f] = acc[bi][bj][r];
+                }
     }
     pad_diag<T>(Bf, w);
     const unsigned long long negmask = neg_mask(d, first, k0, w);
@@ -719,13 +792,11 @@ __global__ __launch_bounds__(256) void k_large_panel(DevPlan d, const int* __res
 }
 
 // Trailing update of one 64x64 lower tile: C -= L_I D_k L_J^T on MFMA, with
-// the operands read straight from the front (no LDS).  Four waves, each a
-// 32x32 quadrant as 2x2 blocks of 16x16; depth = panel width.  The tile that
-// is the next panel's diagonal block then factors, inverts and publishes it
-// (as k_large_diag does), overlapped with the other tiles of the launch.
+// the operands read straight from the front (no LDS).  The next panel's
+// diagonal tile is not in the task list: k_large_diag updates it.
 template <typename T>
-__global__ __launch_bounds__(256, 2) void k_large_update(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
-                                                         T* __restrict__ D, T* __restrict__ Zbuf) {
+__global__ __launch_bounds__(256) void k_large_update(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
+                                                      const T* __restrict__ D) {
     const int* tk = tasks + 4 * xcd_task(blockIdx.x, gridDim.x);
     const int s = tk[0], k0 = tk[1], i0 = tk[2], j0 = tk[3];
     const int first = d.sn_first[s];
@@ -733,78 +804,20 @@ __global__ __launch_bounds__(256, 2) void k_large_update(DevPlan d, const int* _
     const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
     const int w = min(kPanel, p - k0);
     T* __restrict__ A = F + d.L_off[s];
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6, lane = tid & 63;
+    typename Mfma<T>::acc_t acc[2][2];
+    tile_update<T>(A, f, k0, w, i0, j0, D + first + k0, acc);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int lr = lane & 15, lk = lane >> 4;
-    constexpr int KS = kPanel / 4;
-    // Operand loads are unconditional from clamped (valid) addresses and
-    // masked afterwards: no branch per load.
-    T av[KS][2], bv[KS][2];
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks) {
-        const int t = 4 * ks + lk;
-        const bool tv = t < w;
-        const int tc = tv ? t : 0;
-        const int64_t cofs = (int64_t)(k0 + tc) * f;
-        const T dtr = D[first + k0 + tc];
-        const T dt = tv ? dtr : T(0);
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int ri = i0 + wr + 16 * h + lr, rj = j0 + wc + 16 * h + lr;
-            const T a = A[min(ri, f - 1) + cofs], b = A[min(rj, f - 1) + cofs];
-            av[ks][h] = (tv && ri < f) ? a : T(0);
-            bv[ks][h] = (rj < f) ? b * dt : T(0);
-        }
-    }
-    typedef typename Mfma<T>::acc_t acc_t;
-    acc_t acc[2][2];
-#pragma unroll
-    for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-        for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = acc_t{0, 0, 0, 0};
-#pragma unroll
-    for (int ks = 0; ks < KS; ++ks)
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = Mfma<T>::run(av[ks][bi], bv[ks][bj], acc[bi][bj]);
-    const int k1 = k0 + w;
-    const bool next_diag = (i0 == k1 && j0 == k1 && k1 < p);
-    const int w2 = min(kPanel, p - k1);
-    constexpr int LB = kPanel + 1;
-    __shared__ T Bf[kPanel * LB];
-    __shared__ T dv[kPanel];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
         for (int bj = 0; bj < 2; ++bj)
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int li = wr + bi * 16 + Mfma<T>::row(lk, r), lj = wc + bj * 16 + lr;
-                const int gi = i0 + li, gj = j0 + lj;
-                if (gi < f && gj < f && gi >= gj) {
-                    const T nv = A[gi + (int64_t)gj * f] - acc[bi][bj][r];
-                    A[gi + (int64_t)gj * f] = nv;
-                    if (next_diag && li < w2) Bf[li + lj * LB] = nv;
-                }
+                const int gi = i0 + wr + bi * 16 + Mfma<T>::row(lk, r), gj = j0 + wc + bj * 16 + lr;
+                if (gi < f && gj < f && gi >= gj) A[gi + (int64_t)gj * f] = acc[bi][bj][r];
             }
-    if (!next_diag) return;
-    pad_diag<T>(Bf, w2);
-    const unsigned long long negmask = neg_mask(d, first, k1, w2);
-    __syncthreads();
-    const int sys = d.sn_sys[s];
-    unsigned int cnt[4] = {0, 0, 0, 0};
-    bool bad = false;
-    diag_ldlt64<T>(Bf, dv, negmask, w2, d.sys_thr[sys], cnt, bad);
-    tri_inv64<T>(Bf);
-    if (tid == 0) {
-        unsigned long long* in4 = d.inertia + 4 * sys;
-        for (int k = 0; k < 4; ++k)
-            if (cnt[k]) atomicAdd(&in4[k], (unsigned long long)cnt[k]);
-        if (bad) d.nonfinite[0] = 1;
-    }
-    publish_diag<T>(A, f, k1, w2, Bf, dv, D, first, Zbuf + d.M_off[s] + (int64_t)(k1 / kPanel) * (kPanel * kPanel));
 }
 
 // ---------------------------------------------------------------------------
@@ -1579,7 +1592,8 @@ void launch_large_panel(const DevPlan& d, const int* tasks, int count, T* F, con
 template <typename T>
 void launch_large_update(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_large_update<T>, dim3(count), dim3(256), 0, st, d, tasks, F, D, M);
+    (void)M;
+    hipLaunchKernelGGL(k_large_update<T>, dim3(count), dim3(256), 0, st, d, tasks, F, (const T*)D);
 }
 
 template <typename T>

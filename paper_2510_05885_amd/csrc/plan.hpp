@@ -132,9 +132,10 @@ struct Plan {
     std::vector<LargeStep> large_steps;
     // large-front tasks
     std::vector<int> large_asm;      // pairs (front, column)
-    std::vector<int> large_diag;     // pairs (front, 0): first panel's diagonal block factorization + inverse
+    std::vector<int> large_diag;     // pairs (front, k0): diagonal block update, factorization, inverse
     std::vector<int> large_panel;    // triples (front, k0, 32-row block start >= k0 + panel)
-    std::vector<int> large_upd;      // quads (front, k0, tile row start, tile col start)
+    std::vector<int> large_upd;      // quads (front, k0, tile row start, tile col start); the next
+                                     // panel's diagonal tile is left to large_diag
     // solve schedule
     std::vector<SolveStep> solve_steps;
     std::vector<int> solve_t;        // (front, c0, fused, g_first, g_count)
