@@ -119,6 +119,7 @@ __device__ __forceinline__ void wave_fence() {
 template <typename T, bool kTwoRows>
 __device__ void lds_partial_ldlt(T* A, int lda, int f, int p, T* dv, const int8_t* sgn, double thr,
                                  unsigned int* cnt, bool& bad_out) {
+    const T inv_thr = T(1) / (T)thr;   // reciprocal of a perturbed pivot (+-thr)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lk = lane >> 4;
     bool bad_any = false;
@@ -143,8 +144,11 @@ __device__ void lds_partial_ldlt(T* A, int lda, int f, int p, T* dv, const int8_
             for (int t = 0; t < 16; ++t) {
                 if (t >= bw) continue;   // uniform; keeps the loop fully unrolled
                 bool pert, bad;
-                const T dk = static_pivot(bcast(r0[t], t), thr, sgn[kb + t], pert, bad);
-                const T inv = fast_rcp(dk);
+                const T draw = bcast(r0[t], t);
+                const T inv0 = fast_rcp(draw);
+                const int sg = sgn[kb + t];
+                const T dk = static_pivot(draw, thr, sg, pert, bad);
+                const T inv = pert ? (sg > 0 ? inv_thr : -inv_thr) : inv0;
                 T ck[16];
 #pragma unroll
                 for (int u = t + 1; u < 16; ++u) ck[u] = (u < bw) ? bcast(r0[t], u) : T(0);
@@ -244,6 +248,7 @@ template <typename T>
 __device__ __forceinline__ void diag_ldlt64(T* B, T* dv, unsigned long long negmask, int w, double thr, unsigned int* cnt,
                             bool& bad_out) {
     constexpr int LB = kPanel + 1;
+    const T inv_thr = T(1) / (T)thr;   // reciprocal of a perturbed pivot (+-thr)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lk = lane >> 4;
     bool bad_any = false;
@@ -263,8 +268,14 @@ __device__ __forceinline__ void diag_ldlt64(T* B, T* dv, unsigned long long negm
             for (int t = 0; t < 16; ++t) {
                 const int c = kb + t;
                 bool pert, bd;
-                const T dk = static_pivot(bcast(r[t], c), thr, ((negmask >> c) & 1ULL) ? -1 : 1, pert, bd);
-                const T inv = fast_rcp(dk);
+                // The reciprocal starts from the raw pivot; the static-pivot
+                // rule (rarely taken) replaces both afterwards, so its test is
+                // off the dependent chain.
+                const T draw = bcast(r[t], c);
+                const T inv0 = fast_rcp(draw);
+                const int sg = ((negmask >> c) & 1ULL) ? -1 : 1;
+                const T dk = static_pivot(draw, thr, sg, pert, bd);
+                const T inv = pert ? (sg > 0 ? inv_thr : -inv_thr) : inv0;
                 const T l = r[t] * inv;
 #pragma unroll
                 for (int u = t + 1; u < 16; ++u) r[u] -= l * bcast(r[t], kb + u);
@@ -690,17 +701,68 @@ __global__ __launch_bounds__(256) void k_large_diag(DevPlan d, const int* __rest
     __shared__ T Bf[kPanel * LB];
     __shared__ T dv[kPanel];
     const int tid = threadIdx.x;
+    constexpr int kIt = kPanel * kPanel / 256;   // staging: all loads first, then the LDS stores
     if (k0 == 0) {
-        for (int idx = tid; idx < kPanel * kPanel; idx += 256) {
-            const int u = idx & (kPanel - 1), t = idx / kPanel;
-            if (u < w && t <= u) Bf[u + t * LB] = A[(k0 + u) + (int64_t)(k0 + t) * f];
+        T cv[kIt];
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int idx = tid + 256 * it, u = idx & (kPanel - 1), t = idx / kPanel;
+            cv[it] = A[min(u, w - 1) + (int64_t)min(t, w - 1) * f];
+        }
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int idx = tid + 256 * it, u = idx & (kPanel - 1), t = idx / kPanel;
+            if (u < w && t <= u) Bf[u + t * LB] = cv[it];
         }
     } else {
-        typename Mfma<T>::acc_t acc[2][2];
-        tile_update<T>(A, f, k0 - kPanel, kPanel, k0, k0, D + first + k0 - kPanel, acc);
+        // The block's own update by the previous panel (columns kp = k0 - 64
+        // .. k0, all 64 wide): the block C and the panel's 64 rows are staged
+        // in LDS by one coalesced pass, then C -= P D P^T on MFMA.
+        __shared__ T Pf[kPanel * LB];
+        __shared__ T dp[kPanel];
+        const int kp = k0 - kPanel;
+        const int nr = min(kPanel, f - k0);   // rows of the block inside the front
+        T pv[kIt], cv[kIt];
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int idx = tid + 256 * it, u = idx & (kPanel - 1), t = idx / kPanel;
+            const int uc = min(u, nr - 1);
+            pv[it] = A[(k0 + uc) + (int64_t)(kp + t) * f];
+            cv[it] = A[(k0 + uc) + (int64_t)(k0 + min(t, nr - 1)) * f];
+        }
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int idx = tid + 256 * it, u = idx & (kPanel - 1), t = idx / kPanel;
+            const bool in = u < nr;
+            Pf[u + t * LB] = in ? pv[it] : T(0);
+            Bf[u + t * LB] = (in && t <= u) ? cv[it] : T(0);
+        }
+        if (tid < kPanel) dp[tid] = D[first + kp + tid];
+        __syncthreads();
         const int wave = tid >> 6, lane = tid & 63;
         const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
         const int lr = lane & 15, lk = lane >> 4;
+        typedef typename Mfma<T>::acc_t acc_t;
+        acc_t acc[2][2];
+#pragma unroll
+        for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+            for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = acc_t{0, 0, 0, 0};
+#pragma unroll
+        for (int ks = 0; ks < kPanel / 4; ++ks) {
+            const int t = 4 * ks + lk;
+            const T dt = dp[t];
+            T a[2], b[2];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                a[h] = Pf[(wr + 16 * h + lr) + t * LB];
+                b[h] = Pf[(wc + 16 * h + lr) + t * LB] * dt;
+            }
+#pragma unroll
+            for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+                for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = Mfma<T>::run(a[bi], b[bj], acc[bi][bj]);
+        }
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -708,11 +770,12 @@ __global__ __launch_bounds__(256) void k_large_diag(DevPlan d, const int* __rest
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int li = wr + bi * 16 + Mfma<T>::row(lk, r), lj = wc + bj * 16 + lr;
-                    const int gi = k0 + li, gj = k0 + lj;
-                    if (li < lj || gi >= f) continue;
-                    if (li < w) Bf[li + lj * LB] = acc[bi][bj][r];
-                    else A[gi + (int64_t)gj * f] = acc[bi][bj][r];
+                    if (li < lj || li >= nr) continue;
+                    const T v = Bf[li + lj * LB] - acc[bi][bj][r];
+                    if (li < w) Bf[li + lj * LB] = v;
+                    else A[(k0 + li) + (int64_t)(k0 + lj) * f] = v;   // rows past the last pivot
                 }
+        __syncthreads();   // pad_diag below overwrites rows past the last pivot
     }
     pad_diag<T>(Bf, w);
     const unsigned long long negmask = neg_mask(d, first, k0, w);
@@ -885,9 +948,18 @@ __device__ __forceinline__ void row_dot(const T* __restrict__ M, int64_t f, int 
 template <typename T, bool kBackward>
 __device__ __forceinline__ void chain_solve64(const T* __restrict__ L, int f, int c, int ws, T* Ld, T* v, int nrhs) {
     const int tid = threadIdx.x, lane = tid & 63;
-    for (int idx = tid; idx < 64 * ws; idx += 256) {
-        const int a = idx & 63, b = idx >> 6;
-        if (a < ws && b < a) Ld[a * 65 + b] = L[(c + a) + (int64_t)(c + b) * f];
+    {
+        T lv[16];   // all loads first, then the LDS stores
+#pragma unroll
+        for (int it = 0; it < 16; ++it) {
+            const int idx = tid + 256 * it, a = idx & 63, b = idx >> 6;
+            lv[it] = L[(c + min(a, ws - 1)) + (int64_t)(c + min(b, ws - 1)) * f];
+        }
+#pragma unroll
+        for (int it = 0; it < 16; ++it) {
+            const int idx = tid + 256 * it, a = idx & 63, b = idx >> 6;
+            if (a < ws && b < a) Ld[a * 65 + b] = lv[it];
+        }
     }
     __syncthreads();
     if (tid < 64) {
@@ -925,7 +997,14 @@ __device__ __forceinline__ void zmul64(const T* __restrict__ Zb, int ws, T* Zs, 
 #pragma unroll
         for (int j = 0; j < 16; ++j) z[j] = Zb[(16 * q4 + j) * kPanel + lane];   // Z[lane][16 q4 + j]
     } else {
-        for (int idx = tid; idx < kPanel * kPanel; idx += 256) Zs[(idx & 63) + (idx >> 6) * 65] = Zb[idx];
+        T zv[kPanel * kPanel / 256];
+#pragma unroll
+        for (int it = 0; it < kPanel * kPanel / 256; ++it) zv[it] = Zb[tid + 256 * it];
+#pragma unroll
+        for (int it = 0; it < kPanel * kPanel / 256; ++it) {
+            const int idx = tid + 256 * it;
+            Zs[(idx & 63) + (idx >> 6) * 65] = zv[it];
+        }
         __syncthreads();
 #pragma unroll
         for (int j = 0; j < 16; ++j) z[j] = Zs[(16 * q4 + j) + lane * 65];        // Z[16 q4 + j][lane]
