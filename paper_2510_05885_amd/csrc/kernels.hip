@@ -516,7 +516,12 @@ __global__ __launch_bounds__(256) void k_small_fronts(DevPlan d, const int* __re
     __syncthreads();
     for (int64_t e = d.kent_ptr[s] + tid; e < d.kent_ptr[s + 1]; e += 256) A[d.kent_pos[e]] = (T)K[d.kent_csr[e]];
     __syncthreads();
-    // extend-add: pull every child's contribution block, children in order
+    // extend-add: pull every child's contribution block, children in order.
+    // Entry (a, b) of the child's lower CB is element idx = a + 128 b of a
+    // 128-row grid (cc <= f <= 128); 8 loads per thread are issued before
+    // their LDS adds.
+    static_assert(kSmallMax == 128, "the extend-add grid assumes 128 rows");
+    __shared__ int rl[kSmallMax];
     for (int k = d.child_ptr[s]; k < d.child_ptr[s + 1]; ++k) {
         const int ch = d.child_list[k];
         const int fc = (int)(d.sn_rowptr[ch + 1] - d.sn_rowptr[ch]);
@@ -524,9 +529,23 @@ __global__ __launch_bounds__(256) void k_small_fronts(DevPlan d, const int* __re
         const T* __restrict__ CB = F + d.CB_off[ch];
         const int ld = d.CB_ld[ch];
         const int* __restrict__ r = d.rel + d.rel_ptr[ch];
-        for (int b = tj; b < cc; b += 4) {
-            const int col = r[b] * f;
-            for (int a = b + ti; a < cc; a += 64) A[r[a] + col] += CB[a + (int64_t)b * ld];
+        if (tid < cc) rl[tid] = r[tid];
+        __syncthreads();
+        const int n2 = kSmallMax * cc;
+        for (int base = 0; base < n2; base += 256 * 8) {
+            T v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = base + tid + 256 * u;
+                const int a = min(idx & (kSmallMax - 1), cc - 1), b = min(idx >> 7, cc - 1);
+                v[u] = CB[a + (int64_t)b * ld];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int idx = base + tid + 256 * u;
+                const int a = idx & (kSmallMax - 1), b = idx >> 7;
+                if (idx < n2 && a < cc && a >= b) A[rl[a] + rl[b] * f] += v[u];
+            }
         }
         __syncthreads();
     }
@@ -588,7 +607,19 @@ __global__ __launch_bounds__(256) void k_large_asm(DevPlan d, const int* __restr
         const int cc = fc - (d.sn_first[ch + 1] - d.sn_first[ch]);
         const T* __restrict__ CB = F + d.CB_off[ch] + (int64_t)b * d.CB_ld[ch];
         const int* __restrict__ r = d.rel + d.rel_ptr[ch];
-        for (int a = b + tid; a < cc; a += 256) cv[r[a]] += CB[a];
+        for (int a0 = b + tid; a0 < cc; a0 += 256 * 4) {
+            T v[4];
+            int ri[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int a = min(a0 + 256 * u, cc - 1);
+                v[u] = CB[a];
+                ri[u] = r[a];
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (a0 + 256 * u < cc) cv[ri[u]] += v[u];
+        }
         __syncthreads();
     }
     if (kLds)
