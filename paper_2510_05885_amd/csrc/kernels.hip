@@ -1056,6 +1056,36 @@ __device__ __forceinline__ void zmul64(const T* __restrict__ Zb, int ws, T* Zs, 
     __syncthreads();
 }
 
+// Y / Us [rows i0 .. i0 + nrow) -= L[rows, c0 : c0 + w] y for nrow <= 64 rows
+// of front s: lane = row, the four waves split the w <= 256 columns (64 each)
+// and their partial sums meet in LDS (part: 256 x nrhs).  Called by all 256
+// threads.
+template <typename T>
+__device__ __forceinline__ void rows_update64(const T* __restrict__ L, int f, int p, int c, int i0, int nrow, int c0,
+                                              int w, const T* y, T* part, T* __restrict__ Yf, T* __restrict__ Us,
+                                              int64_t N, int nrhs) {
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int k0 = 64 * wave;
+    T acc[kNrhsMax];
+#pragma unroll
+    for (int q = 0; q < kNrhsMax; ++q) acc[q] = T(0);
+    if (k0 < w) row_dot(L, f, i0 + min(lane, nrow - 1), c0 + k0, min(64, w - k0), y + k0, kSolvePanel, nrhs, acc);
+#pragma unroll
+    for (int q = 0; q < kNrhsMax; ++q)
+        if (q < nrhs) part[(wave * 64 + lane) * nrhs + q] = acc[q];
+    __syncthreads();
+    if (tid < nrow) {
+        const int i = i0 + tid;
+        for (int q = 0; q < nrhs; ++q) {
+            const T* pp = part + tid * nrhs + q;
+            const T sub = (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]);
+            if (i < p) Yf[i + q * N] -= sub;
+            else Us[(i - p) + (int64_t)q * c] -= sub;
+        }
+    }
+    __syncthreads();
+}
+
 // Forward T: (c0 == 0) pull the children's update vectors; solve the panel's
 // triangle; when `fused`, also apply the panel to every row below it.
 template <typename T>
@@ -1123,18 +1153,8 @@ __global__ __launch_bounds__(256) void k_fwd_T(DevPlan d, const int* __restrict_
     for (int q = 0; q < nrhs; ++q)
         for (int t = tid; t < w; t += 256) Y[first + c0 + t + q * N] = v[t + q * kSolvePanel];
     if (!fused) return;
-    for (int i = c0 + w + tid; i < f; i += 256) {
-        T acc[kNrhsMax];
-#pragma unroll
-        for (int q = 0; q < kNrhsMax; ++q) acc[q] = T(0);
-        row_dot(L, f, i, c0, w, v, kSolvePanel, nrhs, acc);
-#pragma unroll
-        for (int q = 0; q < kNrhsMax; ++q) {
-            if (q >= nrhs) continue;
-            if (i < p) Y[first + i + q * N] -= acc[q];
-            else Us[(i - p) + (int64_t)q * c] -= acc[q];
-        }
-    }
+    for (int i0 = c0 + w; i0 < f; i0 += 64)
+        rows_update64(L, f, p, c, i0, min(64, f - i0), c0, w, v, part, Y + first, Us, N, nrhs);
 }
 
 // Forward G: rows [r0, r1) of front s minus L[rows, panel] y_panel.
@@ -1143,6 +1163,7 @@ __global__ __launch_bounds__(256) void k_fwd_G(DevPlan d, const int* __restrict_
                                                T* __restrict__ Y, T* __restrict__ U, int nrhs) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* y = reinterpret_cast<T*>(smem_raw);        // kSolvePanel x nrhs
+    T* part = y + kSolvePanel * nrhs;             // 4 x 64 x nrhs
     const int* tk = tasks + 5 * blockIdx.x;
     const int s = tk[0], c0 = tk[1], r0 = tk[2], r1 = tk[3];
     const int first = d.sn_first[s];
@@ -1157,18 +1178,8 @@ __global__ __launch_bounds__(256) void k_fwd_G(DevPlan d, const int* __restrict_
     for (int q = 0; q < nrhs; ++q)
         for (int t = tid; t < kSolvePanel; t += 256) y[t + q * kSolvePanel] = t < w ? Y[first + c0 + t + q * N] : T(0);
     __syncthreads();
-    for (int i = r0 + tid; i < r1; i += 256) {
-        T acc[kNrhsMax];
-#pragma unroll
-        for (int q = 0; q < kNrhsMax; ++q) acc[q] = T(0);
-        row_dot(L, f, i, c0, w, y, kSolvePanel, nrhs, acc);
-#pragma unroll
-        for (int q = 0; q < kNrhsMax; ++q) {
-            if (q >= nrhs) continue;
-            if (i < p) Y[first + i + q * N] -= acc[q];
-            else Us[(i - p) + (int64_t)q * c] -= acc[q];
-        }
-    }
+    for (int i0 = r0; i0 < r1; i0 += 64)
+        rows_update64(L, f, p, c, i0, min(64, r1 - i0), c0, w, y, part, Y + first, Us, N, nrhs);
 }
 
 // Backward G (large fronts only: a G task exists only when more than
@@ -1742,7 +1753,7 @@ void launch_bwd_S(const DevPlan& d, const int* fronts, int count, const T* F, co
 template <typename T>
 void launch_fwd_G(const DevPlan& d, const int* tasks, int count, const T* F, T* Y, T* U, int nrhs, hipStream_t st) {
     if (count <= 0) return;
-    const size_t lds = (size_t)kSolvePanel * nrhs * sizeof(T);
+    const size_t lds = (size_t)(kSolvePanel + 256) * nrhs * sizeof(T);
     hipLaunchKernelGGL(k_fwd_G<T>, dim3(count), dim3(256), lds, st, d, tasks, F, Y, U, nrhs);
 }
 

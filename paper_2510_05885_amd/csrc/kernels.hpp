@@ -11,7 +11,7 @@ constexpr int kPanel = 64;       // pivot block width of the large-front path
 constexpr int kSmallMax = 128;   // largest front order of the LDS-resident path
 constexpr int kTile = 64;        // tile order of the large-front MFMA update
 constexpr int kSolvePanel = 256; // pivot columns per solve panel
-constexpr int kSolveChunk = 256; // rows per solve G task (and fused rows below a panel)
+constexpr int kSolveChunk = 256; // row capacity of a solve G task / of the rows fused below a panel
 constexpr size_t kAsmLdsMax = 96 * 1024;  // large-front column assembly staged in LDS up to this size
 
 // Device copies of the plan (all device pointers), passed by value.

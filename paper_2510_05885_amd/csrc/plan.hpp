@@ -21,8 +21,8 @@ struct PlanConfig {
     int relax_big_front = 128;  // fronts above this order (the global-memory path, swept in
     double relax_big_zeros = 0.2;  // panels anyway) may carry up to this fraction of zeros
     int solve_panel = 256;      // pivot columns per solve panel
-    int solve_fuse_rows = 256;  // rows below a panel handled inside the panel's workgroup
-    int solve_chunk_rows = 256; // rows per G task otherwise
+    int solve_fuse_rows = 64;   // rows below a panel handled inside the panel's workgroup
+    int solve_chunk_rows = 64;  // rows per G task otherwise
 };
 
 struct LevelBatch {            // one launch of the small-front kernel
