@@ -708,8 +708,30 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
             st.asm_first = (int64_t)P.large_asm.size() / 2;
             for (int s : large) {
                 const int f = (int)(P.sn_rowptr[s + 1] - P.sn_rowptr[s]);
+                const int np = P.sn_first[s + 1] - P.sn_first[s];
                 st.asm_fmax = std::max(st.asm_fmax, f);
-                for (int j = 0; j < f; ++j) { P.large_asm.push_back(s); P.large_asm.push_back(j); }
+                for (int j = 0; j < f; ++j) {
+                    P.large_asm.push_back(s); P.large_asm.push_back(j);
+                    if (P.asm_seg_ptr.empty()) P.asm_seg_ptr.push_back(0);
+                    P.asm_col.push_back(P.L_off[s] + (int64_t)j * f);
+                    P.asm_fj.push_back(f); P.asm_fj.push_back(j);
+                    if (j < np) {
+                        P.asm_kr.push_back(P.kcol_ptr[P.kcol_base[s] + j]);
+                        P.asm_kr.push_back(P.kcol_ptr[P.kcol_base[s] + j + 1]);
+                    } else {
+                        P.asm_kr.push_back(0); P.asm_kr.push_back(0);
+                    }
+                    for (int k = P.child_ptr[s]; k < P.child_ptr[s + 1]; ++k) {
+                        const int ch = P.child_list[k];
+                        const int b = P.inv[P.inv_ptr[ch] + j];
+                        if (b < 0) continue;
+                        const int cc = (int)(P.sn_rowptr[ch + 1] - P.sn_rowptr[ch]) - (P.sn_first[ch + 1] - P.sn_first[ch]);
+                        P.asm_seg_cb.push_back(P.CB_off[ch] + (int64_t)b * P.CB_ld[ch]);
+                        P.asm_seg_rel.push_back(P.rel_ptr[ch]);
+                        P.asm_seg_bc.push_back(b); P.asm_seg_bc.push_back(cc);
+                    }
+                    P.asm_seg_ptr.push_back((int64_t)P.asm_seg_cb.size());
+                }
             }
             st.asm_count = (int64_t)P.large_asm.size() / 2 - st.asm_first;
             int maxp = 0;

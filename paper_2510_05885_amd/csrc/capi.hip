@@ -206,6 +206,13 @@ void setup_device(ncl_kkt_s* h) {
     for (auto& x : uo) x *= kNrhsMax;
     d.U_off = upload(h, uo);
     d.M_off = upload(h, P.M_off);
+    d.asm_col = upload(h, P.asm_col);
+    d.asm_fj = upload(h, P.asm_fj);
+    d.asm_kr = upload(h, P.asm_kr);
+    d.asm_seg_ptr = upload(h, P.asm_seg_ptr);
+    d.asm_seg_cb = upload(h, P.asm_seg_cb);
+    d.asm_seg_rel = upload(h, P.asm_seg_rel);
+    d.asm_seg_bc = upload(h, P.asm_seg_bc);
     h->small_list = upload(h, P.small_list);
     h->level_list = upload(h, P.level_list);
     h->large_asm = upload(h, P.large_asm);
@@ -395,7 +402,7 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
             const LargeStep& ls = P.large_steps[lb++];
             {
                 Span sp(h, st, TM_LASM);
-                launch_large_asm<T>(d, h->large_asm + 2 * ls.asm_first, (int)ls.asm_count, ls.asm_fmax, h->K, F, st);
+                launch_large_asm<T>(d, ls.asm_first, (int)ls.asm_count, ls.asm_fmax, h->K, F, st);
             }
             // Step k: panel TRSM, then the trailing update beside the next
             // panel's diagonal block (which updates that block itself) on a

@@ -579,34 +579,32 @@ __global__ __launch_bounds__(256) void k_small_fronts(DevPlan d, const int* __re
 // large fronts (front stored in the factor buffer, ld = f)
 // ---------------------------------------------------------------------------
 // One workgroup per (large front, column j): assemble column j (rows >= j)
-// from K and the children's contribution blocks.  kLds: the column is built
-// in LDS (dynamic, >= f elements) and written once; otherwise in place.
+// from K and the children's contribution blocks.  The task's column base,
+// K-entry range and contribution segments (one per child whose CB maps a
+// column onto j) come precomputed, so the workgroup starts with one round of
+// independent loads.  kLds: the column is built in LDS (dynamic, >= f
+// elements) and written once; otherwise in place.
 template <typename T, bool kLds>
-__global__ __launch_bounds__(256) void k_large_asm(DevPlan d, const int* __restrict__ tasks,
-                                                   const double* __restrict__ K, T* __restrict__ F) {
+__global__ __launch_bounds__(256) void k_large_asm(DevPlan d, int64_t task0, const double* __restrict__ K,
+                                                   T* __restrict__ F) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int s = tasks[2 * blockIdx.x], j = tasks[2 * blockIdx.x + 1];
-    const int p = d.sn_first[s + 1] - d.sn_first[s];
-    const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
-    T* __restrict__ A = F + d.L_off[s];
-    const int64_t col = (int64_t)j * f;
-    T* __restrict__ cv = kLds ? reinterpret_cast<T*>(smem_raw) : A + col;   // cv[i] = A[i, j]
+    const int64_t t = task0 + blockIdx.x;
+    const int64_t colbase = d.asm_col[t];
+    const int f = d.asm_fj[2 * t], j = d.asm_fj[2 * t + 1];
+    const int64_t e0 = d.asm_kr[2 * t], e1 = d.asm_kr[2 * t + 1];
+    const int64_t g0 = d.asm_seg_ptr[t], g1 = d.asm_seg_ptr[t + 1];
+    T* __restrict__ Acol = F + colbase;                      // Acol[i] = A[i, j]
+    T* __restrict__ cv = kLds ? reinterpret_cast<T*>(smem_raw) : Acol;
+    const int64_t jf = (int64_t)j * f;
     const int tid = threadIdx.x;
     for (int i = j + tid; i < f; i += 256) cv[i] = T(0);
     __syncthreads();
-    if (j < p) {
-        const int64_t* cp = d.kcol_ptr + d.kcol_base[s];
-        for (int64_t e = cp[j] + tid; e < cp[j + 1]; e += 256) cv[d.kent_pos[e] - col] = (T)K[d.kent_csr[e]];
-    }
+    for (int64_t e = e0 + tid; e < e1; e += 256) cv[d.kent_pos[e] - jf] = (T)K[d.kent_csr[e]];
     __syncthreads();
-    for (int k = d.child_ptr[s]; k < d.child_ptr[s + 1]; ++k) {
-        const int ch = d.child_list[k];
-        const int b = d.inv[d.inv_ptr[ch] + j];
-        if (b < 0) continue;   // uniform
-        const int fc = (int)(d.sn_rowptr[ch + 1] - d.sn_rowptr[ch]);
-        const int cc = fc - (d.sn_first[ch + 1] - d.sn_first[ch]);
-        const T* __restrict__ CB = F + d.CB_off[ch] + (int64_t)b * d.CB_ld[ch];
-        const int* __restrict__ r = d.rel + d.rel_ptr[ch];
+    for (int64_t g = g0; g < g1; ++g) {
+        const T* __restrict__ CB = F + d.asm_seg_cb[g];
+        const int* __restrict__ r = d.rel + d.asm_seg_rel[g];
+        const int b = d.asm_seg_bc[2 * g], cc = d.asm_seg_bc[2 * g + 1];
         for (int a0 = b + tid; a0 < cc; a0 += 256 * 4) {
             T v[4];
             int ri[4];
@@ -623,7 +621,7 @@ __global__ __launch_bounds__(256) void k_large_asm(DevPlan d, const int* __restr
         __syncthreads();
     }
     if (kLds)
-        for (int i = j + tid; i < f; i += 256) A[i + col] = cv[i];
+        for (int i = j + tid; i < f; i += 256) Acol[i] = cv[i];
 }
 
 // Writes the factored diagonal block of a panel (in LDS: L strictly below the
@@ -1688,14 +1686,13 @@ void launch_small_fronts(const DevPlan& d, const int* list, int count, int fmax,
 }
 
 template <typename T>
-void launch_large_asm(const DevPlan& d, const int* tasks, int count, int fmax, const double* K, T* F,
-                      hipStream_t st) {
+void launch_large_asm(const DevPlan& d, int64_t first, int count, int fmax, const double* K, T* F, hipStream_t st) {
     if (count <= 0) return;
     const size_t lds = (size_t)fmax * sizeof(T);
     if (lds <= kAsmLdsMax)
-        hipLaunchKernelGGL((k_large_asm<T, true>), dim3(count), dim3(256), lds, st, d, tasks, K, F);
+        hipLaunchKernelGGL((k_large_asm<T, true>), dim3(count), dim3(256), lds, st, d, first, K, F);
     else
-        hipLaunchKernelGGL((k_large_asm<T, false>), dim3(count), dim3(256), 0, st, d, tasks, K, F);
+        hipLaunchKernelGGL((k_large_asm<T, false>), dim3(count), dim3(256), 0, st, d, first, K, F);
 }
 
 template <typename T>
@@ -1846,7 +1843,7 @@ hipError_t configure_kernels(int max_dynamic_lds) {
 
 #define NCL_INSTANTIATE(T)                                                                                         \
     template void launch_small_fronts<T>(const DevPlan&, const int*, int, int, const double*, T*, T*, hipStream_t); \
-    template void launch_large_asm<T>(const DevPlan&, const int*, int, int, const double*, T*, hipStream_t);       \
+    template void launch_large_asm<T>(const DevPlan&, int64_t, int, int, const double*, T*, hipStream_t);          \
     template void launch_large_diag<T>(const DevPlan&, const int*, int, T*, T*, T*, hipStream_t);                \
     template void launch_large_panel<T>(const DevPlan&, const int*, int, T*, const T*, const T*, hipStream_t);     \
     template void launch_large_update<T>(const DevPlan&, const int*, int, T*, T*, T*, hipStream_t);              \

@@ -53,6 +53,14 @@ struct DevPlan {
     const int* CB_ld;
     const int64_t* U_off;      // in elements of one column block (times kNrhsMax applied)
     const int64_t* M_off;      // large fronts: offset of the per-panel inverses L_kk^-1 (64 x 64 each)
+    // large-front column assembly tasks (see Plan::asm_*)
+    const int64_t* asm_col;
+    const int* asm_fj;
+    const int64_t* asm_kr;
+    const int64_t* asm_seg_ptr;
+    const int64_t* asm_seg_cb;
+    const int64_t* asm_seg_rel;
+    const int* asm_seg_bc;
     // per system
     const double* sys_thr;     // static-pivot thresholds eps * ||K||_max
     unsigned long long* inertia;  // 4 per system: npos, nneg, nzero, nperturbed
@@ -76,8 +84,7 @@ template <typename T>
 void launch_small_fronts(const DevPlan& d, const int* list, int count, int fmax, const double* K, T* F, T* D,
                          hipStream_t st);
 template <typename T>
-void launch_large_asm(const DevPlan& d, const int* tasks, int count, int fmax, const double* K, T* F,
-                      hipStream_t st);
+void launch_large_asm(const DevPlan& d, int64_t first, int count, int fmax, const double* K, T* F, hipStream_t st);
 template <typename T>
 void launch_large_diag(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st);
 template <typename T>

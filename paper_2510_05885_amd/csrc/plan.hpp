@@ -132,6 +132,11 @@ struct Plan {
     std::vector<LargeStep> large_steps;
     // large-front tasks
     std::vector<int> large_asm;      // pairs (front, column)
+    // per large_asm task: column base in the factor buffer, (f, j), K-entry
+    // range, and its contribution segments (children whose CB has a column
+    // mapping to j): CB column offset, relative-index offset, (first row, rows)
+    std::vector<int64_t> asm_col, asm_kr, asm_seg_ptr, asm_seg_cb, asm_seg_rel;
+    std::vector<int> asm_fj, asm_seg_bc;
     std::vector<int> large_diag;     // pairs (front, k0): diagonal block update, factorization, inverse
     std::vector<int> large_panel;    // triples (front, k0, 32-row block start >= k0 + panel)
     std::vector<int> large_upd;      // quads (front, k0, tile row start, tile col start); the next
