@@ -26,15 +26,18 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "condensed-KKT factor+solve/s at n=500k, rel resid ≤1e-10: FP32+IR vs FP64"
-PEAK = {"hbm_GBs": 8000.0, "fp64_mfma_TFs": 78.6, "fp32_mfma_TFs": 157.3}
+# fp64 vector: 256 CUs x 64 FMA lanes x 2 flops x 2.4 GHz
+PEAK = {"hbm_GBs": 8000.0, "fp64_mfma_TFs": 78.6, "fp32_mfma_TFs": 157.3, "fp64_vector_TFs": 78.6}
 
-# HBM bytes per launch of the dominant kernel, from two rocprofv3 --pmc runs
-# (FETCH_SIZE, WRITE_SIZE in KiB per dispatch), each scaled by what the same
-# counter reads for a device copy of known size.  Valid only for the kernel
-# source it was taken on: reported as null once kernels.hip changes.
-TRAFFIC = {"class": "large_update_mfma", "kernels_sha1": "4258499040d14582ace5acebd9ba96bc9e34ee85",
-           "fetch_kib": 21823.6, "fetch_scale": 2.00, "write_kib": 20665.2, "write_scale": 1.00,
-           "source": "profiles/pmc_traffic_opf_n500k_fp64.txt"}
+# HBM bytes per launch of the large-front kernels, from two rocprofv3 --pmc
+# runs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch, mean over the dispatches
+# of a 2-step run), each scaled by what the same counter reads for a device
+# copy of known size.  Valid only for the kernel source they were taken on:
+# reported as null once kernels.hip changes.
+TRAFFIC = {"kernels_sha1": "3987f9551cc48e9a54ba7b05ab8989762362d2fa", "fetch_scale": 2.00, "write_scale": 1.00,
+           "source": "profiles/pmc_traffic_opf_n500k_fp64.txt",
+           "kib": {"large_diag": (613.8, 1176.7), "large_panel": (4014.8, 6448.2),
+                   "large_update_mfma": (13764.1, 19577.9)}}
 
 
 def measured_traffic(cls):
@@ -42,9 +45,10 @@ def measured_traffic(cls):
     src = os.path.join(ROOT, "paper_2510_05885_amd", "csrc", "kernels.hip")
     with open(src, "rb") as f:
         sha = hashlib.sha1(f.read()).hexdigest()
-    if cls != TRAFFIC["class"] or sha != TRAFFIC["kernels_sha1"]:
+    if cls not in TRAFFIC["kib"] or sha != TRAFFIC["kernels_sha1"]:
         return None
-    return 1024.0 * (TRAFFIC["fetch_kib"] * TRAFFIC["fetch_scale"] + TRAFFIC["write_kib"] * TRAFFIC["write_scale"])
+    fetch, write = TRAFFIC["kib"][cls]
+    return 1024.0 * (fetch * TRAFFIC["fetch_scale"] + write * TRAFFIC["write_scale"])
 
 
 def parse():
@@ -167,7 +171,8 @@ def main():
         roof = {"kernel": dom["kernel"], "bound": dom["bound"], "achieved": dom["achieved"],
                 "peak": dom["peak"], "unit": dom["unit"], "frac": dom["achieved"] / dom["peak"],
                 "traffic": measured_traffic(dom["class"]), "traffic_unit": "bytes/launch", "avg_launch_ms": dom["avg_launch_ms"], "launches_per_step": dom["launches_per_step"]}
-        fact_ms = sum(tm["ms"][k] for k in ("small_fronts", "large_assembly", "large_panel", "large_update_mfma"))
+        fact_ms = sum(tm["ms"][k] for k in ("small_fronts", "large_assembly", "large_panel", "large_update_mfma",
+                                            "large_diag"))
         roof["factor_total_TFs"] = stats["flops_factor"] * args.steps / 1e12 / (fact_ms * 1e-3)
 
     cpu = None
@@ -294,7 +299,10 @@ def kernel_breakdown(tm, stats, steps):
         "TFLOP/s", PEAK["fp64_mfma_TFs"])
     add("large_update_mfma", "k_large_update<double> (64x64 tiles, v_mfma_f64_16x16x4)", tm["update_flops"],
         "mfma", "TFLOP/s", PEAK["fp64_mfma_TFs"])
-    add("large_panel", "k_large_diag0 + k_large_panel<double> (diagonal block, TRSM)", None, "latency", "-", None)
+    add("large_diag", "k_large_diag<double> (diagonal block: tile update, LDL^T, inverse)", tm["diag_flops"],
+        "alu", "TFLOP/s", PEAK["fp64_vector_TFs"])
+    add("large_panel", "k_large_panel<double> (panel solve, v_mfma_f64_16x16x4)", tm["panel_flops"], "mfma",
+        "TFLOP/s", PEAK["fp64_mfma_TFs"])
     add("large_assembly", "k_large_asm<double> (front assembly, extend-add)", None, "hbm", "GB/s", PEAK["hbm_GBs"])
     add("solve_sweeps", "k_fwd_T/G + k_bwd_G/T<double> (panel sweeps)", tm["solve_bytes"], "hbm", "GB/s",
         PEAK["hbm_GBs"])

@@ -120,26 +120,37 @@ T* upload(ncl_kkt_s* h, const std::vector<T>& v) {
 }
 
 // ----- timing helpers ------------------------------------------------------
-enum { TM_ASM = 0, TM_SMALL = 1, TM_LASM = 2, TM_PANEL = 3, TM_UPD = 4, TM_SOLVE = 5, TM_RES = 6, TM_OTHER = 7 };
+enum { TM_ASM = 0, TM_SMALL = 1, TM_LASM = 2, TM_PANEL = 3, TM_UPD = 4, TM_SOLVE = 5, TM_RES = 6, TM_DIAG = 7 };
 
-struct Span {
+// While a Span is alive (timing enabled), every kernel launched on this
+// thread gets its own event pair (the kernel's begin/end timestamps) and
+// counts as one launch of class `cls`; the Span's algorithmic work is booked
+// once, with its first launch.
+struct Span : LaunchTimer {
     ncl_kkt_s* h;
-    hipStream_t st;
     int cls;
-    size_t a = 0;
     double work;
-    int kind;  // 0 none, 1 update flops, 2 small flops, 3 assembly bytes, 4 solve bytes
-    Span(ncl_kkt_s* h_, hipStream_t s_, int c, double w = 0.0, int k = 0) : h(h_), st(s_), cls(c), work(w), kind(k) {
+    int kind;  // 0 none, 1 update flops, 2 small flops, 3 assembly bytes, 4 solve bytes,
+               // 5 panel-solve flops, 6 diagonal-block flops
+    LaunchTimer* prev = nullptr;
+    bool installed = false;
+    Span(ncl_kkt_s* h_, hipStream_t, int c, double w = 0.0, int k = 0) : h(h_), cls(c), work(w), kind(k) {
         if (!h->tm.on) return;
-        if (h->tm.used + 2 > h->tm.pool.size()) { h->tm.on = false; return; }
-        a = h->tm.used++;
-        HIPCHK(hipEventRecord(h->tm.pool[a], st));
+        prev = set_launch_timer(this);
+        installed = true;
     }
-    ~Span() noexcept(false) {
-        if (!h->tm.on) return;
-        size_t b = h->tm.used++;
-        HIPCHK(hipEventRecord(h->tm.pool[b], st));
+    ~Span() override {
+        if (installed) set_launch_timer(prev);
+    }
+    bool take(hipEvent_t* e0, hipEvent_t* e1) override {
+        if (!h->tm.on) return false;
+        if (h->tm.used + 2 > h->tm.pool.size()) { h->tm.on = false; return false; }
+        const size_t a = h->tm.used++, b = h->tm.used++;
+        *e0 = h->tm.pool[a];
+        *e1 = h->tm.pool[b];
         h->tm.recs.push_back({cls, a, b, work, kind});
+        work = 0.0;
+        return true;
     }
 };
 
@@ -155,6 +166,8 @@ void flush_timing(ncl_kkt_s* h) {
         if (r.kind == 2) h->tm.tot.small_flops += r.work;
         if (r.kind == 3) h->tm.tot.assemble_bytes += r.work;
         if (r.kind == 4) h->tm.tot.solve_bytes += r.work;
+        if (r.kind == 5) h->tm.tot.panel_flops += r.work;
+        if (r.kind == 6) h->tm.tot.diag_flops += r.work;
     }
     h->tm.recs.clear();
     h->tm.used = 0;
@@ -367,6 +380,30 @@ int do_analyze(ncl_kkt_t* out, const ncl_kkt_options* o, const std::vector<SysIn
 }
 
 // ----- numeric factorization -----------------------------------------------
+// Algorithmic flops of one step's diagonal-block and panel-solve launches
+// (w = panel width): w^3/3 for the LDL^T and w^3/3 for the inverse of each
+// block, plus w_prev * w^2 for the block's own update after the first panel;
+// rows-below x w^2 for the panel solve.
+double diag_flops(const Plan& P, const LargeStep& ls, size_t k) {
+    double fl = 0.0;
+    for (int64_t t = ls.diag_first[k]; t < ls.diag_first[k] + ls.diag_count[k]; ++t) {
+        const int s = P.large_diag[2 * t], k0 = P.large_diag[2 * t + 1];
+        const double w = std::min(kPanel, P.sn_first[s + 1] - P.sn_first[s] - k0);
+        fl += 2.0 * w * w * w / 3.0 + (k0 > 0 ? (double)kPanel * w * w : 0.0);
+    }
+    return fl;
+}
+double panel_flops(const Plan& P, const LargeStep& ls, size_t k) {
+    double fl = 0.0;
+    for (int64_t t = ls.panel_first[k]; t < ls.panel_first[k] + ls.panel_count[k]; ++t) {
+        const int s = P.large_panel[3 * t], k0 = P.large_panel[3 * t + 1], r0 = P.large_panel[3 * t + 2];
+        const int f = (int)(P.sn_rowptr[s + 1] - P.sn_rowptr[s]);
+        const double w = std::min(kPanel, P.sn_first[s + 1] - P.sn_first[s] - k0);
+        fl += (double)std::min(32, f - r0) * w * w;
+    }
+    return fl;
+}
+
 template <typename T>
 void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
     Plan& P = h->P;
@@ -409,12 +446,12 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
             // third stream; both finish before the next panel.
             const size_t nsteps = ls.panel_first.size();
             {
-                Span sp(h, st, TM_PANEL);
+                Span sp(h, st, TM_DIAG, h->tm.on ? diag_flops(P, ls, 0) : 0.0, 6);
                 launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[0], (int)ls.diag_count[0], F, D, Mb, st);
             }
             for (size_t k = 0; k < nsteps; ++k) {
                 {
-                    Span sp(h, st, TM_PANEL);
+                    Span sp(h, st, TM_PANEL, h->tm.on ? panel_flops(P, ls, k) : 0.0, 5);
                     launch_large_panel<T>(d, h->large_panel + 3 * ls.panel_first[k], (int)ls.panel_count[k], F, D,
                                           Mb, st);
                 }
@@ -423,7 +460,7 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
                     HIPCHK(hipEventRecord(h->diag_ev[0], st));
                     HIPCHK(hipStreamWaitEvent(h->diag_stream, h->diag_ev[0], 0));
                     {
-                        Span sp(h, h->diag_stream, TM_PANEL);
+                        Span sp(h, h->diag_stream, TM_DIAG, h->tm.on ? diag_flops(P, ls, k + 1) : 0.0, 6);
                         launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[k + 1], (int)ls.diag_count[k + 1], F,
                                              D, Mb, h->diag_stream);
                     }

@@ -19,6 +19,7 @@
 //              backward sweep; right-hand sides chunked through LDS.
 //   refinement residual b - K x with per-system max norms.
 // All reductions are deterministic; integer atomics only count inertia.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -1653,24 +1654,48 @@ __global__ __launch_bounds__(256) void k_grad_rho(const int64_t* __restrict__ sy
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+namespace {
+thread_local LaunchTimer* tl_timer = nullptr;
+
+template <typename X> struct same_t { using type = X; };
+
+// Every launch goes through here: plain hipLaunchKernelGGL, or the extended
+// launch with the installed timer's events.
+template <typename... KArgs>
+void launch(void (*k)(KArgs...), dim3 grid, dim3 block, uint32_t lds, hipStream_t st,
+            typename same_t<KArgs>::type... args) {
+    hipEvent_t e0, e1;
+    if (tl_timer && tl_timer->take(&e0, &e1))
+        hipExtLaunchKernelGGL(k, grid, block, lds, st, e0, e1, 0, args...);
+    else
+        hipLaunchKernelGGL(k, grid, block, lds, st, args...);
+}
+}  // namespace
+
+LaunchTimer* set_launch_timer(LaunchTimer* t) {
+    LaunchTimer* old = tl_timer;
+    tl_timer = t;
+    return old;
+}
+
 void launch_assemble(const DevPlan& d, int64_t nnzF, const double* W, const double* Sigma, const double* J,
                      const double* sys_rho, double* K, hipStream_t st) {
     if (nnzF <= 0) return;
-    hipLaunchKernelGGL(k_assemble, dim3(blocks_for(nnzF, 256)), dim3(256), 0, st, d, nnzF, W, Sigma, J, sys_rho, K);
+    launch(k_assemble, dim3(blocks_for(nnzF, 256)), dim3(256), 0, st, d, nnzF, W, Sigma, J, sys_rho, K);
 }
 
 void launch_chunk_norms(const DevPlan& d, const double* K, const int* chunk_row0, const int* chunk_rows, int nchunks,
                         double* partial, hipStream_t st) {
-    hipLaunchKernelGGL(k_chunk_norms, dim3(nchunks), dim3(256), 0, st, d, K, chunk_row0, chunk_rows, partial);
+    launch(k_chunk_norms, dim3(nchunks), dim3(256), 0, st, d, K, chunk_row0, chunk_rows, partial);
 }
 
 void launch_reduce(const int* sys_chunk_ptr, int S, int width, const double* partial, double* out, hipStream_t st) {
-    hipLaunchKernelGGL(k_reduce_partials, dim3(S, width), dim3(256), 0, st, sys_chunk_ptr, width, partial, out);
+    launch(k_reduce_partials, dim3(S, width), dim3(256), 0, st, sys_chunk_ptr, width, partial, out);
 }
 
 void launch_thresholds(int S, const double* norms2, double eps, double* kmax, double* kinf, double* thr,
                        int* nonfinite, hipStream_t st) {
-    hipLaunchKernelGGL(k_thresholds, dim3(blocks_for(S, 64)), dim3(64), 0, st, S, norms2, eps, kmax, kinf, thr,
+    launch(k_thresholds, dim3(blocks_for(S, 64)), dim3(64), 0, st, S, norms2, eps, kmax, kinf, thr,
                        nonfinite);
 }
 
@@ -1680,9 +1705,9 @@ void launch_small_fronts(const DevPlan& d, const int* list, int count, int fmax,
     if (count <= 0) return;
     const size_t lds = (size_t)fmax * fmax * sizeof(T);
     if (fmax <= 64)
-        hipLaunchKernelGGL((k_small_fronts<T, false>), dim3(count), dim3(256), lds, st, d, list, K, F, D);
+        launch(k_small_fronts<T, false>, dim3(count), dim3(256), lds, st, d, list, K, F, D);
     else
-        hipLaunchKernelGGL((k_small_fronts<T, true>), dim3(count), dim3(256), lds, st, d, list, K, F, D);
+        launch(k_small_fronts<T, true>, dim3(count), dim3(256), lds, st, d, list, K, F, D);
 }
 
 template <typename T>
@@ -1690,38 +1715,38 @@ void launch_large_asm(const DevPlan& d, int64_t first, int count, int fmax, cons
     if (count <= 0) return;
     const size_t lds = (size_t)fmax * sizeof(T);
     if (lds <= kAsmLdsMax)
-        hipLaunchKernelGGL((k_large_asm<T, true>), dim3(count), dim3(256), lds, st, d, first, K, F);
+        launch(k_large_asm<T, true>, dim3(count), dim3(256), lds, st, d, first, K, F);
     else
-        hipLaunchKernelGGL((k_large_asm<T, false>), dim3(count), dim3(256), 0, st, d, first, K, F);
+        launch(k_large_asm<T, false>, dim3(count), dim3(256), 0, st, d, first, K, F);
 }
 
 template <typename T>
 void launch_large_diag(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_large_diag<T>, dim3(count), dim3(256), 0, st, d, tasks, F, D, M);
+    launch(k_large_diag<T>, dim3(count), dim3(256), 0, st, d, tasks, F, D, M);
 }
 
 template <typename T>
 void launch_large_panel(const DevPlan& d, const int* tasks, int count, T* F, const T* D, const T* M, hipStream_t st) {
     if (count <= 0) return;
-    hipLaunchKernelGGL(k_large_panel<T>, dim3(count), dim3(256), 0, st, d, tasks, F, D, M);
+    launch(k_large_panel<T>, dim3(count), dim3(256), 0, st, d, tasks, F, D, M);
 }
 
 template <typename T>
 void launch_large_update(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st) {
     if (count <= 0) return;
     (void)M;
-    hipLaunchKernelGGL(k_large_update<T>, dim3(count), dim3(256), 0, st, d, tasks, F, (const T*)D);
+    launch(k_large_update<T>, dim3(count), dim3(256), 0, st, d, tasks, F, (const T*)D);
 }
 
 template <typename T>
 void launch_permute_in(const DevPlan& d, const double* B, int64_t ldb, int nrhs, T* Y, hipStream_t st) {
-    hipLaunchKernelGGL(k_permute_in<T>, dim3(blocks_for(d.N, 256)), dim3(256), 0, st, d, B, ldb, nrhs, Y);
+    launch(k_permute_in<T>, dim3(blocks_for(d.N, 256)), dim3(256), 0, st, d, B, ldb, nrhs, Y);
 }
 
 template <typename T>
 void launch_permute_out(const DevPlan& d, const T* Y, int nrhs, double* X, int64_t ldx, hipStream_t st) {
-    hipLaunchKernelGGL(k_permute_out<T>, dim3(blocks_for(d.N, 256)), dim3(256), 0, st, d, Y, nrhs, X, ldx);
+    launch(k_permute_out<T>, dim3(blocks_for(d.N, 256)), dim3(256), 0, st, d, Y, nrhs, X, ldx);
 }
 
 template <typename T>
@@ -1729,14 +1754,14 @@ void launch_fwd_T(const DevPlan& d, const int* tasks, int count, const T* F, con
                   hipStream_t st) {
     if (count <= 0) return;
     const size_t lds = (size_t)(kSolvePanel * nrhs + 256 * nrhs + 64 * 65) * sizeof(T);
-    hipLaunchKernelGGL(k_fwd_T<T>, dim3(count), dim3(256), lds, st, d, tasks, F, Z, Y, U, nrhs);
+    launch(k_fwd_T<T>, dim3(count), dim3(256), lds, st, d, tasks, F, Z, Y, U, nrhs);
 }
 
 template <typename T>
 void launch_fwd_S(const DevPlan& d, const int* fronts, int count, const T* F, T* Y, T* U, int nrhs, hipStream_t st) {
     if (count <= 0) return;
     const size_t lds = (size_t)4 * kSmallRows * nrhs * sizeof(T);
-    hipLaunchKernelGGL(k_fwd_S<T>, dim3((count + 3) / 4), dim3(256), lds, st, d, fronts, count, F, Y, U, nrhs);
+    launch(k_fwd_S<T>, dim3((count + 3) / 4), dim3(256), lds, st, d, fronts, count, F, Y, U, nrhs);
 }
 
 template <typename T>
@@ -1744,14 +1769,14 @@ void launch_bwd_S(const DevPlan& d, const int* fronts, int count, const T* F, co
                   hipStream_t st) {
     if (count <= 0) return;
     const size_t lds = (size_t)4 * kSmallRows * nrhs * sizeof(T);
-    hipLaunchKernelGGL(k_bwd_S<T>, dim3((count + 3) / 4), dim3(256), lds, st, d, fronts, count, F, D, Y, nrhs);
+    launch(k_bwd_S<T>, dim3((count + 3) / 4), dim3(256), lds, st, d, fronts, count, F, D, Y, nrhs);
 }
 
 template <typename T>
 void launch_fwd_G(const DevPlan& d, const int* tasks, int count, const T* F, T* Y, T* U, int nrhs, hipStream_t st) {
     if (count <= 0) return;
     const size_t lds = (size_t)(kSolvePanel + 256) * nrhs * sizeof(T);
-    hipLaunchKernelGGL(k_fwd_G<T>, dim3(count), dim3(256), lds, st, d, tasks, F, Y, U, nrhs);
+    launch(k_fwd_G<T>, dim3(count), dim3(256), lds, st, d, tasks, F, Y, U, nrhs);
 }
 
 template <typename T>
@@ -1759,7 +1784,7 @@ void launch_bwd_G(const DevPlan& d, const int* tasks, int count, const T* F, con
                   hipStream_t st) {
     if (count <= 0) return;
     const size_t lds = (size_t)kSolveChunk * nrhs * sizeof(T);
-    hipLaunchKernelGGL(k_bwd_G<T>, dim3(count), dim3(256), lds, st, d, tasks, F, Y, partial, nrhs);
+    launch(k_bwd_G<T>, dim3(count), dim3(256), lds, st, d, tasks, F, Y, partial, nrhs);
 }
 
 template <typename T>
@@ -1767,13 +1792,13 @@ void launch_bwd_T(const DevPlan& d, const int* tasks, int count, const T* F, con
                   const T* partial, int nrhs, hipStream_t st) {
     if (count <= 0) return;
     const size_t lds = (size_t)(kSolvePanel * nrhs + kSolveChunk * nrhs + 64 * 65) * sizeof(T);
-    hipLaunchKernelGGL(k_bwd_T<T>, dim3(count), dim3(256), lds, st, d, tasks, F, Z, D, Y, partial, nrhs);
+    launch(k_bwd_T<T>, dim3(count), dim3(256), lds, st, d, tasks, F, Z, D, Y, partial, nrhs);
 }
 
 void launch_residual(const DevPlan& d, const double* K, const double* B, int64_t ldb, const double* X, int64_t ldx,
                      double* R, int nrhs, const int* chunk_row0, const int* chunk_rows, int nchunks, double* partial,
                      hipStream_t st) {
-    hipLaunchKernelGGL(k_residual, dim3(nchunks), dim3(256), 0, st, d, K, B, ldb, X, ldx, R, nrhs, chunk_row0,
+    launch(k_residual, dim3(nchunks), dim3(256), 0, st, d, K, B, ldb, X, ldx, R, nrhs, chunk_row0,
                        chunk_rows, partial);
 }
 
@@ -1783,19 +1808,19 @@ void launch_reduce_partials(const int* sys_chunk_ptr, int S, int width, const do
 }
 
 void launch_axpy_cols(double* X, int64_t ldx, const double* DX, int64_t N, int nrhs, hipStream_t st) {
-    hipLaunchKernelGGL(k_axpy_cols, dim3(blocks_for(N, 256)), dim3(256), 0, st, X, ldx, DX, N, nrhs);
+    launch(k_axpy_cols, dim3(blocks_for(N, 256)), dim3(256), 0, st, X, ldx, DX, N, nrhs);
 }
 
 void launch_copy_cols(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t N, int nrhs, hipStream_t st) {
-    hipLaunchKernelGGL(k_copy_cols, dim3(blocks_for(N, 256)), dim3(256), 0, st, dst, ldd, src, lds, N, nrhs);
+    launch(k_copy_cols, dim3(blocks_for(N, 256)), dim3(256), 0, st, dst, ldd, src, lds, N, nrhs);
 }
 
 void launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st) {
-    if (n > 0) hipLaunchKernelGGL(k_zero_u64, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n);
+    if (n > 0) launch(k_zero_u64, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n);
 }
 
 void launch_zero_i32(int* p, int64_t n, hipStream_t st) {
-    if (n > 0) hipLaunchKernelGGL(k_zero_i32, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n);
+    if (n > 0) launch(k_zero_i32, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n);
 }
 
 void launch_adjoint(const DevPlan& d, int64_t nnzW, const int* W_row, const int* W_col, int64_t nJrows,
@@ -1803,18 +1828,18 @@ void launch_adjoint(const DevPlan& d, int64_t nnzW, const int* W_row, const int*
                     const double* X, const double* Lam, int64_t ld, int nrhs, double* gW, double* gSigma,
                     double* gJ, double* gRho, double* JX, double* JL, const int64_t* sys_jrow, hipStream_t st) {
     if (nJrows > 0)
-        hipLaunchKernelGGL(k_jmul, dim3(blocks_for(nJrows, 256)), dim3(256), 0, st, nJrows, Jp, Jj, Jval, X, Lam, ld,
+        launch(k_jmul, dim3(blocks_for(nJrows, 256)), dim3(256), 0, st, nJrows, Jp, Jj, Jval, X, Lam, ld,
                            nrhs, JX, JL);
     if (gW && nnzW > 0)
-        hipLaunchKernelGGL(k_grad_W, dim3(blocks_for(nnzW, 256)), dim3(256), 0, st, nnzW, W_row, W_col, X, Lam, ld,
+        launch(k_grad_W, dim3(blocks_for(nnzW, 256)), dim3(256), 0, st, nnzW, W_row, W_col, X, Lam, ld,
                            nrhs, gW);
     if (gSigma)
-        hipLaunchKernelGGL(k_grad_S, dim3(blocks_for(d.N, 256)), dim3(256), 0, st, d.N, X, Lam, ld, nrhs, gSigma);
+        launch(k_grad_S, dim3(blocks_for(d.N, 256)), dim3(256), 0, st, d.N, X, Lam, ld, nrhs, gSigma);
     if (gJ && nJrows > 0)
-        hipLaunchKernelGGL(k_grad_J, dim3(blocks_for(nJrows, 256)), dim3(256), 0, st, nJrows, Jp, Jj, Jrow_sys,
+        launch(k_grad_J, dim3(blocks_for(nJrows, 256)), dim3(256), 0, st, nJrows, Jp, Jj, Jrow_sys,
                            sys_rho, X, Lam, ld, nrhs, JX, JL, gJ);
     if (gRho)
-        hipLaunchKernelGGL(k_grad_rho, dim3(d.S), dim3(256), 0, st, sys_jrow, nJrows, nrhs, JX, JL, gRho);
+        launch(k_grad_rho, dim3(d.S), dim3(256), 0, st, sys_jrow, nJrows, nrhs, JX, JL, gRho);
 }
 
 // Allow the LDS-resident kernels to request more than 64 KiB of dynamic LDS

@@ -68,6 +68,16 @@ struct DevPlan {
 };
 
 // ---- assembly (FP64) ------------------------------------------------------
+// Optional per-launch timing.  While a LaunchTimer is installed on the
+// calling thread, every kernel launch asks it for a start/stop event pair and,
+// when given one, is launched with hipExtLaunchKernel, whose events carry the
+// kernel's own begin and end timestamps (no launch gaps in the figure).
+struct LaunchTimer {
+    virtual bool take(hipEvent_t* start, hipEvent_t* stop) = 0;
+    virtual ~LaunchTimer() = default;
+};
+LaunchTimer* set_launch_timer(LaunchTimer* t);   // returns the previous one
+
 void launch_assemble(const DevPlan& d, int64_t nnzF, const double* W, const double* Sigma, const double* J,
                      const double* sys_rho, double* K, hipStream_t st);
 // Block per chunk of rows: partial[2c] = max |K_ij|, partial[2c+1] = max row sum of |K|.

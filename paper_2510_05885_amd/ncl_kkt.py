@@ -55,16 +55,18 @@ class Stats(C.Structure):
 
 class Timing(C.Structure):
     _fields_ = [("ms", C.c_double * 8), ("launches", C.c_int64 * 8), ("update_flops", C.c_double),
-                ("small_flops", C.c_double), ("assemble_bytes", C.c_double), ("solve_bytes", C.c_double)]
+                ("small_flops", C.c_double), ("assemble_bytes", C.c_double), ("solve_bytes", C.c_double),
+                ("panel_flops", C.c_double), ("diag_flops", C.c_double)]
 
     CLASSES = ("assemble", "small_fronts", "large_assembly", "large_panel", "large_update_mfma",
-               "solve_sweeps", "residual", "other")
+               "solve_sweeps", "residual", "large_diag")
 
     def as_dict(self):
         return {"ms": {k: self.ms[i] for i, k in enumerate(self.CLASSES)},
                 "launches": {k: int(self.launches[i]) for i, k in enumerate(self.CLASSES)},
                 "update_flops": self.update_flops, "small_flops": self.small_flops,
-                "assemble_bytes": self.assemble_bytes, "solve_bytes": self.solve_bytes}
+                "assemble_bytes": self.assemble_bytes, "solve_bytes": self.solve_bytes,
+                "panel_flops": self.panel_flops, "diag_flops": self.diag_flops}
 
 
 _lib = None

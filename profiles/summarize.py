@@ -3,6 +3,9 @@
   python profiles/summarize.py kernels DB          per-kernel calls / total ms / avg us
   python profiles/summarize.py pmc DB COUNTER REGEX  per-dispatch counter values of the
                                                      kernels matching REGEX (mean, sum)
+  python profiles/summarize.py split DB REGEX N       average duration of the kernels matching
+                                                     REGEX over N equal consecutive phases of
+                                                     the run (e.g. warmup / timed / evented)
 """
 import re
 import sqlite3
@@ -41,9 +44,25 @@ def pmc(db, counter, regex):
         print(f"{k:60s} {counter} dispatches={len(v):6d} mean={sum(v)/len(v):14.1f} sum={sum(v):16.1f}")
 
 
+def split(db, regex, nphase):
+    con = sqlite3.connect(db)
+    rows = con.execute("select name, start, end-start from kernels order by start").fetchall()
+    by = {}
+    for name, _, dur in rows:
+        if re.search(regex, name):
+            key = name.replace("ncl::(anonymous namespace)::", "").split("(")[0]
+            by.setdefault(key, []).append(dur / 1e3)
+    for k, v in sorted(by.items()):
+        per = len(v) // nphase
+        parts = [sum(v[i * per:(i + 1) * per]) / per for i in range(nphase)] if per else []
+        print(f"{k:40s} calls={len(v):6d} avg_us per phase: " + " ".join(f"{x:8.2f}" for x in parts))
+
+
 if __name__ == "__main__":
     if sys.argv[1] == "kernels":
         kernels(sys.argv[2])
+    elif sys.argv[1] == "split":
+        split(sys.argv[2], sys.argv[3], int(sys.argv[4]))
     elif sys.argv[1] == "pmc":
         pmc(sys.argv[2], sys.argv[3], sys.argv[4])
     else:
