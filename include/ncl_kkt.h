@@ -53,7 +53,8 @@ enum { NCL_ORDER_ND = 0, NCL_ORDER_NATURAL = 1, NCL_ORDER_USER = 2 };
 #define NCL_ERR_ARG (-1)        /* bad argument (sizes, null pointers, rho <= 0, ...) */
 #define NCL_ERR_PATTERN (-2)    /* unsorted / duplicate / out-of-range / upper-triangle index */
 #define NCL_ERR_ALLOC (-3)      /* host or device allocation failed */
-#define NCL_ERR_HIP (-4)        /* a HIP runtime call failed */
+#define NCL_ERR_HIP (-4)        /* a HIP runtime call failed, or a device-side wait of the
+                                   dataflow factorization timed out */
 #define NCL_ERR_STATE (-5)      /* call out of order (solve before factor, ...) */
 #define NCL_ERR_NONFINITE (-6)  /* NaN or Inf met in the assembled matrix or a pivot */
 #define NCL_WARN_INERTIA 1      /* factor done, inertia differs from (n,0,0) / (n,m,0) */
@@ -84,6 +85,14 @@ typedef struct {
                                 in FP64 directly; a factor with max rho < r tries FP32 again
                                 (rho grows along an NCL outer loop, Algorithm 1).  0: always
                                 try FP32 first. */
+    int32_t large_flow;      /* 0 (default): per level, one launch per task kind and panel step
+                                (diagonal blocks on a second stream beside the tile updates).
+                                1: the large fronts of a level are factored by one dataflow
+                                launch whose diagonal-block, panel-solve and tile-update tasks
+                                wait on device counters instead of launch boundaries.  Same
+                                results bit for bit; which is faster depends on the tree (the
+                                dataflow launch shortens single-front chains but loses L2
+                                reuse on levels with many fronts). */
 } ncl_kkt_options;
 
 /* Result of one solve (normwise backward error
@@ -196,6 +205,18 @@ int ncl_kkt_get_perm(ncl_kkt_t h, int32_t *perm);
  * Pass NULL for rows to query only row_ptr. */
 int ncl_kkt_get_supernodes(ncl_kkt_t h, int32_t *first, int32_t *parent, int64_t *row_ptr,
                            int32_t *rows);
+
+/* Schedule of the dataflow large-front launches (options.large_flow), for
+ * inspection.  counts[0..2] = tasks, dependencies, counters; counts[3] =
+ * launches (levels with large fronts).  Each task is 8 int32: type (0
+ * diagonal block, 1 panel solve, 2 tile update), supernode, k0, a, b (panel:
+ * a = first row; update: a, b = tile row, column), first dependency, number of
+ * dependencies, counter signalled (-1: none).  A dependency is (counter,
+ * target): the task starts once the counter has reached the target.  Each
+ * launch is 4 int64: first task, task count, ticket counter, workgroups.
+ * Rows and columns are local to the front.  Pass NULL arrays to query only
+ * the counts. */
+int ncl_kkt_get_flow(ncl_kkt_t h, int64_t *counts, int32_t *tasks, int32_t *deps, int64_t *launches);
 
 /* Kernel timing.  When enabled, factor and solve record HIP events around
  * every kernel class on the caller's stream and accumulate device time (ms)

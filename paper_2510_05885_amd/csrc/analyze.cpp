@@ -765,6 +765,7 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                 st.upd_count.push_back((int64_t)P.large_upd.size() / 4 - st.upd_first.back());
                 st.upd_flops.push_back(fl);
             }
+            build_flow(P, st, large, cfg.flow_workers);
             P.large_steps.push_back(std::move(st));
         }
         // ---------------- solve schedule -----------------------------------

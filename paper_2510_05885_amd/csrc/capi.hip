@@ -62,6 +62,7 @@ struct ncl_kkt_s {
     // schedule arrays (device)
     int *small_list = nullptr, *level_list = nullptr, *large_asm = nullptr, *large_panel = nullptr,
         *large_upd = nullptr, *large_diag = nullptr, *solve_t = nullptr, *solve_g = nullptr, *solve_s = nullptr;
+    int *flow_task = nullptr, *flow_dep = nullptr, *flow_ctr = nullptr;
     int *chunk_row0 = nullptr, *chunk_rows = nullptr, *sys_chunk_ptr = nullptr;
     int nchunks = 0;
     // numeric state
@@ -235,6 +236,9 @@ void setup_device(ncl_kkt_s* h) {
     h->solve_s = upload(h, P.solve_s);
     h->large_panel = upload(h, P.large_panel);
     h->large_upd = upload(h, P.large_upd);
+    h->flow_task = upload(h, P.flow_task);
+    h->flow_dep = upload(h, P.flow_dep);
+    h->flow_ctr = dalloc<int>(h, P.flow_nctr);
     // row chunks (<= 256 rows, never straddling two systems)
     std::vector<int> c0, cn, scp(1, 0);
     for (int s = 0; s < P.S; ++s) {
@@ -333,6 +337,7 @@ void fill_defaults(ncl_kkt_options* o) {
     o->small_front_max = 0;
     o->relax_big_zeros = -1.0;
     o->fp32_sticky = 1;
+    o->large_flow = 0;
 }
 
 int do_analyze(ncl_kkt_t* out, const ncl_kkt_options* o, const std::vector<SysInput>& sys, bool host_only) {
@@ -409,6 +414,8 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
     Plan& P = h->P;
     const DevPlan& d = h->d;
     launch_zero_u64(h->inertia, 4 * (int64_t)P.S, st);
+    const bool flow = h->opt.large_flow != 0;
+    if (flow) launch_zero_i32(h->flow_ctr, P.flow_nctr, st);
     size_t sb = 0, lb = 0;
     for (int l = 0; l < P.nlevels; ++l) {
         // Fronts of one level are independent: when the level has both kinds,
@@ -441,36 +448,42 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
                 Span sp(h, st, TM_LASM);
                 launch_large_asm<T>(d, ls.asm_first, (int)ls.asm_count, ls.asm_fmax, h->K, F, st);
             }
-            // Step k: panel TRSM, then the trailing update beside the next
-            // panel's diagonal block (which updates that block itself) on a
-            // third stream; both finish before the next panel.
-            const size_t nsteps = ls.panel_first.size();
-            {
-                Span sp(h, st, TM_DIAG, h->tm.on ? diag_flops(P, ls, 0) : 0.0, 6);
-                launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[0], (int)ls.diag_count[0], F, D, Mb, st);
-            }
-            for (size_t k = 0; k < nsteps; ++k) {
+            if (flow) {
+                Span sp(h, st, TM_UPD, ls.flow_flops, 1);
+                launch_large_flow<T>(d, h->flow_task + 8 * ls.flow_first, (int)ls.flow_count, h->flow_dep,
+                                     h->flow_ctr, (int)ls.flow_ticket, ls.flow_grid, F, D, Mb, st);
+            } else {
+                // Step k: panel TRSM, then the trailing update beside the next
+                // panel's diagonal block (which updates that block itself) on a
+                // third stream; both finish before the next panel.
+                const size_t nsteps = ls.panel_first.size();
                 {
-                    Span sp(h, st, TM_PANEL, h->tm.on ? panel_flops(P, ls, k) : 0.0, 5);
-                    launch_large_panel<T>(d, h->large_panel + 3 * ls.panel_first[k], (int)ls.panel_count[k], F, D,
-                                          Mb, st);
+                    Span sp(h, st, TM_DIAG, h->tm.on ? diag_flops(P, ls, 0) : 0.0, 6);
+                    launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[0], (int)ls.diag_count[0], F, D, Mb, st);
                 }
-                const bool next = k + 1 < nsteps && ls.diag_count[k + 1] > 0;
-                if (next) {
-                    HIPCHK(hipEventRecord(h->diag_ev[0], st));
-                    HIPCHK(hipStreamWaitEvent(h->diag_stream, h->diag_ev[0], 0));
+                for (size_t k = 0; k < nsteps; ++k) {
                     {
-                        Span sp(h, h->diag_stream, TM_DIAG, h->tm.on ? diag_flops(P, ls, k + 1) : 0.0, 6);
-                        launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[k + 1], (int)ls.diag_count[k + 1], F,
-                                             D, Mb, h->diag_stream);
+                        Span sp(h, st, TM_PANEL, h->tm.on ? panel_flops(P, ls, k) : 0.0, 5);
+                        launch_large_panel<T>(d, h->large_panel + 3 * ls.panel_first[k], (int)ls.panel_count[k], F, D,
+                                              Mb, st);
                     }
-                    HIPCHK(hipEventRecord(h->diag_ev[1], h->diag_stream));
+                    const bool next = k + 1 < nsteps && ls.diag_count[k + 1] > 0;
+                    if (next) {
+                        HIPCHK(hipEventRecord(h->diag_ev[0], st));
+                        HIPCHK(hipStreamWaitEvent(h->diag_stream, h->diag_ev[0], 0));
+                        {
+                            Span sp(h, h->diag_stream, TM_DIAG, h->tm.on ? diag_flops(P, ls, k + 1) : 0.0, 6);
+                            launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[k + 1], (int)ls.diag_count[k + 1], F,
+                                                 D, Mb, h->diag_stream);
+                        }
+                        HIPCHK(hipEventRecord(h->diag_ev[1], h->diag_stream));
+                    }
+                    {
+                        Span sp(h, st, TM_UPD, ls.upd_flops[k], 1);
+                        launch_large_update<T>(d, h->large_upd + 4 * ls.upd_first[k], (int)ls.upd_count[k], F, D, Mb, st);
+                    }
+                    if (next) HIPCHK(hipStreamWaitEvent(st, h->diag_ev[1], 0));
                 }
-                {
-                    Span sp(h, st, TM_UPD, ls.upd_flops[k], 1);
-                    launch_large_update<T>(d, h->large_upd + 4 * ls.upd_first[k], (int)ls.upd_count[k], F, D, Mb, st);
-                }
-                if (next) HIPCHK(hipStreamWaitEvent(st, h->diag_ev[1], 0));
             }
         }
         if (fork) {
@@ -522,6 +535,7 @@ int read_inertia(ncl_kkt_s* h, hipStream_t st) {
         if (h->h_inertia[4 * s + 0] != n || h->h_inertia[4 * s + 1] != want_neg || h->h_inertia[4 * s + 2] != 0)
             h->inertia_ok = false;
     }
+    if (nonfin & 2) return NCL_ERR_HIP;   // a dataflow wait timed out
     if (nonfin) return NCL_ERR_NONFINITE;
     return NCL_OK;
 }
@@ -913,6 +927,26 @@ int ncl_kkt_get_supernodes(ncl_kkt_t h, int32_t* first, int32_t* parent, int64_t
     if (parent) std::memcpy(parent, P.sn_parent.data(), sizeof(int32_t) * P.sn_parent.size());
     if (row_ptr) std::memcpy(row_ptr, P.sn_rowptr.data(), sizeof(int64_t) * P.sn_rowptr.size());
     if (rows) std::memcpy(rows, P.sn_rows.data(), sizeof(int32_t) * P.sn_rows.size());
+    return NCL_OK;
+}
+
+int ncl_kkt_get_flow(ncl_kkt_t h, int64_t* counts, int32_t* tasks, int32_t* deps, int64_t* launches) {
+    if (!h || !counts) return NCL_ERR_ARG;
+    const Plan& P = h->P;
+    counts[0] = (int64_t)P.flow_task.size() / 8;
+    counts[1] = (int64_t)P.flow_dep.size() / 2;
+    counts[2] = P.flow_nctr;
+    counts[3] = (int64_t)P.large_steps.size();
+    if (tasks) std::memcpy(tasks, P.flow_task.data(), sizeof(int32_t) * P.flow_task.size());
+    if (deps) std::memcpy(deps, P.flow_dep.data(), sizeof(int32_t) * P.flow_dep.size());
+    if (launches)
+        for (size_t l = 0; l < P.large_steps.size(); ++l) {
+            const LargeStep& ls = P.large_steps[l];
+            launches[4 * l + 0] = ls.flow_first;
+            launches[4 * l + 1] = ls.flow_count;
+            launches[4 * l + 2] = ls.flow_ticket;
+            launches[4 * l + 3] = ls.flow_grid;
+        }
     return NCL_OK;
 }
 

@@ -247,10 +247,10 @@ __device__ __forceinline__ T rowbcast_n(T v, int u) {   // u: a compile-time con
 // cnt[4].  Called by all 256 threads; ends with a barrier.
 template <typename T>
 __device__ __forceinline__ void diag_ldlt64(T* B, T* dv, unsigned long long negmask, int w, double thr, unsigned int* cnt,
-                            bool& bad_out) {
+                            bool& bad_out, int tid) {
     constexpr int LB = kPanel + 1;
     const T inv_thr = T(1) / (T)thr;   // reciprocal of a perturbed pivot (+-thr)
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lk = lane >> 4;
     bool bad_any = false;
 #pragma unroll
@@ -341,9 +341,9 @@ __device__ __forceinline__ T zget(const T* B, int u, int t) {   // Z[u][t]
 }
 
 template <typename T>
-__device__ __forceinline__ void tri_inv64(T* B) {
+__device__ __forceinline__ void tri_inv64(T* B, int tid) {
     constexpr int LB = kPanel + 1;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    const int wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lk = lane >> 4;
     {
         // wave q: lane (g, j) builds column j of Z_qq (same in each 16-lane
@@ -356,9 +356,14 @@ __device__ __forceinline__ void tri_inv64(T* B) {
             z[u] = (u == j) ? T(1) : T(0);
         }
 #pragma unroll
-        for (int i = 1; i < 16; ++i)
+        for (int i = 1; i < 16; ++i) {
+            // Tie row i's broadcasts to z[i-1]: otherwise all 120 of them are
+            // issued up front and held in registers.
+#pragma unroll
+            for (int u = 0; u < i; ++u) asm volatile("" : "+v"(lrow[u]) : "v"(z[i - 1]));
 #pragma unroll
             for (int u = 0; u < i; ++u) z[i] = __builtin_fma(-rowbcast_n(lrow[u], i), z[u], z[i]);
+        }
         if (lane < 16) {
 #pragma unroll
             for (int i = 1; i < 16; ++i)
@@ -561,7 +566,7 @@ __global__ __launch_bounds__(256) void k_small_fronts(DevPlan d, const int* __re
         unsigned long long* in4 = d.inertia + 4 * sys;
         for (int k = 0; k < 4; ++k)
             if (cnt[k]) atomicAdd(&in4[k], (unsigned long long)cnt[k]);
-        if (bad) d.nonfinite[0] = 1;
+        if (bad) atomicOr(d.nonfinite, 1);
     }
     for (int k = tid; k < p; k += 256) D[first + k] = dv[k];
     // write L (f x p, ld f) and the contribution block (c x c, ld CB_ld)
@@ -631,9 +636,8 @@ __global__ __launch_bounds__(256) void k_large_asm(DevPlan d, int64_t task0, con
 // (strictly lower part of the block), and Zg = Z (column-major, kPanel x
 // kPanel, unit diagonal, identity beyond w) for the panel solves.
 template <typename T>
-__device__ void publish_diag(T* A, int f, int k0, int w, const T* Bf, const T* dv, T* D, int first, T* Zg) {
+__device__ void publish_diag(T* A, int f, int k0, int w, const T* Bf, const T* dv, T* D, int first, T* Zg, int tid) {
     constexpr int LB = kPanel + 1;
-    const int tid = threadIdx.x;
     if (tid < w) D[first + k0 + tid] = dv[tid];
     for (int idx = tid; idx < kPanel * kPanel; idx += 256) {
         const int u = idx & (kPanel - 1), t = idx / kPanel;   // row u, column t
@@ -646,17 +650,17 @@ __device__ void publish_diag(T* A, int f, int k0, int w, const T* Bf, const T* d
 // its upper triangle (entries with u < w and t < w on or below the diagonal
 // are left to the caller).
 template <typename T>
-__device__ __forceinline__ void pad_diag(T* Bf, int w) {
+__device__ __forceinline__ void pad_diag(T* Bf, int w, int tid) {
     constexpr int LB = kPanel + 1;
-    for (int idx = threadIdx.x; idx < kPanel * kPanel; idx += 256) {
+    for (int idx = tid; idx < kPanel * kPanel; idx += 256) {
         const int u = idx & (kPanel - 1), t = idx / kPanel;
         if (u < t) Bf[u + t * LB] = T(0);
         else if (u >= w) Bf[u + t * LB] = (u == t) ? T(1) : T(0);
     }
 }
 
-__device__ __forceinline__ unsigned long long neg_mask(const DevPlan& d, int first, int k0, int w) {
-    const int lane = threadIdx.x & 63;
+__device__ __forceinline__ unsigned long long neg_mask(const DevPlan& d, int first, int k0, int w, int tid) {
+    const int lane = tid & 63;
     const bool neg = lane < w && d.row_sign[d.perm[first + k0 + lane]] < 0;
     return __ballot(neg);
 }
@@ -669,8 +673,8 @@ __device__ __forceinline__ unsigned long long neg_mask(const DevPlan& d, int fir
 // (i0 + wr + 16 bi + row(lk, r), j0 + wc + 16 bj + lr).
 template <typename T>
 __device__ __forceinline__ void tile_update(const T* __restrict__ A, int f, int k0, int w, int i0, int j0,
-                                            const T* __restrict__ Dk, typename Mfma<T>::acc_t (&acc)[2][2]) {
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+                                            const T* __restrict__ Dk, typename Mfma<T>::acc_t (&acc)[2][2], int tid) {
+    const int wave = tid >> 6, lane = tid & 63;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
@@ -719,9 +723,7 @@ __device__ __forceinline__ void tile_update(const T* __restrict__ A, int f, int 
 // belong to the panel rows below it / the contribution block and are written
 // back to the front.
 template <typename T>
-__global__ __launch_bounds__(256) void k_large_diag(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
-                                                    T* __restrict__ D, T* __restrict__ Zbuf) {
-    const int s = tasks[2 * blockIdx.x], k0 = tasks[2 * blockIdx.x + 1];
+__device__ __forceinline__ void diag_body(const DevPlan& d, int s, int k0, T* F, T* D, T* Zbuf, int tid) {
     const int first = d.sn_first[s];
     const int p = d.sn_first[s + 1] - first;
     const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
@@ -730,7 +732,6 @@ __global__ __launch_bounds__(256) void k_large_diag(DevPlan d, const int* __rest
     constexpr int LB = kPanel + 1;
     __shared__ T Bf[kPanel * LB];
     __shared__ T dv[kPanel];
-    const int tid = threadIdx.x;
     constexpr int kIt = kPanel * kPanel / 256;   // staging: all loads first, then the LDS stores
     if (k0 == 0) {
         T cv[kIt];
@@ -807,21 +808,28 @@ __global__ __launch_bounds__(256) void k_large_diag(DevPlan d, const int* __rest
                 }
         __syncthreads();   // pad_diag below overwrites rows past the last pivot
     }
-    pad_diag<T>(Bf, w);
-    const unsigned long long negmask = neg_mask(d, first, k0, w);
+    pad_diag<T>(Bf, w, tid);
+    const unsigned long long negmask = neg_mask(d, first, k0, w, tid);
     __syncthreads();
     const int sys = d.sn_sys[s];
     unsigned int cnt[4] = {0, 0, 0, 0};
     bool bad = false;
-    diag_ldlt64<T>(Bf, dv, negmask, w, d.sys_thr[sys], cnt, bad);
-    tri_inv64<T>(Bf);
+    diag_ldlt64<T>(Bf, dv, negmask, w, d.sys_thr[sys], cnt, bad, tid);
+    tri_inv64<T>(Bf, tid);
     if (tid == 0) {
         unsigned long long* in4 = d.inertia + 4 * sys;
         for (int k = 0; k < 4; ++k)
             if (cnt[k]) atomicAdd(&in4[k], (unsigned long long)cnt[k]);
-        if (bad) d.nonfinite[0] = 1;
+        if (bad) atomicOr(d.nonfinite, 1);
     }
-    publish_diag<T>(A, f, k0, w, Bf, dv, D, first, Zbuf + d.M_off[s] + (int64_t)(k0 / kPanel) * (kPanel * kPanel));
+    publish_diag<T>(A, f, k0, w, Bf, dv, D, first, Zbuf + d.M_off[s] + (int64_t)(k0 / kPanel) * (kPanel * kPanel),
+                    tid);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_large_diag(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
+                                                    T* __restrict__ D, T* __restrict__ Zbuf) {
+    diag_body<T>(d, tasks[2 * blockIdx.x], tasks[2 * blockIdx.x + 1], F, D, Zbuf, threadIdx.x);
 }
 
 // One workgroup per (front, panel, 32-row block) below the panel's diagonal
@@ -832,16 +840,15 @@ __global__ __launch_bounds__(256) void k_large_diag(DevPlan d, const int* __rest
 // and the output column blocks J = w >> 1 and 3 - (w >> 1); Z is lower
 // triangular, so block J contracts over k < 16 (J + 1) only.
 template <typename T>
-__global__ __launch_bounds__(256) void k_large_panel(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
-                                                     const T* __restrict__ D, const T* __restrict__ Zbuf) {
-    const int s = tasks[3 * blockIdx.x], k0 = tasks[3 * blockIdx.x + 1], r0 = tasks[3 * blockIdx.x + 2];
+__device__ __forceinline__ void panel_body(const DevPlan& d, int s, int k0, int r0, T* F, const T* D,
+                                           const T* Zbuf, int tid) {
     const int first = d.sn_first[s];
     const int p = d.sn_first[s + 1] - first;
     const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
     const int w = min(kPanel, p - k0);
     T* __restrict__ A = F + d.L_off[s];
     const T* __restrict__ Zt = Zbuf + d.M_off[s] + (int64_t)(k0 / kPanel) * (kPanel * kPanel);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lk = lane >> 4;
     const int rb = r0 + 16 * (wave & 1);
     const int row = rb + lr;
@@ -884,22 +891,27 @@ __global__ __launch_bounds__(256) void k_large_panel(DevPlan d, const int* __res
     }
 }
 
+template <typename T>
+__global__ __launch_bounds__(256) void k_large_panel(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
+                                                     const T* __restrict__ D, const T* __restrict__ Zbuf) {
+    panel_body<T>(d, tasks[3 * blockIdx.x], tasks[3 * blockIdx.x + 1], tasks[3 * blockIdx.x + 2], F, D, Zbuf,
+                  threadIdx.x);
+}
+
 // Trailing update of one 64x64 lower tile: C -= L_I D_k L_J^T on MFMA, with
 // the operands read straight from the front (no LDS).  The next panel's
 // diagonal tile is not in the task list: k_large_diag updates it.
 template <typename T>
-__global__ __launch_bounds__(256) void k_large_update(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
-                                                      const T* __restrict__ D) {
-    const int* tk = tasks + 4 * xcd_task(blockIdx.x, gridDim.x);
-    const int s = tk[0], k0 = tk[1], i0 = tk[2], j0 = tk[3];
+__device__ __forceinline__ void update_body(const DevPlan& d, int s, int k0, int i0, int j0, T* F, const T* D,
+                                            int tid) {
     const int first = d.sn_first[s];
     const int p = d.sn_first[s + 1] - first;
     const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
     const int w = min(kPanel, p - k0);
     T* __restrict__ A = F + d.L_off[s];
     typename Mfma<T>::acc_t acc[2][2];
-    tile_update<T>(A, f, k0, w, i0, j0, D + first + k0, acc);
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    tile_update<T>(A, f, k0, w, i0, j0, D + first + k0, acc, tid);
+    const int wave = tid >> 6, lane = tid & 63;
     const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
     const int lr = lane & 15, lk = lane >> 4;
 #pragma unroll
@@ -911,6 +923,85 @@ __global__ __launch_bounds__(256) void k_large_update(DevPlan d, const int* __re
                 const int gi = i0 + wr + bi * 16 + Mfma<T>::row(lk, r), gj = j0 + wc + bj * 16 + lr;
                 if (gi < f && gj < f && gi >= gj) A[gi + (int64_t)gj * f] = acc[bi][bj][r];
             }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_large_update(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
+                                                      const T* __restrict__ D) {
+    const int* tk = tasks + 4 * xcd_task(blockIdx.x, gridDim.x);
+    update_body<T>(d, tk[0], tk[1], tk[2], tk[3], F, D, threadIdx.x);
+}
+
+// ---------------------------------------------------------------------------
+// Large fronts of one level as one dataflow launch.  The level's diagonal-
+// block, panel-solve and tile-update tasks (the bodies above) are listed in a
+// topological order; each workgroup takes the next task by an atomic ticket,
+// waits until the counters its inputs depend on reach their targets, runs the
+// task, and bumps the counter it feeds.  Every task waits only on tasks with
+// smaller tickets, which were taken by running workgroups, so the smallest
+// unfinished ticket always progresses: no co-residency is assumed.  Waits are
+// bounded: past kFlowSpinLimit polls a workgroup sets bit 1 of the status word
+// and every later wait returns at once, so the grid always drains.
+// Counters are published with agent-scope release (after every wave's stores
+// reached the L2) and read with agent-scope acquire, which the different
+// XCDs' L2 caches need.
+// ---------------------------------------------------------------------------
+constexpr int kFlowSpinLimit = 1 << 21;
+constexpr int kFlowSleep = 4;    // s_sleep units (64 clocks) between two polls
+constexpr int kFlowChunk = 1;    // consecutive tasks taken per ticket
+
+__device__ __forceinline__ void flow_wait(int* ctr, const int* __restrict__ dep, int nd, int* status) {
+    // Relaxed polls (coherent loads, no cache invalidation per poll), then
+    // one acquire fence for all the dependencies.
+    for (int i = 0; i < nd; ++i) {
+        int* c = ctr + dep[2 * i];
+        const int target = dep[2 * i + 1];
+        int spins = 0;
+        while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
+            if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2) break;
+            if (++spins > kFlowSpinLimit) {
+                __hip_atomic_fetch_or(status, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                break;
+            }
+            __builtin_amdgcn_s_sleep(kFlowSleep);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+template <typename T>
+__global__ __launch_bounds__(256, 2) void k_large_flow(DevPlan d, const int* __restrict__ tasks, int ntask,
+                                                    const int* __restrict__ deps, int* ctr, int ticket, T* F, T* D,
+                                                    T* Zbuf) {
+    __shared__ int s_t;
+    const int tid = threadIdx.x;
+    for (;;) {
+        if (tid == 0)
+            s_t = __hip_atomic_fetch_add(ctr + ticket, kFlowChunk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __syncthreads();
+        const int t0 = __builtin_amdgcn_readfirstlane(s_t);
+        if (t0 >= ntask) break;
+        // A chunk is consecutive tickets run in order: the smallest unfinished
+        // ticket is still always runnable.
+        for (int t = t0; t < t0 + kFlowChunk && t < ntask; ++t) {
+            const int* tk = tasks + 8 * t;
+            const int type = tk[0], s = tk[1], k0 = tk[2], a = tk[3], b = tk[4], sig = tk[7];
+            if (tid == 0) flow_wait(ctr, deps + 2 * tk[5], tk[6], d.nonfinite);
+            __syncthreads();
+            // A fresh thread index per task: nothing derived from it is kept live
+            // across the loop (hoisted address arithmetic would exhaust registers).
+            int tx = tid;
+            asm volatile("" : "+v"(tx));
+            if (type == kFlowDiag) diag_body<T>(d, s, k0, F, D, Zbuf, tx);
+            else if (type == kFlowPanel) panel_body<T>(d, s, k0, a, F, D, Zbuf, tx);
+            else update_body<T>(d, s, k0, a, b, F, D, tx);
+            // Every wave waits for its own stores to reach the L2; after the
+            // barrier one agent-scope release (L2 write-back) covers them all.
+            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+            __syncthreads();
+            if (tid == 0 && sig >= 0) __hip_atomic_fetch_add(ctr + sig, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1740,6 +1831,13 @@ void launch_large_update(const DevPlan& d, const int* tasks, int count, T* F, T*
 }
 
 template <typename T>
+void launch_large_flow(const DevPlan& d, const int* tasks, int ntask, const int* deps, int* ctr, int ticket, int grid,
+                       T* F, T* D, T* M, hipStream_t st) {
+    if (ntask <= 0) return;
+    launch(k_large_flow<T>, dim3(grid < ntask ? grid : ntask), dim3(256), 0, st, d, tasks, ntask, deps, ctr, ticket, F, D, M);
+}
+
+template <typename T>
 void launch_permute_in(const DevPlan& d, const double* B, int64_t ldb, int nrhs, T* Y, hipStream_t st) {
     launch(k_permute_in<T>, dim3(blocks_for(d.N, 256)), dim3(256), 0, st, d, B, ldb, nrhs, Y);
 }
@@ -1872,6 +1970,8 @@ hipError_t configure_kernels(int max_dynamic_lds) {
     template void launch_large_diag<T>(const DevPlan&, const int*, int, T*, T*, T*, hipStream_t);                \
     template void launch_large_panel<T>(const DevPlan&, const int*, int, T*, const T*, const T*, hipStream_t);     \
     template void launch_large_update<T>(const DevPlan&, const int*, int, T*, T*, T*, hipStream_t);              \
+    template void launch_large_flow<T>(const DevPlan&, const int*, int, const int*, int*, int, int, T*, T*, T*,       \
+                                       hipStream_t);                                                              \
     template void launch_permute_in<T>(const DevPlan&, const double*, int64_t, int, T*, hipStream_t);              \
     template void launch_permute_out<T>(const DevPlan&, const T*, int, double*, int64_t, hipStream_t);             \
     template void launch_fwd_T<T>(const DevPlan&, const int*, int, const T*, const T*, T*, T*, int, hipStream_t);           \

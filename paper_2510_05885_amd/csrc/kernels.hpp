@@ -4,6 +4,8 @@
 
 #include <cstdint>
 
+#include "flow_types.hpp"
+
 namespace ncl {
 
 constexpr int kNrhsMax = 16;   // columns per solve sweep (wider solves are chunked)
@@ -103,6 +105,13 @@ template <typename T>
 void launch_large_update(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st);
 
 // ---- solves -----------------------------------------------------------------
+// One level's large-front factorization as a single dataflow launch: tasks
+// are 8 ints (type, front, k0, a, b, first dependency, dependencies, counter
+// signalled or -1), dependencies are (counter, target) pairs, ctr[ticket] is
+// the task ticket; all counters start at zero.
+template <typename T>
+void launch_large_flow(const DevPlan& d, const int* tasks, int ntask, const int* deps, int* ctr, int ticket, int grid,
+                       T* F, T* D, T* M, hipStream_t st);
 template <typename T>
 void launch_permute_in(const DevPlan& d, const double* B, int64_t ldb, int nrhs, T* Y, hipStream_t st);
 template <typename T>

@@ -8,6 +8,8 @@
 #include <string>
 #include <vector>
 
+#include "flow_types.hpp"
+
 namespace ncl {
 
 // Fronts of order above this bound use the global-memory path.  The LDS path
@@ -23,6 +25,7 @@ struct PlanConfig {
     int solve_panel = 256;      // pivot columns per solve panel
     int solve_fuse_rows = 64;   // rows below a panel handled inside the panel's workgroup
     int solve_chunk_rows = 64;  // rows per G task otherwise
+    int flow_workers = 512;     // workgroups of a level's dataflow launch (2 per CU)
 };
 
 struct LevelBatch {            // one launch of the small-front kernel
@@ -40,6 +43,11 @@ struct LargeStep {             // launches of the large-front path for one level
     std::vector<int64_t> panel_first, panel_count;
     std::vector<int64_t> upd_first, upd_count;
     std::vector<double> upd_flops;            // algorithmic flops of each update launch
+    // the same tasks as one dataflow launch (Plan::flow_task / flow_dep)
+    int64_t flow_first = 0, flow_count = 0;   // range in flow_task (8 ints per task)
+    int64_t flow_ticket = 0;                  // counter index of the task ticket
+    int flow_grid = 0;                        // workgroups of the launch
+    double flow_flops = 0.0;                  // algorithmic flops of all its tasks
 };
 
 // Solve schedule: each front is swept in panels of up to kSolvePanel pivot
@@ -141,6 +149,11 @@ struct Plan {
     std::vector<int> large_panel;    // triples (front, k0, 32-row block start >= k0 + panel)
     std::vector<int> large_upd;      // quads (front, k0, tile row start, tile col start); the next
                                      // panel's diagonal tile is left to large_diag
+    // dataflow form of the large-front tasks: per task (type, front, k0, a, b,
+    // first dependency, dependencies, counter signalled or -1); dependencies
+    // are (counter, target) pairs; flow_nctr counters in all, zeroed per factor
+    std::vector<int> flow_task, flow_dep;
+    int64_t flow_nctr = 0;
     // solve schedule
     std::vector<SolveStep> solve_steps;
     std::vector<int> solve_t;        // (front, c0, fused, g_first, g_count)
@@ -156,5 +169,9 @@ struct Plan {
     double analyze_seconds = 0.0;
     PlanConfig cfg;
 };
+
+// Builds the dataflow task list of one level's large fronts (appends to
+// P.flow_task / P.flow_dep and fills st.flow_*).
+void build_flow(Plan& P, LargeStep& st, const std::vector<int>& large, int workers);
 
 }  // namespace ncl

@@ -29,8 +29,8 @@ EXPORTED = [
     "ncl_kkt_default_options", "ncl_kkt_analyze", "ncl_kkt_analyze_host", "ncl_kkt_analyze_batched",
     "ncl_kkt_factor", "ncl_kkt_factor_batched", "ncl_kkt_solve", "ncl_kkt_inertia",
     "ncl_kkt_inertia_batched", "ncl_kkt_backward", "ncl_kkt_get_stats", "ncl_kkt_get_perm",
-    "ncl_kkt_get_supernodes", "ncl_kkt_set_timing", "ncl_kkt_get_timing", "ncl_kkt_destroy",
-    "ncl_kkt_strerror",
+    "ncl_kkt_get_supernodes", "ncl_kkt_get_flow", "ncl_kkt_set_timing", "ncl_kkt_get_timing",
+    "ncl_kkt_destroy", "ncl_kkt_strerror",
 ]
 
 
@@ -38,7 +38,8 @@ class Options(C.Structure):
     _fields_ = [("form", C.c_int32), ("precision", C.c_int32), ("pivot_eps", C.c_double),
                 ("ir_max_steps", C.c_int32), ("ir_tol", C.c_double), ("ir_stall", C.c_double),
                 ("ordering", C.c_int32), ("user_perm", C.POINTER(C.c_int32)), ("use_graphs", C.c_int32),
-                ("small_front_max", C.c_int32), ("relax_big_zeros", C.c_double), ("fp32_sticky", C.c_int32)]
+                ("small_front_max", C.c_int32), ("relax_big_zeros", C.c_double), ("fp32_sticky", C.c_int32),
+                ("large_flow", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -114,6 +115,8 @@ def lib():
     L.ncl_kkt_get_perm.restype = C.c_int
     L.ncl_kkt_get_supernodes.argtypes = [vp, pi32, pi32, C.POINTER(C.c_int64), pi32]
     L.ncl_kkt_get_supernodes.restype = C.c_int
+    L.ncl_kkt_get_flow.argtypes = [vp, C.POINTER(C.c_int64), pi32, pi32, C.POINTER(C.c_int64)]
+    L.ncl_kkt_get_flow.restype = C.c_int
     L.ncl_kkt_set_timing.argtypes = [vp, i32]
     L.ncl_kkt_set_timing.restype = C.c_int
     L.ncl_kkt_get_timing.argtypes = [vp, C.POINTER(Timing)]
@@ -166,7 +169,7 @@ _ORDS = {"nd": NCL_ORDER_ND, "natural": NCL_ORDER_NATURAL, "user": NCL_ORDER_USE
 
 def make_options(form="condensed", precision="fp64", pivot_eps=0.0, ir_max_steps=10, ir_tol=1e-12,
                  ir_stall=0.5, ordering="nd", user_perm=None, use_graphs=True, small_front_max=0,
-                 relax_big_zeros=-1.0, fp32_sticky=True):
+                 relax_big_zeros=-1.0, fp32_sticky=True, large_flow=False):
     o = Options()
     lib().ncl_kkt_default_options(C.byref(o))
     o.form = _FORMS[form] if isinstance(form, str) else int(form)
@@ -179,6 +182,7 @@ def make_options(form="condensed", precision="fp64", pivot_eps=0.0, ir_max_steps
     o.small_front_max = int(small_front_max)
     o.relax_big_zeros = float(relax_big_zeros)
     o.fp32_sticky = 1 if fp32_sticky else 0
+    o.large_flow = 1 if large_flow else 0
     keep = None
     if user_perm is not None:
         keep, p = _i32(user_perm)
@@ -328,6 +332,21 @@ class KKT:
         rows = np.zeros(max(int(rp[-1]), 1), np.int32)
         _check(lib().ncl_kkt_get_supernodes(self._h, None, None, None, rows.ctypes.data_as(P32)), "supernodes")
         return first, parent, rp, rows[:int(rp[-1])]
+
+    def flow_schedule(self):
+        """Dataflow schedule of the large fronts: (tasks [T, 8], deps [D, 2],
+        number of counters, launches [L, 4]); field meanings as in
+        ncl_kkt_get_flow."""
+        P64 = C.POINTER(C.c_int64)
+        P32 = C.POINTER(C.c_int32)
+        cnt = np.zeros(4, np.int64)
+        _check(lib().ncl_kkt_get_flow(self._h, cnt.ctypes.data_as(P64), None, None, None), "ncl_kkt_get_flow")
+        tasks = np.zeros((max(int(cnt[0]), 1), 8), np.int32)
+        deps = np.zeros((max(int(cnt[1]), 1), 2), np.int32)
+        launches = np.zeros((max(int(cnt[3]), 1), 4), np.int64)
+        _check(lib().ncl_kkt_get_flow(self._h, cnt.ctypes.data_as(P64), tasks.ctypes.data_as(P32),
+                                      deps.ctypes.data_as(P32), launches.ctypes.data_as(P64)), "ncl_kkt_get_flow")
+        return tasks[:cnt[0]], deps[:cnt[1]], int(cnt[2]), launches[:cnt[3]]
 
     def set_timing(self, on=True):
         _check(lib().ncl_kkt_set_timing(self._h, 1 if on else 0), "ncl_kkt_set_timing")
