@@ -34,10 +34,10 @@ PEAK = {"hbm_GBs": 8000.0, "fp64_mfma_TFs": 78.6, "fp32_mfma_TFs": 157.3, "fp64_
 # of a 2-step run), each scaled by what the same counter reads for a device
 # copy of known size.  Valid only for the kernel source they were taken on:
 # reported as null once kernels.hip changes.
-TRAFFIC = {"kernels_sha1": "3987f9551cc48e9a54ba7b05ab8989762362d2fa", "fetch_scale": 2.00, "write_scale": 1.00,
+TRAFFIC = {"kernels_sha1": "e2b8504d220744afb2315959049e85e9e035dfe8", "fetch_scale": 2.00, "write_scale": 1.00,
            "source": "profiles/pmc_traffic_opf_n500k_fp64.txt",
-           "kib": {"large_diag": (613.8, 1176.7), "large_panel": (4014.8, 6448.2),
-                   "large_update_mfma": (13764.1, 19577.9)}}
+           "kib": {"large_diag": (614.3, 1176.7), "large_panel": (4014.8, 6446.1),
+                   "large_update_mfma": (13773.8, 19576.0)}}
 
 
 def measured_traffic(cls):
