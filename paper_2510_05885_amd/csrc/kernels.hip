@@ -584,50 +584,62 @@ __global__ __launch_bounds__(256) void k_small_fronts(DevPlan d, const int* __re
 // ---------------------------------------------------------------------------
 // large fronts (front stored in the factor buffer, ld = f)
 // ---------------------------------------------------------------------------
-// One workgroup per (large front, column j): assemble column j (rows >= j)
-// from K and the children's contribution blocks.  The task's column base,
-// K-entry range and contribution segments (one per child whose CB maps a
-// column onto j) come precomputed, so the workgroup starts with one round of
-// independent loads.  kLds: the column is built in LDS (dynamic, >= f
-// elements) and written once; otherwise in place.
+// Orders one wave's accesses to its column: LDS accesses of a wave execute in
+// order; global stores must have completed before other lanes read them back.
+template <bool kLds>
+__device__ __forceinline__ void asm_fence() {
+    if (!kLds) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    wave_fence();
+}
+
+// One wave per (large front, column j), four columns per workgroup: assemble
+// column j (rows >= j) from K and the children's contribution blocks.  The
+// task's column base, K-entry range and contribution segments (one per child
+// whose CB maps a column onto j) come precomputed, so the wave starts with
+// one round of independent loads.  kLds: the column is built in the wave's
+// LDS slice (dynamic, 4 x >= f elements) and written once; otherwise in place.
+// A wave's LDS accesses execute in order, so no workgroup barrier is needed;
+// children are added one after the other (two may map onto the same row).
 template <typename T, bool kLds>
-__global__ __launch_bounds__(256) void k_large_asm(DevPlan d, int64_t task0, const double* __restrict__ K,
-                                                   T* __restrict__ F) {
+__global__ __launch_bounds__(256) void k_large_asm(DevPlan d, int64_t task0, int count, int fcap,
+                                                   const double* __restrict__ K, T* __restrict__ F) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int64_t t = task0 + blockIdx.x;
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t q = 4 * (int64_t)blockIdx.x + wave;
+    if (q >= count) return;
+    const int64_t t = task0 + q;
     const int64_t colbase = d.asm_col[t];
     const int f = d.asm_fj[2 * t], j = d.asm_fj[2 * t + 1];
     const int64_t e0 = d.asm_kr[2 * t], e1 = d.asm_kr[2 * t + 1];
     const int64_t g0 = d.asm_seg_ptr[t], g1 = d.asm_seg_ptr[t + 1];
     T* __restrict__ Acol = F + colbase;                      // Acol[i] = A[i, j]
-    T* __restrict__ cv = kLds ? reinterpret_cast<T*>(smem_raw) : Acol;
+    T* __restrict__ cv = kLds ? reinterpret_cast<T*>(smem_raw) + (int64_t)wave * fcap : Acol;
     const int64_t jf = (int64_t)j * f;
-    const int tid = threadIdx.x;
-    for (int i = j + tid; i < f; i += 256) cv[i] = T(0);
-    __syncthreads();
-    for (int64_t e = e0 + tid; e < e1; e += 256) cv[d.kent_pos[e] - jf] = (T)K[d.kent_csr[e]];
-    __syncthreads();
+    for (int i = j + lane; i < f; i += 64) cv[i] = T(0);
+    asm_fence<kLds>();
+    for (int64_t e = e0 + lane; e < e1; e += 64) cv[d.kent_pos[e] - jf] = (T)K[d.kent_csr[e]];
+    asm_fence<kLds>();
     for (int64_t g = g0; g < g1; ++g) {
         const T* __restrict__ CB = F + d.asm_seg_cb[g];
         const int* __restrict__ r = d.rel + d.asm_seg_rel[g];
         const int b = d.asm_seg_bc[2 * g], cc = d.asm_seg_bc[2 * g + 1];
-        for (int a0 = b + tid; a0 < cc; a0 += 256 * 4) {
+        for (int a0 = b + lane; a0 < cc; a0 += 64 * 4) {
             T v[4];
             int ri[4];
 #pragma unroll
             for (int u = 0; u < 4; ++u) {
-                const int a = min(a0 + 256 * u, cc - 1);
+                const int a = min(a0 + 64 * u, cc - 1);
                 v[u] = CB[a];
                 ri[u] = r[a];
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                if (a0 + 256 * u < cc) cv[ri[u]] += v[u];
+                if (a0 + 64 * u < cc) cv[ri[u]] += v[u];
         }
-        __syncthreads();
+        asm_fence<kLds>();
     }
     if (kLds)
-        for (int i = j + tid; i < f; i += 256) Acol[i] = cv[i];
+        for (int i = j + lane; i < f; i += 64) Acol[i] = cv[i];
 }
 
 // Writes the factored diagonal block of a panel (in LDS: L strictly below the
@@ -1804,11 +1816,12 @@ void launch_small_fronts(const DevPlan& d, const int* list, int count, int fmax,
 template <typename T>
 void launch_large_asm(const DevPlan& d, int64_t first, int count, int fmax, const double* K, T* F, hipStream_t st) {
     if (count <= 0) return;
-    const size_t lds = (size_t)fmax * sizeof(T);
+    const size_t lds = 4 * (size_t)fmax * sizeof(T);
+    const dim3 grid((count + 3) / 4);
     if (lds <= kAsmLdsMax)
-        launch(k_large_asm<T, true>, dim3(count), dim3(256), lds, st, d, first, K, F);
+        launch(k_large_asm<T, true>, grid, dim3(256), lds, st, d, first, count, fmax, K, F);
     else
-        launch(k_large_asm<T, false>, dim3(count), dim3(256), 0, st, d, first, K, F);
+        launch(k_large_asm<T, false>, grid, dim3(256), 0, st, d, first, count, fmax, K, F);
 }
 
 template <typename T>

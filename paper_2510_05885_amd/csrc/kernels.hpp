@@ -14,7 +14,8 @@ constexpr int kSmallMax = 128;   // largest front order of the LDS-resident path
 constexpr int kTile = 64;        // tile order of the large-front MFMA update
 constexpr int kSolvePanel = 256; // pivot columns per solve panel
 constexpr int kSolveChunk = 256; // row capacity of a solve G task / of the rows fused below a panel
-constexpr size_t kAsmLdsMax = 96 * 1024;  // large-front column assembly staged in LDS up to this size
+constexpr size_t kAsmLdsMax = 96 * 1024;  // large-front column assembly staged in LDS (4 columns per
+                                           // workgroup) up to this size
 
 // Device copies of the plan (all device pointers), passed by value.
 struct DevPlan {
