@@ -581,6 +581,114 @@ __global__ __launch_bounds__(256) void k_small_fronts(DevPlan d, const int* __re
     }
 }
 
+// Fronts of order f <= kTinyMax: one wave per front, four fronts per
+// workgroup, no workgroup barrier.  The wave assembles its front in an LDS
+// slice (K entries, then the children's contribution blocks one after the
+// other), loads row `lane` into registers and eliminates the p pivots right-
+// looking with readlane broadcasts (static pivoting of Sec. 3.1), then writes
+// L, D and the contribution block like k_small_fronts.
+constexpr int kTinyMax = 32;
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_tiny_fronts(DevPlan d, const int* __restrict__ list, int count,
+                                                     const double* __restrict__ K, T* __restrict__ F,
+                                                     T* __restrict__ D) {
+    constexpr int LD = kTinyMax;
+    __shared__ T Aall[4][kTinyMax * kTinyMax];
+    __shared__ int rlall[4][kTinyMax];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q = 4 * blockIdx.x + wave;
+    if (q >= count) return;
+    T* A = Aall[wave];
+    int* rl = rlall[wave];
+    const int s = list[q];
+    const int first = d.sn_first[s];
+    const int p = d.sn_first[s + 1] - first;
+    const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
+    const int c = f - p;
+    for (int t = lane; t < kTinyMax * kTinyMax; t += 64) A[t] = T(0);
+    wave_fence();
+    // K entries come with local positions for leading dimension f
+    for (int64_t e = d.kent_ptr[s] + lane; e < d.kent_ptr[s + 1]; e += 64) {
+        const int pos = d.kent_pos[e];
+        A[pos % f + (pos / f) * LD] = (T)K[d.kent_csr[e]];
+    }
+    wave_fence();
+    for (int k = d.child_ptr[s]; k < d.child_ptr[s + 1]; ++k) {
+        const int ch = d.child_list[k];
+        const int fc = (int)(d.sn_rowptr[ch + 1] - d.sn_rowptr[ch]);
+        const int cc = fc - (d.sn_first[ch + 1] - d.sn_first[ch]);
+        if (cc <= 0) continue;   // uniform
+        const T* __restrict__ CB = F + d.CB_off[ch];
+        const int ld = d.CB_ld[ch];
+        if (lane < cc) rl[lane] = d.rel[d.rel_ptr[ch] + lane];
+        wave_fence();
+        T v[kTinyMax * kTinyMax / 64];
+#pragma unroll
+        for (int u = 0; u < kTinyMax * kTinyMax / 64; ++u) {
+            const int idx = lane + 64 * u, a = min(idx % kTinyMax, cc - 1), b = min(idx / kTinyMax, cc - 1);
+            v[u] = CB[a + (int64_t)b * ld];
+        }
+#pragma unroll
+        for (int u = 0; u < kTinyMax * kTinyMax / 64; ++u) {
+            const int idx = lane + 64 * u, a = idx % kTinyMax, b = idx / kTinyMax;
+            if (a < cc && b < cc && a >= b) A[rl[a] + rl[b] * LD] += v[u];
+        }
+        wave_fence();
+    }
+    // row `lane` of the front (lanes >= f hold zeros and are never stored)
+    T r[kTinyMax];
+#pragma unroll
+    for (int j = 0; j < kTinyMax; ++j) r[j] = A[(lane & (kTinyMax - 1)) + j * LD];
+    const bool neg = lane < p && d.row_sign[d.perm[first + lane]] < 0;
+    const unsigned long long negmask = __ballot(neg);
+    const int sys = d.sn_sys[s];
+    const double thr = d.sys_thr[sys];
+    const T inv_thr = T(1) / (T)thr;
+    unsigned int np = 0, nn = 0, nz = 0, npt = 0;
+    bool anybad = false;
+#pragma unroll
+    for (int k = 0; k < kTinyMax; ++k) {
+        if (k < p) {   // uniform
+            bool pert, bd;
+            const T draw = bcast(r[k], k);
+            const T inv0 = fast_rcp(draw);
+            const int sg = ((negmask >> k) & 1ULL) ? -1 : 1;
+            const T dk = static_pivot(draw, thr, sg, pert, bd);
+            const T inv = pert ? (sg > 0 ? inv_thr : -inv_thr) : inv0;
+            const T l = r[k] * inv;
+#pragma unroll
+            for (int j = k + 1; j < kTinyMax; ++j) r[j] -= l * bcast(r[k], j);
+            r[k] = (lane == k) ? dk : l;
+            const double dd = to_d(dk);
+            np += dd > 0.0; nn += dd < 0.0; nz += dd == 0.0; npt += pert;
+            anybad |= bd;
+        }
+    }
+    if (lane == 0) {
+        unsigned long long* in4 = d.inertia + 4 * sys;
+        if (np) atomicAdd(&in4[0], (unsigned long long)np);
+        if (nn) atomicAdd(&in4[1], (unsigned long long)nn);
+        if (nz) atomicAdd(&in4[2], (unsigned long long)nz);
+        if (npt) atomicAdd(&in4[3], (unsigned long long)npt);
+        if (anybad) atomicOr(d.nonfinite, 1);
+    }
+    T* __restrict__ L = F + d.L_off[s];
+    T* __restrict__ CBo = F + d.CB_off[s];
+    const int ldo = d.CB_ld[s];
+#pragma unroll
+    for (int j = 0; j < kTinyMax; ++j) {
+        if (lane < f && lane >= j) {
+            if (j < p) L[lane + (int64_t)j * f] = r[j];
+            else if (c > 0) CBo[(lane - p) + (int64_t)(j - p) * ldo] = r[j];
+        }
+    }
+    T mine = T(0);
+#pragma unroll
+    for (int j = 0; j < kTinyMax; ++j) mine = (lane == j) ? r[j] : mine;
+    if (lane < p) D[first + lane] = mine;
+}
+
 // ---------------------------------------------------------------------------
 // large fronts (front stored in the factor buffer, ld = f)
 // ---------------------------------------------------------------------------
@@ -1806,6 +1914,10 @@ template <typename T>
 void launch_small_fronts(const DevPlan& d, const int* list, int count, int fmax, const double* K, T* F, T* D,
                          hipStream_t st) {
     if (count <= 0) return;
+    if (fmax <= kTinyMax) {
+        launch(k_tiny_fronts<T>, dim3((count + 3) / 4), dim3(256), 0, st, d, list, count, K, F, D);
+        return;
+    }
     const size_t lds = (size_t)fmax * fmax * sizeof(T);
     if (fmax <= 64)
         launch(k_small_fronts<T, false>, dim3(count), dim3(256), lds, st, d, list, K, F, D);
