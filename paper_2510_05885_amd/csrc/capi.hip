@@ -70,6 +70,7 @@ struct ncl_kkt_s {
            *thr = nullptr, *rho = nullptr;
     int* nonfinite = nullptr;
     unsigned long long* inertia = nullptr;
+    unsigned long long* inertia_part = nullptr;
     double *F64 = nullptr, *D64 = nullptr, *Y64 = nullptr, *U64 = nullptr, *P64 = nullptr, *M64 = nullptr;
     float *F32 = nullptr, *D32 = nullptr, *Y32 = nullptr, *U32 = nullptr, *P32 = nullptr, *M32 = nullptr;
     double *R = nullptr, *DX = nullptr, *Xp = nullptr, *partial_res = nullptr, *res_out = nullptr;
@@ -262,8 +263,10 @@ void setup_device(ncl_kkt_s* h) {
     h->rho = dalloc<double>(h, P.S);
     h->nonfinite = dalloc<int>(h, 1);
     h->inertia = dalloc<unsigned long long>(h, 4 * P.S);
+    h->inertia_part = dalloc<unsigned long long>(h, 4 * (int64_t)P.S * kInertiaSlots);
     d.sys_thr = h->thr;
     d.inertia = h->inertia;
+    d.inertia_part = h->inertia_part;
     d.nonfinite = h->nonfinite;
     h->F64 = dalloc<double>(h, P.factor_elems);
     h->D64 = dalloc<double>(h, P.N);
@@ -413,7 +416,7 @@ template <typename T>
 void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
     Plan& P = h->P;
     const DevPlan& d = h->d;
-    launch_zero_u64(h->inertia, 4 * (int64_t)P.S, st);
+    launch_zero_u64(h->inertia_part, 4 * (int64_t)P.S * kInertiaSlots, st);
     const bool flow = h->opt.large_flow != 0;
     if (flow) launch_zero_i32(h->flow_ctr, P.flow_nctr, st);
     size_t sb = 0, lb = 0;
@@ -491,6 +494,7 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
             HIPCHK(hipStreamWaitEvent(st, h->lvl_ev[2 * l + 1], 0));
         }
     }
+    launch_reduce_inertia(d, P.S, st);
 }
 
 // Runs the frontal factorization; with graphs enabled (and timing off) the

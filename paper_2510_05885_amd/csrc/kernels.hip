@@ -47,6 +47,14 @@ __device__ __forceinline__ T static_pivot(T d, double thr, int sign, bool& pertu
     return d;
 }
 
+// Adds a workgroup's pivot counts to one of the system's partial counters
+// (many fronts finish at once; one shared counter would serialize them).
+__device__ __forceinline__ void add_inertia(const DevPlan& d, int sys, const unsigned int* cnt, int slot) {
+    unsigned long long* in4 = d.inertia_part + 4 * ((int64_t)sys * kInertiaSlots + (slot & (kInertiaSlots - 1)));
+    for (int k = 0; k < 4; ++k)
+        if (cnt[k]) atomicAdd(&in4[k], (unsigned long long)cnt[k]);
+}
+
 __device__ __forceinline__ void count_pivot(unsigned long long* in4, double d, bool pert) {
     if (d > 0.0) atomicAdd(&in4[0], 1ULL);
     else if (d < 0.0) atomicAdd(&in4[1], 1ULL);
@@ -563,9 +571,7 @@ __global__ __launch_bounds__(256) void k_small_fronts(DevPlan d, const int* __re
     bool bad = false;
     lds_partial_ldlt<T, kTwoRows>(A, f, f, p, dv, sgn, d.sys_thr[sys], cnt, bad);
     if (tid == 0) {
-        unsigned long long* in4 = d.inertia + 4 * sys;
-        for (int k = 0; k < 4; ++k)
-            if (cnt[k]) atomicAdd(&in4[k], (unsigned long long)cnt[k]);
+        add_inertia(d, sys, cnt, blockIdx.x);
         if (bad) atomicOr(d.nonfinite, 1);
     }
     for (int k = tid; k < p; k += 256) D[first + k] = dv[k];
@@ -666,11 +672,8 @@ __global__ __launch_bounds__(256) void k_tiny_fronts(DevPlan d, const int* __res
         }
     }
     if (lane == 0) {
-        unsigned long long* in4 = d.inertia + 4 * sys;
-        if (np) atomicAdd(&in4[0], (unsigned long long)np);
-        if (nn) atomicAdd(&in4[1], (unsigned long long)nn);
-        if (nz) atomicAdd(&in4[2], (unsigned long long)nz);
-        if (npt) atomicAdd(&in4[3], (unsigned long long)npt);
+        const unsigned int cnt[4] = {np, nn, nz, npt};
+        add_inertia(d, sys, cnt, q);
         if (anybad) atomicOr(d.nonfinite, 1);
     }
     T* __restrict__ L = F + d.L_off[s];
@@ -937,9 +940,7 @@ __device__ __forceinline__ void diag_body(const DevPlan& d, int s, int k0, T* F,
     diag_ldlt64<T>(Bf, dv, negmask, w, d.sys_thr[sys], cnt, bad, tid);
     tri_inv64<T>(Bf, tid);
     if (tid == 0) {
-        unsigned long long* in4 = d.inertia + 4 * sys;
-        for (int k = 0; k < 4; ++k)
-            if (cnt[k]) atomicAdd(&in4[k], (unsigned long long)cnt[k]);
+        add_inertia(d, sys, cnt, s + k0);
         if (bad) atomicOr(d.nonfinite, 1);
     }
     publish_diag<T>(A, f, k0, w, Bf, dv, D, first, Zbuf + d.M_off[s] + (int64_t)(k0 / kPanel) * (kPanel * kPanel),
@@ -1775,6 +1776,15 @@ __global__ void k_copy_cols(double* dst, int64_t ldd, const double* src, int64_t
     for (int q = 0; q < nrhs; ++q) dst[i + q * ldd] = src[i + q * lds];
 }
 
+__global__ void k_reduce_inertia(DevPlan d, int S) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= 4 * S) return;
+    const int sys = t >> 2, k = t & 3;
+    unsigned long long v = 0;
+    for (int q = 0; q < kInertiaSlots; ++q) v += d.inertia_part[4 * ((int64_t)sys * kInertiaSlots + q) + k];
+    d.inertia[t] = v;
+}
+
 __global__ void k_zero_u64(unsigned long long* p, int64_t n) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = 0ULL;
@@ -2040,6 +2050,10 @@ void launch_copy_cols(double* dst, int64_t ldd, const double* src, int64_t lds, 
 
 void launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st) {
     if (n > 0) launch(k_zero_u64, dim3(blocks_for(n, 256)), dim3(256), 0, st, p, n);
+}
+
+void launch_reduce_inertia(const DevPlan& d, int S, hipStream_t st) {
+    launch(k_reduce_inertia, dim3(blocks_for(4 * (int64_t)S, 256)), dim3(256), 0, st, d, S);
 }
 
 void launch_zero_i32(int* p, int64_t n, hipStream_t st) {

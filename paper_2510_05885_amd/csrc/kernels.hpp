@@ -14,6 +14,7 @@ constexpr int kSmallMax = 128;   // largest front order of the LDS-resident path
 constexpr int kTile = 64;        // tile order of the large-front MFMA update
 constexpr int kSolvePanel = 256; // pivot columns per solve panel
 constexpr int kSolveChunk = 256; // row capacity of a solve G task / of the rows fused below a panel
+constexpr int kInertiaSlots = 64;  // partial inertia counters per system (spreads the atomics)
 constexpr size_t kAsmLdsMax = 96 * 1024;  // large-front column assembly staged in LDS (4 columns per
                                            // workgroup) up to this size
 
@@ -67,6 +68,7 @@ struct DevPlan {
     // per system
     const double* sys_thr;     // static-pivot thresholds eps * ||K||_max
     unsigned long long* inertia;  // 4 per system: npos, nneg, nzero, nperturbed
+    unsigned long long* inertia_part;  // kInertiaSlots x 4 per system, summed into inertia
     int* nonfinite;            // set to 1 on a NaN/Inf pivot
 };
 
@@ -146,6 +148,7 @@ void launch_copy_cols(double* dst, int64_t ldd, const double* src, int64_t lds, 
                       hipStream_t st);
 void launch_zero_u64(unsigned long long* p, int64_t n, hipStream_t st);
 void launch_zero_i32(int* p, int64_t n, hipStream_t st);
+void launch_reduce_inertia(const DevPlan& d, int S, hipStream_t st);   // inertia = sum of the partials
 
 // Raises the dynamic-LDS limit of the LDS-resident kernels to the device maximum.
 hipError_t configure_kernels(int max_dynamic_lds);
