@@ -95,6 +95,9 @@ struct ncl_kkt_s {
     // second stream: a level's small fronts run beside its large-front chain
     hipStream_t aux_stream = nullptr;
     std::vector<hipEvent_t> lvl_ev;   // 2 per level: fork, join
+    // fourth stream: a level's small-front batches split over two streams
+    hipStream_t aux2_stream = nullptr;
+    std::vector<hipEvent_t> sb_ev;    // 2 per level: fork, join of the second batch stream
     // third stream: the next panel's diagonal block beside the current update
     hipStream_t diag_stream = nullptr;
     hipEvent_t diag_ev[2] = {nullptr, nullptr};
@@ -309,6 +312,9 @@ void setup_device(ncl_kkt_s* h) {
     for (auto& e : h->diag_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     h->lvl_ev.assign(2 * (size_t)std::max(P.nlevels, 1), nullptr);
     for (auto& e : h->lvl_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    HIPCHK(hipStreamCreateWithFlags(&h->aux2_stream, hipStreamNonBlocking));
+    h->sb_ev.assign(2 * (size_t)std::max(P.nlevels, 1), nullptr);
+    for (auto& e : h->sb_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     {
         int lds = 0;
         HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
@@ -432,8 +438,22 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
             HIPCHK(hipEventRecord(h->lvl_ev[2 * l], st));
             HIPCHK(hipStreamWaitEvent(ss, h->lvl_ev[2 * l], 0));
         }
+        // The level's batches (one per front-size class, each a launch) are
+        // independent: split them over two streams, each batch to the one
+        // with less estimated work (a latency floor plus count x fmax^2).
+        size_t nbl = 0;
+        while (sb + nbl < P.small_batches.size() && P.small_batches[sb + nbl].level == l) ++nbl;
+        const bool split = nbl >= 2;
+        if (split) {
+            HIPCHK(hipEventRecord(h->sb_ev[2 * l], st));
+            HIPCHK(hipStreamWaitEvent(h->aux2_stream, h->sb_ev[2 * l], 0));
+        }
+        double work[2] = {0.0, 0.0};
         while (sb < P.small_batches.size() && P.small_batches[sb].level == l) {
             const LevelBatch& b = P.small_batches[sb++];
+            const int side = split && work[1] < work[0] ? 1 : 0;
+            work[side] += 40.0 + (double)b.count * b.fmax * b.fmax / 2e5;
+            hipStream_t bs = side ? h->aux2_stream : ss;
             double fl = 0.0;
             if (h->tm.on)
                 for (int64_t k = b.first; k < b.first + b.count; ++k) {
@@ -442,9 +462,10 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
                     const int p = P.sn_first[s + 1] - P.sn_first[s];
                     for (int t = 0; t < p; ++t) { double r = f - t - 1; fl += r + r * (r + 1.0); }
                 }
-            Span sp(h, ss, TM_SMALL, fl, 2);
-            launch_small_fronts<T>(d, h->small_list + b.first, (int)b.count, b.fmax, h->K, F, D, ss);
+            Span sp(h, bs, TM_SMALL, fl, 2);
+            launch_small_fronts<T>(d, h->small_list + b.first, (int)b.count, b.fmax, h->K, F, D, bs);
         }
+        if (split) HIPCHK(hipEventRecord(h->sb_ev[2 * l + 1], h->aux2_stream));
         if (lb < P.large_steps.size() && P.large_steps[lb].level == l) {
             const LargeStep& ls = P.large_steps[lb++];
             {
@@ -493,6 +514,7 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
             HIPCHK(hipEventRecord(h->lvl_ev[2 * l + 1], ss));
             HIPCHK(hipStreamWaitEvent(st, h->lvl_ev[2 * l + 1], 0));
         }
+        if (split) HIPCHK(hipStreamWaitEvent(st, h->sb_ev[2 * l + 1], 0));
     }
     launch_reduce_inertia(d, P.S, st);
 }
@@ -991,6 +1013,8 @@ void ncl_kkt_destroy(ncl_kkt_t h) {
             for (auto& g : row) if (g) (void)hipGraphExecDestroy(g);
         if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
         if (h->aux_stream) (void)hipStreamDestroy(h->aux_stream);
+        if (h->aux2_stream) (void)hipStreamDestroy(h->aux2_stream);
+        for (auto& e : h->sb_ev) if (e) (void)hipEventDestroy(e);
         if (h->diag_stream) (void)hipStreamDestroy(h->diag_stream);
         for (auto& e : h->diag_ev) if (e) (void)hipEventDestroy(e);
         for (auto& e : h->lvl_ev) if (e) (void)hipEventDestroy(e);
