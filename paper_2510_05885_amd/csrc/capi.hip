@@ -483,7 +483,8 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
                 const size_t nsteps = ls.panel_first.size();
                 {
                     Span sp(h, st, TM_DIAG, h->tm.on ? diag_flops(P, ls, 0) : 0.0, 6);
-                    launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[0], (int)ls.diag_count[0], F, D, Mb, st);
+                    launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[0], (int)ls.diag_count[0], true, F, D,
+                                         Mb, st);
                 }
                 for (size_t k = 0; k < nsteps; ++k) {
                     {
@@ -497,8 +498,8 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
                         HIPCHK(hipStreamWaitEvent(h->diag_stream, h->diag_ev[0], 0));
                         {
                             Span sp(h, h->diag_stream, TM_DIAG, h->tm.on ? diag_flops(P, ls, k + 1) : 0.0, 6);
-                            launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[k + 1], (int)ls.diag_count[k + 1], F,
-                                                 D, Mb, h->diag_stream);
+                            launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[k + 1], (int)ls.diag_count[k + 1],
+                                                 false, F, D, Mb, h->diag_stream);
                         }
                         HIPCHK(hipEventRecord(h->diag_ev[1], h->diag_stream));
                     }

@@ -846,7 +846,7 @@ __device__ __forceinline__ void tile_update(const T* __restrict__ A, int f, int 
 // belong to the panel rows below it / the contribution block and are written
 // back to the front.
 template <typename T>
-__device__ __forceinline__ void diag_body(const DevPlan& d, int s, int k0, T* F, T* D, T* Zbuf, int tid) {
+__device__ __forceinline__ void diag_body(const DevPlan& d, int s, int k0, T* F, T* D, T* Zbuf, T* Pf, int tid) {
     const int first = d.sn_first[s];
     const int p = d.sn_first[s + 1] - first;
     const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
@@ -872,7 +872,6 @@ __device__ __forceinline__ void diag_body(const DevPlan& d, int s, int k0, T* F,
         // The block's own update by the previous panel (columns kp = k0 - 64
         // .. k0, all 64 wide): the block C and the panel's 64 rows are staged
         // in LDS by one coalesced pass, then C -= P D P^T on MFMA.
-        __shared__ T Pf[kPanel * LB];
         __shared__ T dp[kPanel];
         const int kp = k0 - kPanel;
         const int nr = min(kPanel, f - k0);   // rows of the block inside the front
@@ -947,10 +946,15 @@ __device__ __forceinline__ void diag_body(const DevPlan& d, int s, int k0, T* F,
                     tid);
 }
 
+// Pf (dynamic LDS, kPanel x (kPanel + 1)) stages the previous panel's rows
+// for the block's own update; launches of first panels (k0 = 0) pass none,
+// which doubles the workgroups per CU.
 template <typename T>
 __global__ __launch_bounds__(256) void k_large_diag(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
                                                     T* __restrict__ D, T* __restrict__ Zbuf) {
-    diag_body<T>(d, tasks[2 * blockIdx.x], tasks[2 * blockIdx.x + 1], F, D, Zbuf, threadIdx.x);
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    diag_body<T>(d, tasks[2 * blockIdx.x], tasks[2 * blockIdx.x + 1], F, D, Zbuf, reinterpret_cast<T*>(smem_raw),
+                 threadIdx.x);
 }
 
 // One workgroup per (front, panel, 32-row block) below the panel's diagonal
@@ -1095,6 +1099,7 @@ __global__ __launch_bounds__(256, 2) void k_large_flow(DevPlan d, const int* __r
                                                     const int* __restrict__ deps, int* ctr, int ticket, T* F, T* D,
                                                     T* Zbuf) {
     __shared__ int s_t;
+    __shared__ T Pf[kPanel * (kPanel + 1)];
     const int tid = threadIdx.x;
     for (;;) {
         if (tid == 0)
@@ -1113,7 +1118,7 @@ __global__ __launch_bounds__(256, 2) void k_large_flow(DevPlan d, const int* __r
             // across the loop (hoisted address arithmetic would exhaust registers).
             int tx = tid;
             asm volatile("" : "+v"(tx));
-            if (type == kFlowDiag) diag_body<T>(d, s, k0, F, D, Zbuf, tx);
+            if (type == kFlowDiag) diag_body<T>(d, s, k0, F, D, Zbuf, Pf, tx);
             else if (type == kFlowPanel) panel_body<T>(d, s, k0, a, F, D, Zbuf, tx);
             else update_body<T>(d, s, k0, a, b, F, D, tx);
             // Every wave waits for its own stores to reach the L2; after the
@@ -1947,9 +1952,11 @@ void launch_large_asm(const DevPlan& d, int64_t first, int count, int fmax, cons
 }
 
 template <typename T>
-void launch_large_diag(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st) {
+void launch_large_diag(const DevPlan& d, const int* tasks, int count, bool first_panel, T* F, T* D, T* M,
+                       hipStream_t st) {
     if (count <= 0) return;
-    launch(k_large_diag<T>, dim3(count), dim3(256), 0, st, d, tasks, F, D, M);
+    const size_t lds = first_panel ? 0 : sizeof(T) * kPanel * (kPanel + 1);
+    launch(k_large_diag<T>, dim3(count), dim3(256), lds, st, d, tasks, F, D, M);
 }
 
 template <typename T>
@@ -2091,6 +2098,7 @@ hipError_t configure_kernels(int max_dynamic_lds) {
                          (const void*)k_bwd_T<double>, (const void*)k_bwd_T<float>,
                          (const void*)k_fwd_S<double>, (const void*)k_fwd_S<float>,
                          (const void*)k_large_asm<double, true>, (const void*)k_large_asm<float, true>,
+                         (const void*)k_large_diag<double>, (const void*)k_large_diag<float>,
                          (const void*)k_bwd_S<double>, (const void*)k_bwd_S<float>};
     for (const void* f : fns) {
         hipFuncAttributes at{};
@@ -2106,7 +2114,7 @@ hipError_t configure_kernels(int max_dynamic_lds) {
 #define NCL_INSTANTIATE(T)                                                                                         \
     template void launch_small_fronts<T>(const DevPlan&, const int*, int, int, const double*, T*, T*, hipStream_t); \
     template void launch_large_asm<T>(const DevPlan&, int64_t, int, int, const double*, T*, hipStream_t);          \
-    template void launch_large_diag<T>(const DevPlan&, const int*, int, T*, T*, T*, hipStream_t);                \
+    template void launch_large_diag<T>(const DevPlan&, const int*, int, bool, T*, T*, T*, hipStream_t);          \
     template void launch_large_panel<T>(const DevPlan&, const int*, int, T*, const T*, const T*, hipStream_t);     \
     template void launch_large_update<T>(const DevPlan&, const int*, int, T*, T*, T*, hipStream_t);              \
     template void launch_large_flow<T>(const DevPlan&, const int*, int, const int*, int*, int, int, T*, T*, T*,       \

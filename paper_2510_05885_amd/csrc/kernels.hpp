@@ -101,7 +101,8 @@ void launch_small_fronts(const DevPlan& d, const int* list, int count, int fmax,
 template <typename T>
 void launch_large_asm(const DevPlan& d, int64_t first, int count, int fmax, const double* K, T* F, hipStream_t st);
 template <typename T>
-void launch_large_diag(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st);
+void launch_large_diag(const DevPlan& d, const int* tasks, int count, bool first_panel, T* F, T* D, T* M,
+                       hipStream_t st);   // first_panel: every task has k0 = 0
 template <typename T>
 void launch_large_panel(const DevPlan& d, const int* tasks, int count, T* F, const T* D, const T* M, hipStream_t st);
 template <typename T>
