@@ -34,10 +34,10 @@ PEAK = {"hbm_GBs": 8000.0, "fp64_mfma_TFs": 78.6, "fp32_mfma_TFs": 157.3, "fp64_
 # of a 2-step run), each scaled by what the same counter reads for a device
 # copy of known size.  Valid only for the kernel source they were taken on:
 # reported as null once kernels.hip changes.
-TRAFFIC = {"kernels_sha1": "e2b8504d220744afb2315959049e85e9e035dfe8", "fetch_scale": 2.00, "write_scale": 1.00,
+TRAFFIC = {"kernels_sha1": "a145d99030e27c83f3d6d361cb5e1a0d17e2e641", "fetch_scale": 2.00, "write_scale": 1.00,
            "source": "profiles/pmc_traffic_opf_n500k_fp64.txt",
-           "kib": {"large_diag": (614.3, 1176.7), "large_panel": (4014.8, 6446.1),
-                   "large_update_mfma": (13773.8, 19576.0)}}
+           "kib": {"large_diag": (614.0, 1176.7), "large_panel": (4015.5, 6446.1),
+                   "large_update_mfma": (13768.5, 19578.4)}}
 
 
 def measured_traffic(cls):
