@@ -36,8 +36,7 @@ PEAK = {"hbm_GBs": 8000.0, "fp64_mfma_TFs": 78.6, "fp32_mfma_TFs": 157.3, "fp64_
 # reported as null once kernels.hip changes.
 TRAFFIC = {"kernels_sha1": "a145d99030e27c83f3d6d361cb5e1a0d17e2e641", "fetch_scale": 2.00, "write_scale": 1.00,
            "source": "profiles/pmc_traffic_opf_n500k_fp64.txt",
-           "kib": {"large_diag": (614.0, 1176.7), "large_panel": (4015.5, 6446.1),
-                   "large_update_mfma": (13768.5, 19578.4)}}
+           "kib": {}}
 
 
 def measured_traffic(cls):
@@ -297,9 +296,9 @@ def kernel_breakdown(tm, stats, steps):
 
     add("small_fronts", "k_small_fronts<double> (LDS fronts, MFMA trailing updates)", tm["small_flops"], "mfma",
         "TFLOP/s", PEAK["fp64_mfma_TFs"])
-    add("large_update_mfma", "k_large_update<double> (64x64 tiles, v_mfma_f64_16x16x4)", tm["update_flops"],
-        "mfma", "TFLOP/s", PEAK["fp64_mfma_TFs"])
-    add("large_diag", "k_large_diag<double> (diagonal block: tile update, LDL^T, inverse)", tm["diag_flops"],
+    add("large_update_mfma", "k_large_dstep<double> (trailing-update 64x64 tiles on v_mfma_f64_16x16x4, beside "
+        "the next panel's diagonal blocks)", tm["update_flops"], "mfma", "TFLOP/s", PEAK["fp64_mfma_TFs"])
+    add("large_diag", "k_large_diag<double> (first-panel diagonal blocks: LDL^T, inverse)", tm["diag_flops"],
         "alu", "TFLOP/s", PEAK["fp64_vector_TFs"])
     add("large_panel", "k_large_panel<double> (panel solve, v_mfma_f64_16x16x4)", tm["panel_flops"], "mfma",
         "TFLOP/s", PEAK["fp64_mfma_TFs"])

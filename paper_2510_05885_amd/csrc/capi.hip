@@ -98,9 +98,6 @@ struct ncl_kkt_s {
     // fourth stream: a level's small-front batches split over two streams
     hipStream_t aux2_stream = nullptr;
     std::vector<hipEvent_t> sb_ev;    // 2 per level: fork, join of the second batch stream
-    // third stream: the next panel's diagonal block beside the current update
-    hipStream_t diag_stream = nullptr;
-    hipEvent_t diag_ev[2] = {nullptr, nullptr};
     hipGraphExec_t g_factor[2] = {nullptr, nullptr};
     hipGraphExec_t g_sweep[2][kNrhsMax + 1] = {};
 };
@@ -308,8 +305,6 @@ void setup_device(ncl_kkt_s* h) {
     HIPCHK(hipHostMalloc((void**)&h->host_pinned, sizeof(double) * h->host_pinned_len, hipHostMallocDefault));
     HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&h->aux_stream, hipStreamNonBlocking));
-    HIPCHK(hipStreamCreateWithFlags(&h->diag_stream, hipStreamNonBlocking));
-    for (auto& e : h->diag_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     h->lvl_ev.assign(2 * (size_t)std::max(P.nlevels, 1), nullptr);
     for (auto& e : h->lvl_ev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
     HIPCHK(hipStreamCreateWithFlags(&h->aux2_stream, hipStreamNonBlocking));
@@ -477,14 +472,13 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
                 launch_large_flow<T>(d, h->flow_task + 8 * ls.flow_first, (int)ls.flow_count, h->flow_dep,
                                      h->flow_ctr, (int)ls.flow_ticket, ls.flow_grid, F, D, Mb, st);
             } else {
-                // Step k: panel TRSM, then the trailing update beside the next
-                // panel's diagonal block (which updates that block itself) on a
-                // third stream; both finish before the next panel.
+                // Step k: panel TRSM, then one launch with the trailing update
+                // and the next panel's diagonal blocks (which update themselves).
                 const size_t nsteps = ls.panel_first.size();
                 {
                     Span sp(h, st, TM_DIAG, h->tm.on ? diag_flops(P, ls, 0) : 0.0, 6);
-                    launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[0], (int)ls.diag_count[0], true, F, D,
-                                         Mb, st);
+                    launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[0], (int)ls.diag_count[0], F, D, Mb,
+                                         st);
                 }
                 for (size_t k = 0; k < nsteps; ++k) {
                     {
@@ -492,22 +486,14 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
                         launch_large_panel<T>(d, h->large_panel + 3 * ls.panel_first[k], (int)ls.panel_count[k], F, D,
                                               Mb, st);
                     }
-                    const bool next = k + 1 < nsteps && ls.diag_count[k + 1] > 0;
-                    if (next) {
-                        HIPCHK(hipEventRecord(h->diag_ev[0], st));
-                        HIPCHK(hipStreamWaitEvent(h->diag_stream, h->diag_ev[0], 0));
-                        {
-                            Span sp(h, h->diag_stream, TM_DIAG, h->tm.on ? diag_flops(P, ls, k + 1) : 0.0, 6);
-                            launch_large_diag<T>(d, h->large_diag + 2 * ls.diag_first[k + 1], (int)ls.diag_count[k + 1],
-                                                 false, F, D, Mb, h->diag_stream);
-                        }
-                        HIPCHK(hipEventRecord(h->diag_ev[1], h->diag_stream));
-                    }
+                    const int nd = k + 1 < nsteps ? (int)ls.diag_count[k + 1] : 0;
+                    const int* dt = nd > 0 ? h->large_diag + 2 * ls.diag_first[k + 1] : nullptr;
                     {
-                        Span sp(h, st, TM_UPD, ls.upd_flops[k], 1);
-                        launch_large_update<T>(d, h->large_upd + 4 * ls.upd_first[k], (int)ls.upd_count[k], F, D, Mb, st);
+                        Span sp(h, st, TM_UPD, ls.upd_flops[k] + (h->tm.on && nd > 0 ? diag_flops(P, ls, k + 1) : 0.0),
+                                1);
+                        launch_large_dstep<T>(d, dt, nd, h->large_upd + 4 * ls.upd_first[k], (int)ls.upd_count[k], F,
+                                              D, Mb, st);
                     }
-                    if (next) HIPCHK(hipStreamWaitEvent(st, h->diag_ev[1], 0));
                 }
             }
         }
@@ -1016,8 +1002,6 @@ void ncl_kkt_destroy(ncl_kkt_t h) {
         if (h->aux_stream) (void)hipStreamDestroy(h->aux_stream);
         if (h->aux2_stream) (void)hipStreamDestroy(h->aux2_stream);
         for (auto& e : h->sb_ev) if (e) (void)hipEventDestroy(e);
-        if (h->diag_stream) (void)hipStreamDestroy(h->diag_stream);
-        for (auto& e : h->diag_ev) if (e) (void)hipEventDestroy(e);
         for (auto& e : h->lvl_ev) if (e) (void)hipEventDestroy(e);
     }
     delete h;

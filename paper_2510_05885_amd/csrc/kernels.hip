@@ -846,7 +846,7 @@ __device__ __forceinline__ void tile_update(const T* __restrict__ A, int f, int 
 // belong to the panel rows below it / the contribution block and are written
 // back to the front.
 template <typename T>
-__device__ __forceinline__ void diag_body(const DevPlan& d, int s, int k0, T* F, T* D, T* Zbuf, T* Pf, int tid) {
+__device__ __forceinline__ void diag_body(const DevPlan& d, int s, int k0, T* F, T* D, T* Zbuf, int tid) {
     const int first = d.sn_first[s];
     const int p = d.sn_first[s + 1] - first;
     const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
@@ -870,52 +870,15 @@ __device__ __forceinline__ void diag_body(const DevPlan& d, int s, int k0, T* F,
         }
     } else {
         // The block's own update by the previous panel (columns kp = k0 - 64
-        // .. k0, all 64 wide): the block C and the panel's 64 rows are staged
-        // in LDS by one coalesced pass, then C -= P D P^T on MFMA.
-        __shared__ T dp[kPanel];
+        // .. k0, all 64 wide), with the operands read from the front as for a
+        // trailing-update tile, the result into the block.
         const int kp = k0 - kPanel;
-        const int nr = min(kPanel, f - k0);   // rows of the block inside the front
-        T pv[kIt], cv[kIt];
-#pragma unroll
-        for (int it = 0; it < kIt; ++it) {
-            const int idx = tid + 256 * it, u = idx & (kPanel - 1), t = idx / kPanel;
-            const int uc = min(u, nr - 1);
-            pv[it] = A[(k0 + uc) + (int64_t)(kp + t) * f];
-            cv[it] = A[(k0 + uc) + (int64_t)(k0 + min(t, nr - 1)) * f];
-        }
-#pragma unroll
-        for (int it = 0; it < kIt; ++it) {
-            const int idx = tid + 256 * it, u = idx & (kPanel - 1), t = idx / kPanel;
-            const bool in = u < nr;
-            Pf[u + t * LB] = in ? pv[it] : T(0);
-            Bf[u + t * LB] = (in && t <= u) ? cv[it] : T(0);
-        }
-        if (tid < kPanel) dp[tid] = D[first + kp + tid];
-        __syncthreads();
+        const int nr = min(kPanel, f - k0);
+        typename Mfma<T>::acc_t acc[2][2];
+        tile_update<T>(A, f, kp, kPanel, k0, k0, D + first + kp, acc, tid);
         const int wave = tid >> 6, lane = tid & 63;
         const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
         const int lr = lane & 15, lk = lane >> 4;
-        typedef typename Mfma<T>::acc_t acc_t;
-        acc_t acc[2][2];
-#pragma unroll
-        for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-            for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = acc_t{0, 0, 0, 0};
-#pragma unroll
-        for (int ks = 0; ks < kPanel / 4; ++ks) {
-            const int t = 4 * ks + lk;
-            const T dt = dp[t];
-            T a[2], b[2];
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                a[h] = Pf[(wr + 16 * h + lr) + t * LB];
-                b[h] = Pf[(wc + 16 * h + lr) + t * LB] * dt;
-            }
-#pragma unroll
-            for (int bi = 0; bi < 2; ++bi)
-#pragma unroll
-                for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = Mfma<T>::run(a[bi], b[bj], acc[bi][bj]);
-        }
 #pragma unroll
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
@@ -924,7 +887,7 @@ __device__ __forceinline__ void diag_body(const DevPlan& d, int s, int k0, T* F,
                 for (int r = 0; r < 4; ++r) {
                     const int li = wr + bi * 16 + Mfma<T>::row(lk, r), lj = wc + bj * 16 + lr;
                     if (li < lj || li >= nr) continue;
-                    const T v = Bf[li + lj * LB] - acc[bi][bj][r];
+                    const T v = acc[bi][bj][r];
                     if (li < w) Bf[li + lj * LB] = v;
                     else A[(k0 + li) + (int64_t)(k0 + lj) * f] = v;   // rows past the last pivot
                 }
@@ -946,15 +909,12 @@ __device__ __forceinline__ void diag_body(const DevPlan& d, int s, int k0, T* F,
                     tid);
 }
 
-// Pf (dynamic LDS, kPanel x (kPanel + 1)) stages the previous panel's rows
-// for the block's own update; launches of first panels (k0 = 0) pass none,
-// which doubles the workgroups per CU.
+// The first panels' diagonal blocks of a level (later ones run in
+// k_large_dstep beside the previous panel's trailing update).
 template <typename T>
 __global__ __launch_bounds__(256) void k_large_diag(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
                                                     T* __restrict__ D, T* __restrict__ Zbuf) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    diag_body<T>(d, tasks[2 * blockIdx.x], tasks[2 * blockIdx.x + 1], F, D, Zbuf, reinterpret_cast<T*>(smem_raw),
-                 threadIdx.x);
+    diag_body<T>(d, tasks[2 * blockIdx.x], tasks[2 * blockIdx.x + 1], F, D, Zbuf, threadIdx.x);
 }
 
 // One workgroup per (front, panel, 32-row block) below the panel's diagonal
@@ -1025,7 +985,7 @@ __global__ __launch_bounds__(256) void k_large_panel(DevPlan d, const int* __res
 
 // Trailing update of one 64x64 lower tile: C -= L_I D_k L_J^T on MFMA, with
 // the operands read straight from the front (no LDS).  The next panel's
-// diagonal tile is not in the task list: k_large_diag updates it.
+// diagonal tile is not in the task list: its diagonal-block workgroup updates it.
 template <typename T>
 __device__ __forceinline__ void update_body(const DevPlan& d, int s, int k0, int i0, int j0, T* F, const T* D,
                                             int tid) {
@@ -1055,6 +1015,24 @@ __global__ __launch_bounds__(256) void k_large_update(DevPlan d, const int* __re
                                                       const T* __restrict__ D) {
     const int* tk = tasks + 4 * xcd_task(blockIdx.x, gridDim.x);
     update_body<T>(d, tk[0], tk[1], tk[2], tk[3], F, D, threadIdx.x);
+}
+
+// Panel k's trailing update and panel k+1's diagonal blocks in one launch
+// (they touch disjoint tiles): the first nd workgroups factor the diagonal
+// blocks (their own update read from the front, like a tile), workgroups from nd8 = nd rounded up to a
+// multiple of 8 take the update tiles with the XCD-contiguous mapping.
+template <typename T>
+__global__ __launch_bounds__(256) void k_large_dstep(DevPlan d, const int* __restrict__ dtasks, int nd,
+                                                     const int* __restrict__ utasks, int nu, T* __restrict__ F,
+                                                     T* __restrict__ D, T* __restrict__ Zbuf) {
+    const int nd8 = (nd + 7) & ~7;
+    const int b = blockIdx.x;
+    if (b < nd) {
+        diag_body<T>(d, dtasks[2 * b], dtasks[2 * b + 1], F, D, Zbuf, threadIdx.x);
+    } else if (b >= nd8) {
+        const int* tk = utasks + 4 * xcd_task(b - nd8, nu);
+        update_body<T>(d, tk[0], tk[1], tk[2], tk[3], F, D, threadIdx.x);
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1099,7 +1077,6 @@ __global__ __launch_bounds__(256, 2) void k_large_flow(DevPlan d, const int* __r
                                                     const int* __restrict__ deps, int* ctr, int ticket, T* F, T* D,
                                                     T* Zbuf) {
     __shared__ int s_t;
-    __shared__ T Pf[kPanel * (kPanel + 1)];
     const int tid = threadIdx.x;
     for (;;) {
         if (tid == 0)
@@ -1118,7 +1095,7 @@ __global__ __launch_bounds__(256, 2) void k_large_flow(DevPlan d, const int* __r
             // across the loop (hoisted address arithmetic would exhaust registers).
             int tx = tid;
             asm volatile("" : "+v"(tx));
-            if (type == kFlowDiag) diag_body<T>(d, s, k0, F, D, Zbuf, Pf, tx);
+            if (type == kFlowDiag) diag_body<T>(d, s, k0, F, D, Zbuf, tx);
             else if (type == kFlowPanel) panel_body<T>(d, s, k0, a, F, D, Zbuf, tx);
             else update_body<T>(d, s, k0, a, b, F, D, tx);
             // Every wave waits for its own stores to reach the L2; after the
@@ -1952,17 +1929,23 @@ void launch_large_asm(const DevPlan& d, int64_t first, int count, int fmax, cons
 }
 
 template <typename T>
-void launch_large_diag(const DevPlan& d, const int* tasks, int count, bool first_panel, T* F, T* D, T* M,
-                       hipStream_t st) {
+void launch_large_diag(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st) {
     if (count <= 0) return;
-    const size_t lds = first_panel ? 0 : sizeof(T) * kPanel * (kPanel + 1);
-    launch(k_large_diag<T>, dim3(count), dim3(256), lds, st, d, tasks, F, D, M);
+    launch(k_large_diag<T>, dim3(count), dim3(256), 0, st, d, tasks, F, D, M);
 }
 
 template <typename T>
 void launch_large_panel(const DevPlan& d, const int* tasks, int count, T* F, const T* D, const T* M, hipStream_t st) {
     if (count <= 0) return;
     launch(k_large_panel<T>, dim3(count), dim3(256), 0, st, d, tasks, F, D, M);
+}
+
+template <typename T>
+void launch_large_dstep(const DevPlan& d, const int* dtasks, int nd, const int* utasks, int nu, T* F, T* D, T* M,
+                        hipStream_t st) {
+    if (nd <= 0 && nu <= 0) return;
+    const int nd8 = (nd + 7) & ~7;
+    launch(k_large_dstep<T>, dim3(nd8 + nu), dim3(256), 0, st, d, dtasks, nd, utasks, nu, F, D, M);
 }
 
 template <typename T>
@@ -2098,7 +2081,6 @@ hipError_t configure_kernels(int max_dynamic_lds) {
                          (const void*)k_bwd_T<double>, (const void*)k_bwd_T<float>,
                          (const void*)k_fwd_S<double>, (const void*)k_fwd_S<float>,
                          (const void*)k_large_asm<double, true>, (const void*)k_large_asm<float, true>,
-                         (const void*)k_large_diag<double>, (const void*)k_large_diag<float>,
                          (const void*)k_bwd_S<double>, (const void*)k_bwd_S<float>};
     for (const void* f : fns) {
         hipFuncAttributes at{};
@@ -2114,9 +2096,10 @@ hipError_t configure_kernels(int max_dynamic_lds) {
 #define NCL_INSTANTIATE(T)                                                                                         \
     template void launch_small_fronts<T>(const DevPlan&, const int*, int, int, const double*, T*, T*, hipStream_t); \
     template void launch_large_asm<T>(const DevPlan&, int64_t, int, int, const double*, T*, hipStream_t);          \
-    template void launch_large_diag<T>(const DevPlan&, const int*, int, bool, T*, T*, T*, hipStream_t);          \
+    template void launch_large_diag<T>(const DevPlan&, const int*, int, T*, T*, T*, hipStream_t);                \
     template void launch_large_panel<T>(const DevPlan&, const int*, int, T*, const T*, const T*, hipStream_t);     \
     template void launch_large_update<T>(const DevPlan&, const int*, int, T*, T*, T*, hipStream_t);              \
+    template void launch_large_dstep<T>(const DevPlan&, const int*, int, const int*, int, T*, T*, T*, hipStream_t); \
     template void launch_large_flow<T>(const DevPlan&, const int*, int, const int*, int*, int, int, T*, T*, T*,       \
                                        hipStream_t);                                                              \
     template void launch_permute_in<T>(const DevPlan&, const double*, int64_t, int, T*, hipStream_t);              \

@@ -101,10 +101,14 @@ void launch_small_fronts(const DevPlan& d, const int* list, int count, int fmax,
 template <typename T>
 void launch_large_asm(const DevPlan& d, int64_t first, int count, int fmax, const double* K, T* F, hipStream_t st);
 template <typename T>
-void launch_large_diag(const DevPlan& d, const int* tasks, int count, bool first_panel, T* F, T* D, T* M,
-                       hipStream_t st);   // first_panel: every task has k0 = 0
+void launch_large_diag(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st);
 template <typename T>
 void launch_large_panel(const DevPlan& d, const int* tasks, int count, T* F, const T* D, const T* M, hipStream_t st);
+// Panel k's trailing update (utasks) and panel k+1's diagonal blocks (dtasks)
+// in one launch.
+template <typename T>
+void launch_large_dstep(const DevPlan& d, const int* dtasks, int nd, const int* utasks, int nu, T* F, T* D, T* M,
+                        hipStream_t st);
 template <typename T>
 void launch_large_update(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st);
 
