@@ -223,17 +223,19 @@ int ncl_kkt_get_flow(ncl_kkt_t h, int64_t *counts, int32_t *tasks, int32_t *deps
  * and launch counts, readable with ncl_kkt_get_timing. */
 typedef struct {
     double ms[8];          /* 0 assemble, 1 small fronts, 2 large-front assembly,
-                              3 large-front panel solve, 4 large-front update (MFMA),
+                              3 large-front panel solve, 4 large-front trailing update (MFMA)
+                              with the next panel's diagonal blocks in the same launch,
                               5 forward/backward solve, 6 residual,
-                              7 large-front diagonal blocks (LDL^T + inverse) */
+                              7 large-front first-panel diagonal blocks (LDL^T + inverse) */
     int64_t launches[8];
-    double update_flops;   /* algorithmic flops of all update launches timed */
+    double update_flops;   /* algorithmic flops of all update launches timed (tiles and the
+                              diagonal blocks launched with them) */
     double small_flops;    /* algorithmic flops of all small-front launches timed */
     double assemble_bytes; /* algorithmic bytes of all assembly launches timed */
     double solve_bytes;    /* algorithmic bytes of all solve sweeps timed */
     double panel_flops;    /* algorithmic flops of all panel-solve launches timed (rows x w^2) */
-    double diag_flops;     /* algorithmic flops of all diagonal-block launches timed: per block
-                              w^3/3 (LDL^T) + w^3/3 (inverse) + w^3 (its update, after the first) */
+    double diag_flops;     /* algorithmic flops of all first-panel diagonal-block launches timed:
+                              per block w^3/3 (LDL^T) + w^3/3 (inverse) */
 } ncl_kkt_timing;
 
 int ncl_kkt_set_timing(ncl_kkt_t h, int32_t enable);   /* enabling also clears totals */
