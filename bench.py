@@ -34,10 +34,10 @@ PEAK = {"hbm_GBs": 8000.0, "fp64_mfma_TFs": 78.6, "fp32_mfma_TFs": 157.3, "fp64_
 # of a 2-step run), each scaled by what the same counter reads for a device
 # copy of known size.  Valid only for the kernel source they were taken on:
 # reported as null once kernels.hip changes.
-TRAFFIC = {"kernels_sha1": "e3fab9f55c1cbf5a00396b3e98c59848ff88c2ef", "fetch_scale": 2.00, "write_scale": 1.00,
+TRAFFIC = {"kernels_sha1": "d3e8ded8f82c22a8c28925a840fd0b0c0b605ca0", "fetch_scale": 2.00, "write_scale": 1.00,
            "source": "profiles/pmc_traffic_opf_n500k_fp64.txt",
-           "kib": {"large_update_mfma": (13924.6, 19677.8), "large_diag": (1681.1, 5609.8),
-                   "large_panel": (4015.6, 6447.2)}}
+           "kib": {"large_update_mfma": (13924.8, 19676.4), "large_diag": (1680.2, 5609.8),
+                   "large_panel": (4015.3, 6448.7)}}
 
 
 def measured_traffic(cls):

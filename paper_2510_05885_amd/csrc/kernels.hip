@@ -1010,13 +1010,6 @@ __device__ __forceinline__ void update_body(const DevPlan& d, int s, int k0, int
             }
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_large_update(DevPlan d, const int* __restrict__ tasks, T* __restrict__ F,
-                                                      const T* __restrict__ D) {
-    const int* tk = tasks + 4 * xcd_task(blockIdx.x, gridDim.x);
-    update_body<T>(d, tk[0], tk[1], tk[2], tk[3], F, D, threadIdx.x);
-}
-
 // Panel k's trailing update and panel k+1's diagonal blocks in one launch
 // (they touch disjoint tiles): the first nd workgroups factor the diagonal
 // blocks (their own update read from the front, like a tile), workgroups from nd8 = nd rounded up to a
@@ -1948,12 +1941,6 @@ void launch_large_dstep(const DevPlan& d, const int* dtasks, int nd, const int* 
     launch(k_large_dstep<T>, dim3(nd8 + nu), dim3(256), 0, st, d, dtasks, nd, utasks, nu, F, D, M);
 }
 
-template <typename T>
-void launch_large_update(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st) {
-    if (count <= 0) return;
-    (void)M;
-    launch(k_large_update<T>, dim3(count), dim3(256), 0, st, d, tasks, F, (const T*)D);
-}
 
 template <typename T>
 void launch_large_flow(const DevPlan& d, const int* tasks, int ntask, const int* deps, int* ctr, int ticket, int grid,
@@ -2098,7 +2085,6 @@ hipError_t configure_kernels(int max_dynamic_lds) {
     template void launch_large_asm<T>(const DevPlan&, int64_t, int, int, const double*, T*, hipStream_t);          \
     template void launch_large_diag<T>(const DevPlan&, const int*, int, T*, T*, T*, hipStream_t);                \
     template void launch_large_panel<T>(const DevPlan&, const int*, int, T*, const T*, const T*, hipStream_t);     \
-    template void launch_large_update<T>(const DevPlan&, const int*, int, T*, T*, T*, hipStream_t);              \
     template void launch_large_dstep<T>(const DevPlan&, const int*, int, const int*, int, T*, T*, T*, hipStream_t); \
     template void launch_large_flow<T>(const DevPlan&, const int*, int, const int*, int*, int, int, T*, T*, T*,       \
                                        hipStream_t);                                                              \

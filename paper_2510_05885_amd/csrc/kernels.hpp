@@ -109,8 +109,6 @@ void launch_large_panel(const DevPlan& d, const int* tasks, int count, T* F, con
 template <typename T>
 void launch_large_dstep(const DevPlan& d, const int* dtasks, int nd, const int* utasks, int nu, T* F, T* D, T* M,
                         hipStream_t st);
-template <typename T>
-void launch_large_update(const DevPlan& d, const int* tasks, int count, T* F, T* D, T* M, hipStream_t st);
 
 // ---- solves -----------------------------------------------------------------
 // One level's large-front factorization as a single dataflow launch: tasks
