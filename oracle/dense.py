@@ -11,8 +11,10 @@ from __future__ import annotations
 import numpy as np
 
 
-def ldl(A: np.ndarray, signs=None, pivot_thr: float = 0.0):
-    """A (N x N, symmetric, already permuted) -> (L unit lower, D, nperturbed)."""
+def ldl(A: np.ndarray, signs=None, pivot_thr=0.0):
+    """A (N x N, symmetric, already permuted) -> (L unit lower, D, nperturbed).
+    pivot_thr: one threshold, or a (primal, dual) pair chosen by signs[k]."""
+    tp, td = (pivot_thr, pivot_thr) if np.ndim(pivot_thr) == 0 else pivot_thr
     A = np.array(A, dtype=np.float64, copy=True)
     N = A.shape[0]
     L = np.eye(N)
@@ -20,9 +22,10 @@ def ldl(A: np.ndarray, signs=None, pivot_thr: float = 0.0):
     npert = 0
     for k in range(N):
         d = A[k, k]
-        if pivot_thr > 0.0 and abs(d) < pivot_thr:
-            s = 1 if signs is None else int(signs[k])
-            d = pivot_thr if s > 0 else -pivot_thr
+        s = 1 if signs is None else int(signs[k])
+        t = tp if s > 0 else td
+        if t > 0.0 and abs(d) < t:
+            d = t if s > 0 else -t
             npert += 1
         D[k] = d
         col = A[k + 1:, k].copy()

@@ -483,13 +483,18 @@ static int row_reach(int k, const int *Rp, const int *Rj, const int *parent, int
 
 
 /* Factor P K P^T = L D L^T, K symmetric in lower CSC (original ordering),
- * perm[k] = original index of pivot k.  Static pivot (Sec. 3.1): when
- * |d_k| < pivot_thr (strict), d_k is replaced by sign[perm[k]] * pivot_thr,
- * where sign is +1 for primal rows and -1 for dual rows of the unpermuted
- * matrix.  pivot_thr <= 0 disables the rule.  On NaN/Inf: status -6; on an
- * exact zero pivot that the rule did not replace: status -7. */
+ * perm[k] = original index of pivot k.  Static pivot (Sec. 3.1): pivot k
+ * belongs to the primal block when sign[perm[k]] > 0 and to the dual block
+ * otherwise (blocks of the unpermuted matrix); its threshold t is thr_primal
+ * or thr_dual accordingly.  When |d_k| < t (strict), d_k is replaced by t for
+ * a primal pivot and by -t for a dual pivot.  A threshold <= 0 disables the
+ * rule for its block.  With one global threshold both are equal; with
+ * block-scaled thresholds each block uses its own norm (the -1/rho block of
+ * Sec. 3.2, eq. K2r, is then measured against 1/rho, not against W + Sigma).
+ * On NaN/Inf: status -6; on an exact zero pivot that the rule did not
+ * replace: status -7. */
 or_ldl *or_factor(int N, const int *Kp, const int *Ki, const double *Kx, const int *perm,
-                  const signed char *sign, double pivot_thr, int *status)
+                  const signed char *sign, double thr_primal, double thr_dual, int *status)
 {
     *status = OR_OK;
     or_ldl *F = calloc(1, sizeof(or_ldl));
@@ -580,9 +585,13 @@ or_ldl *or_factor(int N, const int *Kp, const int *Ki, const double *Kx, const i
             F->Lx[p] = lki;
         }
         if (!isfinite(d)) { *status = OR_ERR_NONFINITE; goto fail; }
-        if (pivot_thr > 0.0 && fabs(d) < pivot_thr) {
-            d = (sign[perm[k]] < 0 ? -pivot_thr : pivot_thr);
-            F->nperturbed++;
+        {
+            int dual = sign[perm[k]] < 0;
+            double t = dual ? thr_dual : thr_primal;
+            if (t > 0.0 && fabs(d) < t) {
+                d = dual ? -t : t;
+                F->nperturbed++;
+            }
         }
         if (d > 0.0) F->npos++;
         else if (d < 0.0) F->nneg++;

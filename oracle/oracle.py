@@ -66,7 +66,8 @@ def _L():
         lib.or_norms.restype = None
         lib.or_mindeg.argtypes = [C.c_int, _i32p, _i32p, _i32p]
         lib.or_mindeg.restype = C.c_int
-        lib.or_factor.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i8p, C.c_double, C.POINTER(C.c_int)]
+        lib.or_factor.argtypes = [C.c_int, _i32p, _i32p, _f64p, _i32p, _i8p, C.c_double, C.c_double,
+                                  C.POINTER(C.c_int)]
         lib.or_factor.restype = C.c_void_p
         lib.or_free.argtypes = [C.c_void_p]
         lib.or_free.restype = None
@@ -139,6 +140,28 @@ def norms(K: LowerCSC):
     return a.value, b.value
 
 
+def primal_block_max(K: LowerCSC, n: int) -> float:
+    """max |K_ij| over the primal block i, j < n (the whole matrix for the
+    condensed form; W + Sigma for the stabilized one).  In lower CSC an entry
+    with row i < n also has column j <= i < n."""
+    sel = K.i < n
+    return float(np.abs(K.x[sel]).max()) if np.any(sel) else 0.0
+
+
+def pivot_thresholds(K: LowerCSC, n: int, m: int, form: int, rho: float, eps: float, scale: str = "global"):
+    """(primal, dual) static-pivot thresholds (Sec. 3.1).  "global": both are
+    eps * max_ij |K_ij| of the assembled matrix.  "block": each block of the
+    stabilized matrix uses its own norm, eps * max |K_xx| for primal pivots and
+    eps / rho (the -1/rho I block of Sec. 3.2, eq. K2r) for dual pivots; for
+    the condensed form this is the global rule."""
+    if scale == "global" or form == CONDENSED:
+        t = eps * norms(K)[0]
+        return t, t
+    if scale != "block":
+        raise ValueError(scale)
+    return eps * primal_block_max(K, n), eps / rho
+
+
 def block_signs(n: int, m: int, form: int) -> np.ndarray:
     """+1 for primal rows, -1 for dual rows, in the unpermuted ordering."""
     s = np.ones(n if form == CONDENSED else n + m, np.int8)
@@ -166,13 +189,15 @@ class OracleError(RuntimeError):
 class LDL:
     """P K P^T = L D L^T with static pivoting (Sec. 3.1), K lower CSC."""
 
-    def __init__(self, K: LowerCSC, perm=None, signs=None, pivot_thr: float = 0.0):
+    def __init__(self, K: LowerCSC, perm=None, signs=None, pivot_thr=0.0):
+        """pivot_thr: one threshold for every pivot, or a (primal, dual) pair."""
         lib = _L()
         self.N = K.N
         self.perm = np.ascontiguousarray(mindeg(K) if perm is None else perm, np.int32)
         sg = np.ones(K.N, np.int8) if signs is None else np.ascontiguousarray(signs, np.int8)
+        tp, td = (pivot_thr, pivot_thr) if np.ndim(pivot_thr) == 0 else pivot_thr
         st = C.c_int(0)
-        h = lib.or_factor(K.N, K.p, K.i, K.x, self.perm, sg, float(pivot_thr), C.byref(st))
+        h = lib.or_factor(K.N, K.p, K.i, K.x, self.perm, sg, float(tp), float(td), C.byref(st))
         self.status = st.value
         if not h:
             raise OracleError(f"oracle factorization failed (status {st.value})")
@@ -224,6 +249,26 @@ def backward_error(K: LowerCSC, X, B, Kinf=None) -> np.ndarray:
     return np.abs(R).max(axis=0) / np.where(den > 0, den, 1.0)
 
 
+def componentwise_backward_error(K: LowerCSC, X, B) -> np.ndarray:
+    """Componentwise (Oettli-Prager) backward error per column:
+    max_i |b - Kx|_i / (|K| |x| + |b|)_i, rows with a zero denominator skipped
+    when their residual is zero too (infinite otherwise)."""
+    X2 = np.asarray(X).reshape(K.N, -1); B2 = np.asarray(B).reshape(K.N, -1)
+    R = np.abs(B2 - symv(K, X2))
+    Ka = LowerCSC(K.N, K.p, K.i, np.abs(K.x))
+    den = symv(Ka, np.abs(X2)) + np.abs(B2)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        q = np.where(den > 0, R / np.where(den > 0, den, 1.0), np.where(R > 0, np.inf, 0.0))
+    return q.max(axis=0)
+
+
+def residual_rel2(K: LowerCSC, X, B) -> np.ndarray:
+    """||b - Kx||_2 / ||b||_2 per column."""
+    X2 = np.asarray(X).reshape(K.N, -1); B2 = np.asarray(B).reshape(K.N, -1)
+    nb = np.linalg.norm(B2, axis=0)
+    return np.linalg.norm(B2 - symv(K, X2), axis=0) / np.where(nb > 0, nb, 1.0)
+
+
 @dataclass
 class SolveInfo:
     inertia: tuple = ()
@@ -268,17 +313,19 @@ def refine(K: LowerCSC, F: LDL, B, ir_max: int = 10, ir_tol: float = 1e-12, ir_s
 
 
 def solve(inp, form: int, B, eps=None, ir_max: int = 10, ir_tol: float = 1e-12, ir_stall: float = 0.5,
-          perm=None, K: LowerCSC | None = None):
+          perm=None, K: LowerCSC | None = None, pivot_scale: str = "global"):
     """Assemble, order, factor with static pivoting and refine: the whole path
     in FP64 on the CPU.  eps is relative to max_ij |K_ij| (pivot rule
-    |d| < eps*||K||_max -> d = sign*eps*||K||_max).  Refinement runs only when
+    |d| < eps*||K||_max -> d = sign*eps*||K||_max), or to each block's own norm
+    with pivot_scale="block" (see pivot_thresholds).  Refinement runs only when
     the inertia is the expected one (Sec. 4.3)."""
     if K is None:
         K = assemble(inp, form)
     if eps is None:
         eps = DEFAULT_EPS[form]
     kmax, kinf = norms(K)
-    F = LDL(K, perm=perm, signs=block_signs(inp.n, inp.m, form), pivot_thr=eps * kmax)
+    thr = pivot_thresholds(K, inp.n, inp.m, form, inp.rho, eps, pivot_scale)
+    F = LDL(K, perm=perm, signs=block_signs(inp.n, inp.m, form), pivot_thr=thr)
     if F.status not in (0,):
         raise OracleError(f"factorization status {F.status}")
     info = SolveInfo(inertia=F.inertia(), nnz_L=F.nnz_L())

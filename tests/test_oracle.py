@@ -310,3 +310,153 @@ def test_adjoint_against_finite_differences():
         assert abs(fd("J_val", k) - gJ[k]) <= 1e-6 * abs(gJ[k]) + 1e-8
     lp = loss(inp.with_values(rho=inp.rho + h)); lm = loss(inp.with_values(rho=inp.rho - h))
     assert abs((lp - lm) / (2 * h) - grho) <= 1e-6 * abs(grho) + 1e-9
+
+
+# ---------------------------------------------------------------------------
+# Norms, backward errors and block-scaled pivot thresholds, against dense numpy
+# ---------------------------------------------------------------------------
+
+def _norm_cases():
+    inp, _ = _tiny_input()
+    out = [(inp, O.CONDENSED), (inp, O.STABILIZED)]
+    for seed in range(3):
+        r = synth.random_system(35, 14, seed=20 + seed, rho=1e3, spd=seed != 1)
+        out += [(r, O.CONDENSED), (r, O.STABILIZED)]
+    g = synth.grid_banded(nr=10, nc=12, m=50, band=20, rho=1e4, seed=2)
+    out += [(g, O.CONDENSED), (g, O.STABILIZED)]
+    return out
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_norms_match_dense(case):
+    """max_ij |K_ij| (the static-pivot scale, Sec. 3.1) and ||K||_inf (the
+    backward-error scale) equal the dense matrix's, both forms."""
+    inp, form = _norm_cases()[case]
+    K = O.assemble(inp, form)
+    Kd = K.dense()
+    kmax, kinf = O.norms(K)
+    assert kmax == np.abs(Kd).max()
+    assert abs(kinf - np.abs(Kd).sum(axis=1).max()) <= 1e-15 * kinf
+    n = inp.n
+    assert O.primal_block_max(K, n) == np.abs(Kd[:n, :n]).max()
+
+
+def _mutant_norms_lib(tmp_path, drop):
+    """The oracle's C source with one statement removed, compiled on the side
+    (a planted mistake: the suite must notice it)."""
+    import ctypes
+    import subprocess
+    src = open(os.path.join(os.path.dirname(O.__file__), "ncl_oracle.c")).read()
+    assert drop in src
+    p = tmp_path / "mutant.c"
+    p.write_text(src.replace(drop, ";"))
+    so = tmp_path / "mutant.so"
+    subprocess.check_call(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-o", str(so), str(p), "-lm"])
+    return ctypes.CDLL(str(so))
+
+
+def test_norms_pin_catches_dropped_mirror(tmp_path):
+    """A plausible slip in the row sums (the mirrored off-diagonal entry not
+    counted) changes ||K||_inf and is caught by the dense comparison above."""
+    import ctypes
+    lib = _mutant_norms_lib(tmp_path, "if (Ki[p] != j) rs[j] += a;")
+    inp = synth.random_system(35, 14, seed=21, rho=1e3)
+    K = O.assemble(inp, O.CONDENSED)
+    a, b = ctypes.c_double(), ctypes.c_double()
+    ip = lambda x: x.ctypes.data_as(ctypes.c_void_p)
+    lib.or_norms(ctypes.c_int(K.N), ip(K.p), ip(K.i), ip(K.x), ctypes.byref(a), ctypes.byref(b))
+    assert abs(b.value - np.abs(K.dense()).sum(axis=1).max()) > 1e-6 * b.value
+
+
+@pytest.mark.parametrize("case", range(10))
+def test_backward_errors_match_dense(case):
+    """Normwise omega = ||b-Kx||_inf / (||K||_inf ||x||_inf + ||b||_inf),
+    componentwise max_i |b-Kx|_i / (|K||x|+|b|)_i and ||b-Kx||_2/||b||_2,
+    each against its dense definition, on a perturbed solution."""
+    inp, form = _norm_cases()[case]
+    K = O.assemble(inp, form)
+    Kd = K.dense()
+    rng = np.random.default_rng(case)
+    B = rng.standard_normal((K.N, 3))
+    # relative perturbation 1e-6: residuals far above the rounding of either product
+    X = np.linalg.solve(Kd, B) * (1.0 + 1e-6 * rng.standard_normal((K.N, 3)))
+    R = B - Kd @ X
+    om = np.abs(R).max(0) / (np.abs(Kd).sum(1).max() * np.abs(X).max(0) + np.abs(B).max(0))
+    assert np.allclose(O.backward_error(K, X, B), om, rtol=1e-8, atol=0)
+    cw = (np.abs(R) / (np.abs(Kd) @ np.abs(X) + np.abs(B))).max(0)
+    assert np.allclose(O.componentwise_backward_error(K, X, B), cw, rtol=1e-8, atol=0)
+    r2 = np.linalg.norm(R, axis=0) / np.linalg.norm(B, axis=0)
+    assert np.allclose(O.residual_rel2(K, X, B), r2, rtol=1e-8, atol=0)
+    # the exact solution of a tiny system has a residual at rounding level
+    assert O.componentwise_backward_error(K, np.linalg.solve(Kd, B), B).max() <= 1e-13
+
+
+def test_componentwise_error_sees_what_normwise_misses():
+    """A wrong entry in a row of small |K||x| leaves the normwise omega tiny
+    (||K||_inf is set by other rows) but not the componentwise one."""
+    n = 4
+    Kd = np.diag([1e12, 1.0, 1.0, 1.0])
+    K = O.LowerCSC(n, np.arange(n + 1, dtype=np.int32), np.arange(n, dtype=np.int32), np.diag(Kd).copy())
+    b = np.ones(n)
+    x = np.linalg.solve(Kd, b)
+    x[3] *= 1.5
+    assert O.backward_error(K, x, b)[0] < 1e-12
+    assert O.componentwise_backward_error(K, x, b)[0] == pytest.approx(0.5 / 2.5)
+
+
+@pytest.mark.parametrize("seed", [0, 1])
+def test_block_pivot_scale_dual_block(seed):
+    """Block-scaled thresholds (the -1/rho I block of Sec. 3.2, eq. K2r,
+    against its own norm 1/rho): with the dual block ordered first at
+    rho = 1e14 the global rule replaces every -1/rho pivot by -eps*||K||_max,
+    the block rule keeps -1/rho exactly (eq. ldlk2r: D11 = -1/rho).  Dense
+    brute force under the same thresholds gives the same D."""
+    inp = synth.random_system(20, 6, seed=30 + seed, rho=1e14)
+    n, m = inp.n, inp.m
+    K = O.assemble(inp, O.STABILIZED)
+    Kd = K.dense()
+    perm = np.concatenate([n + np.arange(m), np.arange(n)]).astype(np.int32)
+    sg = O.block_signs(n, m, O.STABILIZED)
+    tg = O.pivot_thresholds(K, n, m, O.STABILIZED, inp.rho, 1e-10, "global")
+    tb = O.pivot_thresholds(K, n, m, O.STABILIZED, inp.rho, 1e-10, "block")
+    assert tg == (1e-10 * np.abs(Kd).max(),) * 2
+    assert tb == (1e-10 * np.abs(Kd[:n, :n]).max(), 1e-10 / inp.rho)
+    Fg = O.LDL(K, perm=perm, signs=sg, pivot_thr=tg)
+    Fb = O.LDL(K, perm=perm, signs=sg, pivot_thr=tb)
+    _, Dg, _ = Fg.factor()
+    _, Db, _ = Fb.factor()
+    assert Fg.inertia() == (n, m, 0, m) and np.all(Dg[:m] == -tg[1])
+    assert Fb.inertia() == (n, m, 0, 0) and np.all(Db[:m] == -1.0 / inp.rho)
+    for thr, D, npert in ((tg, Dg, m), (tb, Db, 0)):
+        _, Dd, npd = dense.ldl(Kd[np.ix_(perm, perm)], signs=sg[perm], pivot_thr=thr)
+        # the dual pivots exactly; the primal ones carry rho * J^T J at rho = 1e14
+        # and differ by rounding between the two elimination orders
+        assert npd == npert and np.array_equal(D[:m], Dd[:m])
+        assert np.allclose(D[m:], Dd[m:], rtol=1e-6, atol=1e-14 * np.abs(Dd).max())
+    # condensed form: the block rule is the global rule
+    Kc = O.assemble(inp, O.CONDENSED)
+    assert O.pivot_thresholds(Kc, n, m, O.CONDENSED, inp.rho, 1e-12, "block") == \
+        O.pivot_thresholds(Kc, n, m, O.CONDENSED, inp.rho, 1e-12, "global")
+
+
+def test_block_pivot_scale_primal_threshold_uses_primal_block():
+    """A primal zero pivot met first is replaced by +eps*max|K_xx| under the
+    block rule (and by +eps*max|K| under the global rule)."""
+    inp = synth.random_system(30, 10, seed=7, rho=1e-3, empty_w_rows=[0], zero_sigma=[0])
+    K = O.assemble(inp, O.STABILIZED)
+    perm = np.arange(K.N, dtype=np.int32)
+    tp, td = O.pivot_thresholds(K, inp.n, inp.m, O.STABILIZED, inp.rho, 1e-10, "block")
+    assert td == 1e-10 / inp.rho and tp < td   # rho < 1: the dual block has the larger norm
+    F = O.LDL(K, perm=perm, signs=O.block_signs(inp.n, inp.m, O.STABILIZED), pivot_thr=(tp, td))
+    _, D, _ = F.factor()
+    assert D[0] == tp and F.inertia()[:3] == (30, 10, 0)
+
+
+def test_norms_golden():
+    """Hand-derived norms of the tiny fixture (tests/golden/assembly_tiny.json)."""
+    inp, g = _tiny_input()
+    K1 = O.assemble(inp, O.CONDENSED)
+    K2 = O.assemble(inp, O.STABILIZED)
+    assert O.norms(K1) == (g["norms"]["condensed"]["max_abs"], g["norms"]["condensed"]["inf"])
+    assert O.norms(K2) == (g["norms"]["stabilized"]["max_abs"], g["norms"]["stabilized"]["inf"])
+    assert O.primal_block_max(K2, inp.n) == g["norms"]["stabilized"]["primal_block_max"]
