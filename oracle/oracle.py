@@ -153,7 +153,11 @@ def pivot_thresholds(K: LowerCSC, n: int, m: int, form: int, rho: float, eps: fl
     eps * max_ij |K_ij| of the assembled matrix.  "block": each block of the
     stabilized matrix uses its own norm, eps * max |K_xx| for primal pivots and
     eps / rho (the -1/rho I block of Sec. 3.2, eq. K2r) for dual pivots; for
-    the condensed form this is the global rule."""
+    the condensed form this is the global rule.  "absolute": the solver's
+    pivot epsilon of Sec. 4.3 taken as an absolute bound, eps for every
+    pivot, in both forms."""
+    if scale == "absolute":
+        return float(eps), float(eps)
     if scale == "global" or form == CONDENSED:
         t = eps * norms(K)[0]
         return t, t
@@ -275,6 +279,7 @@ class SolveInfo:
     ir_steps: int = 0
     omega_history: list = field(default_factory=list)
     backward_error: float = np.inf
+    backward_error_cw: float = np.inf
     inertia_ok: bool = False
     nnz_L: int = 0
 
@@ -285,39 +290,51 @@ def expected_inertia(n: int, m: int, form: int):
 
 
 def refine(K: LowerCSC, F: LDL, B, ir_max: int = 10, ir_tol: float = 1e-12, ir_stall: float = 0.5,
-           Kinf=None):
+           Kinf=None, ir_cw_tol: float = 0.0):
     """Richardson refinement x <- x + F^-1 (b - K x) against the unperturbed K
-    (Sec. 3.1 and 4.3).  Stops when the backward error reaches ir_tol, after
-    ir_max corrections, or when one correction fails to halve it; the best
-    iterate is returned.  Returns (X, omega history, corrections applied)."""
+    (Sec. 3.1 and 4.3).  The target is omega <= ir_tol and, when ir_cw_tol > 0,
+    the componentwise backward error <= ir_cw_tol too; the distance to it is
+    g = max(omega / ir_tol, omega_cw / ir_cw_tol).  Stops at g <= 1, after
+    ir_max corrections, or when one correction fails to bring g below
+    ir_stall times its previous value; the best iterate (smallest g) is
+    returned.  Returns (X, omega history, corrections applied)."""
     B2 = np.asarray(B, np.float64).reshape(K.N, -1)
     if Kinf is None:
         Kinf = norms(K)[1]
+
+    def measure(X):
+        om = float(backward_error(K, X, B2, Kinf).max())
+        g = om / ir_tol if ir_tol > 0 else (np.inf if om > 0 else 0.0)
+        if ir_cw_tol > 0:
+            g = max(g, float(componentwise_backward_error(K, X, B2).max()) / ir_cw_tol)
+        return om, g
+
     X = F.solve(B2)
-    om = float(backward_error(K, X, B2, Kinf).max())
+    om, g = measure(X)
     hist = [om]
-    best_X, best = X, om
+    best_X, best_g, best_om = X, g, om
     steps = 0
-    while om > ir_tol and steps < ir_max:
+    while g > 1.0 and steps < ir_max:
         R = B2 - symv(K, X)
         Xn = X + F.solve(R)
-        omn = float(backward_error(K, Xn, B2, Kinf).max())
+        omn, gn = measure(Xn)
         steps += 1
         hist.append(omn)
-        if omn < best:
-            best_X, best = Xn, omn
-        if omn > ir_stall * om:
+        if gn < best_g:
+            best_X, best_g, best_om = Xn, gn, omn
+        if gn > ir_stall * g:
             break
-        X, om = Xn, omn
+        X, om, g = Xn, omn, gn
     return best_X.reshape(np.shape(B)), hist, steps
 
 
 def solve(inp, form: int, B, eps=None, ir_max: int = 10, ir_tol: float = 1e-12, ir_stall: float = 0.5,
-          perm=None, K: LowerCSC | None = None, pivot_scale: str = "global"):
+          perm=None, K: LowerCSC | None = None, pivot_scale: str = "global", ir_cw_tol: float = 0.0):
     """Assemble, order, factor with static pivoting and refine: the whole path
     in FP64 on the CPU.  eps is relative to max_ij |K_ij| (pivot rule
-    |d| < eps*||K||_max -> d = sign*eps*||K||_max), or to each block's own norm
-    with pivot_scale="block" (see pivot_thresholds).  Refinement runs only when
+    |d| < eps*||K||_max -> d = sign*eps*||K||_max), to each block's own norm
+    with pivot_scale="block", or an absolute bound with pivot_scale="absolute"
+    (see pivot_thresholds).  Refinement runs only when
     the inertia is the expected one (Sec. 4.3)."""
     if K is None:
         K = assemble(inp, form)
@@ -331,11 +348,13 @@ def solve(inp, form: int, B, eps=None, ir_max: int = 10, ir_tol: float = 1e-12, 
     info = SolveInfo(inertia=F.inertia(), nnz_L=F.nnz_L())
     info.inertia_ok = info.inertia[:3] == expected_inertia(inp.n, inp.m, form)
     if info.inertia_ok:
-        X, hist, steps = refine(K, F, B, ir_max, ir_tol, ir_stall, kinf)
+        X, hist, steps = refine(K, F, B, ir_max, ir_tol, ir_stall, kinf, ir_cw_tol)
     else:
         X = F.solve(B)
         hist, steps = [float(backward_error(K, X, B, kinf).max())], 0
-    info.omega_history, info.ir_steps, info.backward_error = hist, steps, hist[-1] if steps == 0 else min(hist)
+    info.omega_history, info.ir_steps = hist, steps
+    info.backward_error = float(backward_error(K, X, B, kinf).max())
+    info.backward_error_cw = float(componentwise_backward_error(K, X, B).max())
     return X, info, F, K
 
 

@@ -460,3 +460,90 @@ def test_norms_golden():
     assert O.norms(K1) == (g["norms"]["condensed"]["max_abs"], g["norms"]["condensed"]["inf"])
     assert O.norms(K2) == (g["norms"]["stabilized"]["max_abs"], g["norms"]["stabilized"]["inf"])
     assert O.primal_block_max(K2, inp.n) == g["norms"]["stabilized"]["primal_block_max"]
+
+
+def test_absolute_pivot_scale():
+    """The pivot epsilon of Sec. 4.3 read as an absolute bound: every pivot
+    with |d| < eps is replaced by +-eps, whatever the norm of K.  With the dual
+    block first at rho = 1e14, -1/rho = -1e-14 is replaced by -eps for
+    eps = 1e-10 and kept for eps = 1e-16; a primal pivot of order 1e-8 (an
+    empty W row with Sigma = 1e-8, eliminated first) is kept for eps = 1e-10
+    although the global and block rules, relative to max |K| >= 1e4,
+    replace it.  Dense brute force under the same thresholds gives the same D."""
+    inp = synth.random_system(20, 6, seed=31, rho=1e14, empty_w_rows=[0], empty_j_cols=[0])
+    inp.Sigma[0] = 1e-8
+    inp.Sigma[1] = 1e4          # max |K| = max |K_xx| >= 1e4: the relative thresholds exceed 1e-8
+    n, m = inp.n, inp.m
+    K = O.assemble(inp, O.STABILIZED)
+    Kd = K.dense()
+    assert Kd[0, 0] == 1e-8 and np.count_nonzero(Kd[0]) == 1
+    sg = O.block_signs(n, m, O.STABILIZED)
+    perm = np.concatenate([[0], n + np.arange(m), np.arange(1, n)]).astype(np.int32)
+    for form in (O.CONDENSED, O.STABILIZED):
+        assert O.pivot_thresholds(K, n, m, form, inp.rho, 1e-10, "absolute") == (1e-10, 1e-10)
+    for eps, dual_pert in ((1e-10, True), (1e-16, False)):
+        thr = O.pivot_thresholds(K, n, m, O.STABILIZED, inp.rho, eps, "absolute")
+        F = O.LDL(K, perm=perm, signs=sg, pivot_thr=thr)
+        _, D, _ = F.factor()
+        assert D[0] == 1e-8                                   # the primal 1e-8 pivot is kept
+        assert np.all(D[1:m + 1] == (-eps if dual_pert else -1.0 / inp.rho))
+        assert F.inertia() == (n, m, 0, m if dual_pert else 0)
+        _, Dd, npd = dense.ldl(Kd[np.ix_(perm, perm)], signs=sg[perm], pivot_thr=thr)
+        assert npd == F.inertia()[3] and np.array_equal(D[:m + 1], Dd[:m + 1])
+    for scale in ("global", "block"):   # both relative rules replace the 1e-8 pivot
+        thr = O.pivot_thresholds(K, n, m, O.STABILIZED, inp.rho, 1e-10, scale)
+        F = O.LDL(K, perm=perm, signs=sg, pivot_thr=thr)
+        assert F.factor()[1][0] == thr[0] > 1e-8
+
+
+@pytest.mark.slow
+def test_adjoint_config5_finite_differences():
+    from fd_util import config5_fd_cases, fd_tolerance
+    """Config 5: the condensed grid system at rho = 1e6, 16 right-hand sides,
+    loss = sum(w * X); the oracle's adjoint gradient against central
+    differences (h = 1e-6) of the oracle's own solves on 200 entries, 50 each
+    of B, W, Sigma and J (tolerance: fd_tolerance)."""
+    inp = synth.grid_banded(rho=1e6)
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((inp.n, 16)); Wt = rng.standard_normal((inp.n, 16))
+    perm = O.mindeg(O.assemble(inp, O.CONDENSED))
+    X, info, F, K = O.solve(inp, O.CONDENSED, B, perm=perm)
+    gB, gW, gS, gJ, _ = O.adjoint_condensed(inp, F, X, Wt)
+    h = 1e-6
+
+    def loss(i, Bm):
+        return float(np.sum(Wt * O.solve(i, O.CONDENSED, Bm, perm=perm)[0]))
+
+    cases = config5_fd_cases(inp, rng)
+    for field, g in (("W_val", gW), ("Sigma", gS), ("J_val", gJ)):
+        tol = fd_tolerance(g, Wt, X, h)
+        for k in cases[field]:
+            v = getattr(inp, field).copy(); v0 = v[k]
+            v[k] = v0 + h; lp = loss(inp.with_values(**{field: v}), B)
+            v[k] = v0 - h; lm = loss(inp.with_values(**{field: v}), B)
+            assert abs((lp - lm) / (2 * h) - g[k]) <= tol[k], (field, k)
+    tol = fd_tolerance(gB, Wt, X, h)
+    for i, c in cases["B"]:
+        Bp = B.copy(); Bp[i, c] += h; lp = loss(inp, Bp)
+        Bp[i, c] -= 2 * h; lm = loss(inp, Bp)
+        assert abs((lp - lm) / (2 * h) - gB[i, c]) <= tol[i, c]
+
+
+def test_refine_componentwise_criterion():
+    """Stabilized OPF-shaped system with Sigma over 16 decades (absolute
+    pivot bound, nothing perturbed): the first solve already has a normwise
+    backward error far below u, so the normwise rule stops with no
+    correction, while the componentwise error (Oettli-Prager, checked against
+    dense numpy) is ~1e-9.  With ir_cw_tol = 1e-14 one correction brings it
+    below the bound, and the returned iterate is the refined one."""
+    inp = synth.opf_network(N=200, seed=3, rho=1e3)
+    B = synth.rhs(inp.n + inp.m, 1, seed=11)
+    x0, i0, _, K = O.solve(inp, O.STABILIZED, B, eps=1e-10, pivot_scale="absolute")
+    x1, i1, _, _ = O.solve(inp, O.STABILIZED, B, eps=1e-10, pivot_scale="absolute", ir_cw_tol=1e-14)
+    Kd = K.dense()
+    cw = lambda x: float(np.max(np.abs(B - Kd @ x) / (np.abs(Kd) @ np.abs(x) + np.abs(B))))
+    assert i0.inertia == i1.inertia == (inp.n, inp.m, 0, 0)
+    assert i0.ir_steps == 0 and i0.backward_error < 1e-18
+    assert cw(x0) > 1e-10 and cw(x0) == pytest.approx(i0.backward_error_cw, rel=1e-6)
+    assert i1.ir_steps >= 1 and cw(x1) <= 1e-14
+    assert i1.backward_error_cw == pytest.approx(cw(x1), rel=0.5)
