@@ -1,22 +1,40 @@
-"""Benchmark: condensed-KKT factor+solve/s at n = 500k, backward error <= 1e-10.
+"""Benchmark: condensed-KKT factor+solve/s at n = 500k, FP32+IR vs FP64.
 
-One step = one refactorization of the OPF-shaped sequence on a fixed pattern
+Workload (the headline): the OPF-shaped refactor sequence on a fixed pattern
 (Delaunay network of 100k nodes, 4 variables per node + 100k edge variables,
-n = 500k, m ~ 300k Jacobian rows): assemble K = W + Sigma + rho J^T J on the
-GPU, factor it (supernodal LDL^T with static pivoting), solve one right-hand
-side and refine in FP64 until the normwise backward error is <= 1e-10.  Step k
-uses Sigma log-uniform in [1e-8, 1e8] (seed 2000 + k) and rho = 10^(2 + 6k/29),
-k = 0..29, cycling.  All inputs are resident in device memory before timing.
-The symbolic analysis runs once, outside the timed region.
+n = 500k, m ~ 300k Jacobian rows).  Refactor k = 0..29 uses Sigma
+log-uniform in [1e-8, 1e8] (seed 2000 + k) and rho = 10^(2 + 6k/29).  One
+refactor = assemble K = W + Sigma + rho J^T J on the GPU, factor it
+(supernodal LDL^T with static pivoting), solve one right-hand side and refine
+in FP64.  One STEP = one pass over the whole 30-refactor sequence, so every
+timed step covers rho from 1e2 to 1e8.  All inputs are resident in device
+memory before timing; the symbolic analysis runs once, outside the timed
+region.
+
+Accuracy gate (both paths, the same): normwise backward error
+omega <= 1e-10 (the metric's "rel resid") AND componentwise backward error
+omega_cw = max_i |b - Kx|_i / (|K||x| + |b|)_i <= 1e-14, with the inertia
+(n, 0, 0).  On these systems omega alone is not binding (it sits near 1e-20
+for any FP64-accurate x: ||K||_inf ||x||_inf mixes rows of very different
+scale); omega_cw <= 1e-14 is what an FP64 factor reaches, so the FP32 factor
+must refine to FP64's accuracy.  Only refactors that pass the gate count in
+`value`.  Static pivots use an absolute bound of 1e-12 (the relative rule
+eps ||K||_max replaces legitimate small pivots of this family; the bench
+reports what it does at rho = 1e2 under "relative_rule_k0").
 
 Prints one JSON line.  `value` is the FP64 path; the FP32-factor + FP64-
-refinement path is reported beside it under "fp32_ir".
+refinement path is under "fp32_ir".  Also in the line: the roofline of the
+dominant kernel, the per-kernel breakdown, the accuracy of both paths against
+the CPU oracle, the mixed-precision sweep of the 2000-variable grid system
+(config 3) and the batched systems (config 4).
 """
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -26,26 +44,29 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 METRIC = "condensed-KKT factor+solve/s at n=500k, rel resid ≤1e-10: FP32+IR vs FP64"
+SEQ = 30
 # fp64 vector: 256 CUs x 64 FMA lanes x 2 flops x 2.4 GHz
 PEAK = {"hbm_GBs": 8000.0, "fp64_mfma_TFs": 78.6, "fp32_mfma_TFs": 157.3, "fp64_vector_TFs": 78.6}
+HEADLINE = dict(pivot_scale="absolute", pivot_eps=1e-12, ir_tol=1e-10, ir_cw_tol=1e-14, ir_max_steps=10)
+GATE_OMEGA, GATE_CW = 1e-10, 1e-14
 
-# HBM bytes per launch of the large-front kernels, from two rocprofv3 --pmc
-# runs (FETCH_SIZE, WRITE_SIZE in KiB per dispatch, mean over the dispatches
-# of a 2-step run), each scaled by what the same counter reads for a device
-# copy of known size.  Valid only for the kernel source they were taken on:
-# reported as null once kernels.hip changes.
-TRAFFIC = {"kernels_sha1": "d3e8ded8f82c22a8c28925a840fd0b0c0b605ca0", "fetch_scale": 2.00, "write_scale": 1.00,
-           "source": "profiles/pmc_traffic_opf_n500k_fp64.txt",
-           "kib": {"large_update_mfma": (13924.8, 19676.4), "large_diag": (1680.2, 5609.8),
-                   "large_panel": (4015.3, 6448.7)}}
+# HBM bytes per launch of kernel classes, from two rocprofv3 --pmc runs
+# (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch, mean over the dispatches of
+# the class in a short FP64 run of this bench), each scaled by what the same
+# counter reads for a device copy of known size (--calibrate-copy).  Valid
+# only for the kernel source they were taken on: null once kernels.hip
+# changes.  Source: profiles/pmc_traffic_opf_n500k_fp64.txt.
+TRAFFIC = {"kernels_sha1": None, "fetch_scale": 2.00, "write_scale": 1.00, "kib": {}}
+
+
+def kernels_sha1():
+    with open(os.path.join(ROOT, "paper_2510_05885_amd", "csrc", "kernels.hip"), "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()
 
 
 def measured_traffic(cls):
-    import hashlib
-    src = os.path.join(ROOT, "paper_2510_05885_amd", "csrc", "kernels.hip")
-    with open(src, "rb") as f:
-        sha = hashlib.sha1(f.read()).hexdigest()
-    if cls not in TRAFFIC["kib"] or sha != TRAFFIC["kernels_sha1"]:
+    """Measured HBM bytes per launch of a kernel class, or None."""
+    if cls not in TRAFFIC["kib"] or kernels_sha1() != TRAFFIC["kernels_sha1"]:
         return None
     fetch, write = TRAFFIC["kib"][cls]
     return 1024.0 * (fetch * TRAFFIC["fetch_scale"] + write * TRAFFIC["write_scale"])
@@ -54,14 +75,15 @@ def measured_traffic(cls):
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=30)
-    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--steps", type=int, default=3, help="timed passes over the 30-refactor sequence")
+    ap.add_argument("--warmup", type=int, default=1, help="untimed passes before timing")
     ap.add_argument("--nodes", type=int, default=100_000, help="Delaunay nodes (n = 5 * nodes)")
     ap.add_argument("--precision", choices=["both", "fp64", "fp32_ir"], default="both")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--ir-tol", type=float, default=1e-10)
+    ap.add_argument("--no-legs", action="store_true", help="skip the accuracy, config-3 and batched legs")
+    ap.add_argument("--no-timing-pass", action="store_true", help="skip the evented per-kernel pass")
     ap.add_argument("--workload", choices=["opf", "batched"], default="opf",
-                    help="opf: the n=500k refactor sequence (headline); batched: 256 independent systems")
+                    help="opf: the n=500k refactor sequence (headline); batched: only the batched systems")
     ap.add_argument("--systems", type=int, default=256)
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="after the run, copy a MIB-sized device buffer 3 times (reference kernel for "
@@ -73,40 +95,69 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def run_path(kkt, dev, W, J, sigmas, rhos, B, steps, warmup, timing):
-    """Warm up, then time `steps` refactorizations (graphs replayed, no
-    per-kernel events).  With `timing`, the same steps are then run once more
-    with HIP events around every kernel launch (eager launches) for the
-    per-kernel breakdown and the roofline."""
+def gate(info, inertia, n):
+    return (info.backward_error <= GATE_OMEGA and info.backward_error_cw <= GATE_CW
+            and tuple(inertia[:3]) == (n, 0, 0))
+
+
+def run_path(kkt, W, J, sigmas, rhos, B, n, steps, warmup, timing):
+    """`warmup` untimed passes, then `steps` timed passes over the sequence
+    (graph replays).  With `timing`, one more pass with HIP events around
+    every kernel launch (eager launches) gives the per-kernel breakdown."""
     import torch
-    nseq = len(rhos)
-    infos = []
     for w in range(warmup):
-        kkt.factor(W, sigmas[w % nseq], J, rhos[w % nseq])
-        kkt.solve(B)
+        for k in range(SEQ):
+            kkt.factor(W, sigmas[k], J, rhos[k])
+            kkt.solve(B)
     torch.cuda.synchronize()
+    recs = []
     t0 = time.perf_counter()
     for s in range(steps):
-        k = (warmup + s) % nseq
-        rc = kkt.factor(W, sigmas[k], J, rhos[k])
-        X, info = kkt.solve(B)
-        infos.append((k, rc, info))
+        for k in range(SEQ):
+            rc = kkt.factor(W, sigmas[k], J, rhos[k])
+            X, info = kkt.solve(B)
+            recs.append((k, rc, info, kkt.inertia()))
     torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    secs = time.perf_counter() - t0
     tm = None
     if timing:
         kkt.set_timing(True)
         torch.cuda.synchronize()
         te = time.perf_counter()
-        for s in range(steps):
-            k = (warmup + s) % nseq
+        for k in range(SEQ):
             kkt.factor(W, sigmas[k], J, rhos[k])
             kkt.solve(B)
         torch.cuda.synchronize()
         tm = kkt.timing()
         tm["eager_seconds"] = time.perf_counter() - te
+        tm["refactors"] = SEQ
         kkt.set_timing(False)
-    return t1 - t0, infos, tm
+    return secs, recs, tm
+
+
+def summarize_path(secs, recs, n, steps):
+    ok = [gate(i, inert, n) for _, _, i, inert in recs]
+    om = [i.backward_error for _, _, i, _ in recs]
+    cw = [i.backward_error_cw for _, _, i, _ in recs]
+    r2 = [i.resid_rel2 for _, _, i, _ in recs]
+    irs = [i.ir_steps for _, _, i, _ in recs]
+    per_rho = {}
+    for (k, rc, i, inert), g in zip(recs, ok):
+        d = per_rho.setdefault(k, {"ir_steps": [], "fell_back": 0, "pass": 0, "npert": 0})
+        d["ir_steps"].append(i.ir_steps)
+        d["fell_back"] += int(i.fell_back_fp64)
+        d["pass"] += int(g)
+        d["npert"] = max(d["npert"], int(inert[3]))
+    nref = len(recs)
+    return {"seconds": secs, "refactors": nref, "refactors_passing_gate": int(sum(ok)),
+            "rate": sum(ok) / secs, "rate_all_refactors": nref / secs, "ms_per_refactor": 1e3 * secs / nref,
+            "ms_per_step": 1e3 * secs / steps, "max_backward_error": max(om), "max_backward_error_cw": max(cw),
+            "max_resid_rel2": max(r2), "ir_steps_mean": float(np.mean(irs)), "ir_steps_max": int(max(irs)),
+            "fp64_fallbacks": int(sum(i.fell_back_fp64 for _, _, i, _ in recs)),
+            "max_perturbed_pivots": int(max(inert[3] for *_, inert in recs)),
+            "per_refactor": [{"k": k, "rho": float(10.0 ** (2 + 6 * k / 29)), "ir_steps": d["ir_steps"][0],
+                              "fell_back": d["fell_back"] > 0, "passes_gate": d["pass"] == len(d["ir_steps"])}
+                             for k, d in sorted(per_rho.items())]}
 
 
 def main():
@@ -122,84 +173,152 @@ def main():
 
     torch.cuda.set_device(0)
     if args.workload == "batched":
-        return bench_batched(args)
+        print(json.dumps(bench_batched(args)))
+        return
     t = time.perf_counter()
     inp = synth.opf_network(N=args.nodes, seed=2)
-    seq = [synth.opf_sequence_values(inp, k) for k in range(30)]
-    log(f"generated n={inp.n} m={inp.m} nnzW={inp.W_colptr[-1]} nnzJ={inp.J_rowptr[-1]} in {time.perf_counter()-t:.1f}s")
+    seq = [synth.opf_sequence_values(inp, k) for k in range(SEQ)]
+    log(f"generated n={inp.n} m={inp.m} nnzW={inp.W_colptr[-1]} nnzJ={inp.J_rowptr[-1]} in "
+        f"{time.perf_counter() - t:.1f}s")
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
     W = dev(inp.W_val)
     J = dev(inp.J_val)
     sigmas = [dev(s) for s, _ in seq]
     rhos = [r for _, r in seq]
-    B = dev(synth.rhs(inp.n, 1, seed=7)[:, 0])
+    b = synth.rhs(inp.n, 1, seed=7)
+    B = dev(b[:, 0])
 
-    results = {}
+    results, xs = {}, {}
     paths = ["fp64", "fp32_ir"] if args.precision == "both" else [args.precision]
     stats = None
     for prec in paths:
         t = time.perf_counter()
-        kkt = KKT.from_input(inp, form="condensed", precision=prec, ir_tol=args.ir_tol, ir_max_steps=10)
+        kkt = KKT.from_input(inp, form="condensed", precision=prec, **HEADLINE)
         st = kkt.stats()
         stats = stats or st
-        log(f"[{prec}] analyze {time.perf_counter()-t:.1f}s: {st}")
-        secs, infos, tm = run_path(kkt, dev, W, J, sigmas, rhos, B, args.steps, args.warmup, timing=(prec == "fp64"))
-        om = [i.backward_error for _, _, i in infos]
-        ok = sum(1 for o in om if o <= 1e-10)
-        fb = sum(1 for _, _, i in infos if i.fell_back_fp64)
-        irs = [i.ir_steps for _, _, i in infos]
-        inert = kkt.inertia()
-        results[prec] = {"seconds": secs, "rate": args.steps / secs, "ms_per_step": 1e3 * secs / args.steps,
-                         "max_backward_error": max(om), "steps_meeting_1e-10": ok, "fp64_fallbacks": fb,
-                         "ir_steps_mean": float(np.mean(irs)), "ir_steps_max": int(max(irs)),
-                         "last_inertia": list(inert), "timing": tm}
-        log(f"[{prec}] {args.steps} steps in {secs:.3f}s -> {args.steps/secs:.2f}/s; max omega {max(om):.2e}; "
-            f"ok {ok}/{args.steps}; fallbacks {fb}; IR steps mean {np.mean(irs):.2f}")
+        log(f"[{prec}] analyze {time.perf_counter() - t:.1f}s: {st}")
+        secs, recs, tm = run_path(kkt, W, J, sigmas, rhos, B, inp.n, args.steps, args.warmup,
+                                  timing=(prec == "fp64" and not args.no_timing_pass))
+        res = summarize_path(secs, recs, inp.n, args.steps)
+        res["timing"] = tm
+        results[prec] = res
+        log(f"[{prec}] {len(recs)} refactors in {secs:.3f}s -> {res['rate']:.2f}/s passing the gate "
+            f"({res['refactors_passing_gate']}/{len(recs)}); max omega {res['max_backward_error']:.2e} "
+            f"cw {res['max_backward_error_cw']:.2e}; fallbacks {res['fp64_fallbacks']}; "
+            f"IR steps mean {res['ir_steps_mean']:.2f}")
         if tm:
-            log(f"[{prec}] kernel ms: " + json.dumps({k: round(v, 3) for k, v in tm['ms'].items()}))
-            log(f"[{prec}] launches: " + json.dumps(tm['launches']))
+            log(f"[{prec}] kernel ms/refactor: " + json.dumps({k: round(v / SEQ, 3) for k, v in tm["ms"].items()}))
+        if not args.no_legs:
+            xs[prec] = {}
+            for k in (0, SEQ - 1):
+                kkt.factor(W, sigmas[k], J, rhos[k])
+                X, info = kkt.solve(B)
+                xs[prec][k] = (X.cpu().numpy().reshape(-1, 1), info)
         kkt.close()
 
-    r64 = results.get("fp64") or results[paths[0]]
-    tm = r64.get("timing")
-    roof, breakdown = None, None
+    out = {
+        "metric": METRIC, "value": results[paths[0]]["rate"], "unit": "factor+solve/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": results[paths[0]]["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"OPF-shaped condensed KKT: Delaunay network of {args.nodes} nodes, n={inp.n}, "
+                               f"m={inp.m}; one step = the 30-refactor sequence rho 1e2..1e8 (Sigma 1e-8..1e8), "
+                               f"1 RHS each, refined to omega<=1e-10 and omega_cw<=1e-14; static pivots below "
+                               f"1e-12 (absolute)",
+                   "n": inp.n, "m": inp.m, "refactors_per_step": SEQ, "nnz_K_lower": stats["nnz_K_lower"],
+                   "nnz_L": stats["nnz_L"], "nnz_L_exact": stats["nnz_L_exact"],
+                   "factor_flops_executed": stats["flops_factor"], "factor_flops_exact": stats["flops_exact"],
+                   "levels": stats["n_levels"], "max_front": stats["max_front"],
+                   "analyze_s": stats["analyze_seconds"]},
+        "gate": {"omega": GATE_OMEGA, "omega_cw": GATE_CW, "inertia": "(n,0,0)"},
+    }
+    for prec in paths:
+        out[prec] = {k: v for k, v in results[prec].items() if k != "timing"}
+    tm = results.get("fp64", {}).get("timing")
     if tm:
-        breakdown = kernel_breakdown(tm, stats, args.steps)
-        # dominant kernel class by device time among those with an algorithmic figure
+        breakdown = kernel_breakdown(tm, SEQ)
         cand = [k for k in breakdown if k.get("achieved") is not None]
-        dom = max(cand, key=lambda k: k["ms_per_step"])
-        roof = {"kernel": dom["kernel"], "bound": dom["bound"], "achieved": dom["achieved"],
-                "peak": dom["peak"], "unit": dom["unit"], "frac": dom["achieved"] / dom["peak"],
-                "traffic": measured_traffic(dom["class"]), "traffic_unit": "bytes/launch", "avg_launch_ms": dom["avg_launch_ms"], "launches_per_step": dom["launches_per_step"]}
+        dom = max(cand, key=lambda k: k["ms_per_refactor"])
+        out["roofline"] = {"kernel": dom["kernel"], "bound": dom["bound"], "achieved": dom["achieved"],
+                           "peak": dom["peak"], "unit": dom["unit"], "frac": dom["achieved"] / dom["peak"],
+                           "traffic": dom["traffic"], "traffic_unit": "bytes/launch",
+                           "avg_launch_ms": dom["avg_launch_ms"], "launches_per_refactor": dom["launches_per_refactor"]}
         fact_ms = sum(tm["ms"][k] for k in ("small_fronts", "large_assembly", "large_panel", "large_update_mfma",
                                             "large_diag"))
-        roof["factor_total_TFs"] = stats["flops_factor"] * args.steps / 1e12 / (fact_ms * 1e-3)
+        out["roofline"]["factor_exact_TFs"] = stats["flops_exact"] * SEQ / 1e12 / (fact_ms * 1e-3)
+        out["kernels"] = breakdown
+    else:
+        out["roofline"] = None
 
     cpu = None
     if not args.no_cpu_baseline:
-        cpu = cpu_baseline(inp, seq, args.ir_tol)
-
-    out = {
-        "metric": METRIC, "value": r64["rate"], "unit": "factor+solve/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": r64["ms_per_step"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
-        "data": "synthetic",
-        "config": {"workload": f"OPF-shaped condensed KKT: Delaunay network of {args.nodes} nodes, "
-                               f"n={inp.n}, m={inp.m}, 30-refactor sequence rho 1e2..1e8, Sigma 1e-8..1e8, "
-                               f"1 RHS, refine to omega<=1e-10",
-                   "n": inp.n, "m": inp.m, "nnz_K_lower": stats["nnz_K_lower"], "nnz_L": stats["nnz_L"],
-                   "factor_flops": stats["flops_factor"], "levels": stats["n_levels"],
-                   "max_front": stats["max_front"], "analyze_s": stats["analyze_seconds"]},
-        "fp64": {k: v for k, v in r64.items() if k != "timing"},
-        "roofline": roof,
-        "kernels": breakdown,
-        "cpu_baseline": cpu,
-    }
-    if "fp32_ir" in results:
-        out["fp32_ir"] = {k: v for k, v in results["fp32_ir"].items() if k != "timing"}
+        cpu, xo = cpu_baseline(inp, seq, b, with_last=not args.no_legs)
+        out["cpu_baseline"] = cpu
+        if not args.no_legs:
+            out["accuracy_vs_oracle"] = {
+                prec: {f"k{k}": {"fwd_err": float(np.abs(x - xo[k]).max() / np.abs(xo[k]).max()),
+                                 "omega": i.backward_error, "omega_cw": i.backward_error_cw,
+                                 "resid_rel2": i.resid_rel2, "ir_steps": i.ir_steps, "fell_back": i.fell_back_fp64}
+                       for k, (x, i) in xs[prec].items()} for prec in xs}
+            out["relative_rule_k0"] = relative_rule_k0(inp, W, J, sigmas[0], rhos[0], B, xo[0])
+    else:
+        out["cpu_baseline"] = None
+    if not args.no_legs:
+        out["config3_fp32_ir"] = config3_leg()
+        out["config4_batched"] = bench_batched(args)
     if args.calibrate_copy > 0:
         calibrate_copy(args.calibrate_copy)
     print(json.dumps(out))
+
+
+def relative_rule_k0(inp, W, J, Sigma, rho, B, xo):
+    """Refactor k = 0 (rho = 1e2) under the relative static-pivot rule
+    (|d| < 1e-12 ||K||_max): how many pivots it replaces and what that does to
+    the solution, against the oracle's x."""
+    from paper_2510_05885_amd.ncl_kkt import KKT
+    kkt = KKT.from_input(inp, form="condensed", precision="fp64", pivot_scale="global", pivot_eps=1e-12,
+                         ir_tol=GATE_OMEGA, ir_cw_tol=GATE_CW)
+    rc = kkt.factor(W, Sigma, J, rho)
+    X, info = kkt.solve(B)
+    x = X.cpu().numpy().reshape(-1, 1)
+    out = {"status": int(info.status), "perturbed_pivots": int(kkt.inertia()[3]), "omega": info.backward_error,
+           "omega_cw": info.backward_error_cw, "ir_steps": info.ir_steps,
+           "fwd_err_vs_oracle": float(np.abs(x - xo).max() / np.abs(xo).max())}
+    kkt.close()
+    log(f"[relative rule, k=0] {out}")
+    return out
+
+
+def config3_leg():
+    """Mixed precision on the 2000-variable grid system (config 3): FP32 factor,
+    FP64 pivot test / residual / refinement (<= 10 steps) to the gate, rho =
+    1e2..1e8, 1 and 16 right-hand sides; forward error against the oracle's x
+    (refined to the same target), refinement steps and FP64 fallbacks."""
+    import torch
+
+    from oracle import oracle as O
+    from paper_2510_05885_amd import synth
+    from paper_2510_05885_amd.ncl_kkt import KKT
+    dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
+    rows = []
+    for rho in (1e2, 1e3, 1e4, 1e5, 1e6, 1e7, 1e8):
+        inp = synth.grid_banded(rho=rho, seed=3)
+        for nrhs in (1, 16):
+            Bh = synth.rhs(inp.n, nrhs, seed=5)
+            kkt = KKT.from_input(inp, precision="fp32_ir", ir_tol=GATE_OMEGA, ir_cw_tol=GATE_CW, fp32_sticky=False)
+            rc = kkt.factor(dev(inp.W_val), dev(inp.Sigma), dev(inp.J_val), rho)
+            Bd = torch.as_tensor(np.ascontiguousarray(Bh.T), device="cuda").t()
+            X, info = kkt.solve(Bd)
+            x = X.cpu().numpy().reshape(inp.n, -1)
+            xo, io, _, _ = O.solve(inp, O.CONDENSED, Bh, ir_tol=GATE_OMEGA, ir_cw_tol=GATE_CW)
+            xo = xo.reshape(inp.n, -1)
+            fe = float(np.max(np.abs(x - xo).max(axis=0) / np.abs(xo).max(axis=0)))
+            rows.append({"rho": rho, "nrhs": nrhs, "omega": info.backward_error, "omega_cw": info.backward_error_cw,
+                         "fwd_err_vs_oracle": fe, "ir_steps": info.ir_steps, "fell_back_fp64": info.fell_back_fp64,
+                         "inertia_ok": kkt.inertia()[:3] == (inp.n, 0, 0)})
+            kkt.close()
+    log(f"[config 3] {rows}")
+    return rows
 
 
 def calibrate_copy(mib):
@@ -216,8 +335,8 @@ def calibrate_copy(mib):
 def bench_batched(args):
     """Independent condensed systems (OPF-shaped, 125..5000 nodes each, n = 5 x
     nodes, per-system rho and Sigma) factored and solved together: one
-    factor call and one solve call per step for the whole batch (the systems
-    form one block-diagonal plan, level-scheduled as a forest)."""
+    factor call and one solve call per batch (one block-diagonal plan,
+    level-scheduled as a forest)."""
     import torch
 
     from paper_2510_05885_amd import synth
@@ -226,8 +345,8 @@ def bench_batched(args):
     sizes = synth.batched_sizes(args.systems)
     inps = [synth.batched_system(k, int(N)) for k, N in enumerate(sizes)]
     n_tot = sum(i.n for i in inps)
-    log(f"generated {len(inps)} systems, n total {n_tot} (min {min(i.n for i in inps)}, max {max(i.n for i in inps)}) "
-        f"in {time.perf_counter()-t:.1f}s")
+    log(f"generated {len(inps)} systems, n total {n_tot} (min {min(i.n for i in inps)}, "
+        f"max {max(i.n for i in inps)}) in {time.perf_counter() - t:.1f}s")
     dev = lambda a: torch.as_tensor(np.ascontiguousarray(a, dtype=np.float64), device="cuda")
     W = dev(np.concatenate([i.W_val for i in inps]))
     S = dev(np.concatenate([i.Sigma for i in inps]))
@@ -235,68 +354,70 @@ def bench_batched(args):
     rho = np.array([i.rho for i in inps])
     B = dev(np.concatenate([synth.rhs(i.n, 1, seed=k)[:, 0] for k, i in enumerate(inps)]))
     out = {}
+    steps = max(args.steps, 3)
     for prec in (["fp64", "fp32_ir"] if args.precision == "both" else [args.precision]):
         t = time.perf_counter()
-        kkt = KKT.analyze_batched(inps, precision=prec, ir_tol=args.ir_tol)
+        kkt = KKT.analyze_batched(inps, precision=prec, **HEADLINE)
         st = kkt.stats()
-        log(f"[batched {prec}] analyze {time.perf_counter()-t:.1f}s: {st}")
-        for _ in range(args.warmup):
+        log(f"[batched {prec}] analyze {time.perf_counter() - t:.1f}s: {st}")
+        for _ in range(max(args.warmup, 1)):
             kkt.factor(W, S, J, rho)
             kkt.solve(B)
         lat = []
-        worst = 0.0
+        worst = [0.0, 0.0]
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for _ in range(args.steps):
+        for _ in range(steps):
             a = time.perf_counter()
             kkt.factor(W, S, J, rho)
             X, info = kkt.solve(B)
             torch.cuda.synchronize()
             lat.append(time.perf_counter() - a)
-            worst = max(worst, info.backward_error)
+            worst = [max(worst[0], info.backward_error), max(worst[1], info.backward_error_cw)]
         secs = time.perf_counter() - t0
         inert = kkt.inertia_batched()
         ok = int(np.sum((inert[:, 0] == np.array([i.n for i in inps])) & (inert[:, 1] == 0)))
-        out[prec] = {"systems_per_s": len(inps) * args.steps / secs, "ms_per_batch": 1e3 * secs / args.steps,
-                     "latency_ms_p50": 1e3 * float(np.percentile(lat, 50)),
-                     "latency_ms_p99": 1e3 * float(np.percentile(lat, 99)),
-                     "max_backward_error": worst, "systems_with_expected_inertia": ok,
-                     "levels": st["n_levels"], "factor_flops": st["flops_factor"]}
+        out[prec] = {"systems_per_s": len(inps) * steps / secs, "ms_per_batch": 1e3 * secs / steps,
+                     "batch_latency_ms_p50": 1e3 * float(np.percentile(lat, 50)),
+                     "batch_latency_ms_p99": 1e3 * float(np.percentile(lat, 99)),
+                     "max_backward_error": worst[0], "max_backward_error_cw": worst[1],
+                     "systems_with_expected_inertia": ok, "levels": st["n_levels"],
+                     "factor_flops_exact": st["flops_exact"]}
         log(f"[batched {prec}] {out[prec]}")
         kkt.close()
-    r = out.get("fp64") or next(iter(out.values()))
-    print(json.dumps({
-        "metric": "batched condensed-KKT factor+solve, systems/s (omega <= 1e-10)",
-        "value": r["systems_per_s"], "unit": "systems/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-        "ms_per_step": r["ms_per_batch"], "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64", "data": "synthetic",
-        "config": {"workload": f"{len(inps)} OPF-shaped condensed systems, 125..5000 nodes (log-uniform), "
-                               f"n total {n_tot}, rho 1e2..1e6, Sigma 1e-6..1e6; per-system latency = the "
-                               f"batch's factor+solve call (all systems complete together)"},
-        "results": out}))
+    return {"metric": "batched condensed-KKT factor+solve, systems/s",
+            "workload": f"{len(inps)} OPF-shaped condensed systems, 125..5000 nodes (log-uniform), n total {n_tot}, "
+                        f"rho 1e2..1e6, Sigma 1e-6..1e6, one batch per factor+solve call; latency is the whole "
+                        f"batch's (all systems complete together)",
+            "steps": steps, "results": out}
 
 
-def kernel_breakdown(tm, stats, steps):
-    """Per kernel class: device ms per step (HIP events around every launch in
-    the timed region), launches, and achieved rate against the algorithmic
-    work the plan assigns to exactly those launches."""
+def kernel_breakdown(tm, refactors):
+    """Per kernel class: device ms per refactor (HIP events around every launch
+    of the evented pass), launches, achieved rate against the algorithmic work
+    the plan assigns to exactly those launches, and measured HBM bytes per
+    launch over the algorithmic bytes where counters were taken."""
     ms, n = tm["ms"], tm["launches"]
     rows = []
 
-    def add(cls, kernel, work, bound, unit, peak):
+    def add(cls, kernel, work, bound, unit, peak, alg_bytes=None):
         if n[cls] == 0:
             return
         sec = ms[cls] * 1e-3
         ach = None
         if work is not None and sec > 0:
             ach = work / sec / (1e12 if unit == "TFLOP/s" else 1e9)
-        rows.append({"class": cls, "kernel": kernel, "ms_per_step": ms[cls] / steps,
-                     "launches_per_step": n[cls] / steps, "avg_launch_ms": ms[cls] / n[cls],
-                     "bound": bound, "unit": unit, "peak": peak, "achieved": ach,
-                     "frac": (ach / peak) if ach is not None else None})
+        traffic = measured_traffic(cls)
+        row = {"class": cls, "kernel": kernel, "ms_per_refactor": ms[cls] / refactors,
+               "launches_per_refactor": n[cls] / refactors, "avg_launch_ms": ms[cls] / n[cls],
+               "bound": bound, "unit": unit, "peak": peak, "achieved": ach,
+               "frac": (ach / peak) if ach is not None else None, "traffic": traffic}
+        if traffic is not None and alg_bytes:
+            row["traffic_over_algorithmic"] = traffic / (alg_bytes / n[cls])
+        rows.append(row)
 
-    add("small_fronts", "k_small_fronts<double> (LDS fronts, MFMA trailing updates)", tm["small_flops"], "mfma",
-        "TFLOP/s", PEAK["fp64_mfma_TFs"])
+    add("small_fronts", "k_small_fronts/k_tiny_fronts<double> (LDS fronts, MFMA trailing updates)",
+        tm["small_flops"], "mfma", "TFLOP/s", PEAK["fp64_mfma_TFs"])
     add("large_update_mfma", "k_large_dstep<double> (trailing-update 64x64 tiles on v_mfma_f64_16x16x4, beside "
         "the next panel's diagonal blocks)", tm["update_flops"], "mfma", "TFLOP/s", PEAK["fp64_mfma_TFs"])
     add("large_diag", "k_large_diag<double> (first-panel diagonal blocks: LDL^T, inverse)", tm["diag_flops"],
@@ -304,38 +425,57 @@ def kernel_breakdown(tm, stats, steps):
     add("large_panel", "k_large_panel<double> (panel solve, v_mfma_f64_16x16x4)", tm["panel_flops"], "mfma",
         "TFLOP/s", PEAK["fp64_mfma_TFs"])
     add("large_assembly", "k_large_asm<double> (front assembly, extend-add)", None, "hbm", "GB/s", PEAK["hbm_GBs"])
-    add("solve_sweeps", "k_fwd_T/G + k_bwd_G/T<double> (panel sweeps)", tm["solve_bytes"], "hbm", "GB/s",
-        PEAK["hbm_GBs"])
+    add("solve_sweeps", "k_fwd_T/G/S + k_bwd_G/T/S<double> (triangular sweeps)", tm["solve_bytes"], "hbm", "GB/s",
+        PEAK["hbm_GBs"], tm["solve_bytes"])
     add("assemble", "k_assemble + norms (K = W + Sigma + rho J^T J)", tm["assemble_bytes"], "hbm", "GB/s",
-        PEAK["hbm_GBs"])
+        PEAK["hbm_GBs"], tm["assemble_bytes"])
     add("residual", "k_residual (b - Kx, FP64)", None, "hbm", "GB/s", PEAK["hbm_GBs"])
     return rows
 
 
-def cpu_baseline(inp, seq, ir_tol):
-    """The FP64 oracle on the host: one refactor (k = 0) of the same sequence —
-    assembly, factorization with static pivoting, one solve and refinement to
-    the same tolerance — single-threaded.  Its ordering is analysis and is
-    timed separately."""
+def cpu_baseline(inp, seq, b, with_last=True):
+    """The FP64 oracle on the host: refactor k = 0 of the same sequence --
+    assembly, factorization with static pivoting (absolute 1e-12), one solve
+    and refinement to the same gate -- single-threaded and timed; its
+    minimum-degree ordering is analysis and timed separately.  With
+    `with_last`, refactor k = 29 too (untimed), as the accuracy reference."""
     from oracle import oracle as O
-    from paper_2510_05885_amd import synth
+    xo = {}
     Sigma, rho = seq[0]
     case = inp.with_values(Sigma=Sigma, rho=rho)
-    b = synth.rhs(inp.n, 1, seed=7)[:, 0]
     t = time.perf_counter()
     K = O.assemble(case, O.CONDENSED)
     perm = O.mindeg(K)
     t_order = time.perf_counter() - t
     t0 = time.perf_counter()
     K = O.assemble(case, O.CONDENSED)
-    x, info, _, _ = O.solve(case, O.CONDENSED, b, perm=perm, K=K, ir_tol=ir_tol)
+    x, info, _, _ = O.solve(case, O.CONDENSED, b, eps=1e-12, pivot_scale="absolute", ir_tol=GATE_OMEGA,
+                            ir_cw_tol=GATE_CW, perm=perm, K=K)
     secs = time.perf_counter() - t0
-    log(f"[cpu oracle] ordering {t_order:.1f}s, factor+solve+IR {secs:.1f}s, omega {info.backward_error:.2e}")
-    return {"value": 1.0 / secs, "unit": "factor+solve/s", "cores": 1, "kind": "oracle",
-            "sample": "one refactor (rho=1e2) of the same n=500k sequence: assembly + up-looking LDL^T with "
-                      "static pivoting + 1 RHS solve + refinement to 1e-10; minimum-degree ordering excluded "
-                      f"({t_order:.1f}s)", "seconds": secs, "nnz_L": info.nnz_L,
-            "backward_error": info.backward_error}
+    xo[0] = x.reshape(-1, 1)
+    log(f"[cpu oracle] ordering {t_order:.1f}s, factor+solve+IR {secs:.1f}s, omega {info.backward_error:.2e} "
+        f"cw {info.backward_error_cw:.2e}")
+    if with_last:
+        Sigma, rho = seq[SEQ - 1]
+        case = inp.with_values(Sigma=Sigma, rho=rho)
+        x, info29, _, _ = O.solve(case, O.CONDENSED, b, eps=1e-12, pivot_scale="absolute", ir_tol=GATE_OMEGA,
+                                  ir_cw_tol=GATE_CW, perm=perm)
+        xo[SEQ - 1] = x.reshape(-1, 1)
+    model = platform.processor() or "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return ({"value": 1.0 / secs, "unit": "factor+solve/s", "cores": 1, "kind": "oracle",
+             "sample": "one refactor (rho=1e2) of the same n=500k sequence: assembly + up-looking LDL^T with "
+                       "static pivoting + 1 RHS solve + refinement to the same gate; minimum-degree ordering "
+                       f"excluded ({t_order:.1f}s)", "seconds": secs, "nnz_L": info.nnz_L,
+             "backward_error": info.backward_error, "backward_error_cw": info.backward_error_cw,
+             "cpu_model": model, "nproc": os.cpu_count(), "threads_used": 1}, xo)
 
 
 if __name__ == "__main__":

@@ -17,12 +17,19 @@
  * a caller that regularizes with delta passes Sigma + delta and rho + delta.
  *
  * Static pivoting (Sec. 3.1 "Sparse LDL^T factorization", Sec. 4.3): a pivot d
- * with |d| < eps * ||K||_max (strict; ||K||_max = max_ij |K_ij| of the
- * assembled, unpermuted K in FP64) is replaced by s * eps * ||K||_max, where
- * s = +1 for a primal row and -1 for a dual row of the unpermuted matrix.  A
- * pivot of the wrong sign and magnitude above the threshold is kept and shows
- * in the inertia.  The factor is thus of a slightly perturbed matrix; solves
- * refine against the unperturbed K (Richardson, Sec. 4.3).
+ * with |d| < t (strict) is replaced by s * t, where s = +1 for a primal row and
+ * -1 for a dual row of the unpermuted matrix, and t is the threshold of that
+ * row's block: t = eps * ||K||_max for every pivot (NCL_PIVOT_GLOBAL, default;
+ * ||K||_max = max_ij |K_ij| of the assembled, unpermuted K in FP64), or, with
+ * NCL_PIVOT_BLOCK in the stabilized form, eps * max |(W + Sigma)_ij| for
+ * primal pivots and eps / rho for dual pivots (the norm of the -1/rho I block
+ * of Sec. 3.2, eq. K2r), or t = eps for every pivot (NCL_PIVOT_ABSOLUTE: the
+ * solver's pivot epsilon of Sec. 4.3 as an absolute bound; it leaves alone
+ * the small but legitimate pivots of a primal block whose Sigma spans many
+ * decades).  A pivot of the wrong sign and magnitude above the
+ * threshold is kept and shows in the inertia.  The factor is thus of a
+ * slightly perturbed matrix; solves refine against the unperturbed K
+ * (Richardson, Sec. 4.3).
  *
  * Memory: patterns are host arrays copied at analyze time.  Values,
  * right-hand sides, solutions and gradients are caller-owned DEVICE buffers
@@ -48,15 +55,17 @@ typedef struct ncl_kkt_s *ncl_kkt_t;
 enum { NCL_CONDENSED = 0, NCL_STABILIZED = 1 };
 enum { NCL_FP64 = 0, NCL_FP32_IR = 1 };
 enum { NCL_ORDER_ND = 0, NCL_ORDER_NATURAL = 1, NCL_ORDER_USER = 2 };
+enum { NCL_PIVOT_GLOBAL = 0, NCL_PIVOT_BLOCK = 1, NCL_PIVOT_ABSOLUTE = 2 };
 
 #define NCL_OK 0
 #define NCL_ERR_ARG (-1)        /* bad argument (sizes, null pointers, rho <= 0, ...) */
 #define NCL_ERR_PATTERN (-2)    /* unsorted / duplicate / out-of-range / upper-triangle index */
 #define NCL_ERR_ALLOC (-3)      /* host or device allocation failed */
-#define NCL_ERR_HIP (-4)        /* a HIP runtime call failed, or a device-side wait of the
-                                   dataflow factorization timed out */
+#define NCL_ERR_HIP (-4)        /* a HIP runtime call failed */
 #define NCL_ERR_STATE (-5)      /* call out of order (solve before factor, ...) */
-#define NCL_ERR_NONFINITE (-6)  /* NaN or Inf met in the assembled matrix or a pivot */
+#define NCL_ERR_NONFINITE (-6)  /* NaN or Inf met in the assembled matrix, or in a pivot of an
+                                   FP64 factorization (an FP32 factor that meets one is
+                                   replaced by an FP64 refactorization instead) */
 #define NCL_WARN_INERTIA 1      /* factor done, inertia differs from (n,0,0) / (n,m,0) */
 #define NCL_WARN_IR_NOT_CONVERGED 2  /* refinement stopped above ir_tol */
 #define NCL_WARN_FELL_BACK_FP64 3    /* FP32 factor insufficient; refactored in FP64 */
@@ -68,9 +77,12 @@ typedef struct {
     double pivot_eps;      /* relative static-pivot epsilon; <= 0: 1e-12 condensed,
                               1e-10 stabilized (the paper's value, Sec. 4.3) */
     int32_t ir_max_steps;  /* max refinement corrections per solve (default 10) */
-    double ir_tol;         /* stop when the backward error is <= ir_tol (default 1e-12) */
-    double ir_stall;       /* stop when a correction does not reduce the backward
-                              error below ir_stall * previous (default 0.5) */
+    double ir_tol;         /* converged when the normwise backward error omega <= ir_tol
+                              (default 1e-12) and, if ir_cw_tol > 0, the componentwise one
+                              <= ir_cw_tol */
+    double ir_stall;       /* stop when a correction does not reduce the distance to the
+                              target, max(omega / ir_tol, omega_cw / ir_cw_tol), below
+                              ir_stall * previous (default 0.5) */
     int32_t ordering;      /* NCL_ORDER_ND (default), NCL_ORDER_NATURAL, NCL_ORDER_USER */
     const int32_t *user_perm; /* host, used when ordering == NCL_ORDER_USER: user_perm[k] =
                                  unpermuted index of the k-th pivot (length n or n+m) */
@@ -85,23 +97,26 @@ typedef struct {
                                 in FP64 directly; a factor with max rho < r tries FP32 again
                                 (rho grows along an NCL outer loop, Algorithm 1).  0: always
                                 try FP32 first. */
-    int32_t large_flow;      /* 0 (default): per level, one launch per task kind and panel step
-                                (diagonal blocks on a second stream beside the tile updates).
-                                1: the large fronts of a level are factored by one dataflow
-                                launch whose diagonal-block, panel-solve and tile-update tasks
-                                wait on device counters instead of launch boundaries.  Same
-                                results bit for bit; which is faster depends on the tree (the
-                                dataflow launch shortens single-front chains but loses L2
-                                reuse on levels with many fronts). */
+    int32_t pivot_scale;     /* NCL_PIVOT_GLOBAL (default), NCL_PIVOT_BLOCK (stabilized form:
+                                each block's own norm, see above; same as global for the
+                                condensed form) or NCL_PIVOT_ABSOLUTE */
+    double ir_cw_tol;        /* > 0: refinement must also bring the componentwise backward
+                                error max_i |b - Kx|_i / (|K||x| + |b|)_i to <= ir_cw_tol;
+                                0 (default): normwise criterion only */
 } ncl_kkt_options;
 
-/* Result of one solve (normwise backward error
- * omega = ||b - Kx||_inf / (||K||_inf ||x||_inf + ||b||_inf), max over columns). */
+/* Result of one solve, each figure the max over columns (and systems), all
+ * measured against the unperturbed K in FP64:
+ *   omega    = ||b - Kx||_inf / (||K||_inf ||x||_inf + ||b||_inf)  (normwise)
+ *   omega_cw = max_i |b - Kx|_i / (|K| |x| + |b|)_i                (componentwise)
+ *   rel2     = ||b - Kx||_2 / ||b||_2 */
 typedef struct {
     int32_t ir_steps;        /* refinement corrections applied */
     int32_t fell_back_fp64;  /* 1 when an FP64 refactor was needed (FP32_IR only) */
     double backward_error;   /* final omega */
     double backward_error0;  /* omega of the unrefined solve */
+    double backward_error_cw;  /* final omega_cw */
+    double resid_rel2;       /* final rel2 */
 } ncl_kkt_solve_info;
 
 /* Sizes of the symbolic analysis. */
@@ -109,13 +124,18 @@ typedef struct {
     int64_t order;          /* n (condensed) or n + m (stabilized), summed over systems */
     int64_t nnz_K_lower;    /* stored lower entries of K (incl. diagonal) */
     int64_t nnz_L;          /* entries of L incl. diagonal, supernodal (with padding zeros) */
-    double flops_factor;    /* flops of the partial frontal factorizations */
+    double flops_factor;    /* flops of the partial frontal factorizations as executed
+                               (amalgamation padding included) */
     int64_t n_supernodes;
     int64_t n_levels;       /* levels of the supernodal tree (leaves = level 0) */
     int64_t max_front;      /* largest front order */
     int64_t n_large_fronts; /* fronts handled by the global-memory MFMA path */
     int64_t device_bytes;   /* device workspace held by the handle */
     double analyze_seconds; /* host time of the symbolic analysis */
+    int64_t nnz_L_exact;    /* entries of L incl. diagonal for the same ordering, without
+                               amalgamation padding (column counts of the elimination tree) */
+    double flops_exact;     /* sum over columns j of c_j (c_j + 2), c_j = entries of column j
+                               of L below the diagonal: the factorization's algorithmic flops */
 } ncl_kkt_stats;
 
 void ncl_kkt_default_options(ncl_kkt_options *o);
@@ -164,8 +184,9 @@ int ncl_kkt_factor_batched(ncl_kkt_t h, const double *W_val, const double *Sigma
  * dimensions >= order), with FP64 iterative refinement against the
  * unperturbed K (Sec. 4.3); refinement runs only when the inertia is the
  * expected one.  B and X must not overlap.  info may be NULL.  Returns
- * NCL_WARN_IR_NOT_CONVERGED when omega stays above ir_tol, and
- * NCL_WARN_FELL_BACK_FP64 when the FP32 factor had to be replaced. */
+ * NCL_WARN_IR_NOT_CONVERGED when refinement stops short of its criterion
+ * (ir_tol, ir_cw_tol), and NCL_WARN_FELL_BACK_FP64 when the FP32 factor had to
+ * be replaced (then the solve refactors in FP64 from the assembled K). */
 int ncl_kkt_solve(ncl_kkt_t h, const double *B, int64_t ldb, double *X, int64_t ldx,
                   int32_t nrhs, void *stream, ncl_kkt_solve_info *info);
 
@@ -206,18 +227,6 @@ int ncl_kkt_get_perm(ncl_kkt_t h, int32_t *perm);
 int ncl_kkt_get_supernodes(ncl_kkt_t h, int32_t *first, int32_t *parent, int64_t *row_ptr,
                            int32_t *rows);
 
-/* Schedule of the dataflow large-front launches (options.large_flow), for
- * inspection.  counts[0..2] = tasks, dependencies, counters; counts[3] =
- * launches (levels with large fronts).  Each task is 8 int32: type (0
- * diagonal block, 1 panel solve, 2 tile update), supernode, k0, a, b (panel:
- * a = first row; update: a, b = tile row, column), first dependency, number of
- * dependencies, counter signalled (-1: none).  A dependency is (counter,
- * target): the task starts once the counter has reached the target.  Each
- * launch is 4 int64: first task, task count, ticket counter, workgroups.
- * Rows and columns are local to the front.  Pass NULL arrays to query only
- * the counts. */
-int ncl_kkt_get_flow(ncl_kkt_t h, int64_t *counts, int32_t *tasks, int32_t *deps, int64_t *launches);
-
 /* Kernel timing.  When enabled, factor and solve record HIP events around
  * every kernel class on the caller's stream and accumulate device time (ms)
  * and launch counts, readable with ncl_kkt_get_timing. */
@@ -228,14 +237,15 @@ typedef struct {
                               5 forward/backward solve, 6 residual,
                               7 large-front first-panel diagonal blocks (LDL^T + inverse) */
     int64_t launches[8];
-    double update_flops;   /* algorithmic flops of all update launches timed (tiles and the
-                              diagonal blocks launched with them) */
-    double small_flops;    /* algorithmic flops of all small-front launches timed */
-    double assemble_bytes; /* algorithmic bytes of all assembly launches timed */
-    double solve_bytes;    /* algorithmic bytes of all solve sweeps timed */
-    double panel_flops;    /* algorithmic flops of all panel-solve launches timed (rows x w^2) */
-    double diag_flops;     /* algorithmic flops of all first-panel diagonal-block launches timed:
-                              per block w^3/3 (LDL^T) + w^3/3 (inverse) */
+    /* Algorithmic work of the timed launches.  Flops of a front are scaled by
+     * its exact / executed ratio and bytes of L by its exact / stored ratio
+     * (amalgamation padding is not work); explicit inverses are not counted. */
+    double update_flops;   /* update launches (tiles and the diagonal blocks launched with them) */
+    double small_flops;    /* small-front launches */
+    double assemble_bytes; /* assembly: 8 (nnz(W) + nnz(J) + n + nnz(lower K)) per launch */
+    double solve_bytes;    /* solve sweeps: L read once per sweep (FP64 size: 8 bytes an entry) */
+    double panel_flops;    /* panel-solve launches (rows x w^2) */
+    double diag_flops;     /* first-panel diagonal-block launches: per block w^3/3 (LDL^T) */
 } ncl_kkt_timing;
 
 int ncl_kkt_set_timing(ncl_kkt_t h, int32_t enable);   /* enabling also clears totals */

@@ -412,6 +412,24 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
             for (int j : gcols[gids[k]]) perm2.push_back(perm[j]);
             P.sn_first.push_back((int)perm2.size());
         }
+        // algorithmic size of the factor for this ordering: the column counts of
+        // the elimination tree, before amalgamation padding (the group order
+        // above is a topological order of the same tree, so each column keeps
+        // its count); per final supernode for the timing classes
+        std::vector<double> col_exact(N), col_cnt(N);
+        P.nnzL_exact = 0;
+        P.flops_exact = 0.0;
+        {
+            std::vector<int> old_pos(N);
+            for (int j = 0; j < N; ++j) old_pos[perm[j]] = j;
+            for (int k = 0; k < N; ++k) {
+                const double c = (double)cc[old_pos[perm2[k]]] - 1.0;
+                col_exact[k] = c * (c + 2.0);
+                col_cnt[k] = c + 1.0;
+                P.nnzL_exact += (int64_t)c + 1;
+                P.flops_exact += col_exact[k];
+            }
+        }
         perm.swap(perm2);
         for (int k = 0; k < N; ++k) iperm[perm[k]] = k;
         P.perm = perm;
@@ -483,6 +501,8 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
         P.flops = P.small_flops = P.large_flops = 0.0;
         P.max_front = 0;
         P.sn_large.assign(nsn, 0);
+        P.sn_flop_ratio.assign(nsn, 1.0);
+        P.sn_nnz_ratio.assign(nsn, 1.0);
         P.n_large = 0;
         for (int s = 0; s < nsn; ++s) {
             const int64_t f = P.sn_rowptr[s + 1] - P.sn_rowptr[s];
@@ -494,6 +514,12 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                 fl += r + r * (r + 1.0);     // column scaling + lower rank-1 update
             }
             P.flops += fl;
+            double ex = 0.0;
+            for (int j = P.sn_first[s]; j < P.sn_first[s + 1]; ++j) ex += col_exact[j];
+            P.sn_flop_ratio[s] = fl > 0.0 ? ex / fl : 1.0;
+            double nz = 0.0;
+            for (int j = P.sn_first[s]; j < P.sn_first[s + 1]; ++j) nz += col_cnt[j];
+            P.sn_nnz_ratio[s] = nz / (double)(p * f - p * (p - 1) / 2);
             P.max_front = std::max<int>(P.max_front, (int)f);
             if (f > cfg.small_front_max) { P.sn_large[s] = 1; P.n_large++; P.large_flops += fl; }
             else P.small_flops += fl;
@@ -757,7 +783,7 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                             P.large_upd.push_back(i0); P.large_upd.push_back(j0);
                             double ri = std::min(T, f - i0), rj = std::min(T, f - j0);
                             double ent = (i0 == j0) ? ri * (ri + 1) / 2 : ri * rj;
-                            fl += 2.0 * ent * (k1 - k0);
+                            fl += 2.0 * ent * (k1 - k0) * P.sn_flop_ratio[s];
                         }
                 }
                 st.diag_count.push_back((int64_t)P.large_diag.size() / 2 - st.diag_first.back());
@@ -765,7 +791,6 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                 st.upd_count.push_back((int64_t)P.large_upd.size() / 4 - st.upd_first.back());
                 st.upd_flops.push_back(fl);
             }
-            build_flow(P, st, large, cfg.flow_workers);
             P.large_steps.push_back(std::move(st));
         }
         // ---------------- solve schedule -----------------------------------
@@ -795,7 +820,7 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                         const int below = f - c0 - w;
                         if (!P.sn_large[s] && p <= 64 && f <= 128) {
                             P.solve_s.push_back(s);
-                            st.fwd_bytes += 8.0 * ((double)w * (w + 1) / 2.0 + (double)below * w);
+                            st.fwd_bytes += 8.0 * ((double)w * (w + 1) / 2.0 + (double)below * w) * P.sn_nnz_ratio[s];
                             continue;
                         }
                         const bool fused = below <= FUSE;
@@ -808,7 +833,7 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                         }
                         P.solve_t.push_back(s); P.solve_t.push_back(c0); P.solve_t.push_back(fused ? 1 : 0);
                         P.solve_t.push_back(gfirst); P.solve_t.push_back(slot - gfirst);
-                        st.fwd_bytes += 8.0 * ((double)w * (w + 1) / 2.0 + (double)below * w);
+                        st.fwd_bytes += 8.0 * ((double)w * (w + 1) / 2.0 + (double)below * w) * P.sn_nnz_ratio[s];
                     }
                     st.t_count = (int64_t)P.solve_t.size() / 5 - st.t_first;
                     st.s_count = (int64_t)P.solve_s.size() - st.s_first;

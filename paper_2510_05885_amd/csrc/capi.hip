@@ -53,6 +53,8 @@ struct ncl_kkt_s {
     Plan P;
     ncl_kkt_options opt{};
     double eps = 0.0;
+    int pivot_mode = 0;               // thresholds: 0 global, 1 per block (stabilized), 2 absolute
+    int nonfinite_bits = 0;           // status word of the last factorization read back
     bool host_only = true;
     int device = 0;
     std::vector<void*> allocs;
@@ -62,11 +64,10 @@ struct ncl_kkt_s {
     // schedule arrays (device)
     int *small_list = nullptr, *level_list = nullptr, *large_asm = nullptr, *large_panel = nullptr,
         *large_upd = nullptr, *large_diag = nullptr, *solve_t = nullptr, *solve_g = nullptr, *solve_s = nullptr;
-    int *flow_task = nullptr, *flow_dep = nullptr, *flow_ctr = nullptr;
     int *chunk_row0 = nullptr, *chunk_rows = nullptr, *sys_chunk_ptr = nullptr;
     int nchunks = 0;
     // numeric state
-    double *K = nullptr, *partial_norm = nullptr, *norms2 = nullptr, *kmax = nullptr, *kinf = nullptr,
+    double *K = nullptr, *partial_norm = nullptr, *norms3 = nullptr, *kmax = nullptr, *kinf = nullptr,
            *thr = nullptr, *rho = nullptr;
     int* nonfinite = nullptr;
     unsigned long long* inertia = nullptr;
@@ -181,6 +182,7 @@ void setup_device(ncl_kkt_s* h) {
     HIPCHK(hipGetDevice(&h->device));
     DevPlan& d = h->d;
     d.N = P.N;
+    d.n_primal = P.form == NCL_STABILIZED ? P.sys_n[0] : P.N;
     d.S = P.S;
     d.form = P.form;
     h->nnzF = (int64_t)P.Kj.size();
@@ -237,9 +239,6 @@ void setup_device(ncl_kkt_s* h) {
     h->solve_s = upload(h, P.solve_s);
     h->large_panel = upload(h, P.large_panel);
     h->large_upd = upload(h, P.large_upd);
-    h->flow_task = upload(h, P.flow_task);
-    h->flow_dep = upload(h, P.flow_dep);
-    h->flow_ctr = dalloc<int>(h, P.flow_nctr);
     // row chunks (<= 256 rows, never straddling two systems)
     std::vector<int> c0, cn, scp(1, 0);
     for (int s = 0; s < P.S; ++s) {
@@ -255,11 +254,11 @@ void setup_device(ncl_kkt_s* h) {
     h->sys_chunk_ptr = upload(h, scp);
     // numeric buffers
     h->K = dalloc<double>(h, h->nnzF);
-    h->partial_norm = dalloc<double>(h, 2 * (int64_t)h->nchunks);
-    h->norms2 = dalloc<double>(h, 2 * P.S);
+    h->partial_norm = dalloc<double>(h, 3 * (int64_t)h->nchunks);
+    h->norms3 = dalloc<double>(h, 3 * P.S);
     h->kmax = dalloc<double>(h, P.S);
     h->kinf = dalloc<double>(h, P.S);
-    h->thr = dalloc<double>(h, P.S);
+    h->thr = dalloc<double>(h, 2 * P.S);
     h->rho = dalloc<double>(h, P.S);
     h->nonfinite = dalloc<int>(h, 1);
     h->inertia = dalloc<unsigned long long>(h, 4 * P.S);
@@ -285,8 +284,8 @@ void setup_device(ncl_kkt_s* h) {
     h->R = dalloc<double>(h, P.N * kNrhsMax);
     h->DX = dalloc<double>(h, P.N * kNrhsMax);
     h->Xp = dalloc<double>(h, P.N * kNrhsMax);
-    h->partial_res = dalloc<double>(h, (int64_t)h->nchunks * kNrhsMax * 3);
-    h->res_out = dalloc<double>(h, (int64_t)P.S * kNrhsMax * 3);
+    h->partial_res = dalloc<double>(h, (int64_t)h->nchunks * kNrhsMax * kResWidth);
+    h->res_out = dalloc<double>(h, (int64_t)P.S * kNrhsMax * kResWidth);
     // adjoint structures
     if (P.form == NCL_CONDENSED) {
         h->W_row = upload(h, P.Wrow_of);
@@ -301,7 +300,7 @@ void setup_device(ncl_kkt_s* h) {
         h->JX = dalloc<double>(h, std::max<int64_t>(P.nJrows, 1) * kNrhsMax);
         h->JL = dalloc<double>(h, std::max<int64_t>(P.nJrows, 1) * kNrhsMax);
     }
-    h->host_pinned_len = (size_t)std::max<int64_t>((int64_t)P.S * kNrhsMax * 3, 8 * (int64_t)P.S + 8);
+    h->host_pinned_len = (size_t)std::max<int64_t>((int64_t)P.S * kNrhsMax * kResWidth, 8 * (int64_t)P.S + 8);
     HIPCHK(hipHostMalloc((void**)&h->host_pinned, sizeof(double) * h->host_pinned_len, hipHostMallocDefault));
     HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&h->aux_stream, hipStreamNonBlocking));
@@ -341,7 +340,8 @@ void fill_defaults(ncl_kkt_options* o) {
     o->small_front_max = 0;
     o->relax_big_zeros = -1.0;
     o->fp32_sticky = 1;
-    o->large_flow = 0;
+    o->pivot_scale = NCL_PIVOT_GLOBAL;
+    o->ir_cw_tol = 0.0;
 }
 
 int do_analyze(ncl_kkt_t* out, const ncl_kkt_options* o, const std::vector<SysInput>& sys, bool host_only) {
@@ -354,6 +354,10 @@ int do_analyze(ncl_kkt_t* out, const ncl_kkt_options* o, const std::vector<SysIn
     if (h->opt.precision != NCL_FP64 && h->opt.precision != NCL_FP32_IR) { delete h; return NCL_ERR_ARG; }
     if (h->opt.ordering < 0 || h->opt.ordering > 2) { delete h; return NCL_ERR_ARG; }
     if (h->opt.ir_max_steps < 0 || !(h->opt.ir_stall > 0.0)) { delete h; return NCL_ERR_ARG; }
+    if (h->opt.pivot_scale < NCL_PIVOT_GLOBAL || h->opt.pivot_scale > NCL_PIVOT_ABSOLUTE) { delete h; return NCL_ERR_ARG; }
+    if (!(h->opt.ir_cw_tol >= 0.0)) { delete h; return NCL_ERR_ARG; }
+    h->pivot_mode = h->opt.pivot_scale == NCL_PIVOT_ABSOLUTE ? 2
+                    : (h->opt.pivot_scale == NCL_PIVOT_BLOCK && h->opt.form == NCL_STABILIZED ? 1 : 0);
     if (sys.size() > 1 && h->opt.form != NCL_CONDENSED) { delete h; return NCL_ERR_ARG; }
     h->eps = h->opt.pivot_eps > 0.0 ? h->opt.pivot_eps : (h->opt.form == NCL_CONDENSED ? 1e-12 : 1e-10);
     PlanConfig cfg;
@@ -390,15 +394,17 @@ int do_analyze(ncl_kkt_t* out, const ncl_kkt_options* o, const std::vector<SysIn
 
 // ----- numeric factorization -----------------------------------------------
 // Algorithmic flops of one step's diagonal-block and panel-solve launches
-// (w = panel width): w^3/3 for the LDL^T and w^3/3 for the inverse of each
-// block, plus w_prev * w^2 for the block's own update after the first panel;
-// rows-below x w^2 for the panel solve.
+// (w = panel width): w^3/3 for the LDL^T of each block (its explicit inverse
+// is the implementation's extra work and is not counted), plus w_prev * w^2
+// for the block's own update after the first panel; rows-below x w^2 for the
+// panel solve.  Each front's figures are scaled by its exact / executed flop
+// ratio, so amalgamation padding is not counted as work.
 double diag_flops(const Plan& P, const LargeStep& ls, size_t k) {
     double fl = 0.0;
     for (int64_t t = ls.diag_first[k]; t < ls.diag_first[k] + ls.diag_count[k]; ++t) {
         const int s = P.large_diag[2 * t], k0 = P.large_diag[2 * t + 1];
         const double w = std::min(kPanel, P.sn_first[s + 1] - P.sn_first[s] - k0);
-        fl += 2.0 * w * w * w / 3.0 + (k0 > 0 ? (double)kPanel * w * w : 0.0);
+        fl += (w * w * w / 3.0 + (k0 > 0 ? (double)kPanel * w * w : 0.0)) * P.sn_flop_ratio[s];
     }
     return fl;
 }
@@ -408,7 +414,7 @@ double panel_flops(const Plan& P, const LargeStep& ls, size_t k) {
         const int s = P.large_panel[3 * t], k0 = P.large_panel[3 * t + 1], r0 = P.large_panel[3 * t + 2];
         const int f = (int)(P.sn_rowptr[s + 1] - P.sn_rowptr[s]);
         const double w = std::min(kPanel, P.sn_first[s + 1] - P.sn_first[s] - k0);
-        fl += (double)std::min(32, f - r0) * w * w;
+        fl += (double)std::min(32, f - r0) * w * w * P.sn_flop_ratio[s];
     }
     return fl;
 }
@@ -418,8 +424,6 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
     Plan& P = h->P;
     const DevPlan& d = h->d;
     launch_zero_u64(h->inertia_part, 4 * (int64_t)P.S * kInertiaSlots, st);
-    const bool flow = h->opt.large_flow != 0;
-    if (flow) launch_zero_i32(h->flow_ctr, P.flow_nctr, st);
     size_t sb = 0, lb = 0;
     for (int l = 0; l < P.nlevels; ++l) {
         // Fronts of one level are independent: when the level has both kinds,
@@ -455,7 +459,9 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
                     const int s = P.small_list[k];
                     const double f = (double)(P.sn_rowptr[s + 1] - P.sn_rowptr[s]);
                     const int p = P.sn_first[s + 1] - P.sn_first[s];
-                    for (int t = 0; t < p; ++t) { double r = f - t - 1; fl += r + r * (r + 1.0); }
+                    double ff = 0.0;
+                    for (int t = 0; t < p; ++t) { double r = f - t - 1; ff += r + r * (r + 1.0); }
+                    fl += ff * P.sn_flop_ratio[s];
                 }
             Span sp(h, bs, TM_SMALL, fl, 2);
             launch_small_fronts<T>(d, h->small_list + b.first, (int)b.count, b.fmax, h->K, F, D, bs);
@@ -467,11 +473,7 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
                 Span sp(h, st, TM_LASM);
                 launch_large_asm<T>(d, ls.asm_first, (int)ls.asm_count, ls.asm_fmax, h->K, F, st);
             }
-            if (flow) {
-                Span sp(h, st, TM_UPD, ls.flow_flops, 1);
-                launch_large_flow<T>(d, h->flow_task + 8 * ls.flow_first, (int)ls.flow_count, h->flow_dep,
-                                     h->flow_ctr, (int)ls.flow_ticket, ls.flow_grid, F, D, Mb, st);
-            } else {
+            {
                 // Step k: panel TRSM, then one launch with the trailing update
                 // and the next panel's diagonal blocks (which update themselves).
                 const size_t nsteps = ls.panel_first.size();
@@ -540,6 +542,7 @@ int read_inertia(ncl_kkt_s* h, hipStream_t st) {
     HIPCHK(hipStreamSynchronize(st));
     int nonfin = 0;
     std::memcpy(&nonfin, h->host_pinned + 4 * S, sizeof(int));
+    h->nonfinite_bits = nonfin;
     h->inertia_ok = true;
     for (int s = 0; s < S; ++s) {
         for (int k = 0; k < 4; ++k) h->h_inertia[4 * s + k] = (int64_t)hp[4 * s + k];
@@ -548,9 +551,20 @@ int read_inertia(ncl_kkt_s* h, hipStream_t st) {
         if (h->h_inertia[4 * s + 0] != n || h->h_inertia[4 * s + 1] != want_neg || h->h_inertia[4 * s + 2] != 0)
             h->inertia_ok = false;
     }
-    if (nonfin & 2) return NCL_ERR_HIP;   // a dataflow wait timed out
     if (nonfin) return NCL_ERR_NONFINITE;
     return NCL_OK;
+}
+
+// Replaces the FP32 factor in use by an FP64 factorization of the same
+// assembled K (whose norms and thresholds are already on the device), and
+// remembers the rho at which FP32 was insufficient (sticky policy).
+int refactor_fp64(ncl_kkt_s* h, hipStream_t st) {
+    launch_zero_i32(h->nonfinite, 1, st);
+    run_factor<double>(h, st);
+    h->factor_prec = 0;
+    h->fell_back = true;
+    h->fp32_rho_limit = std::min(h->fp32_rho_limit, h->cur_rho_max);
+    return read_inertia(h, st);
 }
 
 int factor_impl(ncl_kkt_s* h, const double* W, const double* Sigma, const double* J, const double* rho_host,
@@ -568,13 +582,14 @@ int factor_impl(ncl_kkt_s* h, const double* W, const double* Sigma, const double
         HIPCHK(hipMemcpyAsync(h->rho, h->host_pinned, sizeof(double) * P.S, hipMemcpyHostToDevice, st));
         launch_zero_i32(h->nonfinite, 1, st);
         {
-            const double bytes = (double)h->nnzF * (8 + 4 + 4 + 4 + 1 + 8) + 8.0 * (P.nnzW + P.nnzJ + P.N) +
-                                 (double)P.prod_a.size() * 8.0;
+            // algorithmic bytes: read W, Sigma, J once, write the lower triangle of K
+            const double bytes = 8.0 * ((double)P.nnzW + (double)P.nnzJ + (double)P.N + (double)P.nnz_lower);
             Span sp(h, st, TM_ASM, bytes, 3);
             launch_assemble(h->d, h->nnzF, W, Sigma, J, h->rho, h->K, st);
             launch_chunk_norms(h->d, h->K, h->chunk_row0, h->chunk_rows, h->nchunks, h->partial_norm, st);
-            launch_reduce(h->sys_chunk_ptr, P.S, 2, h->partial_norm, h->norms2, st);
-            launch_thresholds(P.S, h->norms2, h->eps, h->kmax, h->kinf, h->thr, h->nonfinite, st);
+            launch_reduce(h->sys_chunk_ptr, P.S, 3, 3, 0u, h->partial_norm, h->norms3, st);
+            launch_thresholds(P.S, h->norms3, h->eps, h->pivot_mode, h->rho, h->kmax, h->kinf, h->thr, h->nonfinite,
+                              st);
         }
         HIPCHK(hipGetLastError());
         double rho_max = 0.0;
@@ -584,27 +599,20 @@ int factor_impl(ncl_kkt_s* h, const double* W, const double* Sigma, const double
         if (h->opt.precision == NCL_FP32_IR && !skip32) {
             run_factor<float>(h, st);
             h->factor_prec = 1;
-        } else if (h->opt.precision == NCL_FP32_IR) {
-            // an FP32 factor failed at a smaller rho of this sequence: FP64 directly
-            run_factor<double>(h, st);
-            h->factor_prec = 0;
-            h->fell_back = true;
         } else {
+            // FP64, or an FP32 factor failed at a smaller rho of this sequence
             run_factor<double>(h, st);
             h->factor_prec = 0;
+            h->fell_back = h->opt.precision == NCL_FP32_IR;
         }
         HIPCHK(hipGetLastError());
         int rc = read_inertia(h, st);
-        if (rc) { flush_timing(h); return rc; }
-        if (!h->inertia_ok && h->factor_prec == 1) {
-            // an FP32 factor with the wrong inertia: refactor in FP64
-            run_factor<double>(h, st);
-            h->factor_prec = 0;
-            h->fell_back = true;
-            h->fp32_rho_limit = std::min(h->fp32_rho_limit, rho_max);
-            rc = read_inertia(h, st);
-            if (rc) { flush_timing(h); return rc; }
+        if (h->factor_prec == 1 && (!h->inertia_ok || rc == NCL_ERR_NONFINITE)) {
+            // An FP32 factor with the wrong inertia, or one that met a non-finite
+            // pivot (FP32 range) while K itself is finite: refactor in FP64.
+            if (rc == NCL_OK || !(h->nonfinite_bits & kNonfiniteInput)) rc = refactor_fp64(h, st);
         }
+        if (rc) { flush_timing(h); return rc; }
         // host copy of ||K||_inf per system for the backward error
         HIPCHK(hipMemcpyAsync(h->host_pinned, h->kinf, sizeof(double) * P.S, hipMemcpyDeviceToHost, st));
         HIPCHK(hipStreamSynchronize(st));
@@ -725,53 +733,75 @@ void solve_with_factor(ncl_kkt_s* h, const double* B, int64_t ldb, double* X, in
         solve_once<double>(h, B, ldb, X, ldx, nrhs, h->F64, h->M64, h->D64, h->Y64, h->U64, h->P64, st);
 }
 
-// Backward error of X against B (max over systems and columns).
-double backward_error(ncl_kkt_s* h, const double* B, int64_t ldb, const double* X, int64_t ldx, int nrhs,
-                      hipStream_t st) {
+// Backward errors of X against B, each the max over systems and columns.
+struct Backward {
+    double omega = 0.0;   // normwise
+    double cw = 0.0;      // componentwise
+    double rel2 = 0.0;    // ||b - Kx||_2 / ||b||_2
+};
+
+Backward backward_error(ncl_kkt_s* h, const double* B, int64_t ldb, const double* X, int64_t ldx, int nrhs,
+                        hipStream_t st) {
     Plan& P = h->P;
     {
         Span sp(h, st, TM_RES);
         launch_residual(h->d, h->K, B, ldb, X, ldx, h->R, nrhs, h->chunk_row0, h->chunk_rows, h->nchunks,
                         h->partial_res, st);
-        launch_reduce(h->sys_chunk_ptr, P.S, 3 * nrhs, h->partial_res, h->res_out, st);
+        launch_reduce(h->sys_chunk_ptr, P.S, kResWidth * nrhs, kResWidth, (1u << 3) | (1u << 4), h->partial_res,
+                      h->res_out, st);
     }
-    HIPCHK(hipMemcpyAsync(h->host_pinned, h->res_out, sizeof(double) * 3 * nrhs * P.S, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(h->host_pinned, h->res_out, sizeof(double) * kResWidth * nrhs * P.S,
+                          hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    double om = 0.0;
+    Backward out;
+    auto upd = [](double& m, double w) { m = std::isnan(w) ? INFINITY : std::max(m, w); };
     for (int s = 0; s < P.S; ++s)
         for (int q = 0; q < nrhs; ++q) {
-            const double* v = h->host_pinned + ((int64_t)s * nrhs + q) * 3;
+            const double* v = h->host_pinned + ((int64_t)s * nrhs + q) * kResWidth;
             const double den = h->h_kinf[s] * v[1] + v[2];
-            const double w = den > 0.0 ? v[0] / den : (v[0] > 0.0 ? INFINITY : 0.0);
-            om = std::isnan(w) ? INFINITY : std::max(om, w);
+            upd(out.omega, den > 0.0 ? v[0] / den : (v[0] > 0.0 ? INFINITY : 0.0));
+            upd(out.cw, v[5]);
+            upd(out.rel2, v[4] > 0.0 ? std::sqrt(v[3] / v[4]) : (v[3] > 0.0 ? INFINITY : 0.0));
         }
-    return om;
+    return out;
 }
 
-// One chunk of <= kNrhsMax columns: solve + refinement.  Returns the final omega.
-double solve_refine(ncl_kkt_s* h, const double* B, int64_t ldb, double* X, int64_t ldx, int nrhs, hipStream_t st,
-                    int& steps, double& om0) {
+// Distance to the refinement target: <= 1 when converged.
+double ir_gap(const ncl_kkt_s* h, const Backward& b) {
+    double g = h->opt.ir_tol > 0.0 ? b.omega / h->opt.ir_tol : (b.omega > 0.0 ? INFINITY : 0.0);
+    if (h->opt.ir_cw_tol > 0.0) g = std::max(g, b.cw / h->opt.ir_cw_tol);
+    return std::isnan(g) ? INFINITY : g;
+}
+bool converged(const ncl_kkt_s* h, const Backward& b) { return ir_gap(h, b) <= 1.0; }
+
+// One chunk of <= kNrhsMax columns: solve + refinement.  Returns the final
+// backward errors; om0 = omega of the unrefined solve.
+Backward solve_refine(ncl_kkt_s* h, const double* B, int64_t ldb, double* X, int64_t ldx, int nrhs, hipStream_t st,
+                      int& steps, double& om0) {
     const int64_t N = h->P.N;
     solve_with_factor(h, B, ldb, X, ldx, nrhs, st);
-    double om = backward_error(h, B, ldb, X, ldx, nrhs, st);
-    om0 = om;
+    Backward om = backward_error(h, B, ldb, X, ldx, nrhs, st);
+    om0 = om.omega;
     steps = 0;
     if (!h->inertia_ok) return om;
-    while (om > h->opt.ir_tol && steps < h->opt.ir_max_steps) {
+    double gap = ir_gap(h, om);
+    while (gap > 1.0 && steps < h->opt.ir_max_steps) {
         // correction from the residual left in R by backward_error
         solve_with_factor(h, h->R, N, h->DX, N, nrhs, st);
         launch_copy_cols(h->Xp, N, X, ldx, N, nrhs, st);
         launch_axpy_cols(X, ldx, h->DX, N, nrhs, st);
-        const double omn = backward_error(h, B, ldb, X, ldx, nrhs, st);
+        const Backward omn = backward_error(h, B, ldb, X, ldx, nrhs, st);
+        const double gapn = ir_gap(h, omn);
         ++steps;
-        if (!(omn <= om)) {          // worse (or NaN): keep the previous iterate
+        if (!(gapn <= gap)) {          // worse (or NaN): keep the previous iterate
             launch_copy_cols(X, ldx, h->Xp, N, N, nrhs, st);
             // R must match X again for a caller that continues
             backward_error(h, B, ldb, X, ldx, nrhs, st);
             break;
         }
-        const bool stalled = omn > h->opt.ir_stall * om;
+        const bool stalled = gapn > h->opt.ir_stall * gap;
         om = omn;
+        gap = gapn;
         if (stalled) break;
     }
     return om;
@@ -829,7 +859,8 @@ int ncl_kkt_solve(ncl_kkt_t h, const double* B, int64_t ldb, double* X, int64_t 
     if (!B || !X || nrhs < 1 || ldb < h->P.N || ldx < h->P.N) return NCL_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
     int total_steps = 0;
-    double om_all = 0.0, om0_all = 0.0;
+    Backward om_all;
+    double om0_all = 0.0;
     bool fell = h->fell_back;
     try {
         HIPCHK(hipSetDevice(h->device));
@@ -839,21 +870,20 @@ int ncl_kkt_solve(ncl_kkt_t h, const double* B, int64_t ldb, double* X, int64_t 
             double* Xq = X + (int64_t)q0 * ldx;
             int steps = 0;
             double om0 = 0.0;
-            double om = solve_refine(h, Bq, ldb, Xq, ldx, nq, st, steps, om0);
-            if (om > h->opt.ir_tol && h->factor_prec == 1 && h->inertia_ok) {
+            Backward om = solve_refine(h, Bq, ldb, Xq, ldx, nq, st, steps, om0);
+            if (!converged(h, om) && h->factor_prec == 1 && h->inertia_ok) {
                 // FP32 factor not accurate enough: refactor in FP64 from the assembled K
-                run_factor<double>(h, st);
-                h->factor_prec = 0;
-                h->fell_back = fell = true;
-                h->fp32_rho_limit = std::min(h->fp32_rho_limit, h->cur_rho_max);
-                int rc = read_inertia(h, st);
+                int rc = refactor_fp64(h, st);
+                fell = true;
                 if (rc) { flush_timing(h); return rc; }
                 int steps2 = 0;
                 om = solve_refine(h, Bq, ldb, Xq, ldx, nq, st, steps2, om0);
                 steps += steps2;
             }
             total_steps += steps;
-            om_all = std::max(om_all, om);
+            om_all.omega = std::max(om_all.omega, om.omega);
+            om_all.cw = std::max(om_all.cw, om.cw);
+            om_all.rel2 = std::max(om_all.rel2, om.rel2);
             om0_all = std::max(om0_all, om0);
         }
         flush_timing(h);
@@ -863,11 +893,13 @@ int ncl_kkt_solve(ncl_kkt_t h, const double* B, int64_t ldb, double* X, int64_t 
     if (info) {
         info->ir_steps = total_steps;
         info->fell_back_fp64 = fell ? 1 : 0;
-        info->backward_error = om_all;
+        info->backward_error = om_all.omega;
         info->backward_error0 = om0_all;
+        info->backward_error_cw = om_all.cw;
+        info->resid_rel2 = om_all.rel2;
     }
     if (!h->inertia_ok) return NCL_WARN_INERTIA;
-    if (om_all > h->opt.ir_tol && h->opt.ir_max_steps > 0) return NCL_WARN_IR_NOT_CONVERGED;
+    if (!converged(h, om_all) && h->opt.ir_max_steps > 0) return NCL_WARN_IR_NOT_CONVERGED;
     return fell ? NCL_WARN_FELL_BACK_FP64 : NCL_OK;
 }
 
@@ -924,6 +956,8 @@ int ncl_kkt_get_stats(ncl_kkt_t h, ncl_kkt_stats* st) {
     // host-only handles report the factor buffer they would need in FP64
     st->device_bytes = h->host_only ? P.factor_elems * 8 : h->dev_bytes;
     st->analyze_seconds = P.analyze_seconds;
+    st->nnz_L_exact = P.nnzL_exact;
+    st->flops_exact = P.flops_exact;
     return NCL_OK;
 }
 
@@ -940,26 +974,6 @@ int ncl_kkt_get_supernodes(ncl_kkt_t h, int32_t* first, int32_t* parent, int64_t
     if (parent) std::memcpy(parent, P.sn_parent.data(), sizeof(int32_t) * P.sn_parent.size());
     if (row_ptr) std::memcpy(row_ptr, P.sn_rowptr.data(), sizeof(int64_t) * P.sn_rowptr.size());
     if (rows) std::memcpy(rows, P.sn_rows.data(), sizeof(int32_t) * P.sn_rows.size());
-    return NCL_OK;
-}
-
-int ncl_kkt_get_flow(ncl_kkt_t h, int64_t* counts, int32_t* tasks, int32_t* deps, int64_t* launches) {
-    if (!h || !counts) return NCL_ERR_ARG;
-    const Plan& P = h->P;
-    counts[0] = (int64_t)P.flow_task.size() / 8;
-    counts[1] = (int64_t)P.flow_dep.size() / 2;
-    counts[2] = P.flow_nctr;
-    counts[3] = (int64_t)P.large_steps.size();
-    if (tasks) std::memcpy(tasks, P.flow_task.data(), sizeof(int32_t) * P.flow_task.size());
-    if (deps) std::memcpy(deps, P.flow_dep.data(), sizeof(int32_t) * P.flow_dep.size());
-    if (launches)
-        for (size_t l = 0; l < P.large_steps.size(); ++l) {
-            const LargeStep& ls = P.large_steps[l];
-            launches[4 * l + 0] = ls.flow_first;
-            launches[4 * l + 1] = ls.flow_count;
-            launches[4 * l + 2] = ls.flow_ticket;
-            launches[4 * l + 3] = ls.flow_grid;
-        }
     return NCL_OK;
 }
 

@@ -37,13 +37,28 @@ namespace {
 __device__ __forceinline__ double to_d(double x) { return x; }
 __device__ __forceinline__ double to_d(float x) { return (double)x; }
 
-// Static-pivot rule (Sec. 3.1): returns the pivot to use; flags perturbation.
+// Static-pivot thresholds of one system (Sec. 3.1): p for pivots of the
+// primal block, n for pivots of the dual block (equal unless the thresholds
+// are block-scaled), with the reciprocals of the replacement pivots +p, -n.
 template <typename T>
-__device__ __forceinline__ T static_pivot(T d, double thr, int sign, bool& perturbed, bool& bad) {
+struct PivThr {
+    double p, n;
+    T inv_p, inv_n;
+    __device__ PivThr(const DevPlan& d, int sys)
+        : p(d.sys_thr[2 * sys]), n(d.sys_thr[2 * sys + 1]), inv_p(T(1) / (T)p), inv_n(-(T(1) / (T)n)) {}
+    __device__ __forceinline__ T inv(int sign) const { return sign > 0 ? inv_p : inv_n; }
+};
+
+// Static-pivot rule (Sec. 3.1): returns the pivot to use; flags perturbation.
+// |d| < t (strict) with t the threshold of the pivot's block is replaced by +t
+// for a primal pivot and by -t for a dual one.
+template <typename T>
+__device__ __forceinline__ T static_pivot(T d, const PivThr<T>& th, int sign, bool& perturbed, bool& bad) {
     const double dd = to_d(d);
+    const double t = sign > 0 ? th.p : th.n;
     bad = !isfinite(dd);
-    perturbed = fabs(dd) < thr;
-    if (perturbed) return (T)(sign > 0 ? thr : -thr);
+    perturbed = fabs(dd) < t;
+    if (perturbed) return (T)(sign > 0 ? t : -t);
     return d;
 }
 
@@ -126,9 +141,8 @@ __device__ __forceinline__ void wave_fence() {
 // kTwoRows: f may exceed 64 + (sub-panel start), so a lane holds two rows.
 // Must be called by all 256 threads; ends with a barrier.
 template <typename T, bool kTwoRows>
-__device__ void lds_partial_ldlt(T* A, int lda, int f, int p, T* dv, const int8_t* sgn, double thr,
+__device__ void lds_partial_ldlt(T* A, int lda, int f, int p, T* dv, const int8_t* sgn, const PivThr<T>& thr,
                                  unsigned int* cnt, bool& bad_out) {
-    const T inv_thr = T(1) / (T)thr;   // reciprocal of a perturbed pivot (+-thr)
     const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lk = lane >> 4;
     bool bad_any = false;
@@ -157,7 +171,7 @@ __device__ void lds_partial_ldlt(T* A, int lda, int f, int p, T* dv, const int8_
                 const T inv0 = fast_rcp(draw);
                 const int sg = sgn[kb + t];
                 const T dk = static_pivot(draw, thr, sg, pert, bad);
-                const T inv = pert ? (sg > 0 ? inv_thr : -inv_thr) : inv0;
+                const T inv = pert ? thr.inv(sg) : inv0;
                 T ck[16];
 #pragma unroll
                 for (int u = t + 1; u < 16; ++u) ck[u] = (u < bw) ? bcast(r0[t], u) : T(0);
@@ -254,10 +268,9 @@ __device__ __forceinline__ T rowbcast_n(T v, int u) {   // u: a compile-time con
 // and in dv; lane 0 of wave 0 has added the counts of the first w pivots to
 // cnt[4].  Called by all 256 threads; ends with a barrier.
 template <typename T>
-__device__ __forceinline__ void diag_ldlt64(T* B, T* dv, unsigned long long negmask, int w, double thr, unsigned int* cnt,
-                            bool& bad_out, int tid) {
+__device__ __forceinline__ void diag_ldlt64(T* B, T* dv, unsigned long long negmask, int w, const PivThr<T>& thr,
+                                            unsigned int* cnt, bool& bad_out, int tid) {
     constexpr int LB = kPanel + 1;
-    const T inv_thr = T(1) / (T)thr;   // reciprocal of a perturbed pivot (+-thr)
     const int wave = tid >> 6, lane = tid & 63;
     const int lr = lane & 15, lk = lane >> 4;
     bool bad_any = false;
@@ -284,7 +297,7 @@ __device__ __forceinline__ void diag_ldlt64(T* B, T* dv, unsigned long long negm
                 const T inv0 = fast_rcp(draw);
                 const int sg = ((negmask >> c) & 1ULL) ? -1 : 1;
                 const T dk = static_pivot(draw, thr, sg, pert, bd);
-                const T inv = pert ? (sg > 0 ? inv_thr : -inv_thr) : inv0;
+                const T inv = pert ? thr.inv(sg) : inv0;
                 const T l = r[t] * inv;
 #pragma unroll
                 for (int u = t + 1; u < 16; ++u) r[u] -= l * bcast(r[t], kb + u);
@@ -441,70 +454,94 @@ __global__ void k_assemble(DevPlan d, int64_t nnzF, const double* __restrict__ W
     K[e] = v;
 }
 
-// Block per chunk of rows (one system): max |K_ij| and max row sum of |K|.
-// Eight lanes share a row (coalesced reads of the row's entries).
+// Block per chunk of rows (one system): max |K_ij|, max row sum of |K|, and
+// max |K_ij| over the primal block (i, j < n_primal).  Eight lanes share a row
+// (coalesced reads of the row's entries).
 __global__ __launch_bounds__(256) void k_chunk_norms(DevPlan d, const double* __restrict__ K,
                                                      const int* __restrict__ chunk_row0,
                                                      const int* __restrict__ chunk_rows, double* partial) {
     const int c = blockIdx.x;
     const int tid = threadIdx.x, sub = tid & 7, grp = tid >> 3;   // 32 row groups of 8 lanes
-    double mx = 0.0, rsmax = 0.0;
+    double mx = 0.0, rsmax = 0.0, pmx = 0.0;
     bool bad = false;
     for (int r = grp; r < chunk_rows[c]; r += 32) {
         const int row = chunk_row0[c] + r;
+        const bool prow = row < d.n_primal;
         double rs = 0.0;
         for (int64_t e = d.Kp[row] + sub; e < d.Kp[row + 1]; e += 8) {
             const double v = K[e];
             bad |= !isfinite(v);
             const double a = fabs(v);
             mx = fmax(mx, a);
+            if (prow && d.Kj[e] < d.n_primal) pmx = fmax(pmx, a);
             rs += a;
         }
         for (int o = 4; o > 0; o >>= 1) rs += __shfl_xor(rs, o, 8);
         rsmax = fmax(rsmax, rs);
     }
-    if (bad) { mx = INFINITY; rsmax = INFINITY; }
-    __shared__ double sm[2][256];
+    if (bad) { mx = INFINITY; rsmax = INFINITY; pmx = INFINITY; }
+    __shared__ double sm[3][256];
     sm[0][tid] = mx;
     sm[1][tid] = rsmax;
+    sm[2][tid] = pmx;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
         if (tid < o) {
             sm[0][tid] = fmax(sm[0][tid], sm[0][tid + o]);
             sm[1][tid] = fmax(sm[1][tid], sm[1][tid + o]);
+            sm[2][tid] = fmax(sm[2][tid], sm[2][tid + o]);
         }
         __syncthreads();
     }
-    if (tid == 0) { partial[2 * c] = sm[0][0]; partial[2 * c + 1] = sm[1][0]; }
+    if (tid == 0) {
+        partial[3 * c] = sm[0][0];
+        partial[3 * c + 1] = sm[1][0];
+        partial[3 * c + 2] = sm[2][0];
+    }
 }
 
-// Block per (system, column group): max over the system's chunks of `width` values.
-__global__ __launch_bounds__(256) void k_reduce_partials(const int* __restrict__ sys_chunk_ptr, int width,
-                                                         const double* __restrict__ partial, double* out) {
+// Block per (system, column group): reduction over the system's chunks of
+// `width` values, in a fixed order (deterministic): a sum for the columns k
+// with bit (k mod period) of sum_mask set, a max otherwise.
+__global__ __launch_bounds__(256) void k_reduce_partials(const int* __restrict__ sys_chunk_ptr, int width, int period,
+                                                         unsigned int sum_mask, const double* __restrict__ partial,
+                                                         double* out) {
     const int s = blockIdx.x;
     const int k = blockIdx.y;
     const int tid = threadIdx.x;
-    double mx = 0.0;
-    for (int c = sys_chunk_ptr[s] + tid; c < sys_chunk_ptr[s + 1]; c += 256) mx = fmax(mx, partial[(int64_t)c * width + k]);
+    const bool sum = (sum_mask >> (k % period)) & 1u;
+    double acc = 0.0;
+    for (int c = sys_chunk_ptr[s] + tid; c < sys_chunk_ptr[s + 1]; c += 256) {
+        const double v = partial[(int64_t)c * width + k];
+        acc = sum ? acc + v : fmax(acc, v);
+    }
     __shared__ double sm[256];
-    sm[tid] = mx;
+    sm[tid] = acc;
     __syncthreads();
     for (int o = 128; o > 0; o >>= 1) {
-        if (tid < o) sm[tid] = fmax(sm[tid], sm[tid + o]);
+        if (tid < o) sm[tid] = sum ? sm[tid] + sm[tid + o] : fmax(sm[tid], sm[tid + o]);
         __syncthreads();
     }
     if (tid == 0) out[(int64_t)s * width + k] = sm[0];
 }
 
-__global__ void k_thresholds(int S, const double* norms2, double eps, double* kmax, double* kinf, double* thr,
-                             int* nonfinite) {
+// Per system, from the reduced norms (max |K_ij|, ||K||_inf, max over the
+// primal block): kmax, kinf and the two static-pivot thresholds of Sec. 3.1.
+// mode 0, global rule: both eps * max |K_ij|.  mode 1, block rule (stabilized
+// form): primal pivots eps * max |K_xx|, dual pivots eps / rho, the norm of
+// the -1/rho I block of Sec. 3.2, eq. K2r.  mode 2: eps itself for both (the
+// pivot epsilon of Sec. 4.3 as an absolute bound).  Non-finite norms set
+// kNonfiniteInput.
+__global__ void k_thresholds(int S, const double* norms3, double eps, int mode, const double* sys_rho,
+                             double* kmax, double* kinf, double* thr, int* nonfinite) {
     const int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= S) return;
-    const double a = norms2[2 * s], b = norms2[2 * s + 1];
+    const double a = norms3[3 * s], b = norms3[3 * s + 1], pm = norms3[3 * s + 2];
     kmax[s] = a;
     kinf[s] = b;
-    thr[s] = eps * a;
-    if (!isfinite(a) || !isfinite(b)) nonfinite[0] = 1;
+    thr[2 * s] = mode == 2 ? eps : (mode == 1 ? pm : a) * eps;
+    thr[2 * s + 1] = mode == 2 ? eps : (mode == 1 ? eps / sys_rho[s] : eps * a);
+    if (!isfinite(a) || !isfinite(b)) atomicOr(nonfinite, kNonfiniteInput);
 }
 
 // ---------------------------------------------------------------------------
@@ -569,10 +606,10 @@ __global__ __launch_bounds__(256) void k_small_fronts(DevPlan d, const int* __re
     __syncthreads();
     unsigned int cnt[4] = {0, 0, 0, 0};
     bool bad = false;
-    lds_partial_ldlt<T, kTwoRows>(A, f, f, p, dv, sgn, d.sys_thr[sys], cnt, bad);
+    lds_partial_ldlt<T, kTwoRows>(A, f, f, p, dv, sgn, PivThr<T>(d, sys), cnt, bad);
     if (tid == 0) {
         add_inertia(d, sys, cnt, blockIdx.x);
-        if (bad) atomicOr(d.nonfinite, 1);
+        if (bad) atomicOr(d.nonfinite, kNonfiniteFactor);
     }
     for (int k = tid; k < p; k += 256) D[first + k] = dv[k];
     // write L (f x p, ld f) and the contribution block (c x c, ld CB_ld)
@@ -649,8 +686,7 @@ __global__ __launch_bounds__(256) void k_tiny_fronts(DevPlan d, const int* __res
     const bool neg = lane < p && d.row_sign[d.perm[first + lane]] < 0;
     const unsigned long long negmask = __ballot(neg);
     const int sys = d.sn_sys[s];
-    const double thr = d.sys_thr[sys];
-    const T inv_thr = T(1) / (T)thr;
+    const PivThr<T> thr(d, sys);
     unsigned int np = 0, nn = 0, nz = 0, npt = 0;
     bool anybad = false;
 #pragma unroll
@@ -661,7 +697,7 @@ __global__ __launch_bounds__(256) void k_tiny_fronts(DevPlan d, const int* __res
             const T inv0 = fast_rcp(draw);
             const int sg = ((negmask >> k) & 1ULL) ? -1 : 1;
             const T dk = static_pivot(draw, thr, sg, pert, bd);
-            const T inv = pert ? (sg > 0 ? inv_thr : -inv_thr) : inv0;
+            const T inv = pert ? thr.inv(sg) : inv0;
             const T l = r[k] * inv;
 #pragma unroll
             for (int j = k + 1; j < kTinyMax; ++j) r[j] -= l * bcast(r[k], j);
@@ -674,7 +710,7 @@ __global__ __launch_bounds__(256) void k_tiny_fronts(DevPlan d, const int* __res
     if (lane == 0) {
         const unsigned int cnt[4] = {np, nn, nz, npt};
         add_inertia(d, sys, cnt, q);
-        if (anybad) atomicOr(d.nonfinite, 1);
+        if (anybad) atomicOr(d.nonfinite, kNonfiniteFactor);
     }
     T* __restrict__ L = F + d.L_off[s];
     T* __restrict__ CBo = F + d.CB_off[s];
@@ -701,6 +737,15 @@ template <bool kLds>
 __device__ __forceinline__ void asm_fence() {
     if (!kLds) asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
     wave_fence();
+}
+
+// Reads back an element of the column being built.  In global memory (front
+// too large for the LDS slice) the read bypasses the CU's L1, which may hold a
+// copy of the line from before the wave's own stores.
+template <bool kLds, typename T>
+__device__ __forceinline__ T col_read(const T* p) {
+    if (kLds) return *p;
+    return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // One wave per (large front, column j), four columns per workgroup: assemble
@@ -745,7 +790,7 @@ __global__ __launch_bounds__(256) void k_large_asm(DevPlan d, int64_t task0, int
             }
 #pragma unroll
             for (int u = 0; u < 4; ++u)
-                if (a0 + 64 * u < cc) cv[ri[u]] += v[u];
+                if (a0 + 64 * u < cc) cv[ri[u]] = col_read<kLds>(cv + ri[u]) + v[u];
         }
         asm_fence<kLds>();
     }
@@ -899,11 +944,11 @@ __device__ __forceinline__ void diag_body(const DevPlan& d, int s, int k0, T* F,
     const int sys = d.sn_sys[s];
     unsigned int cnt[4] = {0, 0, 0, 0};
     bool bad = false;
-    diag_ldlt64<T>(Bf, dv, negmask, w, d.sys_thr[sys], cnt, bad, tid);
+    diag_ldlt64<T>(Bf, dv, negmask, w, PivThr<T>(d, sys), cnt, bad, tid);
     tri_inv64<T>(Bf, tid);
     if (tid == 0) {
         add_inertia(d, sys, cnt, s + k0);
-        if (bad) atomicOr(d.nonfinite, 1);
+        if (bad) atomicOr(d.nonfinite, kNonfiniteFactor);
     }
     publish_diag<T>(A, f, k0, w, Bf, dv, D, first, Zbuf + d.M_off[s] + (int64_t)(k0 / kPanel) * (kPanel * kPanel),
                     tid);
@@ -1025,78 +1070,6 @@ __global__ __launch_bounds__(256) void k_large_dstep(DevPlan d, const int* __res
     } else if (b >= nd8) {
         const int* tk = utasks + 4 * xcd_task(b - nd8, nu);
         update_body<T>(d, tk[0], tk[1], tk[2], tk[3], F, D, threadIdx.x);
-    }
-}
-
-// ---------------------------------------------------------------------------
-// Large fronts of one level as one dataflow launch.  The level's diagonal-
-// block, panel-solve and tile-update tasks (the bodies above) are listed in a
-// topological order; each workgroup takes the next task by an atomic ticket,
-// waits until the counters its inputs depend on reach their targets, runs the
-// task, and bumps the counter it feeds.  Every task waits only on tasks with
-// smaller tickets, which were taken by running workgroups, so the smallest
-// unfinished ticket always progresses: no co-residency is assumed.  Waits are
-// bounded: past kFlowSpinLimit polls a workgroup sets bit 1 of the status word
-// and every later wait returns at once, so the grid always drains.
-// Counters are published with agent-scope release (after every wave's stores
-// reached the L2) and read with agent-scope acquire, which the different
-// XCDs' L2 caches need.
-// ---------------------------------------------------------------------------
-constexpr int kFlowSpinLimit = 1 << 21;
-constexpr int kFlowSleep = 4;    // s_sleep units (64 clocks) between two polls
-constexpr int kFlowChunk = 1;    // consecutive tasks taken per ticket
-
-__device__ __forceinline__ void flow_wait(int* ctr, const int* __restrict__ dep, int nd, int* status) {
-    // Relaxed polls (coherent loads, no cache invalidation per poll), then
-    // one acquire fence for all the dependencies.
-    for (int i = 0; i < nd; ++i) {
-        int* c = ctr + dep[2 * i];
-        const int target = dep[2 * i + 1];
-        int spins = 0;
-        while (__hip_atomic_load(c, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target) {
-            if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2) break;
-            if (++spins > kFlowSpinLimit) {
-                __hip_atomic_fetch_or(status, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                break;
-            }
-            __builtin_amdgcn_s_sleep(kFlowSleep);
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-}
-
-template <typename T>
-__global__ __launch_bounds__(256, 2) void k_large_flow(DevPlan d, const int* __restrict__ tasks, int ntask,
-                                                    const int* __restrict__ deps, int* ctr, int ticket, T* F, T* D,
-                                                    T* Zbuf) {
-    __shared__ int s_t;
-    const int tid = threadIdx.x;
-    for (;;) {
-        if (tid == 0)
-            s_t = __hip_atomic_fetch_add(ctr + ticket, kFlowChunk, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        __syncthreads();
-        const int t0 = __builtin_amdgcn_readfirstlane(s_t);
-        if (t0 >= ntask) break;
-        // A chunk is consecutive tickets run in order: the smallest unfinished
-        // ticket is still always runnable.
-        for (int t = t0; t < t0 + kFlowChunk && t < ntask; ++t) {
-            const int* tk = tasks + 8 * t;
-            const int type = tk[0], s = tk[1], k0 = tk[2], a = tk[3], b = tk[4], sig = tk[7];
-            if (tid == 0) flow_wait(ctr, deps + 2 * tk[5], tk[6], d.nonfinite);
-            __syncthreads();
-            // A fresh thread index per task: nothing derived from it is kept live
-            // across the loop (hoisted address arithmetic would exhaust registers).
-            int tx = tid;
-            asm volatile("" : "+v"(tx));
-            if (type == kFlowDiag) diag_body<T>(d, s, k0, F, D, Zbuf, tx);
-            else if (type == kFlowPanel) panel_body<T>(d, s, k0, a, F, D, Zbuf, tx);
-            else update_body<T>(d, s, k0, a, b, F, D, tx);
-            // Every wave waits for its own stores to reach the L2; after the
-            // barrier one agent-scope release (L2 write-back) covers them all.
-            asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-            __syncthreads();
-            if (tid == 0 && sig >= 0) __hip_atomic_fetch_add(ctr + sig, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-        }
     }
 }
 
@@ -1693,7 +1666,9 @@ __global__ __launch_bounds__(256, 4) void k_bwd_S(DevPlan d, const int* __restri
 // refinement
 // ---------------------------------------------------------------------------
 // Block per chunk of rows (one system); eight lanes share a row.  R = B - K X
-// and, per column, the chunk's max |R|, |X|, |B|.
+// and, per column, the chunk's kResWidth figures: max |r_i|, max |x_i|,
+// max |b_i|, sum r_i^2, sum b_i^2, and max_i |r_i| / (|K| |x| + |b|)_i (the
+// componentwise backward error; 0/0 counts as 0, r/0 as infinite).
 __global__ __launch_bounds__(256) void k_residual(DevPlan d, const double* __restrict__ K,
                                                   const double* __restrict__ B, int64_t ldb,
                                                   const double* __restrict__ X, int64_t ldx, double* __restrict__ R,
@@ -1701,40 +1676,49 @@ __global__ __launch_bounds__(256) void k_residual(DevPlan d, const double* __res
                                                   const int* __restrict__ chunk_rows, double* partial) {
     const int c = blockIdx.x;
     const int tid = threadIdx.x, sub = tid & 7, grp = tid >> 3;
-    __shared__ double sm[3][256];
+    __shared__ double sm[kResWidth][256];
     for (int q = 0; q < nrhs; ++q) {
         const double* __restrict__ x = X + q * ldx;
-        double rm = 0.0, xm = 0.0, bm = 0.0;
+        double v[kResWidth] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (int r = grp; r < chunk_rows[c]; r += 32) {
             const int row = chunk_row0[c] + r;
-            double acc = 0.0;
-            for (int64_t e = d.Kp[row] + sub; e < d.Kp[row + 1]; e += 8) acc += K[e] * x[d.Kj[e]];
-            for (int o = 4; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 8);
+            double acc = 0.0, aacc = 0.0;
+            for (int64_t e = d.Kp[row] + sub; e < d.Kp[row + 1]; e += 8) {
+                const double k = K[e], xv = x[d.Kj[e]];
+                acc += k * xv;
+                aacc += fabs(k) * fabs(xv);
+            }
+            for (int o = 4; o > 0; o >>= 1) {
+                acc += __shfl_xor(acc, o, 8);
+                aacc += __shfl_xor(aacc, o, 8);
+            }
             if (sub == 0) {
                 const double b = B[row + q * ldb];
                 const double rr = b - acc;
                 R[row + q * d.N] = rr;
-                rm = (rr == rr) ? fmax(rm, fabs(rr)) : INFINITY;   // NaN residual -> infinite
-                xm = fmax(xm, fabs(x[row]));
-                bm = fmax(bm, fabs(b));
+                const bool nan = rr != rr;
+                const double den = aacc + fabs(b);
+                const double cw = nan ? INFINITY : (den > 0.0 ? fabs(rr) / den : (rr != 0.0 ? INFINITY : 0.0));
+                v[0] = nan ? INFINITY : fmax(v[0], fabs(rr));   // NaN residual -> infinite
+                v[1] = fmax(v[1], fabs(x[row]));
+                v[2] = fmax(v[2], fabs(b));
+                v[3] += nan ? INFINITY : rr * rr;
+                v[4] += b * b;
+                v[5] = fmax(v[5], cw);
             }
         }
-        sm[0][tid] = rm;
-        sm[1][tid] = xm;
-        sm[2][tid] = bm;
+#pragma unroll
+        for (int k = 0; k < kResWidth; ++k) sm[k][tid] = v[k];
         __syncthreads();
         for (int o = 128; o > 0; o >>= 1) {
             if (tid < o) {
-                sm[0][tid] = fmax(sm[0][tid], sm[0][tid + o]);
-                sm[1][tid] = fmax(sm[1][tid], sm[1][tid + o]);
-                sm[2][tid] = fmax(sm[2][tid], sm[2][tid + o]);
+#pragma unroll
+                for (int k = 0; k < kResWidth; ++k)
+                    sm[k][tid] = (k == 3 || k == 4) ? sm[k][tid] + sm[k][tid + o] : fmax(sm[k][tid], sm[k][tid + o]);
             }
             __syncthreads();
         }
-        if (tid == 0) {
-            double* o = partial + ((int64_t)c * nrhs + q) * 3;
-            o[0] = sm[0][0]; o[1] = sm[1][0]; o[2] = sm[2][0];
-        }
+        if (tid < kResWidth) partial[((int64_t)c * nrhs + q) * kResWidth + tid] = sm[tid][0];
         __syncthreads();
     }
 }
@@ -1885,14 +1869,16 @@ void launch_chunk_norms(const DevPlan& d, const double* K, const int* chunk_row0
     launch(k_chunk_norms, dim3(nchunks), dim3(256), 0, st, d, K, chunk_row0, chunk_rows, partial);
 }
 
-void launch_reduce(const int* sys_chunk_ptr, int S, int width, const double* partial, double* out, hipStream_t st) {
-    launch(k_reduce_partials, dim3(S, width), dim3(256), 0, st, sys_chunk_ptr, width, partial, out);
+void launch_reduce(const int* sys_chunk_ptr, int S, int width, int period, unsigned int sum_mask,
+                   const double* partial, double* out, hipStream_t st) {
+    launch(k_reduce_partials, dim3(S, width), dim3(256), 0, st, sys_chunk_ptr, width, period, sum_mask, partial,
+           out);
 }
 
-void launch_thresholds(int S, const double* norms2, double eps, double* kmax, double* kinf, double* thr,
-                       int* nonfinite, hipStream_t st) {
-    launch(k_thresholds, dim3(blocks_for(S, 64)), dim3(64), 0, st, S, norms2, eps, kmax, kinf, thr,
-                       nonfinite);
+void launch_thresholds(int S, const double* norms3, double eps, int mode, const double* sys_rho, double* kmax,
+                       double* kinf, double* thr, int* nonfinite, hipStream_t st) {
+    launch(k_thresholds, dim3(blocks_for(S, 64)), dim3(64), 0, st, S, norms3, eps, mode, sys_rho, kmax, kinf, thr,
+           nonfinite);
 }
 
 template <typename T>
@@ -1941,13 +1927,6 @@ void launch_large_dstep(const DevPlan& d, const int* dtasks, int nd, const int* 
     launch(k_large_dstep<T>, dim3(nd8 + nu), dim3(256), 0, st, d, dtasks, nd, utasks, nu, F, D, M);
 }
 
-
-template <typename T>
-void launch_large_flow(const DevPlan& d, const int* tasks, int ntask, const int* deps, int* ctr, int ticket, int grid,
-                       T* F, T* D, T* M, hipStream_t st) {
-    if (ntask <= 0) return;
-    launch(k_large_flow<T>, dim3(grid < ntask ? grid : ntask), dim3(256), 0, st, d, tasks, ntask, deps, ctr, ticket, F, D, M);
-}
 
 template <typename T>
 void launch_permute_in(const DevPlan& d, const double* B, int64_t ldb, int nrhs, T* Y, hipStream_t st) {
@@ -2010,11 +1989,6 @@ void launch_residual(const DevPlan& d, const double* K, const double* B, int64_t
                      hipStream_t st) {
     launch(k_residual, dim3(nchunks), dim3(256), 0, st, d, K, B, ldb, X, ldx, R, nrhs, chunk_row0,
                        chunk_rows, partial);
-}
-
-void launch_reduce_partials(const int* sys_chunk_ptr, int S, int width, const double* partial, double* out,
-                            hipStream_t st) {
-    launch_reduce(sys_chunk_ptr, S, width, partial, out, st);
 }
 
 void launch_axpy_cols(double* X, int64_t ldx, const double* DX, int64_t N, int nrhs, hipStream_t st) {
@@ -2086,8 +2060,6 @@ hipError_t configure_kernels(int max_dynamic_lds) {
     template void launch_large_diag<T>(const DevPlan&, const int*, int, T*, T*, T*, hipStream_t);                \
     template void launch_large_panel<T>(const DevPlan&, const int*, int, T*, const T*, const T*, hipStream_t);     \
     template void launch_large_dstep<T>(const DevPlan&, const int*, int, const int*, int, T*, T*, T*, hipStream_t); \
-    template void launch_large_flow<T>(const DevPlan&, const int*, int, const int*, int*, int, int, T*, T*, T*,       \
-                                       hipStream_t);                                                              \
     template void launch_permute_in<T>(const DevPlan&, const double*, int64_t, int, T*, hipStream_t);              \
     template void launch_permute_out<T>(const DevPlan&, const T*, int, double*, int64_t, hipStream_t);             \
     template void launch_fwd_T<T>(const DevPlan&, const int*, int, const T*, const T*, T*, T*, int, hipStream_t);           \

@@ -4,7 +4,6 @@
 
 #include <cstdint>
 
-#include "flow_types.hpp"
 
 namespace ncl {
 
@@ -15,12 +14,16 @@ constexpr int kTile = 64;        // tile order of the large-front MFMA update
 constexpr int kSolvePanel = 256; // pivot columns per solve panel
 constexpr int kSolveChunk = 256; // row capacity of a solve G task / of the rows fused below a panel
 constexpr int kInertiaSlots = 64;  // partial inertia counters per system (spreads the atomics)
+constexpr int kNonfiniteInput = 1;   // status bit: NaN/Inf in the assembled K (its norms)
+constexpr int kNonfiniteFactor = 4;  // status bit: NaN/Inf pivot met by the factorization
+constexpr int kResWidth = 6;         // residual figures per (row chunk, column), see launch_residual
 constexpr size_t kAsmLdsMax = 96 * 1024;  // large-front column assembly staged in LDS (4 columns per
                                            // workgroup) up to this size
 
 // Device copies of the plan (all device pointers), passed by value.
 struct DevPlan {
     int64_t N;
+    int64_t n_primal;          // rows [0, n_primal) form the primal block (N for the condensed form)
     int S;
     int form;
     // full CSR of K with value sources
@@ -66,10 +69,10 @@ struct DevPlan {
     const int64_t* asm_seg_rel;
     const int* asm_seg_bc;
     // per system
-    const double* sys_thr;     // static-pivot thresholds eps * ||K||_max
+    const double* sys_thr;     // static-pivot thresholds, 2 per system: primal, dual pivots
     unsigned long long* inertia;  // 4 per system: npos, nneg, nzero, nperturbed
     unsigned long long* inertia_part;  // kInertiaSlots x 4 per system, summed into inertia
-    int* nonfinite;            // set to 1 on a NaN/Inf pivot
+    int* nonfinite;            // status bits kNonfiniteInput | kNonfiniteFactor
 };
 
 // ---- assembly (FP64) ------------------------------------------------------
@@ -85,14 +88,21 @@ LaunchTimer* set_launch_timer(LaunchTimer* t);   // returns the previous one
 
 void launch_assemble(const DevPlan& d, int64_t nnzF, const double* W, const double* Sigma, const double* J,
                      const double* sys_rho, double* K, hipStream_t st);
-// Block per chunk of rows: partial[2c] = max |K_ij|, partial[2c+1] = max row sum of |K|.
+// Block per chunk of rows: partial[3c..3c+2] = max |K_ij|, max row sum of |K|,
+// max |K_ij| over the primal block.
 void launch_chunk_norms(const DevPlan& d, const double* K, const int* chunk_row0, const int* chunk_rows, int nchunks,
                         double* partial, hipStream_t st);
-// out[s*width + k] = max over the chunks of system s of partial[c*width + k].
-void launch_reduce(const int* sys_chunk_ptr, int S, int width, const double* partial, double* out, hipStream_t st);
-// kmax, kinf, thr = eps * kmax per system from the reduced norms; flags non-finite norms.
-void launch_thresholds(int S, const double* norms2, double eps, double* kmax, double* kinf, double* thr,
-                       int* nonfinite, hipStream_t st);
+// out[s*width + k] = reduction over the chunks of system s of partial[c*width + k]:
+// a sum where bit (k mod period) of sum_mask is set, else a max.  Fixed order
+// (deterministic).  1 <= period <= 32.
+void launch_reduce(const int* sys_chunk_ptr, int S, int width, int period, unsigned int sum_mask,
+                   const double* partial, double* out, hipStream_t st);
+// kmax, kinf and the two static-pivot thresholds per system (thr[2s] primal,
+// thr[2s+1] dual) from the reduced norms.  mode 0: eps * max |K_ij| for both;
+// 1, block rule: primal eps * max |K_xx|, dual eps / rho; 2: eps for both.
+// Flags non-finite norms.
+void launch_thresholds(int S, const double* norms3, double eps, int mode, const double* sys_rho, double* kmax,
+                       double* kinf, double* thr, int* nonfinite, hipStream_t st);
 
 // ---- numeric factorization (T = double or float) --------------------------
 template <typename T>
@@ -111,13 +121,6 @@ void launch_large_dstep(const DevPlan& d, const int* dtasks, int nd, const int* 
                         hipStream_t st);
 
 // ---- solves -----------------------------------------------------------------
-// One level's large-front factorization as a single dataflow launch: tasks
-// are 8 ints (type, front, k0, a, b, first dependency, dependencies, counter
-// signalled or -1), dependencies are (counter, target) pairs, ctr[ticket] is
-// the task ticket; all counters start at zero.
-template <typename T>
-void launch_large_flow(const DevPlan& d, const int* tasks, int ntask, const int* deps, int* ctr, int ticket, int grid,
-                       T* F, T* D, T* M, hipStream_t st);
 template <typename T>
 void launch_permute_in(const DevPlan& d, const double* B, int64_t ldb, int nrhs, T* Y, hipStream_t st);
 template <typename T>
@@ -140,12 +143,11 @@ void launch_bwd_T(const DevPlan& d, const int* tasks, int count, const T* F, con
                   const T* partial, int nrhs, hipStream_t st);
 
 // ---- refinement -------------------------------------------------------------
-// R = B - K X; per chunk of rows (all of one system) the maxima of |R|, |X|, |B| per column.
+// R = B - K X; per chunk of rows (all of one system) and column, kResWidth figures:
+// max |r|, max |x|, max |b|, sum r^2, sum b^2, max |r_i| / (|K||x| + |b|)_i.
 void launch_residual(const DevPlan& d, const double* K, const double* B, int64_t ldb, const double* X,
                      int64_t ldx, double* R, int nrhs, const int* chunk_row0, const int* chunk_rows, int nchunks,
                      double* partial, hipStream_t st);
-void launch_reduce_partials(const int* sys_chunk_ptr, int S, int width, const double* partial, double* out,
-                            hipStream_t st);
 void launch_axpy_cols(double* X, int64_t ldx, const double* DX, int64_t N, int nrhs, hipStream_t st);
 void launch_copy_cols(double* dst, int64_t ldd, const double* src, int64_t lds, int64_t N, int nrhs,
                       hipStream_t st);

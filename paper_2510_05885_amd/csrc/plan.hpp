@@ -8,8 +8,6 @@
 #include <string>
 #include <vector>
 
-#include "flow_types.hpp"
-
 namespace ncl {
 
 // Fronts of order above this bound use the global-memory path.  The LDS path
@@ -25,7 +23,6 @@ struct PlanConfig {
     int solve_panel = 256;      // pivot columns per solve panel
     int solve_fuse_rows = 64;   // rows below a panel handled inside the panel's workgroup
     int solve_chunk_rows = 64;  // rows per G task otherwise
-    int flow_workers = 512;     // workgroups of a level's dataflow launch (2 per CU)
 };
 
 struct LevelBatch {            // one launch of the small-front kernel
@@ -43,11 +40,6 @@ struct LargeStep {             // launches of the large-front path for one level
     std::vector<int64_t> panel_first, panel_count;
     std::vector<int64_t> upd_first, upd_count;
     std::vector<double> upd_flops;            // algorithmic flops of each update launch
-    // the same tasks as one dataflow launch (Plan::flow_task / flow_dep)
-    int64_t flow_first = 0, flow_count = 0;   // range in flow_task (8 ints per task)
-    int64_t flow_ticket = 0;                  // counter index of the task ticket
-    int flow_grid = 0;                        // workgroups of the launch
-    double flow_flops = 0.0;                  // algorithmic flops of all its tasks
 };
 
 // Solve schedule: each front is swept in panels of up to kSolvePanel pivot
@@ -59,7 +51,8 @@ struct SolveStep {
     int64_t t_first = 0, t_count = 0;   // tasks in Plan::solve_t (5 ints each)
     int64_t g_first = 0, g_count = 0;   // tasks in Plan::solve_g (5 ints each)
     int64_t s_first = 0, s_count = 0;   // small fronts in Plan::solve_s (one wave each)
-    double fwd_bytes = 0.0;             // algorithmic bytes of L read by the step
+    double fwd_bytes = 0.0;             // algorithmic bytes of L read by the step (FP64; padding
+                                        // zeros of amalgamated fronts not counted)
 };
 
 struct Plan {
@@ -149,11 +142,6 @@ struct Plan {
     std::vector<int> large_panel;    // triples (front, k0, 32-row block start >= k0 + panel)
     std::vector<int> large_upd;      // quads (front, k0, tile row start, tile col start); the next
                                      // panel's diagonal tile is left to large_diag
-    // dataflow form of the large-front tasks: per task (type, front, k0, a, b,
-    // first dependency, dependencies, counter signalled or -1); dependencies
-    // are (counter, target) pairs; flow_nctr counters in all, zeroed per factor
-    std::vector<int> flow_task, flow_dep;
-    int64_t flow_nctr = 0;
     // solve schedule
     std::vector<SolveStep> solve_steps;
     std::vector<int> solve_t;        // (front, c0, fused, g_first, g_count)
@@ -163,15 +151,16 @@ struct Plan {
 
     // ---- stats ------------------------------------------------------------
     int64_t nnzL = 0;
-    double flops = 0.0, small_flops = 0.0, large_flops = 0.0;
+    double flops = 0.0, small_flops = 0.0, large_flops = 0.0;   // as executed (padding included)
+    int64_t nnzL_exact = 0;          // column counts of the elimination tree (no padding)
+    double flops_exact = 0.0;        // sum over columns of c (c + 2), c = below-diagonal count
+    std::vector<double> sn_flop_ratio;  // per supernode: exact / executed flops of its pivots
+    std::vector<double> sn_nnz_ratio;   // per supernode: exact / stored entries of its L columns
     int max_front = 0;
     int n_large = 0;
     double analyze_seconds = 0.0;
     PlanConfig cfg;
 };
 
-// Builds the dataflow task list of one level's large fronts (appends to
-// P.flow_task / P.flow_dep and fills st.flow_*).
-void build_flow(Plan& P, LargeStep& st, const std::vector<int>& large, int workers);
 
 }  // namespace ncl

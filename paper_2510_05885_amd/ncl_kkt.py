@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libncl_kkt.so")
 NCL_CONDENSED, NCL_STABILIZED = 0, 1
 NCL_FP64, NCL_FP32_IR = 0, 1
 NCL_ORDER_ND, NCL_ORDER_NATURAL, NCL_ORDER_USER = 0, 1, 2
+NCL_PIVOT_GLOBAL, NCL_PIVOT_BLOCK, NCL_PIVOT_ABSOLUTE = 0, 1, 2
 NCL_OK = 0
 NCL_WARN_INERTIA, NCL_WARN_IR_NOT_CONVERGED, NCL_WARN_FELL_BACK_FP64 = 1, 2, 3
 
@@ -29,7 +30,7 @@ EXPORTED = [
     "ncl_kkt_default_options", "ncl_kkt_analyze", "ncl_kkt_analyze_host", "ncl_kkt_analyze_batched",
     "ncl_kkt_factor", "ncl_kkt_factor_batched", "ncl_kkt_solve", "ncl_kkt_inertia",
     "ncl_kkt_inertia_batched", "ncl_kkt_backward", "ncl_kkt_get_stats", "ncl_kkt_get_perm",
-    "ncl_kkt_get_supernodes", "ncl_kkt_get_flow", "ncl_kkt_set_timing", "ncl_kkt_get_timing",
+    "ncl_kkt_get_supernodes", "ncl_kkt_set_timing", "ncl_kkt_get_timing",
     "ncl_kkt_destroy", "ncl_kkt_strerror",
 ]
 
@@ -39,19 +40,20 @@ class Options(C.Structure):
                 ("ir_max_steps", C.c_int32), ("ir_tol", C.c_double), ("ir_stall", C.c_double),
                 ("ordering", C.c_int32), ("user_perm", C.POINTER(C.c_int32)), ("use_graphs", C.c_int32),
                 ("small_front_max", C.c_int32), ("relax_big_zeros", C.c_double), ("fp32_sticky", C.c_int32),
-                ("large_flow", C.c_int32)]
+                ("pivot_scale", C.c_int32), ("ir_cw_tol", C.c_double)]
 
 
 class SolveInfo(C.Structure):
     _fields_ = [("ir_steps", C.c_int32), ("fell_back_fp64", C.c_int32),
-                ("backward_error", C.c_double), ("backward_error0", C.c_double)]
+                ("backward_error", C.c_double), ("backward_error0", C.c_double),
+                ("backward_error_cw", C.c_double), ("resid_rel2", C.c_double)]
 
 
 class Stats(C.Structure):
     _fields_ = [("order", C.c_int64), ("nnz_K_lower", C.c_int64), ("nnz_L", C.c_int64),
                 ("flops_factor", C.c_double), ("n_supernodes", C.c_int64), ("n_levels", C.c_int64),
                 ("max_front", C.c_int64), ("n_large_fronts", C.c_int64), ("device_bytes", C.c_int64),
-                ("analyze_seconds", C.c_double)]
+                ("analyze_seconds", C.c_double), ("nnz_L_exact", C.c_int64), ("flops_exact", C.c_double)]
 
 
 class Timing(C.Structure):
@@ -115,8 +117,6 @@ def lib():
     L.ncl_kkt_get_perm.restype = C.c_int
     L.ncl_kkt_get_supernodes.argtypes = [vp, pi32, pi32, C.POINTER(C.c_int64), pi32]
     L.ncl_kkt_get_supernodes.restype = C.c_int
-    L.ncl_kkt_get_flow.argtypes = [vp, C.POINTER(C.c_int64), pi32, pi32, C.POINTER(C.c_int64)]
-    L.ncl_kkt_get_flow.restype = C.c_int
     L.ncl_kkt_set_timing.argtypes = [vp, i32]
     L.ncl_kkt_set_timing.restype = C.c_int
     L.ncl_kkt_get_timing.argtypes = [vp, C.POINTER(Timing)]
@@ -147,10 +147,42 @@ def _i32(a):
 
 
 def _ptr(t):
-    """Device pointer of a torch tensor (must be float64, contiguous along rows)."""
+    """Device pointer of a torch tensor (checked by _dev first)."""
     if t is None:
         return None
     return C.c_void_p(t.data_ptr())
+
+
+def _dev(t, numel, name, allow_none=False):
+    """Checks that t is a contiguous float64 tensor on a GPU with `numel`
+    elements (the library reads and writes exactly that many)."""
+    if t is None:
+        if allow_none:
+            return None
+        raise ValueError(f"{name} is required")
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if t.numel() != numel:
+        raise ValueError(f"{name} has {t.numel()} elements, expected {numel}")
+    return _ptr(t)
+
+
+def _dev_cols(t, rows, name):
+    """Checks a (rows, nrhs) column-major (or (rows,)) float64 CUDA tensor;
+    returns (pointer, leading dimension, nrhs)."""
+    import torch
+    if not isinstance(t, torch.Tensor) or t.dtype != torch.float64 or not t.is_cuda:
+        raise TypeError(f"{name} must be a float64 CUDA tensor")
+    if t.dim() == 1 or (t.dim() == 2 and t.shape[1] == 1):
+        if t.shape[0] != rows or t.stride(0) != 1:
+            raise ValueError(f"{name} must be a contiguous vector of length {rows}")
+        return _ptr(t), rows, 1
+    if t.dim() != 2 or t.shape[0] != rows or t.stride(0) != 1 or t.stride(1) < rows:
+        raise ValueError(f"{name} must be ({rows}, nrhs) column-major with leading dimension >= {rows}")
+    return _ptr(t), t.stride(1), t.shape[1]
 
 
 def _stream(stream):
@@ -165,11 +197,12 @@ def _stream(stream):
 _FORMS = {"condensed": NCL_CONDENSED, "stabilized": NCL_STABILIZED}
 _PRECS = {"fp64": NCL_FP64, "fp32_ir": NCL_FP32_IR}
 _ORDS = {"nd": NCL_ORDER_ND, "natural": NCL_ORDER_NATURAL, "user": NCL_ORDER_USER}
+_PIVS = {"global": NCL_PIVOT_GLOBAL, "block": NCL_PIVOT_BLOCK, "absolute": NCL_PIVOT_ABSOLUTE}
 
 
 def make_options(form="condensed", precision="fp64", pivot_eps=0.0, ir_max_steps=10, ir_tol=1e-12,
                  ir_stall=0.5, ordering="nd", user_perm=None, use_graphs=True, small_front_max=0,
-                 relax_big_zeros=-1.0, fp32_sticky=True, large_flow=False):
+                 relax_big_zeros=-1.0, fp32_sticky=True, pivot_scale="global", ir_cw_tol=0.0):
     o = Options()
     lib().ncl_kkt_default_options(C.byref(o))
     o.form = _FORMS[form] if isinstance(form, str) else int(form)
@@ -182,7 +215,8 @@ def make_options(form="condensed", precision="fp64", pivot_eps=0.0, ir_max_steps
     o.small_front_max = int(small_front_max)
     o.relax_big_zeros = float(relax_big_zeros)
     o.fp32_sticky = 1 if fp32_sticky else 0
-    o.large_flow = 1 if large_flow else 0
+    o.pivot_scale = _PIVS[pivot_scale] if isinstance(pivot_scale, str) else int(pivot_scale)
+    o.ir_cw_tol = float(ir_cw_tol)
     keep = None
     if user_perm is not None:
         keep, p = _i32(user_perm)
@@ -200,18 +234,22 @@ class Info:
     fell_back_fp64: bool
     backward_error: float
     backward_error0: float
+    backward_error_cw: float
+    resid_rel2: float
 
 
 class KKT:
     """One analyzed KKT pattern (or a batch of independent ones)."""
 
-    def __init__(self, handle, order, S, nnzW, nnzJ, form):
+    def __init__(self, handle, order, S, nnzW, nnzJ, form, n=None):
         self._h = handle
         self.order = order
         self.S = S
         self.nnzW = nnzW
         self.nnzJ = nnzJ
         self.form = form
+        self.n = order if n is None else n    # primal size (length of Sigma)
+        self.generation = 0                   # bumped by every factor call
 
     # ---------------------------------------------------------------- create
     @classmethod
@@ -223,7 +261,7 @@ class KKT:
         _check(f(C.byref(h), C.byref(o), int(n), int(m), *[a[1] for a in arrs]), "ncl_kkt_analyze")
         del keep
         order = n if o.form == NCL_CONDENSED else n + m
-        return cls(h, order, 1, int(arrs[0][0][-1]), int(arrs[2][0][-1]) if m > 0 else 0, o.form)
+        return cls(h, order, 1, int(arrs[0][0][-1]), int(arrs[2][0][-1]) if m > 0 else 0, o.form, n=int(n))
 
     @classmethod
     def from_input(cls, inp, host_only=False, **opts):
@@ -266,31 +304,43 @@ class KKT:
 
     # ---------------------------------------------------------------- numeric
     def factor(self, W_val, Sigma, J_val, rho, stream=None):
-        """Assemble and factor on the device.  Returns the status (0 or a warning)."""
+        """Assemble and factor on the device (W_val, Sigma, J_val: float64 CUDA
+        tensors of nnz(W), n and nnz(J) elements; rho a float, or one per
+        system for a batched handle).  Returns the status (0 or a warning)."""
+        pw = _dev(W_val, self.nnzW, "W_val", allow_none=self.nnzW == 0)
+        ps = _dev(Sigma, self.n, "Sigma")
+        pj = _dev(J_val, self.nnzJ, "J_val", allow_none=self.nnzJ == 0)
         st = _stream(stream)
+        self.generation += 1
         if self.S == 1 and np.ndim(rho) == 0:
-            rc = lib().ncl_kkt_factor(self._h, _ptr(W_val), _ptr(Sigma), _ptr(J_val), float(rho), st)
+            rc = lib().ncl_kkt_factor(self._h, pw, ps, pj, float(rho), st)
         else:
             r = np.ascontiguousarray(np.asarray(rho, np.float64).reshape(-1))
-            rc = lib().ncl_kkt_factor_batched(self._h, _ptr(W_val), _ptr(Sigma), _ptr(J_val),
-                                              r.ctypes.data_as(C.POINTER(C.c_double)), st)
+            if r.size != self.S:
+                raise ValueError(f"rho has {r.size} values, expected one per system ({self.S})")
+            rc = lib().ncl_kkt_factor_batched(self._h, pw, ps, pj, r.ctypes.data_as(C.POINTER(C.c_double)), st)
         return _check(rc, "ncl_kkt_factor")
 
     def solve(self, B, X=None, stream=None):
         """Solve K X = B (B: (order,) or (order, nrhs) float64 on the device)."""
         import torch
+        if not isinstance(B, torch.Tensor) or B.dtype != torch.float64 or not B.is_cuda:
+            raise TypeError("B must be a float64 CUDA tensor")
         vec = B.dim() == 1
         B2 = B.reshape(self.order, -1)
         Bc = B2.t().contiguous().t() if not B2.t().is_contiguous() else B2   # column-major view
         nrhs = Bc.shape[1]
         if X is None:
             X = torch.empty((nrhs, self.order), dtype=torch.float64, device=B.device).t()
+        px, ldx, nx = _dev_cols(X, self.order, "X")
+        if nx != nrhs:
+            raise ValueError(f"X has {nx} columns, expected {nrhs}")
         info = SolveInfo()
-        rc = lib().ncl_kkt_solve(self._h, _ptr(Bc), self.order, _ptr(X), self.order, nrhs, _stream(stream),
-                                 C.byref(info))
+        rc = lib().ncl_kkt_solve(self._h, _ptr(Bc), self.order, px, ldx, nrhs, _stream(stream), C.byref(info))
         _check(rc, "ncl_kkt_solve")
         out = X.reshape(self.order) if vec else X
-        return out, Info(rc, info.ir_steps, bool(info.fell_back_fp64), info.backward_error, info.backward_error0)
+        return out, Info(rc, info.ir_steps, bool(info.fell_back_fp64), info.backward_error, info.backward_error0,
+                         info.backward_error_cw, info.resid_rel2)
 
     def inertia(self):
         v = [C.c_int64() for _ in range(4)]
@@ -304,10 +354,18 @@ class KKT:
         return out.reshape(self.S, 4)
 
     def backward(self, J_val, X, Lam, gW=None, gSigma=None, gJ=None, gRho=None, stream=None):
-        X2 = X.reshape(self.order, -1)
-        L2 = Lam.reshape(self.order, -1)
-        _check(lib().ncl_kkt_backward(self._h, _ptr(J_val), _ptr(X2), _ptr(L2), self.order, X2.shape[1],
-                                      _ptr(gW), _ptr(gSigma), _ptr(gJ), _ptr(gRho), _stream(stream)),
+        """Adjoint of the last factorization's solve (condensed form): X and Lam
+        are (order, nrhs) column-major with the same leading dimension;
+        gradients are overwritten (gRho: one value per system)."""
+        px, ldx, nx = _dev_cols(X, self.order, "X")
+        pl, ldl, nl = _dev_cols(Lam, self.order, "Lambda")
+        if nx != nl or ldx != ldl:
+            raise ValueError("X and Lambda must have the same shape and leading dimension")
+        pj = _dev(J_val, self.nnzJ, "J_val", allow_none=self.nnzJ == 0)
+        _check(lib().ncl_kkt_backward(self._h, pj, px, pl, ldx, nx,
+                                      _dev(gW, self.nnzW, "gW", True), _dev(gSigma, self.order, "gSigma", True),
+                                      _dev(gJ, self.nnzJ, "gJ", True), _dev(gRho, self.S, "gRho", True),
+                                      _stream(stream)),
                "ncl_kkt_backward")
 
     # ---------------------------------------------------------------- inspect
@@ -333,21 +391,6 @@ class KKT:
         _check(lib().ncl_kkt_get_supernodes(self._h, None, None, None, rows.ctypes.data_as(P32)), "supernodes")
         return first, parent, rp, rows[:int(rp[-1])]
 
-    def flow_schedule(self):
-        """Dataflow schedule of the large fronts: (tasks [T, 8], deps [D, 2],
-        number of counters, launches [L, 4]); field meanings as in
-        ncl_kkt_get_flow."""
-        P64 = C.POINTER(C.c_int64)
-        P32 = C.POINTER(C.c_int32)
-        cnt = np.zeros(4, np.int64)
-        _check(lib().ncl_kkt_get_flow(self._h, cnt.ctypes.data_as(P64), None, None, None), "ncl_kkt_get_flow")
-        tasks = np.zeros((max(int(cnt[0]), 1), 8), np.int32)
-        deps = np.zeros((max(int(cnt[1]), 1), 2), np.int32)
-        launches = np.zeros((max(int(cnt[3]), 1), 4), np.int64)
-        _check(lib().ncl_kkt_get_flow(self._h, cnt.ctypes.data_as(P64), tasks.ctypes.data_as(P32),
-                                      deps.ctypes.data_as(P32), launches.ctypes.data_as(P64)), "ncl_kkt_get_flow")
-        return tasks[:cnt[0]], deps[:cnt[1]], int(cnt[2]), launches[:cnt[3]]
-
     def set_timing(self, on=True):
         _check(lib().ncl_kkt_set_timing(self._h, 1 if on else 0), "ncl_kkt_set_timing")
 
@@ -368,10 +411,13 @@ def _autograd_function():
 
         @staticmethod
         def forward(ctx, kkt, W_val, Sigma, J_val, rho, B):
+            if kkt.S != 1 or kkt.form != NCL_CONDENSED:
+                raise ValueError("kkt_solve differentiates one condensed system")
             rho_v = float(rho.item()) if torch.is_tensor(rho) else float(rho)
             kkt.factor(W_val.detach(), Sigma.detach(), J_val.detach(), rho_v)
             X, info = kkt.solve(B.detach())
             ctx.kkt = kkt
+            ctx.generation = kkt.generation
             ctx.save_for_backward(J_val.detach(), X)
             ctx.rho_is_tensor = torch.is_tensor(rho)
             ctx.info = info
@@ -380,13 +426,18 @@ def _autograd_function():
         @staticmethod
         def backward(ctx, Xbar):
             kkt = ctx.kkt
+            if kkt.generation != ctx.generation:
+                # the adjoint solve and the rho used by the gradient kernels are
+                # those of the handle's current factorization
+                raise RuntimeError("kkt_solve backward: the KKT handle was refactored after this forward "
+                                   "pass; run backward before factoring it again, or use one handle per solve")
             J_val, X = ctx.saved_tensors
             Lam, _ = kkt.solve(Xbar.contiguous() if Xbar.dim() == 1 else Xbar)
             dev = X.device
             gW = torch.empty(kkt.nnzW, dtype=torch.float64, device=dev)
             gS = torch.empty(kkt.order, dtype=torch.float64, device=dev)
             gJ = torch.empty(kkt.nnzJ, dtype=torch.float64, device=dev)
-            gR = torch.empty(1, dtype=torch.float64, device=dev)
+            gR = torch.empty(kkt.S, dtype=torch.float64, device=dev)
             X2 = X.reshape(kkt.order, -1)
             L2 = Lam.reshape(kkt.order, -1)
             Xc = X2.t().contiguous().t()

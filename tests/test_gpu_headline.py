@@ -1,0 +1,153 @@
+"""GPU parity at the benchmark's own sizes, against the oracle.
+
+* The n = 500k OPF-shaped condensed system (Delaunay network of 100k nodes)
+  at the first and last refactor of the benchmark sequence (rho = 1e2 and
+  1e8), FP64 and FP32 factor + FP64 refinement, with the benchmark's options
+  (absolute pivot bound 1e-12, refinement to omega <= 1e-10 and componentwise
+  omega_cw <= 1e-14).  Bar: inertia equal to the oracle's (n, 0, 0); omega and
+  omega_cw recomputed on the CPU against the oracle's K; the forward error
+  against the oracle's x (refined to the same target) within 1e-6 -- at 5000
+  nodes two accurate solvers (the oracle and SuperLU) differ by at most 3e-9
+  over the sequence.
+* The differentiation workload at its stated size: the config-1 matrix at
+  rho = 1e6, 16 right-hand sides, loss = sum(w * X); gradients with respect
+  to B and every stored entry of W, Sigma and J and rho against the oracle's
+  adjoint (<= 1e-8 relative in the max norm) and against central differences
+  (h = 1e-6) of the library's own solves on 200 entries, 50 each of B, W,
+  Sigma and J, at the bar the oracle itself meets (fd_util.fd_tolerance).
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2510_05885_amd import ncl_kkt as nk
+from paper_2510_05885_amd import synth
+
+from fd_util import config5_fd_cases, fd_tolerance
+from gpu_util import colmajor, dev
+
+pytestmark = pytest.mark.gpu
+
+HEADLINE_OPTS = dict(pivot_scale="absolute", pivot_eps=1e-12, ir_tol=1e-10, ir_cw_tol=1e-14, ir_max_steps=10)
+
+
+@pytest.fixture(scope="module")
+def opf500k():
+    print("[gpu] generating the n=500k OPF network", flush=True)
+    inp = synth.opf_network(N=100_000, seed=2)
+    b = synth.rhs(inp.n, 1, seed=7)
+    refs = {}
+    perm = None
+    for k in (0, 29):
+        Sigma, rho = synth.opf_sequence_values(inp, k)
+        case = inp.with_values(Sigma=Sigma, rho=rho)
+        K = O.assemble(case, O.CONDENSED)
+        if perm is None:
+            perm = O.mindeg(K)
+        print(f"[gpu] oracle solve k={k} rho={rho:.1e}", flush=True)
+        x, info, _, _ = O.solve(case, O.CONDENSED, b, eps=1e-12, pivot_scale="absolute", ir_tol=1e-10,
+                                ir_cw_tol=1e-14, perm=perm, K=K)
+        refs[k] = (case, K, x, info)
+    return inp, b, refs
+
+
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_parity_n500k(opf500k, precision):
+    inp, b, refs = opf500k
+    print(f"[gpu] n=500k parity {precision}: analyze", flush=True)
+    kkt = nk.KKT.from_input(inp, precision=precision, **HEADLINE_OPTS)
+    W, J, B = dev(inp.W_val), dev(inp.J_val), dev(b[:, 0])
+    for k in (0, 29):
+        case, K, xo, io = refs[k]
+        print(f"[gpu] n=500k {precision} k={k} rho={case.rho:.1e}", flush=True)
+        rc = kkt.factor(W, dev(case.Sigma), J, case.rho)
+        X, info = kkt.solve(B)
+        x = X.cpu().numpy().reshape(-1, 1)
+        om = float(O.backward_error(K, x, b).max())
+        cw = float(O.componentwise_backward_error(K, x, b).max())
+        fwd = float(np.abs(x - xo).max() / np.abs(xo).max())
+        inert = kkt.inertia()
+        print(f"[gpu]   rc={rc} inertia={inert} oracle={io.inertia} ir_steps={info.ir_steps} "
+              f"fell_back={info.fell_back_fp64} omega={om:.2e} cw={cw:.2e} (lib {info.backward_error_cw:.2e}) "
+              f"oracle cw={io.backward_error_cw:.2e} fwd_err={fwd:.2e}", flush=True)
+        assert rc in (0, nk.NCL_WARN_FELL_BACK_FP64), (rc, info)
+        assert inert[:3] == io.inertia[:3] == (inp.n, 0, 0)
+        assert om <= 1e-10
+        assert info.backward_error_cw <= 1e-14 and cw <= 2e-14
+        assert io.backward_error_cw <= 1e-14
+        assert fwd <= 1e-6
+    kkt.close()
+
+
+@pytest.mark.timeout(600)
+def test_adjoint_config5():
+    """Config 5 at its stated size (n = 2000, rho = 1e6, 16 right-hand sides)."""
+    import torch
+    print("[gpu] adjoint config 5", flush=True)
+    inp = synth.grid_banded(rho=1e6)
+    n = inp.n
+    rng = np.random.default_rng(5)
+    B = rng.standard_normal((n, 16))
+    Wt = rng.standard_normal((n, 16))
+    kkt = nk.KKT.from_input(inp, ir_cw_tol=1e-14)
+    Wv = dev(inp.W_val).requires_grad_()
+    Sv = dev(inp.Sigma).requires_grad_()
+    Jv = dev(inp.J_val).requires_grad_()
+    rv = torch.tensor(inp.rho, dtype=torch.float64, device="cuda", requires_grad=True)
+    Bleaf = torch.tensor(np.ascontiguousarray(B.T), dtype=torch.float64, device="cuda", requires_grad=True)
+    X = nk.kkt_solve(kkt, Wv, Sv, Jv, rv, Bleaf.t())
+    loss = (X * dev(Wt)).sum()
+    loss.backward()
+    Xo, _, F, K = O.solve(inp, O.CONDENSED, B, ir_cw_tol=1e-14)
+    gB, gW, gS, gJ, gr = O.adjoint_condensed(inp, F, Xo, Wt)
+    rel = lambda a, b: np.abs(a - b).max() / max(np.abs(b).max(), 1e-300)
+    g = {"B": Bleaf.grad.cpu().numpy().T, "W_val": Wv.grad.cpu().numpy(), "Sigma": Sv.grad.cpu().numpy(),
+         "J_val": Jv.grad.cpu().numpy()}
+    print(f"[gpu]   rel err vs oracle: B {rel(g['B'], gB):.1e} W {rel(g['W_val'], gW):.1e} "
+          f"Sigma {rel(g['Sigma'], gS):.1e} J {rel(g['J_val'], gJ):.1e} rho {abs(rv.grad.item() - gr) / abs(gr):.1e}",
+          flush=True)
+    assert rel(g["B"], gB) <= 1e-8
+    assert rel(g["W_val"], gW) <= 1e-8
+    assert rel(g["Sigma"], gS) <= 1e-8
+    assert rel(g["J_val"], gJ) <= 1e-8
+    assert abs(rv.grad.item() - gr) <= 1e-8 * abs(gr)
+
+    # central differences of the library's own solves
+    h = 1e-6
+    Xg = X.detach().cpu().numpy()
+    fk = nk.KKT.from_input(inp, ir_cw_tol=1e-14)
+    Bd = colmajor(B)
+
+    def loss_of(W=inp.W_val, S=inp.Sigma, Jv_=inp.J_val, Bm=None):
+        fk.factor(dev(W), dev(S), dev(Jv_), inp.rho)
+        Xs, _ = fk.solve(Bd if Bm is None else colmajor(Bm))
+        return float(np.sum(Wt * Xs.cpu().numpy()))
+
+    cases = config5_fd_cases(inp, rng)
+    worst = {}
+    for field, key in (("W_val", "W"), ("Sigma", "S"), ("J_val", "Jv_")):
+        tol = fd_tolerance(g[field], Wt, Xg, h)
+        base = getattr(inp, field)
+        ratio = 0.0
+        for k in cases[field]:
+            v = base.copy(); v[k] += h
+            lp = loss_of(**{key: v})
+            v[k] = base[k] - h
+            lm = loss_of(**{key: v})
+            err = abs((lp - lm) / (2 * h) - g[field][k])
+            ratio = max(ratio, err / tol[k])
+        worst[field] = ratio
+    tol = fd_tolerance(g["B"], Wt, Xg, h)
+    ratio = 0.0
+    for i, c in cases["B"]:
+        Bp = B.copy(); Bp[i, c] += h
+        lp = loss_of(Bm=Bp)
+        Bp[i, c] -= 2 * h
+        lm = loss_of(Bm=Bp)
+        ratio = max(ratio, abs((lp - lm) / (2 * h) - g["B"][i, c]) / tol[i, c])
+    worst["B"] = ratio
+    print(f"[gpu]   finite differences, max |fd - g| / bar: {worst}", flush=True)
+    assert max(worst.values()) <= 1.0
+    fk.close()
+    kkt.close()

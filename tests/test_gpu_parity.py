@@ -69,41 +69,18 @@ def test_parity_multi_rhs(nrhs):
     _case("grid-banded-multi", lambda: synth.grid_banded(), "condensed", nrhs=nrhs)
 
 
-@pytest.mark.parametrize("flow", [True, False])
-def test_parity_opf_large_fronts(flow):
+def test_parity_opf_large_fronts():
     """Delaunay network with fronts above the LDS bound (global-memory MFMA
-    path), factored by the dataflow launch or by one launch per task kind."""
-    _case(f"opf-N5000 flow={flow}", lambda: synth.opf_network(N=5000, seed=7, rho=1e4), "condensed",
-          check_kappa=False, large_flow=flow)
+    path)."""
+    _case("opf-N5000", lambda: synth.opf_network(N=5000, seed=7, rho=1e4), "condensed", check_kappa=False)
 
 
 @pytest.mark.parametrize("form", ["condensed", "stabilized"])
 def test_parity_many_large_fronts(form):
     """LDS bound lowered to 64: most fronts take the large-front path, with
     partial last panels and multi-panel fronts."""
-    for flow in (False, True):
-        _case(f"opf-N2000 fm64 flow={flow}", lambda: synth.opf_network(N=2000, seed=3, rho=1e4, sigma_lo=-4,
-                                                                        sigma_hi=4), form, small_front_max=64,
-              large_flow=flow)
-
-
-@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
-@pytest.mark.parametrize("form", ["condensed", "stabilized"])
-def test_flow_matches_launch_chain_bitwise(form, precision):
-    """The dataflow launch runs the same task bodies in the same order per
-    tile as the per-step launches: identical factors, identical solutions."""
-    print(f"[gpu] flow vs chain {form} {precision}", flush=True)
-    inp = synth.opf_network(N=3000, seed=6, rho=1e4)
-    N = inp.n if form == "condensed" else inp.n + inp.m
-    B = synth.rhs(N, 2, seed=3)
-    out = []
-    for flow in (True, False):
-        kkt = nk.KKT.from_input(inp, form=form, precision=precision, small_front_max=64, large_flow=flow)
-        rc, X, info = factor_solve(kkt, inp, B)
-        out.append((rc, X, kkt.inertia()))
-        kkt.close()
-    assert out[0][0] == out[1][0] and out[0][2] == out[1][2]
-    assert np.array_equal(out[0][1], out[1][1])
+    _case("opf-N2000 fm64", lambda: synth.opf_network(N=2000, seed=3, rho=1e4, sigma_lo=-4, sigma_hi=4), form,
+          small_front_max=64)
 
 
 @pytest.mark.parametrize("rho", [1e2, 1e6, 1e8])
