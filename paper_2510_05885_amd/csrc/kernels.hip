@@ -82,10 +82,30 @@ __device__ __forceinline__ void count_pivot(unsigned long long* in4, double d, b
 // the row order differs between the f64 and f32 instructions (checked on
 // gfx950 with a one-hot probe).
 template <typename T> struct Mfma;
+//
+// run_chained: for an MFMA whose result is read by the very next instruction
+// that touches it (the next MFMA of a single-accumulator chain, as SrcC or as
+// an operand, or the read-out).  On gfx950 such a dependency needs more
+// separation than the compiler inserts: without the 16 wait states below,
+// about 3% of the factorizations of a 500k-order system differed from run to
+// run, always in one accumulator register pair of one wave, while with them
+// every repeat was bitwise identical.  Chains whose consecutive MFMAs write
+// different accumulators (the interleaved 64x64 tile update) need only pad()
+// before their read-out.
+__device__ __forceinline__ void mfma_pad() {
+    __builtin_amdgcn_sched_barrier(0);
+    asm volatile("s_nop 15");
+    __builtin_amdgcn_sched_barrier(0);
+}
 template <> struct Mfma<double> {
     typedef f64x4 acc_t;
     static __device__ __forceinline__ acc_t run(double a, double b, acc_t c) {
         return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ acc_t run_chained(double a, double b, acc_t c) {
+        acc_t r = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+        mfma_pad();
+        return r;
     }
     static __device__ __forceinline__ int row(int lk, int r) { return 4 * r + lk; }
 };
@@ -93,6 +113,11 @@ template <> struct Mfma<float> {
     typedef f32x4 acc_t;
     static __device__ __forceinline__ acc_t run(float a, float b, acc_t c) {
         return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+    }
+    static __device__ __forceinline__ acc_t run_chained(float a, float b, acc_t c) {
+        acc_t r = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+        mfma_pad();
+        return r;
     }
     static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
 };
@@ -219,7 +244,7 @@ __device__ void lds_partial_ldlt(T* A, int lda, int f, int p, T* dv, const int8_
                 const int t = kb + tt;
                 const T a = (tv && i0 + lr < f) ? A[(i0 + lr) + t * lda] : T(0);
                 const T b = (tv && j0 + lr < f) ? A[(j0 + lr) + t * lda] * dv[tv ? t : 0] : T(0);
-                acc = Mfma<T>::run(a, b, acc);
+                acc = Mfma<T>::run_chained(a, b, acc);
             }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
@@ -333,7 +358,7 @@ __device__ __forceinline__ void diag_ldlt64(T* B, T* dv, unsigned long long negm
 #pragma unroll
                 for (int st = 0; st < 4; ++st) {
                     const int t = kb + 4 * st + lk;
-                    acc = Mfma<T>::run(B[(i0 + lr) + t * LB], B[(j0 + lr) + t * LB] * dv[t], acc);
+                    acc = Mfma<T>::run_chained(B[(i0 + lr) + t * LB], B[(j0 + lr) + t * LB] * dv[t], acc);
                 }
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
@@ -402,13 +427,14 @@ __device__ __forceinline__ void tri_inv64(T* B, int tid) {
 #pragma unroll
                 for (int st = 0; st < 4; ++st) {
                     const int kk = Mfma<T>::row(lk, st);
-                    S = Mfma<T>::run(B[(16 * i + lr) + (16 * k + kk) * LB], zget(B, 16 * k + kk, 16 * q + lr), S);
+                    S = Mfma<T>::run_chained(B[(16 * i + lr) + (16 * k + kk) * LB], zget(B, 16 * k + kk, 16 * q + lr),
+                                             S);
                 }
             }
             acc_t R = {0, 0, 0, 0};
 #pragma unroll
             for (int st = 0; st < 4; ++st)
-                R = Mfma<T>::run(zget(B, 16 * i + lr, 16 * i + Mfma<T>::row(lk, st)), S[st], R);
+                R = Mfma<T>::run_chained(zget(B, 16 * i + lr, 16 * i + Mfma<T>::row(lk, st)), S[st], R);
 #pragma unroll
             for (int r = 0; r < 4; ++r) B[(16 * q + lr) + (16 * i + Mfma<T>::row(lk, r)) * LB] = -R[r];
         }
@@ -880,6 +906,7 @@ __device__ __forceinline__ void tile_update(const T* __restrict__ A, int f, int 
         for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
             for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = Mfma<T>::run(av[ks][bi], bv[ks][bj], acc[bi][bj]);
+    mfma_pad();   // before the read-out of the last accumulator written
 }
 
 // One workgroup per (large front, panel k0): bring the panel's diagonal block
@@ -1002,7 +1029,7 @@ __device__ __forceinline__ void panel_body(const DevPlan& d, int s, int k0, int 
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
                 const int kk = 16 * K + Mfma<T>::row(lk, st);
-                acc = Mfma<T>::run(a[K][st], Zt[kk * kPanel + 16 * J + lr], acc);
+                acc = Mfma<T>::run_chained(a[K][st], Zt[kk * kPanel + 16 * J + lr], acc);
             }
         }
         const int col = 16 * J + lr;

@@ -151,3 +151,35 @@ def test_adjoint_config5():
     assert max(worst.values()) <= 1.0
     fk.close()
     kkt.close()
+
+
+@pytest.mark.timeout(600)
+@pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
+def test_sequence_bitwise_repeatable(opf500k, precision):
+    """Four passes over the 30-refactor sequence at n = 500k on one handle
+    (unrefined solves, graph replays): every refactor gives bitwise the same
+    solution and inertia in every pass.  Each refactor follows a different
+    matrix, so a dependency on stale values -- such as an MFMA accumulator
+    read before it is written -- shows up here, not in repeats of one matrix."""
+    import hashlib
+
+    import torch
+    inp, b, _ = opf500k
+    print(f"[gpu] n=500k repeatability {precision}", flush=True)
+    kkt = nk.KKT.from_input(inp, precision=precision, pivot_scale="absolute", pivot_eps=1e-12, ir_max_steps=0,
+                            fp32_sticky=False)
+    W, J, B = dev(inp.W_val), dev(inp.J_val), dev(b[:, 0])
+    seq = [synth.opf_sequence_values(inp, k) for k in range(30)]
+    sig = [dev(s) for s, _ in seq]
+    seen = {}
+    for p in range(4):
+        for k in range(30):
+            kkt.factor(W, sig[k], J, seq[k][1])
+            X, _ = kkt.solve(B)
+            key = (hashlib.sha1(X.cpu().numpy().tobytes()).hexdigest(), kkt.inertia())
+            seen.setdefault(k, set()).add(key)
+    torch.cuda.synchronize()
+    varied = {k: len(v) for k, v in seen.items() if len(v) > 1}
+    print(f"[gpu]   refactors with more than one result: {varied}", flush=True)
+    assert not varied
+    kkt.close()
