@@ -66,6 +66,8 @@ enum { NCL_PIVOT_GLOBAL = 0, NCL_PIVOT_BLOCK = 1, NCL_PIVOT_ABSOLUTE = 2 };
 #define NCL_ERR_NONFINITE (-6)  /* NaN or Inf met in the assembled matrix, or in a pivot of an
                                    FP64 factorization (an FP32 factor that meets one is
                                    replaced by an FP64 refactorization instead) */
+#define NCL_ERR_SCRATCH (-7)    /* ncl_kkt_backward_noalloc: 2 x m x nrhs exceeds its fixed
+                                   scratch of 2^21 doubles */
 #define NCL_WARN_INERTIA 1      /* factor done, inertia differs from (n,0,0) / (n,m,0) */
 #define NCL_WARN_IR_NOT_CONVERGED 2  /* refinement stopped above ir_tol */
 #define NCL_WARN_FELL_BACK_FP64 3    /* FP32 factor insufficient; refactored in FP64 */
@@ -213,6 +215,18 @@ int ncl_kkt_inertia_batched(ncl_kkt_t h, int64_t *out);
  * gSigma, gJ, gRho may be NULL.  Stream-ordered, no synchronization. */
 int ncl_kkt_backward(ncl_kkt_t h, const double *J_val, const double *X, const double *Lambda, int64_t ld,
                      int32_t nrhs, double *gW, double *gSigma, double *gJ, double *gRho, void *stream);
+
+/* ncl_kkt_backward for callers that cannot allocate device memory during the
+ * call (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid hipMalloc): same arguments, results and errors, but the staging of
+ * J X and J Lambda (m x nrhs each) lives in the library's fixed device
+ * scratch of 2^21 doubles (16 MiB, one copy per GPU, held until the process
+ * ends) instead of the handle's workspace; it calls no allocator.  Returns
+ * NCL_ERR_SCRATCH when 2 x m x nrhs > 2^21.  Calls that overlap on one GPU
+ * share that scratch and race: order them on one stream.  Every value in it is
+ * written by the call before it is read (nothing needs clearing). */
+int ncl_kkt_backward_noalloc(ncl_kkt_t h, const double *J_val, const double *X, const double *Lambda, int64_t ld,
+                             int32_t nrhs, double *gW, double *gSigma, double *gJ, double *gRho, void *stream);
 
 int ncl_kkt_get_stats(ncl_kkt_t h, ncl_kkt_stats *st);
 

@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -47,6 +48,32 @@ struct Timer {
     ncl_kkt_timing tot{};
 };
 
+}  // namespace
+
+// Staging memory of ncl_kkt_backward_noalloc: a file-scope device array, one
+// copy per GPU, held until the process ends.  Host code never passes its name
+// to a kernel: the device address comes from hipGetSymbolAddress, resolved
+// once per device with that device current.
+constexpr int64_t kScratchDoubles = int64_t(1) << 21;   // 16 MiB
+static __device__ __align__(256) double scratch[kScratchDoubles];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[kMaxDevices] = {};
+
+hipError_t scratch_on_device(int dev, double** out) {
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        g_scratch_ptr[dev] = static_cast<double*>(p);
+    }
+    *out = g_scratch_ptr[dev];
+    return hipSuccess;
+}
 }  // namespace
 
 struct ncl_kkt_s {
@@ -942,6 +969,29 @@ int ncl_kkt_backward(ncl_kkt_t h, const double* J_val, const double* X, const do
     return NCL_OK;
 }
 
+int ncl_kkt_backward_noalloc(ncl_kkt_t h, const double* J_val, const double* X, const double* Lambda, int64_t ld,
+                             int32_t nrhs, double* gW, double* gSigma, double* gJ, double* gRho, void* stream) {
+    if (!h) return NCL_ERR_ARG;
+    if (h->host_only || !h->factored) return NCL_ERR_STATE;
+    if (h->P.form != NCL_CONDENSED) return NCL_ERR_ARG;
+    if (!X || !Lambda || nrhs < 1 || nrhs > kNrhsMax || ld < h->P.N) return NCL_ERR_ARG;
+    if ((gJ || gRho) && h->P.nnzJ > 0 && !J_val) return NCL_ERR_ARG;
+    const int64_t need = 2 * h->P.nJrows * (int64_t)nrhs;   // J X and J Lambda, nJrows x nrhs each
+    if (need > kScratchDoubles) return NCL_ERR_SCRATCH;
+    hipStream_t st = (hipStream_t)stream;
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        double* ws = nullptr;
+        HIPCHK(scratch_on_device(h->device, &ws));
+        launch_adjoint(h->d, h->P.nnzW, h->W_row, h->W_col, h->P.nJrows, h->Jp, h->Jj, h->Jrow_sys, J_val, h->rho, X,
+                       Lambda, ld, nrhs, gW, gSigma, gJ, gRho, ws, ws + h->P.nJrows * (int64_t)nrhs, h->sys_jrow, st);
+        HIPCHK(hipGetLastError());
+    } catch (const HipError&) {
+        return NCL_ERR_HIP;
+    }
+    return NCL_OK;
+}
+
 int ncl_kkt_get_stats(ncl_kkt_t h, ncl_kkt_stats* st) {
     if (!h || !st) return NCL_ERR_ARG;
     const Plan& P = h->P;
@@ -1030,6 +1080,9 @@ const char* ncl_kkt_strerror(int code) {
         case NCL_ERR_HIP: return "HIP runtime error";
         case NCL_ERR_STATE: return "call out of order (no numeric factorization or host-only handle)";
         case NCL_ERR_NONFINITE: return "NaN or Inf in the assembled matrix or a pivot";
+        case NCL_ERR_SCRATCH:
+            return "problem too large for the no-allocation entry point's fixed scratch (2 x m x nrhs > 2^21 "
+                   "doubles); use the allocating entry point";
         case NCL_WARN_INERTIA: return "warning: inertia differs from the expected (n,0,0) / (n,m,0)";
         case NCL_WARN_IR_NOT_CONVERGED: return "warning: iterative refinement stopped above the tolerance";
         case NCL_WARN_FELL_BACK_FP64: return "warning: FP32 factor replaced by an FP64 refactorization";

@@ -24,12 +24,13 @@ NCL_FP64, NCL_FP32_IR = 0, 1
 NCL_ORDER_ND, NCL_ORDER_NATURAL, NCL_ORDER_USER = 0, 1, 2
 NCL_PIVOT_GLOBAL, NCL_PIVOT_BLOCK, NCL_PIVOT_ABSOLUTE = 0, 1, 2
 NCL_OK = 0
+NCL_ERR_SCRATCH = -7
 NCL_WARN_INERTIA, NCL_WARN_IR_NOT_CONVERGED, NCL_WARN_FELL_BACK_FP64 = 1, 2, 3
 
 EXPORTED = [
     "ncl_kkt_default_options", "ncl_kkt_analyze", "ncl_kkt_analyze_host", "ncl_kkt_analyze_batched",
     "ncl_kkt_factor", "ncl_kkt_factor_batched", "ncl_kkt_solve", "ncl_kkt_inertia",
-    "ncl_kkt_inertia_batched", "ncl_kkt_backward", "ncl_kkt_get_stats", "ncl_kkt_get_perm",
+    "ncl_kkt_inertia_batched", "ncl_kkt_backward", "ncl_kkt_backward_noalloc", "ncl_kkt_get_stats", "ncl_kkt_get_perm",
     "ncl_kkt_get_supernodes", "ncl_kkt_set_timing", "ncl_kkt_get_timing",
     "ncl_kkt_destroy", "ncl_kkt_strerror",
 ]
@@ -109,8 +110,10 @@ def lib():
     L.ncl_kkt_inertia.restype = C.c_int
     L.ncl_kkt_inertia_batched.argtypes = [vp, C.POINTER(C.c_int64)]
     L.ncl_kkt_inertia_batched.restype = C.c_int
-    L.ncl_kkt_backward.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, vp]
-    L.ncl_kkt_backward.restype = C.c_int
+    for nm in ("ncl_kkt_backward", "ncl_kkt_backward_noalloc"):
+        f = getattr(L, nm)
+        f.argtypes = [vp, vp, vp, vp, i64, i32, vp, vp, vp, vp, vp]
+        f.restype = C.c_int
     L.ncl_kkt_get_stats.argtypes = [vp, C.POINTER(Stats)]
     L.ncl_kkt_get_stats.restype = C.c_int
     L.ncl_kkt_get_perm.argtypes = [vp, pi32]
@@ -353,16 +356,18 @@ class KKT:
                "ncl_kkt_inertia_batched")
         return out.reshape(self.S, 4)
 
-    def backward(self, J_val, X, Lam, gW=None, gSigma=None, gJ=None, gRho=None, stream=None):
+    def backward(self, J_val, X, Lam, gW=None, gSigma=None, gJ=None, gRho=None, stream=None, noalloc=False):
         """Adjoint of the last factorization's solve (condensed form): X and Lam
         are (order, nrhs) column-major with the same leading dimension;
-        gradients are overwritten (gRho: one value per system)."""
+        gradients are overwritten (gRho: one value per system).  noalloc=True
+        calls ncl_kkt_backward_noalloc (fixed library scratch)."""
         px, ldx, nx = _dev_cols(X, self.order, "X")
         pl, ldl, nl = _dev_cols(Lam, self.order, "Lambda")
         if nx != nl or ldx != ldl:
             raise ValueError("X and Lambda must have the same shape and leading dimension")
         pj = _dev(J_val, self.nnzJ, "J_val", allow_none=self.nnzJ == 0)
-        _check(lib().ncl_kkt_backward(self._h, pj, px, pl, ldx, nx,
+        f = lib().ncl_kkt_backward_noalloc if noalloc else lib().ncl_kkt_backward
+        _check(f(self._h, pj, px, pl, ldx, nx,
                                       _dev(gW, self.nnzW, "gW", True), _dev(gSigma, self.order, "gSigma", True),
                                       _dev(gJ, self.nnzJ, "gJ", True), _dev(gRho, self.S, "gRho", True),
                                       _stream(stream)),
