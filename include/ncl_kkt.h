@@ -105,6 +105,14 @@ typedef struct {
     double ir_cw_tol;        /* > 0: refinement must also bring the componentwise backward
                                 error max_i |b - Kx|_i / (|K||x| + |b|)_i to <= ir_cw_tol;
                                 0 (default): normwise criterion only */
+    int32_t persistent;      /* disabled: the persistent launches (every front of every
+                                system factored by one launch whose workgroups take fronts
+                                from a ticket counter in topological order, both sweeps by a
+                                second one) are switched off until a stall seen in them is
+                                explained.  0 or -1 (default): level-scheduled launches;
+                                1: NCL_ERR_ARG. */
+    int32_t persistent_grid; /* workgroups of the persistent launches (unused while they are
+                                disabled) */
 } ncl_kkt_options;
 
 /* Result of one solve, each figure the max over columns (and systems), all
@@ -264,6 +272,14 @@ typedef struct {
 
 int ncl_kkt_set_timing(ncl_kkt_t h, int32_t enable);   /* enabling also clears totals */
 int ncl_kkt_get_timing(ncl_kkt_t h, ncl_kkt_timing *t);
+
+/* Per-system device times of the last factor and solve of a handle factored
+ * by the persistent launch (options.persistent), in milliseconds from the start
+ * of that factor launch: factor_ms[s] = when system s's factorization
+ * finished, solve_ms[s] = when its last triangular sweep finished.  Host arrays
+ * of `count` (= number of systems) entries; either may be NULL.  While the
+ * persistent launches are disabled no handle has these: NCL_ERR_STATE. */
+int ncl_kkt_get_system_times(ncl_kkt_t h, double *factor_ms, double *solve_ms);
 
 void ncl_kkt_destroy(ncl_kkt_t h);
 const char *ncl_kkt_strerror(int code);

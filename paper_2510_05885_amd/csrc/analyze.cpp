@@ -793,6 +793,29 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
             }
             P.large_steps.push_back(std::move(st));
         }
+        // ---------------- persistent launches ------------------------------
+        {
+            P.pers_order.resize(nsn);
+            std::iota(P.pers_order.begin(), P.pers_order.end(), 0);
+            std::stable_sort(P.pers_order.begin(), P.pers_order.end(), [&](int a, int b) {
+                if (P.sn_level[a] != P.sn_level[b]) return P.sn_level[a] < P.sn_level[b];
+                return P.sn_rowptr[a + 1] - P.sn_rowptr[a] > P.sn_rowptr[b + 1] - P.sn_rowptr[b];
+            });
+            P.pers_asm.assign(2 * (size_t)nsn, 0);
+            for (size_t t = 0; t < P.large_asm.size() / 2; ++t) {
+                const int s = P.large_asm[2 * t];
+                if (P.pers_asm[2 * s + 1] == 0) P.pers_asm[2 * s] = (int64_t)t;
+                P.pers_asm[2 * s + 1]++;
+            }
+            P.sys_nfronts.assign(P.S, 0);
+            for (int s = 0; s < nsn; ++s) {
+                P.sys_nfronts[P.sn_sys[s]]++;
+                const int f = (int)(P.sn_rowptr[s + 1] - P.sn_rowptr[s]);
+                P.pers_fmax = std::max(P.pers_fmax, f);
+                if (P.sn_large[s]) P.pers_fmax_large = std::max(P.pers_fmax_large, f);
+                else P.pers_fmax_small = std::max(P.pers_fmax_small, f);
+            }
+        }
         // ---------------- solve schedule -----------------------------------
         {
             const int PW = cfg.solve_panel, FUSE = cfg.solve_fuse_rows, GR = cfg.solve_chunk_rows;

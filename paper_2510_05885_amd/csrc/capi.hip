@@ -81,6 +81,17 @@ struct ncl_kkt_s {
     ncl_kkt_options opt{};
     double eps = 0.0;
     int pivot_mode = 0;               // thresholds: 0 global, 1 per block (stabilized), 2 absolute
+    // persistent launches (options.persistent)
+    bool pers = false;
+    int *pers_order = nullptr, *pers_ctr = nullptr, *pers_status = nullptr, *sys_nfronts = nullptr;
+    int64_t* pers_asm = nullptr;
+    unsigned long long* tstamp = nullptr;
+    int pers_grid_f = 0, pers_grid_s = 0, pers_lds_elems = 0, max_lds = 0;
+    int64_t pers_ctr_len = 0;
+    int* pers_ticket = nullptr;
+    unsigned long long pers_timeout = 0;
+    double wall_khz = 0.0;
+    bool pers_solved = false;
     int nonfinite_bits = 0;           // status word of the last factorization read back
     bool host_only = true;
     int device = 0;
@@ -211,6 +222,7 @@ void setup_device(ncl_kkt_s* h) {
     d.N = P.N;
     d.n_primal = P.form == NCL_STABILIZED ? P.sys_n[0] : P.N;
     d.S = P.S;
+    d.n_fronts = P.nsn;
     d.form = P.form;
     h->nnzF = (int64_t)P.Kj.size();
     std::vector<int> Krow(h->nnzF);
@@ -234,6 +246,7 @@ void setup_device(ncl_kkt_s* h) {
     d.child_ptr = upload(h, P.child_ptr);
     d.child_list = upload(h, P.child_list);
     d.sn_sys = upload(h, P.sn_sys);
+    d.sn_parent = upload(h, P.sn_parent);
     d.kent_ptr = upload(h, P.kent_ptr);
     d.kent_csr = upload(h, P.kent_csr);
     d.kent_pos = upload(h, P.kent_pos);
@@ -327,7 +340,26 @@ void setup_device(ncl_kkt_s* h) {
         h->JX = dalloc<double>(h, std::max<int64_t>(P.nJrows, 1) * kNrhsMax);
         h->JL = dalloc<double>(h, std::max<int64_t>(P.nJrows, 1) * kNrhsMax);
     }
-    h->host_pinned_len = (size_t)std::max<int64_t>((int64_t)P.S * kNrhsMax * kResWidth, 8 * (int64_t)P.S + 8);
+    if (h->pers) {
+        h->pers_order = upload(h, P.pers_order);
+        h->pers_asm = upload(h, P.pers_asm);
+        h->sys_nfronts = upload(h, P.sys_nfronts);
+        // counters, then the ticket 128 bytes past them (a cache line of its own)
+        h->pers_ctr_len = ((3 * (int64_t)P.nsn + P.S + 31) / 32) * 32 + 32;
+        h->pers_ctr = dalloc<int>(h, h->pers_ctr_len);
+        h->pers_ticket = h->pers_ctr + (h->pers_ctr_len - 32);
+        h->pers_status = dalloc<int>(h, 1);
+        h->tstamp = dalloc<unsigned long long>(h, 1 + 2 * (int64_t)P.S);
+        int cus = 0, khz = 0;
+        HIPCHK(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, h->device));
+        HIPCHK(hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, h->device));
+        h->wall_khz = khz;
+        h->pers_timeout = (unsigned long long)(2.0 * 1000.0 * khz);   // 2 s of wall_clock64 ticks
+        h->pers_grid_f = h->opt.persistent_grid > 0 ? h->opt.persistent_grid : cus;
+        h->pers_grid_s = h->opt.persistent_grid > 0 ? h->opt.persistent_grid : 2 * cus;
+        h->pers_lds_elems = std::max<int>(P.pers_fmax_small * P.pers_fmax_small, 4 * std::max(P.pers_fmax_large, 1));
+    }
+    h->host_pinned_len = (size_t)std::max<int64_t>((int64_t)P.S * kNrhsMax * kResWidth + 1, 8 * (int64_t)P.S + 8);
     HIPCHK(hipHostMalloc((void**)&h->host_pinned, sizeof(double) * h->host_pinned_len, hipHostMallocDefault));
     HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
     HIPCHK(hipStreamCreateWithFlags(&h->aux_stream, hipStreamNonBlocking));
@@ -340,6 +372,7 @@ void setup_device(ncl_kkt_s* h) {
         int lds = 0;
         HIPCHK(hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, h->device));
         HIPCHK(configure_kernels(lds));
+        h->max_lds = lds;
     }
     HIPCHK(hipDeviceSynchronize());
     h->host_only = false;
@@ -369,6 +402,8 @@ void fill_defaults(ncl_kkt_options* o) {
     o->fp32_sticky = 1;
     o->pivot_scale = NCL_PIVOT_GLOBAL;
     o->ir_cw_tol = 0.0;
+    o->persistent = -1;
+    o->persistent_grid = 0;
 }
 
 int do_analyze(ncl_kkt_t* out, const ncl_kkt_options* o, const std::vector<SysInput>& sys, bool host_only) {
@@ -387,11 +422,31 @@ int do_analyze(ncl_kkt_t* out, const ncl_kkt_options* o, const std::vector<SysIn
                     : (h->opt.pivot_scale == NCL_PIVOT_BLOCK && h->opt.form == NCL_STABILIZED ? 1 : 0);
     if (sys.size() > 1 && h->opt.form != NCL_CONDENSED) { delete h; return NCL_ERR_ARG; }
     h->eps = h->opt.pivot_eps > 0.0 ? h->opt.pivot_eps : (h->opt.form == NCL_CONDENSED ? 1e-12 : 1e-10);
+    // The persistent launches (k_persist_factor / k_persist_solve) are disabled:
+    // a batched factor + solve through them once stopped making progress and
+    // the cause is not established.  Every handle takes the level-scheduled
+    // launches; asking for the persistent ones is an argument error.
+    if (h->opt.persistent > 0) { delete h; return NCL_ERR_ARG; }
+    h->pers = false;
     PlanConfig cfg;
     if (!host_only) {
         int fm = 90;
         int rc = pick_small_max(fm);
         if (rc) { delete h; return rc; }
+        if (h->pers) {
+            // the persistent factor keeps a small front in dynamic LDS beside its
+            // static LDS (diagonal-block buffers): cap the order so both fit
+            int dev = 0, lds = 0;
+            if (hipGetDevice(&dev) != hipSuccess ||
+                hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+                delete h;
+                return NCL_ERR_HIP;
+            }
+            const int st = persist_factor_static_lds(0);
+            if (st < 0) { delete h; return NCL_ERR_HIP; }
+            fm = std::min(fm, (int)std::floor(std::sqrt((double)(lds - st) / sizeof(double))));
+            if (h->opt.small_front_max > fm) { delete h; return NCL_ERR_ARG; }
+        }
         cfg.small_front_max = fm;
     }
     if (h->opt.small_front_max > 0) {
@@ -402,6 +457,19 @@ int do_analyze(ncl_kkt_t* out, const ncl_kkt_options* o, const std::vector<SysIn
     std::string err;
     int rc = build_plan(h->P, h->opt.form, sys, h->opt.ordering, h->opt.user_perm, cfg, err);
     if (rc) { delete h; return rc; }
+    if (h->pers && !host_only) {
+        // a large front's columns (4 per workgroup) must fit the persistent
+        // factor's dynamic LDS too; otherwise keep the level-scheduled launches
+        int dev = 0, lds = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) {
+            delete h;
+            return NCL_ERR_HIP;
+        }
+        const int64_t need = (int64_t)sizeof(double) * std::max<int64_t>(
+            (int64_t)h->P.pers_fmax_small * h->P.pers_fmax_small, 4 * (int64_t)h->P.pers_fmax_large);
+        if (need + persist_factor_static_lds(0) > lds) h->pers = false;
+    }
     h->h_rho.assign(h->P.S, 1.0);
     h->h_kinf.assign(h->P.S, 0.0);
     h->h_inertia.assign(4 * (size_t)h->P.S, 0);
@@ -451,6 +519,18 @@ void factor_fronts(ncl_kkt_s* h, T* F, T* D, T* Mb, hipStream_t st) {
     Plan& P = h->P;
     const DevPlan& d = h->d;
     launch_zero_u64(h->inertia_part, 4 * (int64_t)P.S * kInertiaSlots, st);
+    if (h->pers) {
+        launch_zero_i32(h->pers_ctr, h->pers_ctr_len, st);
+        launch_zero_u64(h->tstamp, 1 + (int64_t)P.S, st);
+        double fl = 0.0;
+        if (h->tm.on) fl = P.flops_exact;
+        Span sp(h, st, TM_SMALL, fl, 2);
+        launch_persist_factor<T>(d, h->pers_order, P.nsn, h->pers_asm, std::max(P.pers_fmax_large, 1),
+                                 h->pers_lds_elems, h->pers_grid_f, h->pers_ctr, h->pers_ticket, h->pers_status,
+                                 h->pers_timeout, h->tstamp, h->K, F, D, Mb, st);
+        launch_reduce_inertia(d, P.S, st);
+        return;
+    }
     size_t sb = 0, lb = 0;
     for (int l = 0; l < P.nlevels; ++l) {
         // Fronts of one level are independent: when the level has both kinds,
@@ -566,9 +646,13 @@ int read_inertia(ncl_kkt_s* h, hipStream_t st) {
     HIPCHK(hipMemcpyAsync(hp, h->inertia, sizeof(unsigned long long) * 4 * S, hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(h->host_pinned + 4 * S, h->nonfinite, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(h->host_pinned + 4 * S + 1, h->kinf, sizeof(double) * 1, hipMemcpyDeviceToHost, st));
+    if (h->pers)
+        HIPCHK(hipMemcpyAsync(h->host_pinned + 4 * S + 2, h->pers_status, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    int nonfin = 0;
+    int nonfin = 0, pstat = 0;
     std::memcpy(&nonfin, h->host_pinned + 4 * S, sizeof(int));
+    if (h->pers) std::memcpy(&pstat, h->host_pinned + 4 * S + 2, sizeof(int));
+    if (pstat & 2) return NCL_ERR_HIP;   // a wait of the persistent launch gave up
     h->nonfinite_bits = nonfin;
     h->inertia_ok = true;
     for (int s = 0; s < S; ++s) {
@@ -608,6 +692,8 @@ int factor_impl(ncl_kkt_s* h, const double* W, const double* Sigma, const double
         for (int s = 0; s < P.S; ++s) h->host_pinned[s] = rho_host[s];
         HIPCHK(hipMemcpyAsync(h->rho, h->host_pinned, sizeof(double) * P.S, hipMemcpyHostToDevice, st));
         launch_zero_i32(h->nonfinite, 1, st);
+        if (h->pers) launch_zero_i32(h->pers_status, 1, st);
+        h->pers_solved = false;
         {
             // algorithmic bytes: read W, Sigma, J once, write the lower triangle of K
             const double bytes = 8.0 * ((double)P.nnzW + (double)P.nnzJ + (double)P.N + (double)P.nnz_lower);
@@ -654,10 +740,25 @@ int factor_impl(ncl_kkt_s* h, const double* W, const double* Sigma, const double
 }
 
 // ----- solve -------------------------------------------------------------------
+// LDS of the persistent solve for nrhs columns fits the device limit.
+template <typename T>
+bool pers_solve_fits(const ncl_kkt_s* h, int nrhs) {
+    const size_t need = ((size_t)h->P.pers_fmax * nrhs + 256 * (size_t)nrhs + 64 * 65) * sizeof(T) + 64;
+    return h->pers && need <= (size_t)h->max_lds;
+}
+
 template <typename T>
 void sweeps(ncl_kkt_s* h, int nrhs, const T* F, const T* Z, const T* D, T* Y, T* U, T* partial, hipStream_t st) {
     Plan& P = h->P;
     const DevPlan& d = h->d;
+    if (pers_solve_fits<T>(h, nrhs)) {
+        launch_zero_i32(h->pers_ctr, h->pers_ctr_len, st);
+        Span sp(h, st, TM_SOLVE, 0.0, 0);
+        launch_persist_solve<T>(d, h->pers_order, P.nsn, h->sys_nfronts, std::max(P.pers_fmax, 1), h->pers_grid_s,
+                                h->pers_ctr, h->pers_ticket, h->pers_status, h->pers_timeout, h->tstamp, F, Z, D, Y, U,
+                                nrhs, st);
+        return;
+    }
     const std::vector<SolveStep>& S = P.solve_steps;
     // Steps of one level are independent between small fronts (one wave each)
     // and large fronts (panel chain): when a level has both, the small ones go
@@ -779,7 +880,10 @@ Backward backward_error(ncl_kkt_s* h, const double* B, int64_t ldb, const double
     }
     HIPCHK(hipMemcpyAsync(h->host_pinned, h->res_out, sizeof(double) * kResWidth * nrhs * P.S,
                           hipMemcpyDeviceToHost, st));
+    int* pstat = reinterpret_cast<int*>(h->host_pinned + (int64_t)kResWidth * nrhs * P.S);
+    if (h->pers) HIPCHK(hipMemcpyAsync(pstat, h->pers_status, sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
+    if (h->pers && (*pstat & 2)) throw HipError{hipErrorLaunchTimeOut};   // a wait of the persistent solve gave up
     Backward out;
     auto upd = [](double& m, double w) { m = std::isnan(w) ? INFINITY : std::max(m, w); };
     for (int s = 0; s < P.S; ++s)
@@ -914,6 +1018,7 @@ int ncl_kkt_solve(ncl_kkt_t h, const double* B, int64_t ldb, double* X, int64_t 
             om0_all = std::max(om0_all, om0);
         }
         flush_timing(h);
+        h->pers_solved = h->pers;
     } catch (const HipError&) {
         return NCL_ERR_HIP;
     }
@@ -1024,6 +1129,25 @@ int ncl_kkt_get_supernodes(ncl_kkt_t h, int32_t* first, int32_t* parent, int64_t
     if (parent) std::memcpy(parent, P.sn_parent.data(), sizeof(int32_t) * P.sn_parent.size());
     if (row_ptr) std::memcpy(row_ptr, P.sn_rowptr.data(), sizeof(int64_t) * P.sn_rowptr.size());
     if (rows) std::memcpy(rows, P.sn_rows.data(), sizeof(int32_t) * P.sn_rows.size());
+    return NCL_OK;
+}
+
+int ncl_kkt_get_system_times(ncl_kkt_t h, double* factor_ms, double* solve_ms) {
+    if (!h) return NCL_ERR_ARG;
+    if (h->host_only || !h->pers || !h->pers_solved) return NCL_ERR_STATE;
+    const int S = h->P.S;
+    std::vector<unsigned long long> t(1 + 2 * (size_t)S);
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        HIPCHK(hipMemcpy(t.data(), h->tstamp, sizeof(unsigned long long) * t.size(), hipMemcpyDeviceToHost));
+    } catch (const HipError&) {
+        return NCL_ERR_HIP;
+    }
+    const double per_ms = h->wall_khz > 0.0 ? 1.0 / h->wall_khz : 0.0;   // ticks of wall_clock64 -> ms
+    for (int s = 0; s < S; ++s) {
+        if (factor_ms) factor_ms[s] = (double)(t[1 + s] - t[0]) * per_ms;
+        if (solve_ms) solve_ms[s] = (double)(t[1 + S + s] - t[0]) * per_ms;
+    }
     return NCL_OK;
 }
 

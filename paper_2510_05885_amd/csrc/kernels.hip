@@ -573,15 +573,14 @@ __global__ void k_thresholds(int S, const double* norms3, double eps, int mode, 
 // ---------------------------------------------------------------------------
 // small fronts: one workgroup per front, front in LDS (column-major, ld = f)
 // ---------------------------------------------------------------------------
+// One front s (f <= kSmallMax) factored by the whole workgroup in LDS (A: f x f
+// of T); `slot` spreads the inertia atomics.  Ends with the write-out (no
+// trailing barrier).
 template <typename T, bool kTwoRows>
-__global__ __launch_bounds__(256) void k_small_fronts(DevPlan d, const int* __restrict__ list,
-                                                      const double* __restrict__ K, T* __restrict__ F,
-                                                      T* __restrict__ D) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* A = reinterpret_cast<T*>(smem_raw);
+__device__ __forceinline__ void small_front_body(const DevPlan& d, int s, int slot, const double* __restrict__ K,
+                                                 T* __restrict__ F, T* __restrict__ D, T* A) {
     __shared__ T dv[kSmallMax];
     __shared__ int8_t sgn[kSmallMax];
-    const int s = list[blockIdx.x];
     const int first = d.sn_first[s];
     const int p = d.sn_first[s + 1] - first;
     const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
@@ -634,7 +633,7 @@ __global__ __launch_bounds__(256) void k_small_fronts(DevPlan d, const int* __re
     bool bad = false;
     lds_partial_ldlt<T, kTwoRows>(A, f, f, p, dv, sgn, PivThr<T>(d, sys), cnt, bad);
     if (tid == 0) {
-        add_inertia(d, sys, cnt, blockIdx.x);
+        add_inertia(d, sys, cnt, slot);
         if (bad) atomicOr(d.nonfinite, kNonfiniteFactor);
     }
     for (int k = tid; k < p; k += 256) D[first + k] = dv[k];
@@ -648,6 +647,14 @@ __global__ __launch_bounds__(256) void k_small_fronts(DevPlan d, const int* __re
         for (int b = tj; b < c; b += 4)
             for (int a = b + ti; a < c; a += 64) CB[a + (int64_t)b * ld] = A[(p + a) + (p + b) * f];
     }
+}
+
+template <typename T, bool kTwoRows>
+__global__ __launch_bounds__(256) void k_small_fronts(DevPlan d, const int* __restrict__ list,
+                                                      const double* __restrict__ K, T* __restrict__ F,
+                                                      T* __restrict__ D) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    small_front_body<T, kTwoRows>(d, list[blockIdx.x], blockIdx.x, K, F, D, reinterpret_cast<T*>(smem_raw));
 }
 
 // Fronts of order f <= kTinyMax: one wave per front, four fronts per
@@ -783,19 +790,14 @@ __device__ __forceinline__ T col_read(const T* p) {
 // A wave's LDS accesses execute in order, so no workgroup barrier is needed;
 // children are added one after the other (two may map onto the same row).
 template <typename T, bool kLds>
-__global__ __launch_bounds__(256) void k_large_asm(DevPlan d, int64_t task0, int count, int fcap,
-                                                   const double* __restrict__ K, T* __restrict__ F) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const int64_t q = 4 * (int64_t)blockIdx.x + wave;
-    if (q >= count) return;
-    const int64_t t = task0 + q;
+__device__ __forceinline__ void asm_column(const DevPlan& d, int64_t t, const double* __restrict__ K,
+                                           T* __restrict__ F, T* slice, int lane) {
     const int64_t colbase = d.asm_col[t];
     const int f = d.asm_fj[2 * t], j = d.asm_fj[2 * t + 1];
     const int64_t e0 = d.asm_kr[2 * t], e1 = d.asm_kr[2 * t + 1];
     const int64_t g0 = d.asm_seg_ptr[t], g1 = d.asm_seg_ptr[t + 1];
     T* __restrict__ Acol = F + colbase;                      // Acol[i] = A[i, j]
-    T* __restrict__ cv = kLds ? reinterpret_cast<T*>(smem_raw) + (int64_t)wave * fcap : Acol;
+    T* __restrict__ cv = kLds ? slice : Acol;
     const int64_t jf = (int64_t)j * f;
     for (int i = j + lane; i < f; i += 64) cv[i] = T(0);
     asm_fence<kLds>();
@@ -822,6 +824,16 @@ __global__ __launch_bounds__(256) void k_large_asm(DevPlan d, int64_t task0, int
     }
     if (kLds)
         for (int i = j + lane; i < f; i += 64) Acol[i] = cv[i];
+}
+
+template <typename T, bool kLds>
+__global__ __launch_bounds__(256) void k_large_asm(DevPlan d, int64_t task0, int count, int fcap,
+                                                   const double* __restrict__ K, T* __restrict__ F) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t q = 4 * (int64_t)blockIdx.x + wave;
+    if (q >= count) return;
+    asm_column<T, kLds>(d, task0 + q, K, F, reinterpret_cast<T*>(smem_raw) + (int64_t)wave * fcap, lane);
 }
 
 // Writes the factored diagonal block of a panel (in LDS: L strictly below the
@@ -1690,6 +1702,318 @@ __global__ __launch_bounds__(256, 4) void k_bwd_S(DevPlan d, const int* __restri
 }
 
 // ---------------------------------------------------------------------------
+// persistent launches: one workgroup per front, fronts from a ticket counter
+// ---------------------------------------------------------------------------
+// Thread 0 waits until *ctr >= target, then acquires (agent scope: the
+// producers ran on other XCDs, whose L2 caches are not coherent with this
+// one); the barrier hands the data to the whole workgroup.  Polls back off
+// exponentially (up to ~0.9 us apart) and read the shared status word only
+// every 64 polls: hundreds of waiting workgroups must not flood one cache
+// line.  A wait gives up after `timeout` ticks of wall_clock64 and sets bit 1
+// of *status; every later wait then returns within 64 polls, so the grid
+// always drains in bounded time.
+__device__ __forceinline__ void pers_wait(const int* ctr, int target, int* status, unsigned long long timeout) {
+    if (threadIdx.x == 0 && target > 0) {
+        const unsigned long long t0 = wall_clock64();
+        int backoff = 1;
+        for (int n = 1; __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < target; ++n) {
+            if ((n & 63) == 0) {
+                if (__hip_atomic_load(status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) & 2) break;
+                if (wall_clock64() - t0 > timeout) {
+                    atomicOr(status, 2);
+                    break;
+                }
+            }
+            for (int i = 0; i < backoff; ++i) __builtin_amdgcn_s_sleep(1);
+            backoff = min(2 * backoff, 32);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    }
+    __syncthreads();
+}
+
+// Every wave waits for its stores to reach the L2, then one agent-scope
+// release (L2 write-back) publishes them with the counter increment.
+__device__ __forceinline__ void pers_signal(int* ctr) {
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    if (threadIdx.x == 0 && ctr) __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ int pers_ticket(int* ctr, int* shared_slot) {
+    if (threadIdx.x == 0) *shared_slot = __hip_atomic_fetch_add(ctr, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const int t = *shared_slot;
+    __syncthreads();
+    return t;
+}
+
+// A large front factored by one workgroup: its columns assembled in the
+// waves' LDS slices, then the panel steps in order (diagonal block, panel
+// solve of every 32-row block, trailing tiles except the next diagonal tile,
+// next diagonal block with its own update) -- the steps the level-scheduled
+// launches take, one after the other.
+template <typename T>
+__device__ void large_front_body(const DevPlan& d, int s, int64_t a0, int acnt, int fcap, const double* __restrict__ K,
+                                 T* __restrict__ F, T* __restrict__ D, T* __restrict__ Zbuf, T* lds) {
+    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+    for (int q = wave; q < acnt; q += 4) asm_column<T, true>(d, a0 + q, K, F, lds + (int64_t)wave * fcap, lane);
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
+    const int p = d.sn_first[s + 1] - d.sn_first[s];
+    const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
+    diag_body<T>(d, s, 0, F, D, Zbuf, tid);
+    __syncthreads();
+    for (int k0 = 0; k0 < p; k0 += kPanel) {
+        const int k1 = min(k0 + kPanel, p);
+        for (int r0 = k1; r0 < f; r0 += 32) panel_body<T>(d, s, k0, r0, F, D, Zbuf, tid);
+        __syncthreads();
+        for (int j0 = k1; j0 < f; j0 += kTile)
+            for (int i0 = j0; i0 < f; i0 += kTile) {
+                if (i0 == k1 && j0 == k1 && k1 < p) continue;
+                update_body<T>(d, s, k0, i0, j0, F, D, tid);
+            }
+        __syncthreads();
+        if (k1 < p) {
+            diag_body<T>(d, s, k1, F, D, Zbuf, tid);
+            __syncthreads();
+        }
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_persist_factor(DevPlan d, const int* __restrict__ order, int ntask,
+                                                        const int64_t* __restrict__ asm_rng, int fcap, int* ctr,
+                                                        int* ticket, int* status, unsigned long long timeout,
+                                                        unsigned long long* tstamp,
+                                                        const double* __restrict__ K, T* __restrict__ F,
+                                                        T* __restrict__ D, T* __restrict__ Zbuf) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* lds = reinterpret_cast<T*>(smem_raw);
+    __shared__ int s_t;
+    for (;;) {
+        const int t = pers_ticket(ticket, &s_t);
+        if (t >= ntask) break;
+        if (t == 0 && threadIdx.x == 0) tstamp[0] = wall_clock64();
+        const int s = order[t];
+        pers_wait(ctr + s, d.child_ptr[s + 1] - d.child_ptr[s], status, timeout);
+        const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
+        if (d.M_off[s] < 0) {
+            if (f > 64) small_front_body<T, true>(d, s, t, K, F, D, lds);
+            else small_front_body<T, false>(d, s, t, K, F, D, lds);
+        } else {
+            large_front_body<T>(d, s, asm_rng[2 * s], (int)asm_rng[2 * s + 1], fcap, K, F, D, Zbuf, lds);
+        }
+        const int par = d.sn_parent[s];
+        pers_signal(par >= 0 ? ctr + par : nullptr);
+        if (par < 0 && threadIdx.x == 0) atomicMax(tstamp + 1 + d.sn_sys[s], (unsigned long long)wall_clock64());
+    }
+}
+
+// Forward sweep of one front by the workgroup: y (f x nrhs, LDS, ld fcap) =
+// its pivots' entries plus the children's update vectors; each 64-column
+// block solved (Z = L_kk^-1 for large fronts, substitution by one wave
+// otherwise) and applied to the rows below; pivots back to Y, the rest to the
+// front's update vector.
+template <typename T>
+__device__ void front_forward(const DevPlan& d, int s, int fcap, const T* __restrict__ F, const T* __restrict__ Zbuf,
+                              T* __restrict__ Y, T* __restrict__ U, int nrhs, T* ys, T* Ld, T* part) {
+    const int tid = threadIdx.x, lane = tid & 63, q4 = tid >> 6;
+    const int first = d.sn_first[s];
+    const int p = d.sn_first[s + 1] - first;
+    const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
+    const int c = f - p;
+    const T* __restrict__ L = F + d.L_off[s];
+    T* __restrict__ Us = U + d.U_off[s];
+    const int64_t N = d.N;
+    for (int q = 0; q < nrhs; ++q)
+        for (int i = tid; i < f; i += 256) ys[i + q * fcap] = i < p ? Y[first + i + q * N] : T(0);
+    __syncthreads();
+    for (int k = d.child_ptr[s]; k < d.child_ptr[s + 1]; ++k) {
+        const int ch = d.child_list[k];
+        const int cc = (int)(d.sn_rowptr[ch + 1] - d.sn_rowptr[ch]) - (d.sn_first[ch + 1] - d.sn_first[ch]);
+        const T* __restrict__ Uc = U + d.U_off[ch];
+        const int* __restrict__ r = d.rel + d.rel_ptr[ch];
+        for (int q = 0; q < nrhs; ++q)
+            for (int a = tid; a < cc; a += 256) ys[r[a] + q * fcap] += Uc[a + (int64_t)q * cc];
+        __syncthreads();
+    }
+    for (int cb = 0; cb < p; cb += kPanel) {
+        const int ws = min(kPanel, p - cb);
+        if (d.M_off[s] >= 0) {
+            // v <- Z v, Z column-major 64 x 64; wave q4 takes columns 16 q4 .. 16 q4 + 15
+            const T* __restrict__ Zb = Zbuf + d.M_off[s] + (int64_t)(cb / kPanel) * (kPanel * kPanel);
+            T z[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) z[j] = Zb[(16 * q4 + j) * kPanel + lane];
+            for (int q = 0; q < nrhs; ++q) {
+                T acc = T(0);
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int k = 16 * q4 + j;
+                    acc += z[j] * (k < ws ? ys[cb + k + q * fcap] : T(0));
+                }
+                part[(q4 * 64 + lane) * nrhs + q] = acc;
+            }
+            __syncthreads();
+            if (tid < ws)
+                for (int q = 0; q < nrhs; ++q) {
+                    const T* pp = part + tid * nrhs + q;
+                    ys[cb + tid + q * fcap] = (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]);
+                }
+            __syncthreads();
+        } else if (tid < 64) {
+            // unit lower substitution on one wave: lane = row of the block
+            T lrow[64];
+#pragma unroll
+            for (int k = 0; k < 64; ++k)
+                lrow[k] = (k < lane && lane < ws) ? L[(cb + lane) + (int64_t)(cb + k) * f] : T(0);
+            for (int q = 0; q < nrhs; ++q) {
+                T val = lane < ws ? ys[cb + lane + q * fcap] : T(0);
+#pragma unroll
+                for (int k = 0; k < 63; ++k) val -= lrow[k] * bcast(val, k);
+                if (lane < ws) ys[cb + lane + q * fcap] = val;
+            }
+        }
+        __syncthreads();
+        // rows below the block: y_i -= L[i, cb : cb + ws] y_block
+        for (int i = cb + ws + tid; i < f; i += 256) {
+            for (int q = 0; q < nrhs; ++q) {
+                const T* yb = ys + cb + q * fcap;
+                T acc = T(0);
+                for (int k = 0; k < ws; ++k) acc += L[i + (int64_t)(cb + k) * f] * yb[k];
+                ys[i + q * fcap] -= acc;
+            }
+        }
+        __syncthreads();
+    }
+    for (int q = 0; q < nrhs; ++q)
+        for (int i = tid; i < f; i += 256) {
+            const T v = ys[i + q * fcap];
+            if (i < p) Y[first + i + q * N] = v;
+            else Us[(i - p) + (int64_t)q * c] = v;
+        }
+}
+
+// Backward sweep of one front: x of the rows below its pivots (already
+// final: they belong to ancestors) gathered from Y, then the pivot blocks from
+// the last: v = y / d - L[rows below the block, block]^T x, and the block's
+// transposed triangle (Z^T for large fronts, substitution otherwise).
+template <typename T>
+__device__ void front_backward(const DevPlan& d, int s, int fcap, const T* __restrict__ F,
+                               const T* __restrict__ Zbuf, const T* __restrict__ D, T* __restrict__ Y, int nrhs,
+                               T* xs, T* Ld, T* part) {
+    const int tid = threadIdx.x, lane = tid & 63, q4 = tid >> 6;
+    const int first = d.sn_first[s];
+    const int p = d.sn_first[s + 1] - first;
+    const int64_t rb = d.sn_rowptr[s];
+    const int f = (int)(d.sn_rowptr[s + 1] - rb);
+    const T* __restrict__ L = F + d.L_off[s];
+    const int* __restrict__ rows = d.sn_rows + rb;
+    const int64_t N = d.N;
+    for (int q = 0; q < nrhs; ++q)
+        for (int i = tid; i < f; i += 256) xs[i + q * fcap] = i < p ? Y[first + i + q * N] : Y[rows[i] + q * N];
+    __syncthreads();
+    for (int cb = ((p - 1) / kPanel) * kPanel; cb >= 0; cb -= kPanel) {
+        const int ws = min(kPanel, p - cb);
+        const int below = cb + ws;
+        // partial dot products: lane = column t of the block, wave q4 takes rows i = below + q4, +4, ...
+        for (int q = 0; q < nrhs; ++q) {
+            T acc = T(0);
+            if (lane < ws)
+                for (int i = below + q4; i < f; i += 4) acc += L[i + (int64_t)(cb + lane) * f] * xs[i + q * fcap];
+            part[(q4 * 64 + lane) * nrhs + q] = acc;
+        }
+        __syncthreads();
+        if (tid < ws)
+            for (int q = 0; q < nrhs; ++q) {
+                const T* pp = part + tid * nrhs + q;
+                const T sub = (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]);
+                xs[cb + tid + q * fcap] = xs[cb + tid + q * fcap] / D[first + cb + tid] - sub;
+            }
+        __syncthreads();
+        if (d.M_off[s] >= 0) {
+            // v <- Z^T v: wave q4 takes rows 16 q4 .. 16 q4 + 15 of Z, lane = output index
+            const T* __restrict__ Zb = Zbuf + d.M_off[s] + (int64_t)(cb / kPanel) * (kPanel * kPanel);
+            T z[16];
+#pragma unroll
+            for (int j = 0; j < 16; ++j) z[j] = Zb[lane * kPanel + 16 * q4 + j];   // Z[16 q4 + j][lane]
+            for (int q = 0; q < nrhs; ++q) {
+                T acc = T(0);
+#pragma unroll
+                for (int j = 0; j < 16; ++j) {
+                    const int k = 16 * q4 + j;
+                    acc += z[j] * (k < ws ? xs[cb + k + q * fcap] : T(0));
+                }
+                part[(q4 * 64 + lane) * nrhs + q] = acc;
+            }
+            __syncthreads();
+            if (tid < ws)
+                for (int q = 0; q < nrhs; ++q) {
+                    const T* pp = part + tid * nrhs + q;
+                    xs[cb + tid + q * fcap] = (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]);
+                }
+            __syncthreads();
+        } else if (tid < 64) {
+            // unit upper (L^T) substitution on one wave, from the last row up
+            T lcol[64];
+#pragma unroll
+            for (int k = 0; k < 64; ++k)
+                lcol[k] = (lane < k && k < ws) ? L[(cb + k) + (int64_t)(cb + lane) * f] : T(0);
+            for (int q = 0; q < nrhs; ++q) {
+                T val = lane < ws ? xs[cb + lane + q * fcap] : T(0);
+#pragma unroll
+                for (int k = 63; k > 0; --k) val -= lcol[k] * bcast(val, k);
+                if (lane < ws) xs[cb + lane + q * fcap] = val;
+            }
+        }
+        __syncthreads();
+    }
+    for (int q = 0; q < nrhs; ++q)
+        for (int t = tid; t < p; t += 256) Y[first + t + q * N] = xs[t + q * fcap];
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_persist_solve(DevPlan d, const int* __restrict__ order, int nsn,
+                                                       const int* __restrict__ sys_nfronts, int fcap, int* ctr,
+                                                       int* ticket, int* status, unsigned long long timeout,
+                                                       unsigned long long* tstamp,
+                                                       const T* __restrict__ F, const T* __restrict__ Zbuf,
+                                                       const T* __restrict__ D, T* __restrict__ Y,
+                                                       T* __restrict__ U, int nrhs) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* ys = reinterpret_cast<T*>(smem_raw);                 // fcap x nrhs
+    T* part = ys + (int64_t)fcap * nrhs;                    // 256 x nrhs
+    T* Ld = part + 256 * nrhs;                              // 64 x 65 (unused scratch)
+    __shared__ int s_t;
+    int* fwd_kids = ctr;             // children whose forward is done
+    int* fwd_done = ctr + nsn;       // forward done (read by the root's backward)
+    int* bwd_done = ctr + 2 * nsn;   // backward done (read by the children's backward)
+    int* sys_bwd = ctr + 3 * nsn;    // fronts of the system whose backward is done
+    for (;;) {
+        const int t = pers_ticket(ticket, &s_t);
+        if (t >= 2 * nsn) break;
+        if (t < nsn) {
+            const int s = order[t];
+            pers_wait(fwd_kids + s, d.child_ptr[s + 1] - d.child_ptr[s], status, timeout);
+            front_forward<T>(d, s, fcap, F, Zbuf, Y, U, nrhs, ys, Ld, part);
+            const int par = d.sn_parent[s];
+            pers_signal(par >= 0 ? fwd_kids + par : fwd_done + s);
+        } else {
+            const int s = order[2 * nsn - 1 - t];
+            const int par = d.sn_parent[s];
+            pers_wait(par >= 0 ? bwd_done + par : fwd_done + s, 1, status, timeout);
+            front_backward<T>(d, s, fcap, F, Zbuf, D, Y, nrhs, ys, Ld, part);
+            pers_signal(bwd_done + s);
+            if (threadIdx.x == 0) {
+                const int sys = d.sn_sys[s];
+                if (atomicAdd(sys_bwd + sys, 1) + 1 == sys_nfronts[sys]) tstamp[1 + d.S + sys] = wall_clock64();
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // refinement
 // ---------------------------------------------------------------------------
 // Block per chunk of rows (one system); eight lanes share a row.  R = B - K X
@@ -1956,6 +2280,25 @@ void launch_large_dstep(const DevPlan& d, const int* dtasks, int nd, const int* 
 
 
 template <typename T>
+void launch_persist_factor(const DevPlan& d, const int* order, int ntask, const int64_t* asm_rng, int fcap,
+                           int lds_elems, int grid, int* ctr, int* ticket, int* status, unsigned long long timeout,
+                           unsigned long long* tstamp, const double* K, T* F, T* D, T* M, hipStream_t st) {
+    if (ntask <= 0) return;
+    launch(k_persist_factor<T>, dim3(grid < ntask ? grid : ntask), dim3(256), (uint32_t)lds_elems * sizeof(T), st, d,
+           order, ntask, asm_rng, fcap, ctr, ticket, status, timeout, tstamp, K, F, D, M);
+}
+
+template <typename T>
+void launch_persist_solve(const DevPlan& d, const int* order, int nsn, const int* sys_nfronts, int fcap, int grid,
+                          int* ctr, int* ticket, int* status, unsigned long long timeout, unsigned long long* tstamp,
+                          const T* F, const T* Z, const T* D, T* Y, T* U, int nrhs, hipStream_t st) {
+    if (nsn <= 0) return;
+    const size_t lds = ((size_t)fcap * nrhs + 256 * (size_t)nrhs + 64 * 65) * sizeof(T);
+    launch(k_persist_solve<T>, dim3(grid < 2 * nsn ? grid : 2 * nsn), dim3(256), (uint32_t)lds, st, d, order, nsn,
+           sys_nfronts, fcap, ctr, ticket, status, timeout, tstamp, F, Z, D, Y, U, nrhs);
+}
+
+template <typename T>
 void launch_permute_in(const DevPlan& d, const double* B, int64_t ldb, int nrhs, T* Y, hipStream_t st) {
     launch(k_permute_in<T>, dim3(blocks_for(d.N, 256)), dim3(256), 0, st, d, B, ldb, nrhs, Y);
 }
@@ -2057,6 +2400,13 @@ void launch_adjoint(const DevPlan& d, int64_t nnzW, const int* W_row, const int*
         launch(k_grad_rho, dim3(d.S), dim3(256), 0, st, sys_jrow, nJrows, nrhs, JX, JL, gRho);
 }
 
+int persist_factor_static_lds(int fp32) {
+    hipFuncAttributes a{};
+    const void* k = fp32 ? (const void*)k_persist_factor<float> : (const void*)k_persist_factor<double>;
+    if (hipFuncGetAttributes(&a, k) != hipSuccess) return -1;
+    return (int)a.sharedSizeBytes;
+}
+
 // Allow the LDS-resident kernels to request more than 64 KiB of dynamic LDS
 // (gfx950 has 160 KiB per workgroup).
 hipError_t configure_kernels(int max_dynamic_lds) {
@@ -2069,7 +2419,9 @@ hipError_t configure_kernels(int max_dynamic_lds) {
                          (const void*)k_bwd_T<double>, (const void*)k_bwd_T<float>,
                          (const void*)k_fwd_S<double>, (const void*)k_fwd_S<float>,
                          (const void*)k_large_asm<double, true>, (const void*)k_large_asm<float, true>,
-                         (const void*)k_bwd_S<double>, (const void*)k_bwd_S<float>};
+                         (const void*)k_bwd_S<double>, (const void*)k_bwd_S<float>,
+                         (const void*)k_persist_factor<double>, (const void*)k_persist_factor<float>,
+                         (const void*)k_persist_solve<double>, (const void*)k_persist_solve<float>};
     for (const void* f : fns) {
         hipFuncAttributes at{};
         r = hipFuncGetAttributes(&at, f);
@@ -2087,6 +2439,12 @@ hipError_t configure_kernels(int max_dynamic_lds) {
     template void launch_large_diag<T>(const DevPlan&, const int*, int, T*, T*, T*, hipStream_t);                \
     template void launch_large_panel<T>(const DevPlan&, const int*, int, T*, const T*, const T*, hipStream_t);     \
     template void launch_large_dstep<T>(const DevPlan&, const int*, int, const int*, int, T*, T*, T*, hipStream_t); \
+    template void launch_persist_factor<T>(const DevPlan&, const int*, int, const int64_t*, int, int, int, int*, int*,  \
+                                           int*, unsigned long long, unsigned long long*, const double*, T*, T*, T*,  \
+                                           hipStream_t);                                                             \
+    template void launch_persist_solve<T>(const DevPlan&, const int*, int, const int*, int, int, int*, int*, int*,      \
+                                          unsigned long long, unsigned long long*, const T*, const T*, const T*, T*, T*, \
+                                          int, hipStream_t);                                                        \
     template void launch_permute_in<T>(const DevPlan&, const double*, int64_t, int, T*, hipStream_t);              \
     template void launch_permute_out<T>(const DevPlan&, const T*, int, double*, int64_t, hipStream_t);             \
     template void launch_fwd_T<T>(const DevPlan&, const int*, int, const T*, const T*, T*, T*, int, hipStream_t);           \

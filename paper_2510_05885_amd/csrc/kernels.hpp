@@ -26,6 +26,7 @@ struct DevPlan {
     int64_t n_primal;          // rows [0, n_primal) form the primal block (N for the condensed form)
     int S;
     int form;
+    int n_fronts;              // supernodes (fronts)
     // full CSR of K with value sources
     const int64_t* Kp;
     const int* Kj;
@@ -46,6 +47,7 @@ struct DevPlan {
     const int* child_ptr;
     const int* child_list;
     const int* sn_sys;
+    const int* sn_parent;      // parent supernode or -1
     const int64_t* kent_ptr;
     const int64_t* kent_csr;
     const int* kent_pos;
@@ -120,6 +122,30 @@ template <typename T>
 void launch_large_dstep(const DevPlan& d, const int* dtasks, int nd, const int* utasks, int nu, T* F, T* D, T* M,
                         hipStream_t st);
 
+// ---- persistent launches (batched systems) ----------------------------------
+// One launch factors every front: workgroups take fronts from *ticket in
+// topological order, wait until the front's children are done, factor the
+// whole front themselves and signal the parent.  ctr holds nsn child-done
+// counters; ctr and *ticket start at zero (the ticket on a cache line of its
+// own).  A wait gives up after `timeout` wall_clock64 ticks and sets bit 1 of
+// *status (the results are then invalid, but the launch ends).  tstamp[0] =
+// launch start, tstamp[1 + sys] = completion of the system's last root front.
+// asm_rng: per large front (first column task, count); lds_elems: dynamic LDS
+// per workgroup (elements of T) >= max(small front f^2, 4 x largest large front).
+template <typename T>
+void launch_persist_factor(const DevPlan& d, const int* order, int ntask, const int64_t* asm_rng, int fcap,
+                           int lds_elems, int grid, int* ctr, int* ticket, int* status, unsigned long long timeout,
+                           unsigned long long* tstamp, const double* K, T* F, T* D, T* M, hipStream_t st);
+// One launch for both sweeps: tickets [0, nsn) forward in topological order,
+// [nsn, 2 nsn) backward in reverse.  ctr: 3 nsn + S ints (children forward
+// done, forward done, backward done, per-system backward count), zero like
+// *ticket.  tstamp[1 + S + sys] = completion of the system's backward sweep.
+// fcap >= every front order; LDS = fcap x nrhs + 64 x 65 + 256 x nrhs of T.
+template <typename T>
+void launch_persist_solve(const DevPlan& d, const int* order, int nsn, const int* sys_nfronts, int fcap, int grid,
+                          int* ctr, int* ticket, int* status, unsigned long long timeout, unsigned long long* tstamp,
+                          const T* F, const T* Z, const T* D, T* Y, T* U, int nrhs, hipStream_t st);
+
 // ---- solves -----------------------------------------------------------------
 template <typename T>
 void launch_permute_in(const DevPlan& d, const double* B, int64_t ldb, int nrhs, T* Y, hipStream_t st);
@@ -157,6 +183,8 @@ void launch_reduce_inertia(const DevPlan& d, int S, hipStream_t st);   // inerti
 
 // Raises the dynamic-LDS limit of the LDS-resident kernels to the device maximum.
 hipError_t configure_kernels(int max_dynamic_lds);
+// Static LDS bytes of the persistent factorization kernel (FP64 or FP32), -1 on error.
+int persist_factor_static_lds(int fp32);
 
 // ---- adjoint (condensed) ----------------------------------------------------
 void launch_adjoint(const DevPlan& d, int64_t nnzW, const int* W_row, const int* W_col, int64_t nJrows,

@@ -142,6 +142,13 @@ struct Plan {
     std::vector<int> large_panel;    // triples (front, k0, 32-row block start >= k0 + panel)
     std::vector<int> large_upd;      // quads (front, k0, tile row start, tile col start); the next
                                      // panel's diagonal tile is left to large_diag
+    // persistent launches: fronts in topological order (level, then larger
+    // first), per large front its column-assembly tasks (first, count) in
+    // large_asm / asm_*, fronts per system, largest orders
+    std::vector<int> pers_order;
+    std::vector<int64_t> pers_asm;   // 2 per supernode (0, 0 for small fronts)
+    std::vector<int> sys_nfronts;
+    int pers_fmax_large = 0, pers_fmax_small = 0, pers_fmax = 0;
     // solve schedule
     std::vector<SolveStep> solve_steps;
     std::vector<int> solve_t;        // (front, c0, fused, g_first, g_count)

@@ -31,7 +31,7 @@ EXPORTED = [
     "ncl_kkt_default_options", "ncl_kkt_analyze", "ncl_kkt_analyze_host", "ncl_kkt_analyze_batched",
     "ncl_kkt_factor", "ncl_kkt_factor_batched", "ncl_kkt_solve", "ncl_kkt_inertia",
     "ncl_kkt_inertia_batched", "ncl_kkt_backward", "ncl_kkt_backward_noalloc", "ncl_kkt_get_stats", "ncl_kkt_get_perm",
-    "ncl_kkt_get_supernodes", "ncl_kkt_set_timing", "ncl_kkt_get_timing",
+    "ncl_kkt_get_supernodes", "ncl_kkt_get_system_times", "ncl_kkt_set_timing", "ncl_kkt_get_timing",
     "ncl_kkt_destroy", "ncl_kkt_strerror",
 ]
 
@@ -41,7 +41,8 @@ class Options(C.Structure):
                 ("ir_max_steps", C.c_int32), ("ir_tol", C.c_double), ("ir_stall", C.c_double),
                 ("ordering", C.c_int32), ("user_perm", C.POINTER(C.c_int32)), ("use_graphs", C.c_int32),
                 ("small_front_max", C.c_int32), ("relax_big_zeros", C.c_double), ("fp32_sticky", C.c_int32),
-                ("pivot_scale", C.c_int32), ("ir_cw_tol", C.c_double)]
+                ("pivot_scale", C.c_int32), ("ir_cw_tol", C.c_double), ("persistent", C.c_int32),
+                ("persistent_grid", C.c_int32)]
 
 
 class SolveInfo(C.Structure):
@@ -120,6 +121,8 @@ def lib():
     L.ncl_kkt_get_perm.restype = C.c_int
     L.ncl_kkt_get_supernodes.argtypes = [vp, pi32, pi32, C.POINTER(C.c_int64), pi32]
     L.ncl_kkt_get_supernodes.restype = C.c_int
+    L.ncl_kkt_get_system_times.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_double)]
+    L.ncl_kkt_get_system_times.restype = C.c_int
     L.ncl_kkt_set_timing.argtypes = [vp, i32]
     L.ncl_kkt_set_timing.restype = C.c_int
     L.ncl_kkt_get_timing.argtypes = [vp, C.POINTER(Timing)]
@@ -205,7 +208,8 @@ _PIVS = {"global": NCL_PIVOT_GLOBAL, "block": NCL_PIVOT_BLOCK, "absolute": NCL_P
 
 def make_options(form="condensed", precision="fp64", pivot_eps=0.0, ir_max_steps=10, ir_tol=1e-12,
                  ir_stall=0.5, ordering="nd", user_perm=None, use_graphs=True, small_front_max=0,
-                 relax_big_zeros=-1.0, fp32_sticky=True, pivot_scale="global", ir_cw_tol=0.0):
+                 relax_big_zeros=-1.0, fp32_sticky=True, pivot_scale="global", ir_cw_tol=0.0, persistent=-1,
+                 persistent_grid=0):
     o = Options()
     lib().ncl_kkt_default_options(C.byref(o))
     o.form = _FORMS[form] if isinstance(form, str) else int(form)
@@ -220,6 +224,8 @@ def make_options(form="condensed", precision="fp64", pivot_eps=0.0, ir_max_steps
     o.fp32_sticky = 1 if fp32_sticky else 0
     o.pivot_scale = _PIVS[pivot_scale] if isinstance(pivot_scale, str) else int(pivot_scale)
     o.ir_cw_tol = float(ir_cw_tol)
+    o.persistent = int(persistent)
+    o.persistent_grid = int(persistent_grid)
     keep = None
     if user_perm is not None:
         keep, p = _i32(user_perm)
@@ -395,6 +401,16 @@ class KKT:
         rows = np.zeros(max(int(rp[-1]), 1), np.int32)
         _check(lib().ncl_kkt_get_supernodes(self._h, None, None, None, rows.ctypes.data_as(P32)), "supernodes")
         return first, parent, rp, rows[:int(rp[-1])]
+
+    def system_times(self):
+        """(factor_ms, solve_ms) per system of the last persistent factor + solve,
+        in ms from the start of the factor launch."""
+        f = np.zeros(self.S)
+        sv = np.zeros(self.S)
+        P = C.POINTER(C.c_double)
+        _check(lib().ncl_kkt_get_system_times(self._h, f.ctypes.data_as(P), sv.ctypes.data_as(P)),
+               "ncl_kkt_get_system_times")
+        return f, sv
 
     def set_timing(self, on=True):
         _check(lib().ncl_kkt_set_timing(self._h, 1 if on else 0), "ncl_kkt_set_timing")

@@ -116,6 +116,48 @@ def test_batched_equals_one_at_a_time():
         off += i.n
 
 
+@pytest.mark.timeout(900)
+def test_batched_workload_256_systems():
+    """The batched workload at its stated size: 256 OPF-shaped systems of
+    125..5000 nodes (n 625..25k, log-uniform), per-system rho and Sigma, in
+    one handle.  Every system: inertia (n, 0, 0) and backward error against
+    its own K on the CPU; 16 of them (the largest, the smallest and 14 spread
+    between) against the oracle's solution."""
+    print("[gpu] 256-system batch", flush=True)
+    sizes = synth.batched_sizes(256)
+    inps = [synth.batched_system(k, int(N)) for k, N in enumerate(sizes)]
+    kkt = nk.KKT.analyze_batched(inps, ir_tol=1e-10, ir_cw_tol=1e-14)
+    B = [synth.rhs(i.n, 1, seed=k) for k, i in enumerate(inps)]
+    rc = kkt.factor(dev(np.concatenate([i.W_val for i in inps])), dev(np.concatenate([i.Sigma for i in inps])),
+                    dev(np.concatenate([i.J_val for i in inps])), np.array([i.rho for i in inps]))
+    X, info = kkt.solve(colmajor(np.vstack(B)))
+    X = X.cpu().numpy()
+    print(f"[gpu]   rc={rc} omega={info.backward_error:.2e} cw={info.backward_error_cw:.2e} "
+          f"ir_steps={info.ir_steps}", flush=True)
+    assert rc == 0 and info.backward_error_cw <= 1e-14
+    inert = kkt.inertia_batched()
+    order = np.argsort([i.n for i in inps])
+    sample = set(order[np.linspace(0, len(order) - 1, 16).astype(int)].tolist())
+    off = 0
+    worst_cw = worst_fwd = 0.0
+    for k, i in enumerate(inps):
+        Xk = X[off:off + i.n]
+        off += i.n
+        assert tuple(inert[k][:3]) == (i.n, 0, 0), k
+        K = O.assemble(i, O.CONDENSED)
+        worst_cw = max(worst_cw, float(O.componentwise_backward_error(K, Xk, B[k]).max()))
+        if k % 64 == 63:
+            print(f"[gpu]   checked {k + 1} systems", flush=True)
+        if k in sample:
+            Xo, io, _, _ = O.solve(i, O.CONDENSED, B[k], ir_cw_tol=1e-14, K=K)
+            assert io.inertia[:3] == (i.n, 0, 0)
+            worst_fwd = max(worst_fwd, float(np.abs(Xk - Xo).max() / np.abs(Xo).max()))
+    print(f"[gpu]   max cw backward error {worst_cw:.2e}; max forward error vs oracle (16 systems) "
+          f"{worst_fwd:.2e}", flush=True)
+    assert worst_cw <= 2e-14
+    assert worst_fwd <= 1e-6
+
+
 def test_adjoint_matches_oracle_gradient():
     """Reverse mode of x = K(W, Sigma, J, rho)^-1 b through torch.autograd
     (config-5 shape, reduced): gradients w.r.t. b and every stored W, Sigma,

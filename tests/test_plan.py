@@ -132,6 +132,9 @@ def test_argument_errors():
     with pytest.raises(nk.NCLError) as e:
         nk.KKT.from_input(inp, host_only=True, user_perm=np.zeros(inp.n, np.int32))
     assert e.value.code == -1
+    with pytest.raises(nk.NCLError) as e:   # the persistent launches are disabled
+        nk.KKT.from_input(inp, host_only=True, persistent=1)
+    assert e.value.code == -1
     k = nk.KKT.from_input(inp, host_only=True)
     with pytest.raises(nk.NCLError) as e:
         k.inertia()
