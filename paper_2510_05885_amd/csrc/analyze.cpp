@@ -818,7 +818,17 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
         }
         // ---------------- solve schedule -----------------------------------
         {
-            const int PW = cfg.solve_panel, FUSE = cfg.solve_fuse_rows, GR = cfg.solve_chunk_rows;
+            const int PW = 64, GR = 64;   // kPanel, kSolveRows
+            // entries [a0, a1) of child ch's update vector landing in parent rows [lo, hi)
+            auto child_range = [&](int ch, int lo, int hi, int& a0, int& a1) {
+                const int* r = P.rel.data() + P.rel_ptr[ch];
+                const int cc = (int)(P.rel_ptr[ch + 1] - P.rel_ptr[ch]);
+                a0 = (int)(std::lower_bound(r, r + cc, lo) - r);
+                a1 = (int)(std::lower_bound(r, r + cc, hi) - r);
+            };
+            for (int s = 0; s < nsn; ++s)
+                for (int64_t q = P.rel_ptr[s] + 1; q < P.rel_ptr[s + 1]; ++q)
+                    if (P.rel[q] <= P.rel[q - 1]) throw AnalyzeError(-4, "internal: update-vector map not increasing");
             for (int l = 0; l < P.nlevels; ++l) {
                 int maxj = 0;
                 for (int k = P.level_ptr[l]; k < P.level_ptr[l + 1]; ++k) {
@@ -829,8 +839,7 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                 for (int j = 0; j < maxj; ++j) {
                     SolveStep st;
                     st.level = l; st.j = j;
-                    st.t_first = (int64_t)P.solve_t.size() / 5;
-                    st.g_first = (int64_t)P.solve_g.size() / 5;
+                    st.p_first = (int64_t)P.solve_p.size() / 6;
                     st.s_first = (int64_t)P.solve_s.size();
                     int slot = 0;
                     for (int k = P.level_ptr[l]; k < P.level_ptr[l + 1]; ++k) {
@@ -841,26 +850,39 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                         if (c0 >= p) continue;
                         const int w = std::min(PW, p - c0);
                         const int below = f - c0 - w;
+                        st.fwd_bytes += 8.0 * ((double)w * (w + 1) / 2.0 + (double)below * w) * P.sn_nnz_ratio[s];
                         if (!P.sn_large[s] && p <= 64 && f <= 128) {
                             P.solve_s.push_back(s);
-                            st.fwd_bytes += 8.0 * ((double)w * (w + 1) / 2.0 + (double)below * w) * P.sn_nnz_ratio[s];
                             continue;
                         }
-                        const bool fused = below <= FUSE;
-                        const int gfirst = slot;
-                        if (!fused) {
-                            for (int r0 = c0 + w; r0 < f; r0 += GR) {
-                                P.solve_g.push_back(s); P.solve_g.push_back(c0); P.solve_g.push_back(r0);
-                                P.solve_g.push_back(std::min(f, r0 + GR)); P.solve_g.push_back(slot++);
+                        const int pid = (int)(P.solve_pan.size() / 7);
+                        const int ntask = std::max(1, (below + GR - 1) / GR);
+                        const int seg0 = (int)(P.solve_seg.size() / 3);
+                        if (c0 == 0)
+                            for (int q = P.child_ptr[s]; q < P.child_ptr[s + 1]; ++q) {
+                                int a0, a1;
+                                child_range(P.child_list[q], 0, w, a0, a1);
+                                if (a1 > a0) { P.solve_seg.push_back(P.child_list[q]); P.solve_seg.push_back(a0); P.solve_seg.push_back(a1); }
                             }
+                        const int nseg = (int)(P.solve_seg.size() / 3) - seg0;
+                        for (int v : {s, c0, w, slot, ntask, seg0, nseg}) P.solve_pan.push_back(v);
+                        for (int t = 0; t < ntask; ++t) {
+                            const int r0 = below > 0 ? c0 + w + t * GR : f;
+                            const int r1 = below > 0 ? std::min(f, r0 + GR) : f;
+                            const int tseg0 = (int)(P.solve_seg.size() / 3);
+                            if (c0 == 0 && r1 > r0)
+                                for (int q = P.child_ptr[s]; q < P.child_ptr[s + 1]; ++q) {
+                                    int a0, a1;
+                                    child_range(P.child_list[q], r0, r1, a0, a1);
+                                    if (a1 > a0) { P.solve_seg.push_back(P.child_list[q]); P.solve_seg.push_back(a0); P.solve_seg.push_back(a1); }
+                                }
+                            const int tnseg = (int)(P.solve_seg.size() / 3) - tseg0;
+                            for (int v : {pid, r0, r1, t, tseg0, tnseg}) P.solve_p.push_back(v);
                         }
-                        P.solve_t.push_back(s); P.solve_t.push_back(c0); P.solve_t.push_back(fused ? 1 : 0);
-                        P.solve_t.push_back(gfirst); P.solve_t.push_back(slot - gfirst);
-                        st.fwd_bytes += 8.0 * ((double)w * (w + 1) / 2.0 + (double)below * w) * P.sn_nnz_ratio[s];
+                        slot += ntask;
                     }
-                    st.t_count = (int64_t)P.solve_t.size() / 5 - st.t_first;
+                    st.p_count = (int64_t)P.solve_p.size() / 6 - st.p_first;
                     st.s_count = (int64_t)P.solve_s.size() - st.s_first;
-                    st.g_count = (int64_t)P.solve_g.size() / 5 - st.g_first;
                     P.solve_max_slots = std::max<int64_t>(P.solve_max_slots, slot);
                     P.solve_steps.push_back(st);
                 }

@@ -101,7 +101,8 @@ struct ncl_kkt_s {
     int64_t nnzF = 0;
     // schedule arrays (device)
     int *small_list = nullptr, *level_list = nullptr, *large_asm = nullptr, *large_panel = nullptr,
-        *large_upd = nullptr, *large_diag = nullptr, *solve_t = nullptr, *solve_g = nullptr, *solve_s = nullptr;
+        *large_upd = nullptr, *large_diag = nullptr, *solve_pan = nullptr, *solve_p = nullptr, *solve_seg = nullptr, *solve_s = nullptr,
+        *solve_cnt = nullptr;
     int *chunk_row0 = nullptr, *chunk_rows = nullptr, *sys_chunk_ptr = nullptr;
     int nchunks = 0;
     // numeric state
@@ -274,8 +275,13 @@ void setup_device(ncl_kkt_s* h) {
     h->level_list = upload(h, P.level_list);
     h->large_asm = upload(h, P.large_asm);
     h->large_diag = upload(h, P.large_diag);
-    h->solve_t = upload(h, P.solve_t);
-    h->solve_g = upload(h, P.solve_g);
+    h->solve_pan = upload(h, P.solve_pan);
+    h->solve_p = upload(h, P.solve_p);
+    h->solve_seg = upload(h, P.solve_seg);
+    // per-panel arrival counters of the backward sweep: zero here, and every
+    // panel's last task sets its counter back to zero
+    h->solve_cnt = dalloc<int>(h, std::max<int64_t>((int64_t)P.solve_pan.size() / kPanInts, 1));
+    HIPCHK(hipMemset(h->solve_cnt, 0, sizeof(int) * std::max<size_t>(P.solve_pan.size() / kPanInts, 1)));
     h->solve_s = upload(h, P.solve_s);
     h->large_panel = upload(h, P.large_panel);
     h->large_upd = upload(h, P.large_upd);
@@ -310,16 +316,16 @@ void setup_device(ncl_kkt_s* h) {
     h->F64 = dalloc<double>(h, P.factor_elems);
     h->D64 = dalloc<double>(h, P.N);
     h->M64 = dalloc<double>(h, P.M_elems);
-    h->Y64 = dalloc<double>(h, P.N * kNrhsMax);
+    h->Y64 = dalloc<double>(h, 2 * P.N * kNrhsMax);   // right-hand side, then the pivots' y / x
     h->U64 = dalloc<double>(h, P.U_elems * kNrhsMax);
-    h->P64 = dalloc<double>(h, std::max<int64_t>(P.solve_max_slots, 1) * kSolvePanel * kNrhsMax);
+    h->P64 = dalloc<double>(h, std::max<int64_t>(P.solve_max_slots, 1) * kPanel * kNrhsMax);
     if (h->opt.precision == NCL_FP32_IR) {
         h->F32 = dalloc<float>(h, P.factor_elems);
         h->D32 = dalloc<float>(h, P.N);
         h->M32 = dalloc<float>(h, P.M_elems);
-        h->Y32 = dalloc<float>(h, P.N * kNrhsMax);
+        h->Y32 = dalloc<float>(h, 2 * P.N * kNrhsMax);
         h->U32 = dalloc<float>(h, P.U_elems * kNrhsMax);
-        h->P32 = dalloc<float>(h, std::max<int64_t>(P.solve_max_slots, 1) * kSolvePanel * kNrhsMax);
+        h->P32 = dalloc<float>(h, std::max<int64_t>(P.solve_max_slots, 1) * kPanel * kNrhsMax);
     }
     h->R = dalloc<double>(h, P.N * kNrhsMax);
     h->DX = dalloc<double>(h, P.N * kNrhsMax);
@@ -755,29 +761,30 @@ void sweeps(ncl_kkt_s* h, int nrhs, const T* F, const T* Z, const T* D, T* Y, T*
         launch_zero_i32(h->pers_ctr, h->pers_ctr_len, st);
         Span sp(h, st, TM_SOLVE, 0.0, 0);
         launch_persist_solve<T>(d, h->pers_order, P.nsn, h->sys_nfronts, std::max(P.pers_fmax, 1), h->pers_grid_s,
-                                h->pers_ctr, h->pers_ticket, h->pers_status, h->pers_timeout, h->tstamp, F, Z, D, Y, U,
-                                nrhs, st);
+                                h->pers_ctr, h->pers_ticket, h->pers_status, h->pers_timeout, h->tstamp, F, Z, D, Y,
+                                Y + P.N * kNrhsMax, U, nrhs, st);
         return;
     }
+    T* Y2 = Y + P.N * kNrhsMax;
     const std::vector<SolveStep>& S = P.solve_steps;
-    // Steps of one level are independent between small fronts (one wave each)
-    // and large fronts (panel chain): when a level has both, the small ones go
-    // to the second stream, forked at the level's first step and joined after
-    // its last.
+    // Steps of one level are independent between the one-wave fronts and the
+    // panel tasks: when a level has both, the one-wave fronts go to the second
+    // stream, forked at the level's first step and joined after its last.
     auto level_end = [&](size_t i) {
         size_t e = i;
         while (e < S.size() && S[e].level == S[i].level) ++e;
         return e;
     };
-    auto has_large = [&](size_t i0, size_t i1) {
+    auto has_panels = [&](size_t i0, size_t i1) {
         for (size_t i = i0; i < i1; ++i)
-            if (S[i].t_count > 0 || S[i].g_count > 0) return true;
+            if (S[i].p_count > 0) return true;
         return false;
     };
+    const int* pan = h->solve_pan;
     for (size_t i0 = 0; i0 < S.size();) {
         const size_t i1 = level_end(i0);
         const int l = S[i0].level;
-        const bool fork = S[i0].s_count > 0 && has_large(i0, i1);
+        const bool fork = S[i0].s_count > 0 && has_panels(i0, i1);
         hipStream_t ss = fork ? h->aux_stream : st;
         if (fork) {
             HIPCHK(hipEventRecord(h->lvl_ev[2 * l], st));
@@ -787,11 +794,13 @@ void sweeps(ncl_kkt_s* h, int nrhs, const T* F, const T* Z, const T* D, T* Y, T*
             const SolveStep& ss_ = S[i];
             if (ss_.s_count > 0) {
                 Span sp(h, ss, TM_SOLVE, 0.0, 0);
-                launch_fwd_S<T>(d, h->solve_s + ss_.s_first, (int)ss_.s_count, F, Y, U, nrhs, ss);
+                launch_fwd_S<T>(d, h->solve_s + ss_.s_first, (int)ss_.s_count, F, Y, Y2, U, nrhs, ss);
             }
-            Span sp(h, st, TM_SOLVE, ss_.fwd_bytes * sizeof(T) / 8.0, 4);
-            launch_fwd_T<T>(d, h->solve_t + 5 * ss_.t_first, (int)ss_.t_count, F, Z, Y, U, nrhs, st);
-            launch_fwd_G<T>(d, h->solve_g + 5 * ss_.g_first, (int)ss_.g_count, F, Y, U, nrhs, st);
+            if (ss_.p_count > 0) {
+                Span sp(h, st, TM_SOLVE, ss_.fwd_bytes * sizeof(T) / 8.0, 4);
+                launch_fwd_P<T>(d, pan, h->solve_p + kPTaskInts * ss_.p_first, (int)ss_.p_count, h->solve_seg, F, Z, Y,
+                                Y2, U, nrhs, st);
+            }
         }
         if (fork) {
             HIPCHK(hipEventRecord(h->lvl_ev[2 * l + 1], ss));
@@ -805,7 +814,7 @@ void sweeps(ncl_kkt_s* h, int nrhs, const T* F, const T* Z, const T* D, T* Y, T*
     for (auto it = starts.rbegin(); it != starts.rend(); ++it) {
         const size_t i0 = *it, i1 = level_end(i0);
         const int l = S[i0].level;
-        const bool fork = S[i0].s_count > 0 && has_large(i0, i1);
+        const bool fork = S[i0].s_count > 0 && has_panels(i0, i1);
         hipStream_t ss = fork ? h->aux_stream : st;
         if (fork) {
             HIPCHK(hipEventRecord(h->lvl_ev[2 * l], st));
@@ -813,14 +822,14 @@ void sweeps(ncl_kkt_s* h, int nrhs, const T* F, const T* Z, const T* D, T* Y, T*
         }
         for (size_t i = i1; i-- > i0;) {
             const SolveStep& ss_ = S[i];
-            {
+            if (ss_.p_count > 0) {
                 Span sp(h, st, TM_SOLVE, ss_.fwd_bytes * sizeof(T) / 8.0, 4);
-                launch_bwd_G<T>(d, h->solve_g + 5 * ss_.g_first, (int)ss_.g_count, F, Y, partial, nrhs, st);
-                launch_bwd_T<T>(d, h->solve_t + 5 * ss_.t_first, (int)ss_.t_count, F, Z, D, Y, partial, nrhs, st);
+                launch_bwd_P<T>(d, pan, h->solve_p + kPTaskInts * ss_.p_first, (int)ss_.p_count, F, Z, D, Y2, partial,
+                                h->solve_cnt, nrhs, st);
             }
             if (ss_.s_count > 0) {
                 Span sp(h, ss, TM_SOLVE, 0.0, 0);
-                launch_bwd_S<T>(d, h->solve_s + ss_.s_first, (int)ss_.s_count, F, D, Y, nrhs, ss);
+                launch_bwd_S<T>(d, h->solve_s + ss_.s_first, (int)ss_.s_count, F, D, Y2, nrhs, ss);
             }
         }
         if (fork) {
@@ -851,7 +860,7 @@ void solve_once(ncl_kkt_s* h, const double* B, int64_t ldb, double* X, int64_t l
         }
         HIPCHK(hipGraphLaunch(ge, st));
     }
-    launch_permute_out<T>(d, Y, nrhs, X, ldx, st);
+    launch_permute_out<T>(d, Y + h->P.N * kNrhsMax, nrhs, X, ldx, st);
 }
 
 void solve_with_factor(ncl_kkt_s* h, const double* B, int64_t ldb, double* X, int64_t ldx, int nrhs, hipStream_t st) {

@@ -1131,15 +1131,27 @@ __global__ void k_permute_out(DevPlan d, const T* __restrict__ Y, int nrhs, doub
     for (int q = 0; q < nrhs; ++q) X[dst + q * ldx] = to_d(Y[k + q * d.N]);
 }
 
-// ---- panel-based sweeps ----------------------------------------------------
-// Task layouts: T = (front, c0, fused, g_first, g_count), G = (front, c0, r0, r1, slot).
-// Panel = pivot columns [c0, c0 + w), w <= kSolvePanel, of front s, taken in
-// 64-column sub-blocks.  For a large front the sub-block's triangle is applied
-// through its inverse Z = L_kk^-1 published by the factorization (a GEMV, no
-// dependent chain), and L^T is read from the front's upper triangle; a small
-// front solves the sub-block by substitution (one wave, readlane broadcasts).
-// Dot products load 64 operands per thread at a time (memory-level
-// parallelism); vectors in LDS are zero beyond their length.
+// ---- sweeps of the fronts outside the one-wave path ----------------------
+// One launch per panel step of a level.  Panel = pivot columns [c0, c0 + w),
+// w <= kPanel, of front s.  Its triangle is applied through the inverse
+// Z = L_kk^-1 that the factorization published (a GEMV, no dependent chain)
+// for large fronts, by one-wave substitution otherwise.  The rows below the
+// panel are split into tasks of kSolveRows rows, one workgroup each:
+//   forward: every task recomputes y = Z b of its panel (b = the pivots' right-
+//     hand side, plus the children's update vectors at the first panel),
+//     subtracts L[rows, panel] y from its own rows and writes them back; task 0
+//     also stores y.  No task reads what another task of the launch writes: the
+//     pivots' results go to a second vector Y2 (y after the forward sweep, x
+//     after the backward one), the right-hand side stays in Y.
+//   backward: every task forms the partial sums L[rows, panel]^T x of its rows
+//     (x of rows below the panel is final) and the last task of the panel to
+//     finish (one agent-scope counter per panel; nothing waits on it) adds the
+//     panel's partial sums in task order, forms v = y / d - sum and x = Z^T v.
+// Panel table (kPanInts ints): s, c0, w, first partial slot, tasks, first and
+// count of the pivot rows' contribution segments.  Task (kPTaskInts ints):
+// panel, rows [r0, r1) (r0 == r1 = f for a panel with nothing below), index
+// within the panel, first and count of its rows' segments.  Segment (3 ints):
+// child, entries [a0, a1) of its update vector that land in the rows.
 
 // acc[q] += sum_{k < n} M[row + (col0 + k) * f] v[k + q * ldv], q < nrhs,
 // in chunks of kDotChunk operands loaded before use.
@@ -1173,9 +1185,11 @@ __device__ __forceinline__ void row_dot(const T* __restrict__ M, int64_t f, int 
 }
 
 // Small fronts: the sub-block's unit lower triangle staged in Ld (64 x 65),
-// then one wave substitutes (forward: rows; backward: transposed).
+// then one wave substitutes (forward: rows; backward: transposed); v has
+// leading dimension vld.
 template <typename T, bool kBackward>
-__device__ __forceinline__ void chain_solve64(const T* __restrict__ L, int f, int c, int ws, T* Ld, T* v, int nrhs) {
+__device__ __forceinline__ void chain_solve64(const T* __restrict__ L, int f, int c, int ws, T* Ld, T* v, int vld,
+                                              int nrhs) {
     const int tid = threadIdx.x, lane = tid & 63;
     {
         T lv[16];   // all loads first, then the LDS stores
@@ -1201,7 +1215,7 @@ __device__ __forceinline__ void chain_solve64(const T* __restrict__ L, int f, in
             for (int k = 0; k < 64; ++k) lrow[k] = (lane < k && k < ws) ? Ld[k * 65 + lane] : T(0);
         }
         for (int q = 0; q < nrhs; ++q) {
-            T val = lane < ws ? v[lane + q * kSolvePanel] : T(0);
+            T val = lane < ws ? v[lane + q * vld] : T(0);
             if (!kBackward) {
 #pragma unroll
                 for (int k = 0; k < 63; ++k) val -= lrow[k] * bcast(val, k);
@@ -1209,330 +1223,282 @@ __device__ __forceinline__ void chain_solve64(const T* __restrict__ L, int f, in
 #pragma unroll
                 for (int k = 63; k > 0; --k) val -= lrow[k] * bcast(val, k);
             }
-            if (lane < ws) v[lane + q * kSolvePanel] = val;
+            if (lane < ws) v[lane + q * vld] = val;
         }
     }
     __syncthreads();
 }
 
-// Large fronts: v[0:64) <- Z v (forward) or Z^T v (backward) for one 64-block,
-// the 4 waves splitting the contraction; Zs (64 x 65 LDS) stages Z for the
-// transposed product; part holds 4 x 64 x nrhs partial sums.
-template <typename T, bool kBackward>
-__device__ __forceinline__ void zmul64(const T* __restrict__ Zb, int ws, T* Zs, T* part, T* v, int nrhs) {
-    const int tid = threadIdx.x, lane = tid & 63, q4 = tid >> 6;
-    T z[16];
-    if (!kBackward) {
-#pragma unroll
-        for (int j = 0; j < 16; ++j) z[j] = Zb[(16 * q4 + j) * kPanel + lane];   // Z[lane][16 q4 + j]
-    } else {
-        T zv[kPanel * kPanel / 256];
-#pragma unroll
-        for (int it = 0; it < kPanel * kPanel / 256; ++it) zv[it] = Zb[tid + 256 * it];
-#pragma unroll
-        for (int it = 0; it < kPanel * kPanel / 256; ++it) {
-            const int idx = tid + 256 * it;
-            Zs[(idx & 63) + (idx >> 6) * 65] = zv[it];
-        }
+// dst[r - base] += the children's update-vector entries of segments
+// [g0, g0 + gn), one child after the other (two children may add to one row).
+template <typename T>
+__device__ __forceinline__ void add_segments(const DevPlan& d, const T* __restrict__ U, const int* __restrict__ segs,
+                                             int g0, int gn, int base, T* dst, int ld, int nrhs) {
+    for (int g = g0; g < g0 + gn; ++g) {
+        const int ch = segs[3 * g], a0 = segs[3 * g + 1], a1 = segs[3 * g + 2];
+        const int cc = (int)(d.sn_rowptr[ch + 1] - d.sn_rowptr[ch]) - (d.sn_first[ch + 1] - d.sn_first[ch]);
+        const T* __restrict__ Uc = U + d.U_off[ch];
+        const int* __restrict__ r = d.rel + d.rel_ptr[ch];
+        for (int q = 0; q < nrhs; ++q)
+            for (int a = a0 + (int)threadIdx.x; a < a1; a += 256) dst[r[a] - base + q * ld] += Uc[a + (int64_t)q * cc];
         __syncthreads();
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_fwd_P(DevPlan d, const int* __restrict__ ptab, const int* __restrict__ tasks,
+                                               const int* __restrict__ segs, const T* __restrict__ F,
+                                               const T* __restrict__ Zbuf, T* __restrict__ Y, T* __restrict__ Y2,
+                                               T* __restrict__ U, int nrhs) {
+    extern __shared__ __align__(16) unsigned char smem_raw[];
+    T* v = reinterpret_cast<T*>(smem_raw);        // kPanel x nrhs: b of the pivots, then y
+    T* rw = v + kPanel * nrhs;                    // kSolveRows x nrhs: the task's rows
+    T* part = rw + kSolveRows * nrhs;             // 256 x nrhs
+    T* Ld = part + 256 * nrhs;                    // 64 x 65
+    const int* tk = tasks + kPTaskInts * blockIdx.x;
+    const int* pt = ptab + kPanInts * tk[0];
+    const int s = pt[0], c0 = pt[1], w = pt[2];
+    const int r0 = tk[1], nr = tk[2] - tk[1], chunk = tk[3];
+    const int first = d.sn_first[s];
+    const int p = d.sn_first[s + 1] - first;
+    const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
+    const int c = f - p;
+    const T* __restrict__ L = F + d.L_off[s];
+    T* __restrict__ Us = U + d.U_off[s];
+    const int tid = threadIdx.x, lane = tid & 63, q4 = tid >> 6;
+    const int64_t N = d.N;
+    const bool large = d.M_off[s] >= 0;
+    const int k0 = 16 * q4;
+    // Operands that depend on nothing computed here are loaded first, so
+    // their latency overlaps the right-hand side's: Z[lane][k0 + j] (large
+    // fronts) and this thread's row of L[rows, panel] (lane = row, wave q4 =
+    // panel columns [k0, k0 + 16)).
+    T z[16], lv[16];
+    if (large) {
+        const T* __restrict__ Zb = Zbuf + d.M_off[s] + (int64_t)(c0 / kPanel) * (kPanel * kPanel);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) z[j] = Zs[(16 * q4 + j) + lane * 65];        // Z[16 q4 + j][lane]
+        for (int j = 0; j < 16; ++j) z[j] = Zb[(k0 + j) * kPanel + lane];
+    }
+    {
+        const int64_t row = r0 + min(lane, max(nr - 1, 0));
+#pragma unroll
+        for (int j = 0; j < 16; ++j) lv[j] = (nr > 0 && k0 + j < w) ? L[row + (int64_t)(c0 + k0 + j) * f] : T(0);
     }
     for (int q = 0; q < nrhs; ++q) {
-        const T* vq = v + 16 * q4 + q * kSolvePanel;
+        if (tid < kPanel) v[tid + q * kPanel] = tid < w ? Y[first + c0 + tid + q * N] : T(0);
+        else if (tid < kPanel + kSolveRows) {
+            const int i = tid - kPanel, gi = r0 + i;
+            T val = T(0);
+            if (i < nr) val = gi < p ? Y[first + gi + q * N] : (c0 == 0 ? T(0) : Us[(gi - p) + (int64_t)q * c]);
+            rw[i + q * kSolveRows] = val;
+        }
+    }
+    __syncthreads();
+    if (c0 == 0) {
+        add_segments(d, U, segs, pt[5], pt[6], 0, v, kPanel, nrhs);
+        add_segments(d, U, segs, tk[4], tk[5], r0, rw, kSolveRows, nrhs);
+    }
+    if (large) {
+        // y = Z b: the 4 waves split the contraction, partial sums meet in part
+        for (int q = 0; q < nrhs; ++q) {
+            const T* vq = v + k0 + q * kPanel;
+            T acc = T(0);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc += z[j] * vq[j];
+            part[(q4 * 64 + lane) * nrhs + q] = acc;
+        }
+        __syncthreads();
+        if (tid < w)
+            for (int q = 0; q < nrhs; ++q) {
+                const T* pp = part + tid * nrhs + q;
+                v[tid + q * kPanel] = (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]);
+            }
+        __syncthreads();
+    } else {
+        chain_solve64<T, false>(L, f, c0, w, Ld, v, kPanel, nrhs);
+    }
+    if (chunk == 0)
+        for (int q = 0; q < nrhs; ++q)
+            if (tid < w) Y2[first + c0 + tid + q * N] = v[tid + q * kPanel];
+    if (nr == 0) return;
+    // rows: y_i -= L[i, panel] y
+#pragma unroll
+    for (int q = 0; q < kNrhsMax; ++q) {
+        if (q >= nrhs) continue;
+        const T* vq = v + k0 + q * kPanel;
         T acc = T(0);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) acc += z[j] * vq[j];
+        for (int j = 0; j < 16; ++j) acc += lv[j] * vq[j];
         part[(q4 * 64 + lane) * nrhs + q] = acc;
     }
     __syncthreads();
-    if (tid < ws)
+    if (tid < nr) {
+        const int gi = r0 + tid;
         for (int q = 0; q < nrhs; ++q) {
             const T* pp = part + tid * nrhs + q;
-            v[tid + q * kSolvePanel] = (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]);
-        }
-    __syncthreads();
-}
-
-// Y / Us [rows i0 .. i0 + nrow) -= L[rows, c0 : c0 + w] y for nrow <= 64 rows
-// of front s: lane = row, the four waves split the w <= 256 columns (64 each)
-// and their partial sums meet in LDS (part: 256 x nrhs).  Called by all 256
-// threads.
-template <typename T>
-__device__ __forceinline__ void rows_update64(const T* __restrict__ L, int f, int p, int c, int i0, int nrow, int c0,
-                                              int w, const T* y, T* part, T* __restrict__ Yf, T* __restrict__ Us,
-                                              int64_t N, int nrhs) {
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int k0 = 64 * wave;
-    T acc[kNrhsMax];
-#pragma unroll
-    for (int q = 0; q < kNrhsMax; ++q) acc[q] = T(0);
-    if (k0 < w) row_dot(L, f, i0 + min(lane, nrow - 1), c0 + k0, min(64, w - k0), y + k0, kSolvePanel, nrhs, acc);
-#pragma unroll
-    for (int q = 0; q < kNrhsMax; ++q)
-        if (q < nrhs) part[(wave * 64 + lane) * nrhs + q] = acc[q];
-    __syncthreads();
-    if (tid < nrow) {
-        const int i = i0 + tid;
-        for (int q = 0; q < nrhs; ++q) {
-            const T* pp = part + tid * nrhs + q;
-            const T sub = (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]);
-            if (i < p) Yf[i + q * N] -= sub;
-            else Us[(i - p) + (int64_t)q * c] -= sub;
+            const T val = rw[tid + q * kSolveRows] - ((pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]));
+            if (gi < p) Y[first + gi + q * N] = val;
+            else Us[(gi - p) + (int64_t)q * c] = val;
         }
     }
-    __syncthreads();
 }
 
-// Forward T: (c0 == 0) pull the children's update vectors; solve the panel's
-// triangle; when `fused`, also apply the panel to every row below it.
 template <typename T>
-__global__ __launch_bounds__(256) void k_fwd_T(DevPlan d, const int* __restrict__ tasks, const T* __restrict__ F,
-                                               const T* __restrict__ Zbuf, T* __restrict__ Y, T* __restrict__ U,
-                                               int nrhs) {
+__global__ __launch_bounds__(256) void k_bwd_P(DevPlan d, const int* __restrict__ ptab, const int* __restrict__ tasks,
+                                               const T* __restrict__ F, const T* __restrict__ Zbuf,
+                                               const T* __restrict__ D, T* __restrict__ Y2, T* __restrict__ partial,
+                                               int* __restrict__ pcnt, int nrhs) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* v = reinterpret_cast<T*>(smem_raw);        // kSolvePanel x nrhs
-    T* part = v + kSolvePanel * nrhs;             // 4 x 64 x nrhs
+    T* xs = reinterpret_cast<T*>(smem_raw);       // kSolveRows x nrhs: x of the task's rows
+    T* v = xs + kSolveRows * nrhs;                // kPanel x nrhs
+    T* part = v + kPanel * nrhs;                  // 256 x nrhs
     T* Ld = part + 256 * nrhs;                    // 64 x 65
-    const int* tk = tasks + 5 * blockIdx.x;
-    const int s = tk[0], c0 = tk[1], fused = tk[2];
-    const int first = d.sn_first[s];
-    const int p = d.sn_first[s + 1] - first;
-    const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
-    const int c = f - p;
-    const int w = min(kSolvePanel, p - c0);
-    const T* __restrict__ L = F + d.L_off[s];
-    T* __restrict__ Us = U + d.U_off[s];
-    const int tid = threadIdx.x;
-    const int64_t N = d.N;
-    const int64_t zoff = d.M_off[s];
-    if (c0 == 0) {
-        for (int q = 0; q < nrhs; ++q)
-            for (int i = tid; i < c; i += 256) Us[i + (int64_t)q * c] = T(0);
-        __syncthreads();
-        for (int k = d.child_ptr[s]; k < d.child_ptr[s + 1]; ++k) {
-            const int ch = d.child_list[k];
-            const int fc = (int)(d.sn_rowptr[ch + 1] - d.sn_rowptr[ch]);
-            const int cc = fc - (d.sn_first[ch + 1] - d.sn_first[ch]);
-            const T* __restrict__ Uc = U + d.U_off[ch];
-            const int* __restrict__ r = d.rel + d.rel_ptr[ch];
-            for (int q = 0; q < nrhs; ++q)
-                for (int a = tid; a < cc; a += 256) {
-                    const int t = r[a];
-                    const T val = Uc[a + (int64_t)q * cc];
-                    if (t < p) Y[first + t + q * N] += val;
-                    else Us[(t - p) + (int64_t)q * c] += val;
-                }
-            __syncthreads();
-        }
-    }
-    for (int q = 0; q < nrhs; ++q)
-        for (int t = tid; t < kSolvePanel; t += 256) v[t + q * kSolvePanel] = t < w ? Y[first + c0 + t + q * N] : T(0);
-    __syncthreads();
-    for (int sb = 0; sb < w; sb += 64) {
-        const int ws = min(64, w - sb);
-        if (zoff >= 0)
-            zmul64<T, false>(Zbuf + zoff + (int64_t)((c0 + sb) / kPanel) * (kPanel * kPanel), ws, Ld, part, v + sb,
-                             nrhs);
-        else
-            chain_solve64<T, false>(L, f, c0 + sb, ws, Ld, v + sb, nrhs);
-        const int t = sb + ws + tid;
-        if (t < w) {
-            T acc[kNrhsMax];
-#pragma unroll
-            for (int q = 0; q < kNrhsMax; ++q) acc[q] = T(0);
-            row_dot(L, f, c0 + t, c0 + sb, ws, v + sb, kSolvePanel, nrhs, acc);
-#pragma unroll
-            for (int q = 0; q < kNrhsMax; ++q)
-                if (q < nrhs) v[t + q * kSolvePanel] -= acc[q];
-        }
-        __syncthreads();
-    }
-    for (int q = 0; q < nrhs; ++q)
-        for (int t = tid; t < w; t += 256) Y[first + c0 + t + q * N] = v[t + q * kSolvePanel];
-    if (!fused) return;
-    for (int i0 = c0 + w; i0 < f; i0 += 64)
-        rows_update64(L, f, p, c, i0, min(64, f - i0), c0, w, v, part, Y + first, Us, N, nrhs);
-}
-
-// Forward G: rows [r0, r1) of front s minus L[rows, panel] y_panel.
-template <typename T>
-__global__ __launch_bounds__(256) void k_fwd_G(DevPlan d, const int* __restrict__ tasks, const T* __restrict__ F,
-                                               T* __restrict__ Y, T* __restrict__ U, int nrhs) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* y = reinterpret_cast<T*>(smem_raw);        // kSolvePanel x nrhs
-    T* part = y + kSolvePanel * nrhs;             // 4 x 64 x nrhs
-    const int* tk = tasks + 5 * blockIdx.x;
-    const int s = tk[0], c0 = tk[1], r0 = tk[2], r1 = tk[3];
-    const int first = d.sn_first[s];
-    const int p = d.sn_first[s + 1] - first;
-    const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
-    const int c = f - p;
-    const int w = min(kSolvePanel, p - c0);
-    const T* __restrict__ L = F + d.L_off[s];
-    T* __restrict__ Us = U + d.U_off[s];
-    const int tid = threadIdx.x;
-    const int64_t N = d.N;
-    for (int q = 0; q < nrhs; ++q)
-        for (int t = tid; t < kSolvePanel; t += 256) y[t + q * kSolvePanel] = t < w ? Y[first + c0 + t + q * N] : T(0);
-    __syncthreads();
-    for (int i0 = r0; i0 < r1; i0 += 64)
-        rows_update64(L, f, p, c, i0, min(64, r1 - i0), c0, w, y, part, Y + first, Us, N, nrhs);
-}
-
-// Backward G (large fronts only: a G task exists only when more than
-// kSolveChunk rows lie below the panel): partial[slot][t][q] = sum over rows
-// [r0, r1) of L[i, c0 + t] x_i, read as rows of L^T (upper triangle).
-template <typename T>
-__global__ __launch_bounds__(256) void k_bwd_G(DevPlan d, const int* __restrict__ tasks, const T* __restrict__ F,
-                                               const T* __restrict__ Y, T* __restrict__ partial, int nrhs) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* xs = reinterpret_cast<T*>(smem_raw);       // kSolveChunk x nrhs
-    const int* tk = tasks + 5 * blockIdx.x;
-    const int s = tk[0], c0 = tk[1], r0 = tk[2], r1 = tk[3], slot = tk[4];
+    __shared__ int s_last;
+    const int* tk = tasks + kPTaskInts * blockIdx.x;
+    const int pid = tk[0];
+    const int* pt = ptab + kPanInts * pid;
+    const int s = pt[0], c0 = pt[1], w = pt[2], slot0 = pt[3], ntask = pt[4];
+    const int r0 = tk[1], nr = tk[2] - tk[1], chunk = tk[3];
     const int first = d.sn_first[s];
     const int p = d.sn_first[s + 1] - first;
     const int64_t rb = d.sn_rowptr[s];
     const int f = (int)(d.sn_rowptr[s + 1] - rb);
-    const int w = min(kSolvePanel, p - c0);
     const T* __restrict__ L = F + d.L_off[s];
     const int* __restrict__ rows = d.sn_rows + rb;
-    const int tid = threadIdx.x;
+    const bool large = d.M_off[s] >= 0;
+    const int tid = threadIdx.x, lane = tid & 63, q4 = tid >> 6;
     const int64_t N = d.N;
-    const int nr = r1 - r0;
+    // Loads that depend on nothing computed here first: this thread's L^T
+    // operands (lane = panel column, wave q4 = rows q4, q4 + 4, ...; L^T is
+    // stored in a large front's upper triangle), Z for the transposed
+    // triangle, and 1 / d of the panel's pivots.
+    T lv[kSolveRows / 4], zv[kPanel * kPanel / 256];
+    if (large) {
+        const T* __restrict__ lt = L + (c0 + min(lane, w - 1)) + (int64_t)r0 * f;
+#pragma unroll
+        for (int m = 0; m < kSolveRows / 4; ++m) {
+            const int i = q4 + 4 * m;
+            lv[m] = (lane < w && i < nr) ? lt[(int64_t)i * f] : T(0);
+        }
+        const T* __restrict__ Zb = Zbuf + d.M_off[s] + (int64_t)(c0 / kPanel) * (kPanel * kPanel);
+#pragma unroll
+        for (int it = 0; it < kPanel * kPanel / 256; ++it) zv[it] = Zb[tid + 256 * it];
+    }
+    const T dinv = tid < w ? T(1) / D[first + c0 + tid] : T(0);
     for (int q = 0; q < nrhs; ++q)
-        for (int i = tid; i < kSolveChunk; i += 256) {
-            const int gi = r0 + i;
-            xs[i + q * kSolveChunk] = i >= nr ? T(0) : gi < p ? Y[first + gi + q * N] : Y[rows[gi] + q * N];
+        if (tid < kSolveRows) {
+            const int gi = r0 + tid;
+            xs[tid + q * kSolveRows] = tid >= nr ? T(0) : gi < p ? Y2[first + gi + q * N] : Y2[rows[gi] + q * N];
         }
+    if (!large && nr > 0) {
+        // column-major L only: stage L[rows, panel] as Ld[i + 65 t] (coalesced reads)
+        for (int idx = tid; idx < kSolveRows * kPanel; idx += 256) {
+            const int i = idx & (kSolveRows - 1), t = idx / kSolveRows;
+            Ld[i + 65 * t] = (i < nr && t < w) ? L[(r0 + i) + (int64_t)(c0 + t) * f] : T(0);
+        }
+    }
     __syncthreads();
-    for (int t = tid; t < w; t += 256) {
-        T acc[kNrhsMax];
+    // partial sums over the task's rows
 #pragma unroll
-        for (int q = 0; q < kNrhsMax; ++q) acc[q] = T(0);
-        row_dot(L, f, c0 + t, r0, nr, xs, kSolveChunk, nrhs, acc);
+    for (int q = 0; q < kNrhsMax; ++q) {
+        if (q >= nrhs) continue;
+        T a = T(0);
+        if (large) {
 #pragma unroll
-        for (int q = 0; q < kNrhsMax; ++q)
-            if (q < nrhs) partial[((int64_t)slot * kSolvePanel + t) * kNrhsMax + q] = acc[q];
-    }
-}
-
-// Backward T: v = D^-1 y - (rows below, from G partials or computed here when
-// fused), then the panel's transposed triangle in reverse sub-blocks.
-template <typename T>
-__global__ __launch_bounds__(256) void k_bwd_T(DevPlan d, const int* __restrict__ tasks, const T* __restrict__ F,
-                                               const T* __restrict__ Zbuf, const T* __restrict__ D,
-                                               T* __restrict__ Y, const T* __restrict__ partial, int nrhs) {
-    extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* v = reinterpret_cast<T*>(smem_raw);        // kSolvePanel x nrhs
-    T* xs = v + kSolvePanel * nrhs;               // kSolveChunk x nrhs: fused rows below, then partial sums
-    T* part = xs;
-    T* Ld = xs + kSolveChunk * nrhs;              // 64 x 65
-    const int* tk = tasks + 5 * blockIdx.x;
-    const int s = tk[0], c0 = tk[1], fused = tk[2], gfirst = tk[3], gcount = tk[4];
-    const int first = d.sn_first[s];
-    const int p = d.sn_first[s + 1] - first;
-    const int64_t rb = d.sn_rowptr[s];
-    const int f = (int)(d.sn_rowptr[s + 1] - rb);
-    const int w = min(kSolvePanel, p - c0);
-    const T* __restrict__ L = F + d.L_off[s];
-    const int* __restrict__ rows = d.sn_rows + rb;
-    const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
-    const int64_t N = d.N;
-    const int64_t zoff = d.M_off[s];
-    const bool large = zoff >= 0;
-    const int below0 = c0 + w;
-    const int nb = f - below0;
-    if (fused && nb > 0) {
-        for (int q = 0; q < nrhs; ++q)
-            for (int i = tid; i < kSolveChunk; i += 256) {
-                const int gi = below0 + i;
-                xs[i + q * kSolveChunk] = i >= nb ? T(0) : gi < p ? Y[first + gi + q * N] : Y[rows[gi] + q * N];
-            }
-        __syncthreads();
-    }
-    for (int t = tid; t < kSolvePanel; t += 256) {
-        if (t >= w) {
-            for (int q = 0; q < nrhs; ++q) v[t + q * kSolvePanel] = T(0);
-            continue;
+            for (int m = 0; m < kSolveRows / 4; ++m) a += lv[m] * xs[q4 + 4 * m + q * kSolveRows];
+        } else if (lane < w) {
+            for (int m = 0; m < kSolveRows / 4; ++m) a += Ld[q4 + 4 * m + 65 * lane] * xs[q4 + 4 * m + q * kSolveRows];
         }
-        const T dinv = T(1) / D[first + c0 + t];
-        T acc[kNrhsMax];
-#pragma unroll
-        for (int q = 0; q < kNrhsMax; ++q) acc[q] = T(0);
-        if (fused && nb > 0) {
-            if (large) {
-                row_dot(L, f, c0 + t, below0, nb, xs, kSolveChunk, nrhs, acc);
-            } else {
-                const T* __restrict__ col = L + (int64_t)(c0 + t) * f + below0;
-#pragma unroll
-                for (int q = 0; q < kNrhsMax; ++q) {
-                    if (q >= nrhs) continue;
-                    const T* xq = xs + q * kSolveChunk;
-                    T a = T(0);
-#pragma unroll 8
-                    for (int i = 0; i < nb; ++i) a += col[i] * xq[i];
-                    acc[q] = a;
-                }
+        part[(q4 * 64 + lane) * nrhs + q] = a;
+    }
+    __syncthreads();
+    if (ntask > 1) {
+        // Publish this task's sums; the last task of the panel goes on.  The
+        // sums are agent-scope atomic stores (coherent across the XCDs' L2
+        // caches) and every wave waits for their completion before the count
+        // is raised -- no whole-L2 write-back, which a release fence would
+        // cost every task.  The last task acquires (invalidating stale lines
+        // in its caches) and reads them with ordinary loads.
+        if (tid < kPanel)
+            for (int q = 0; q < nrhs; ++q) {
+                const T* pp = part + tid * nrhs + q;
+                __hip_atomic_store(partial + ((int64_t)(slot0 + chunk) * kPanel + tid) * kNrhsMax + q,
+                                   (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
             }
-        } else if (!fused) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __syncthreads();
+        if (tid == 0) {
+            const int seen = __hip_atomic_fetch_add(pcnt + pid, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            s_last = seen == ntask - 1;
+            if (s_last) {
+                __hip_atomic_store(pcnt + pid, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            }
+        }
+        __syncthreads();
+        if (!s_last) return;
+        // wave q4 adds the tasks g = q4, q4 + 4, ... (eight loads in flight
+        // per thread), then the four waves' sums meet in part
+        T acc2[kNrhsMax];
+#pragma unroll
+        for (int q = 0; q < kNrhsMax; ++q) acc2[q] = T(0);
+        for (int g0 = q4; g0 < ntask; g0 += 32) {
+            T pv[8];
 #pragma unroll
             for (int q = 0; q < kNrhsMax; ++q) {
                 if (q >= nrhs) continue;
-                T a = T(0);
-                for (int g = 0; g < gcount; ++g) a += partial[((int64_t)(gfirst + g) * kSolvePanel + t) * kNrhsMax + q];
-                acc[q] = a;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int g = g0 + 4 * u;
+                    pv[u] = g < ntask ? partial[((int64_t)(slot0 + g) * kPanel + lane) * kNrhsMax + q] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc2[q] += pv[u];
             }
         }
+        __syncthreads();
 #pragma unroll
         for (int q = 0; q < kNrhsMax; ++q)
-            if (q < nrhs) v[t + q * kSolvePanel] = Y[first + c0 + t + q * N] * dinv - acc[q];
+            if (q < nrhs) part[(q4 * 64 + lane) * nrhs + q] = acc2[q];
+        __syncthreads();
     }
-    __syncthreads();
-    for (int sb = ((w - 1) / 64) * 64; sb >= 0; sb -= 64) {
-        const int ws = min(64, w - sb);
-        const int ub = sb + ws;
-        if (ub < w) {
-            // v[sb + i] -= sum_{u in [ub, w)} L[c0 + u, c0 + sb + i] x_u
-            if (large) {
-                // wave k takes u in [ub + 64 k, ub + 64 k + 64); lane = i
-                const int u0 = ub + 64 * wave;
-                T acc[kNrhsMax];
-#pragma unroll
-                for (int q = 0; q < kNrhsMax; ++q) acc[q] = T(0);
-                if (u0 < w) row_dot(L, f, c0 + sb + lane, c0 + u0, min(64, w - u0), v + u0, kSolvePanel, nrhs, acc);
-#pragma unroll
-                for (int q = 0; q < kNrhsMax; ++q)
-                    if (q < nrhs) part[(wave * 64 + lane) * nrhs + q] = acc[q];
-                __syncthreads();
-                if (tid < ws)
-                    for (int q = 0; q < nrhs; ++q) {
-                        const T* pp = part + tid * nrhs + q;
-                        v[sb + tid + q * kSolvePanel] -= (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]);
-                    }
-            } else if (tid < ws) {
-                const T* __restrict__ col = L + (int64_t)(c0 + sb + tid) * f + c0;
-                for (int q = 0; q < nrhs; ++q) {
-                    const T* vq = v + q * kSolvePanel;
-                    T acc = T(0);
-#pragma unroll 8
-                    for (int u = ub; u < w; ++u) acc += col[u] * vq[u];
-                    v[sb + tid + q * kSolvePanel] -= acc;
-                }
-            }
-            __syncthreads();
+    // v = y / d - sums
+    if (tid < kPanel)
+        for (int q = 0; q < nrhs; ++q) {
+            const T* pp = part + tid * nrhs + q;
+            const T sum = (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]);
+            v[tid + q * kPanel] = tid < w ? Y2[first + c0 + tid + q * N] * dinv - sum : T(0);
         }
-        if (large)
-            zmul64<T, true>(Zbuf + zoff + (int64_t)((c0 + sb) / kPanel) * (kPanel * kPanel), ws, Ld, part, v + sb,
-                            nrhs);
-        else
-            chain_solve64<T, true>(L, f, c0 + sb, ws, Ld, v + sb, nrhs);
+    if (large) {
+        // x = Z^T v: Z staged transposed in Ld, wave q4 takes rows 16 q4 .. 16 q4 + 15
+#pragma unroll
+        for (int it = 0; it < kPanel * kPanel / 256; ++it) {
+            const int idx = tid + 256 * it;
+            Ld[(idx & 63) + (idx >> 6) * 65] = zv[it];
+        }
+        __syncthreads();
+        for (int q = 0; q < nrhs; ++q) {
+            const T* vq = v + 16 * q4 + q * kPanel;
+            T acc = T(0);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc += Ld[(16 * q4 + j) + lane * 65] * vq[j];
+            part[(q4 * 64 + lane) * nrhs + q] = acc;
+        }
+        __syncthreads();
+        if (tid < w)
+            for (int q = 0; q < nrhs; ++q) {
+                const T* pp = part + tid * nrhs + q;
+                Y2[first + c0 + tid + q * N] = (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]);
+            }
+    } else {
+        __syncthreads();
+        chain_solve64<T, true>(L, f, c0, w, Ld, v, kPanel, nrhs);
+        for (int q = 0; q < nrhs; ++q)
+            if (tid < w) Y2[first + c0 + tid + q * N] = v[tid + q * kPanel];
     }
-    for (int q = 0; q < nrhs; ++q)
-        for (int t = tid; t < w; t += 256) Y[first + c0 + t + q * N] = v[t + q * kSolvePanel];
 }
 
-// ---- small fronts: one wave per front ---------------------------------------
 // Fronts with p <= 64 pivots and f <= kSmallRows rows (L is f x p, ld f).  Each
 // wave keeps its front's right-hand-side rows in LDS (ld kSmallRows) and
 // synchronizes only with itself; a workgroup carries four fronts.
@@ -1542,8 +1508,8 @@ constexpr int kSmallRows = 128;
 // pivot row, readlane broadcasts), apply them to the rows below, write back.
 template <typename T>
 __global__ __launch_bounds__(256, 4) void k_fwd_S(DevPlan d, const int* __restrict__ fronts, int count,
-                                               const T* __restrict__ F, T* __restrict__ Y, T* __restrict__ U,
-                                               int nrhs) {
+                                               const T* __restrict__ F, const T* __restrict__ Y, T* __restrict__ Y2,
+                                               T* __restrict__ U, int nrhs) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int task = blockIdx.x * 4 + wv;
@@ -1620,7 +1586,7 @@ __global__ __launch_bounds__(256, 4) void k_fwd_S(DevPlan d, const int* __restri
     for (int q = 0; q < nrhs; ++q)
         for (int i = lane; i < f; i += 64) {
             const T v = ys[i + q * kSmallRows];
-            if (i < p) Y[first + i + q * N] = v;
+            if (i < p) Y2[first + i + q * N] = v;
             else Us[(i - p) + (int64_t)q * c] = v;
         }
 }
@@ -1631,7 +1597,7 @@ __global__ __launch_bounds__(256, 4) void k_fwd_S(DevPlan d, const int* __restri
 template <typename T>
 __global__ __launch_bounds__(256, 4) void k_bwd_S(DevPlan d, const int* __restrict__ fronts, int count,
                                                const T* __restrict__ F, const T* __restrict__ D,
-                                               T* __restrict__ Y, int nrhs) {
+                                               T* __restrict__ Y2, int nrhs) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int task = blockIdx.x * 4 + wv;
@@ -1647,7 +1613,7 @@ __global__ __launch_bounds__(256, 4) void k_bwd_S(DevPlan d, const int* __restri
     const int64_t N = d.N;
     for (int q = 0; q < nrhs; ++q)
         for (int i = lane; i < f; i += 64)
-            xs[i + q * kSmallRows] = i < p ? Y[first + i + q * N] : Y[rows[i] + q * N];
+            xs[i + q * kSmallRows] = i < p ? Y2[first + i + q * N] : Y2[rows[i] + q * N];
     wave_fence();
     const int t = lane;
     const bool tv = t < p;
@@ -1698,7 +1664,7 @@ __global__ __launch_bounds__(256, 4) void k_bwd_S(DevPlan d, const int* __restri
         wave_fence();
     }
     for (int q = 0; q < nrhs; ++q)
-        if (tv) Y[first + t + q * N] = xs[t + q * kSmallRows];
+        if (tv) Y2[first + t + q * N] = xs[t + q * kSmallRows];
 }
 
 // ---------------------------------------------------------------------------
@@ -1817,7 +1783,8 @@ __global__ __launch_bounds__(256) void k_persist_factor(DevPlan d, const int* __
 // front's update vector.
 template <typename T>
 __device__ void front_forward(const DevPlan& d, int s, int fcap, const T* __restrict__ F, const T* __restrict__ Zbuf,
-                              T* __restrict__ Y, T* __restrict__ U, int nrhs, T* ys, T* Ld, T* part) {
+                              const T* __restrict__ Y, T* __restrict__ Y2, T* __restrict__ U, int nrhs, T* ys, T* Ld,
+                              T* part) {
     const int tid = threadIdx.x, lane = tid & 63, q4 = tid >> 6;
     const int first = d.sn_first[s];
     const int p = d.sn_first[s + 1] - first;
@@ -1890,7 +1857,7 @@ __device__ void front_forward(const DevPlan& d, int s, int fcap, const T* __rest
     for (int q = 0; q < nrhs; ++q)
         for (int i = tid; i < f; i += 256) {
             const T v = ys[i + q * fcap];
-            if (i < p) Y[first + i + q * N] = v;
+            if (i < p) Y2[first + i + q * N] = v;
             else Us[(i - p) + (int64_t)q * c] = v;
         }
 }
@@ -1901,7 +1868,7 @@ __device__ void front_forward(const DevPlan& d, int s, int fcap, const T* __rest
 // transposed triangle (Z^T for large fronts, substitution otherwise).
 template <typename T>
 __device__ void front_backward(const DevPlan& d, int s, int fcap, const T* __restrict__ F,
-                               const T* __restrict__ Zbuf, const T* __restrict__ D, T* __restrict__ Y, int nrhs,
+                               const T* __restrict__ Zbuf, const T* __restrict__ D, T* __restrict__ Y2, int nrhs,
                                T* xs, T* Ld, T* part) {
     const int tid = threadIdx.x, lane = tid & 63, q4 = tid >> 6;
     const int first = d.sn_first[s];
@@ -1912,7 +1879,7 @@ __device__ void front_backward(const DevPlan& d, int s, int fcap, const T* __res
     const int* __restrict__ rows = d.sn_rows + rb;
     const int64_t N = d.N;
     for (int q = 0; q < nrhs; ++q)
-        for (int i = tid; i < f; i += 256) xs[i + q * fcap] = i < p ? Y[first + i + q * N] : Y[rows[i] + q * N];
+        for (int i = tid; i < f; i += 256) xs[i + q * fcap] = i < p ? Y2[first + i + q * N] : Y2[rows[i] + q * N];
     __syncthreads();
     for (int cb = ((p - 1) / kPanel) * kPanel; cb >= 0; cb -= kPanel) {
         const int ws = min(kPanel, p - cb);
@@ -1970,7 +1937,7 @@ __device__ void front_backward(const DevPlan& d, int s, int fcap, const T* __res
         __syncthreads();
     }
     for (int q = 0; q < nrhs; ++q)
-        for (int t = tid; t < p; t += 256) Y[first + t + q * N] = xs[t + q * fcap];
+        for (int t = tid; t < p; t += 256) Y2[first + t + q * N] = xs[t + q * fcap];
 }
 
 template <typename T>
@@ -1979,8 +1946,8 @@ __global__ __launch_bounds__(256) void k_persist_solve(DevPlan d, const int* __r
                                                        int* ticket, int* status, unsigned long long timeout,
                                                        unsigned long long* tstamp,
                                                        const T* __restrict__ F, const T* __restrict__ Zbuf,
-                                                       const T* __restrict__ D, T* __restrict__ Y,
-                                                       T* __restrict__ U, int nrhs) {
+                                                       const T* __restrict__ D, const T* __restrict__ Y,
+                                                       T* __restrict__ Y2, T* __restrict__ U, int nrhs) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* ys = reinterpret_cast<T*>(smem_raw);                 // fcap x nrhs
     T* part = ys + (int64_t)fcap * nrhs;                    // 256 x nrhs
@@ -1996,14 +1963,14 @@ __global__ __launch_bounds__(256) void k_persist_solve(DevPlan d, const int* __r
         if (t < nsn) {
             const int s = order[t];
             pers_wait(fwd_kids + s, d.child_ptr[s + 1] - d.child_ptr[s], status, timeout);
-            front_forward<T>(d, s, fcap, F, Zbuf, Y, U, nrhs, ys, Ld, part);
+            front_forward<T>(d, s, fcap, F, Zbuf, Y, Y2, U, nrhs, ys, Ld, part);
             const int par = d.sn_parent[s];
             pers_signal(par >= 0 ? fwd_kids + par : fwd_done + s);
         } else {
             const int s = order[2 * nsn - 1 - t];
             const int par = d.sn_parent[s];
             pers_wait(par >= 0 ? bwd_done + par : fwd_done + s, 1, status, timeout);
-            front_backward<T>(d, s, fcap, F, Zbuf, D, Y, nrhs, ys, Ld, part);
+            front_backward<T>(d, s, fcap, F, Zbuf, D, Y2, nrhs, ys, Ld, part);
             pers_signal(bwd_done + s);
             if (threadIdx.x == 0) {
                 const int sys = d.sn_sys[s];
@@ -2291,11 +2258,11 @@ void launch_persist_factor(const DevPlan& d, const int* order, int ntask, const 
 template <typename T>
 void launch_persist_solve(const DevPlan& d, const int* order, int nsn, const int* sys_nfronts, int fcap, int grid,
                           int* ctr, int* ticket, int* status, unsigned long long timeout, unsigned long long* tstamp,
-                          const T* F, const T* Z, const T* D, T* Y, T* U, int nrhs, hipStream_t st) {
+                          const T* F, const T* Z, const T* D, const T* Y, T* Y2, T* U, int nrhs, hipStream_t st) {
     if (nsn <= 0) return;
     const size_t lds = ((size_t)fcap * nrhs + 256 * (size_t)nrhs + 64 * 65) * sizeof(T);
     launch(k_persist_solve<T>, dim3(grid < 2 * nsn ? grid : 2 * nsn), dim3(256), (uint32_t)lds, st, d, order, nsn,
-           sys_nfronts, fcap, ctr, ticket, status, timeout, tstamp, F, Z, D, Y, U, nrhs);
+           sys_nfronts, fcap, ctr, ticket, status, timeout, tstamp, F, Z, D, Y, Y2, U, nrhs);
 }
 
 template <typename T>
@@ -2309,49 +2276,35 @@ void launch_permute_out(const DevPlan& d, const T* Y, int nrhs, double* X, int64
 }
 
 template <typename T>
-void launch_fwd_T(const DevPlan& d, const int* tasks, int count, const T* F, const T* Z, T* Y, T* U, int nrhs,
-                  hipStream_t st) {
-    if (count <= 0) return;
-    const size_t lds = (size_t)(kSolvePanel * nrhs + 256 * nrhs + 64 * 65) * sizeof(T);
-    launch(k_fwd_T<T>, dim3(count), dim3(256), lds, st, d, tasks, F, Z, Y, U, nrhs);
-}
-
-template <typename T>
-void launch_fwd_S(const DevPlan& d, const int* fronts, int count, const T* F, T* Y, T* U, int nrhs, hipStream_t st) {
-    if (count <= 0) return;
-    const size_t lds = (size_t)4 * kSmallRows * nrhs * sizeof(T);
-    launch(k_fwd_S<T>, dim3((count + 3) / 4), dim3(256), lds, st, d, fronts, count, F, Y, U, nrhs);
-}
-
-template <typename T>
-void launch_bwd_S(const DevPlan& d, const int* fronts, int count, const T* F, const T* D, T* Y, int nrhs,
+void launch_fwd_S(const DevPlan& d, const int* fronts, int count, const T* F, const T* Y, T* Y2, T* U, int nrhs,
                   hipStream_t st) {
     if (count <= 0) return;
     const size_t lds = (size_t)4 * kSmallRows * nrhs * sizeof(T);
-    launch(k_bwd_S<T>, dim3((count + 3) / 4), dim3(256), lds, st, d, fronts, count, F, D, Y, nrhs);
+    launch(k_fwd_S<T>, dim3((count + 3) / 4), dim3(256), lds, st, d, fronts, count, F, Y, Y2, U, nrhs);
 }
 
 template <typename T>
-void launch_fwd_G(const DevPlan& d, const int* tasks, int count, const T* F, T* Y, T* U, int nrhs, hipStream_t st) {
-    if (count <= 0) return;
-    const size_t lds = (size_t)(kSolvePanel + 256) * nrhs * sizeof(T);
-    launch(k_fwd_G<T>, dim3(count), dim3(256), lds, st, d, tasks, F, Y, U, nrhs);
-}
-
-template <typename T>
-void launch_bwd_G(const DevPlan& d, const int* tasks, int count, const T* F, const T* Y, T* partial, int nrhs,
+void launch_bwd_S(const DevPlan& d, const int* fronts, int count, const T* F, const T* D, T* Y2, int nrhs,
                   hipStream_t st) {
     if (count <= 0) return;
-    const size_t lds = (size_t)kSolveChunk * nrhs * sizeof(T);
-    launch(k_bwd_G<T>, dim3(count), dim3(256), lds, st, d, tasks, F, Y, partial, nrhs);
+    const size_t lds = (size_t)4 * kSmallRows * nrhs * sizeof(T);
+    launch(k_bwd_S<T>, dim3((count + 3) / 4), dim3(256), lds, st, d, fronts, count, F, D, Y2, nrhs);
 }
 
 template <typename T>
-void launch_bwd_T(const DevPlan& d, const int* tasks, int count, const T* F, const T* Z, const T* D, T* Y,
-                  const T* partial, int nrhs, hipStream_t st) {
+void launch_fwd_P(const DevPlan& d, const int* ptab, const int* tasks, int count, const int* segs, const T* F,
+                  const T* Z, T* Y, T* Y2, T* U, int nrhs, hipStream_t st) {
     if (count <= 0) return;
-    const size_t lds = (size_t)(kSolvePanel * nrhs + kSolveChunk * nrhs + 64 * 65) * sizeof(T);
-    launch(k_bwd_T<T>, dim3(count), dim3(256), lds, st, d, tasks, F, Z, D, Y, partial, nrhs);
+    const size_t lds = (size_t)((kPanel + kSolveRows + 256) * nrhs + 64 * 65) * sizeof(T);
+    launch(k_fwd_P<T>, dim3(count), dim3(256), lds, st, d, ptab, tasks, segs, F, Z, Y, Y2, U, nrhs);
+}
+
+template <typename T>
+void launch_bwd_P(const DevPlan& d, const int* ptab, const int* tasks, int count, const T* F, const T* Z,
+                  const T* D, T* Y2, T* partial, int* pcnt, int nrhs, hipStream_t st) {
+    if (count <= 0) return;
+    const size_t lds = (size_t)((kPanel + kSolveRows + 256) * nrhs + 64 * 65) * sizeof(T);
+    launch(k_bwd_P<T>, dim3(count), dim3(256), lds, st, d, ptab, tasks, F, Z, D, Y2, partial, pcnt, nrhs);
 }
 
 void launch_residual(const DevPlan& d, const double* K, const double* B, int64_t ldb, const double* X, int64_t ldx,
@@ -2413,10 +2366,8 @@ hipError_t configure_kernels(int max_dynamic_lds) {
     hipError_t e = hipSuccess, r;
     const void* fns[] = {(const void*)k_small_fronts<double, true>, (const void*)k_small_fronts<float, true>,
                          (const void*)k_small_fronts<double, false>, (const void*)k_small_fronts<float, false>,
-                         (const void*)k_fwd_T<double>, (const void*)k_fwd_T<float>,
-                         (const void*)k_fwd_G<double>, (const void*)k_fwd_G<float>,
-                         (const void*)k_bwd_G<double>, (const void*)k_bwd_G<float>,
-                         (const void*)k_bwd_T<double>, (const void*)k_bwd_T<float>,
+                         (const void*)k_fwd_P<double>, (const void*)k_fwd_P<float>,
+                         (const void*)k_bwd_P<double>, (const void*)k_bwd_P<float>,
                          (const void*)k_fwd_S<double>, (const void*)k_fwd_S<float>,
                          (const void*)k_large_asm<double, true>, (const void*)k_large_asm<float, true>,
                          (const void*)k_bwd_S<double>, (const void*)k_bwd_S<float>,
@@ -2443,17 +2394,16 @@ hipError_t configure_kernels(int max_dynamic_lds) {
                                            int*, unsigned long long, unsigned long long*, const double*, T*, T*, T*,  \
                                            hipStream_t);                                                             \
     template void launch_persist_solve<T>(const DevPlan&, const int*, int, const int*, int, int, int*, int*, int*,      \
-                                          unsigned long long, unsigned long long*, const T*, const T*, const T*, T*, T*, \
-                                          int, hipStream_t);                                                        \
+                                          unsigned long long, unsigned long long*, const T*, const T*, const T*,       \
+                                          const T*, T*, T*, int, hipStream_t);                                      \
     template void launch_permute_in<T>(const DevPlan&, const double*, int64_t, int, T*, hipStream_t);              \
     template void launch_permute_out<T>(const DevPlan&, const T*, int, double*, int64_t, hipStream_t);             \
-    template void launch_fwd_T<T>(const DevPlan&, const int*, int, const T*, const T*, T*, T*, int, hipStream_t);           \
-    template void launch_fwd_G<T>(const DevPlan&, const int*, int, const T*, T*, T*, int, hipStream_t);           \
-    template void launch_fwd_S<T>(const DevPlan&, const int*, int, const T*, T*, T*, int, hipStream_t);           \
+    template void launch_fwd_S<T>(const DevPlan&, const int*, int, const T*, const T*, T*, T*, int, hipStream_t);  \
     template void launch_bwd_S<T>(const DevPlan&, const int*, int, const T*, const T*, T*, int, hipStream_t);     \
-    template void launch_bwd_G<T>(const DevPlan&, const int*, int, const T*, const T*, T*, int, hipStream_t);     \
-    template void launch_bwd_T<T>(const DevPlan&, const int*, int, const T*, const T*, const T*, T*, const T*, int,        \
-                                  hipStream_t);
+    template void launch_fwd_P<T>(const DevPlan&, const int*, const int*, int, const int*, const T*, const T*, T*,  \
+                                  T*, T*, int, hipStream_t);                                                       \
+    template void launch_bwd_P<T>(const DevPlan&, const int*, const int*, int, const T*, const T*, const T*, T*,    \
+                                  T*, int*, int, hipStream_t);
 
 NCL_INSTANTIATE(double)
 NCL_INSTANTIATE(float)

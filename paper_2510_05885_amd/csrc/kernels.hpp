@@ -11,8 +11,9 @@ constexpr int kNrhsMax = 16;   // columns per solve sweep (wider solves are chun
 constexpr int kPanel = 64;       // pivot block width of the large-front path
 constexpr int kSmallMax = 128;   // largest front order of the LDS-resident path
 constexpr int kTile = 64;        // tile order of the large-front MFMA update
-constexpr int kSolvePanel = 256; // pivot columns per solve panel
-constexpr int kSolveChunk = 256; // row capacity of a solve G task / of the rows fused below a panel
+constexpr int kSolveRows = 64;   // rows below a solve panel per task
+constexpr int kPanInts = 7;      // ints per solve panel: s, c0, w, slot0, tasks, seg0, nseg
+constexpr int kPTaskInts = 6;    // ints per solve task: panel, r0, r1, index, seg0, nseg
 constexpr int kInertiaSlots = 64;  // partial inertia counters per system (spreads the atomics)
 constexpr int kNonfiniteInput = 1;   // status bit: NaN/Inf in the assembled K (its norms)
 constexpr int kNonfiniteFactor = 4;  // status bit: NaN/Inf pivot met by the factorization
@@ -144,29 +145,32 @@ void launch_persist_factor(const DevPlan& d, const int* order, int ntask, const 
 template <typename T>
 void launch_persist_solve(const DevPlan& d, const int* order, int nsn, const int* sys_nfronts, int fcap, int grid,
                           int* ctr, int* ticket, int* status, unsigned long long timeout, unsigned long long* tstamp,
-                          const T* F, const T* Z, const T* D, T* Y, T* U, int nrhs, hipStream_t st);
+                          const T* F, const T* Z, const T* D, const T* Y, T* Y2, T* U, int nrhs,
+                          hipStream_t st);
 
 // ---- solves -----------------------------------------------------------------
 template <typename T>
 void launch_permute_in(const DevPlan& d, const double* B, int64_t ldb, int nrhs, T* Y, hipStream_t st);
 template <typename T>
 void launch_permute_out(const DevPlan& d, const T* Y, int nrhs, double* X, int64_t ldx, hipStream_t st);
+// Y: right-hand side in pivot order (updated in place by the forward sweep
+// for rows that are not yet solved); Y2: the pivots' y after the forward sweep,
+// their x after the backward sweep.  One-wave fronts (p <= 64, f <= 128):
 template <typename T>
-void launch_fwd_T(const DevPlan& d, const int* tasks, int count, const T* F, const T* Z, T* Y, T* U, int nrhs,
+void launch_fwd_S(const DevPlan& d, const int* fronts, int count, const T* F, const T* Y, T* Y2, T* U, int nrhs,
                   hipStream_t st);
 template <typename T>
-void launch_fwd_S(const DevPlan& d, const int* fronts, int count, const T* F, T* Y, T* U, int nrhs, hipStream_t st);
-template <typename T>
-void launch_bwd_S(const DevPlan& d, const int* fronts, int count, const T* F, const T* D, T* Y, int nrhs,
+void launch_bwd_S(const DevPlan& d, const int* fronts, int count, const T* F, const T* D, T* Y2, int nrhs,
                   hipStream_t st);
+// The other fronts, one launch per panel step of a level (panel table ptab,
+// tasks, contribution segments: see the sweep kernels).  partial: slots x
+// kPanel x kNrhsMax; pcnt: one zero counter per panel (left zero).
 template <typename T>
-void launch_fwd_G(const DevPlan& d, const int* tasks, int count, const T* F, T* Y, T* U, int nrhs, hipStream_t st);
+void launch_fwd_P(const DevPlan& d, const int* ptab, const int* tasks, int count, const int* segs, const T* F,
+                  const T* Z, T* Y, T* Y2, T* U, int nrhs, hipStream_t st);
 template <typename T>
-void launch_bwd_G(const DevPlan& d, const int* tasks, int count, const T* F, const T* Y, T* partial, int nrhs,
-                  hipStream_t st);
-template <typename T>
-void launch_bwd_T(const DevPlan& d, const int* tasks, int count, const T* F, const T* Z, const T* D, T* Y,
-                  const T* partial, int nrhs, hipStream_t st);
+void launch_bwd_P(const DevPlan& d, const int* ptab, const int* tasks, int count, const T* F, const T* Z,
+                  const T* D, T* Y2, T* partial, int* pcnt, int nrhs, hipStream_t st);
 
 // ---- refinement -------------------------------------------------------------
 // R = B - K X; per chunk of rows (all of one system) and column, kResWidth figures:

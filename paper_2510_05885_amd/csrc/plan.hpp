@@ -20,9 +20,6 @@ struct PlanConfig {
     int nd_leaf = 64;           // nested-dissection leaf size (compressed vertices)
     int relax_big_front = 128;  // fronts above this order (the global-memory path, swept in
     double relax_big_zeros = 0.2;  // panels anyway) may carry up to this fraction of zeros
-    int solve_panel = 256;      // pivot columns per solve panel
-    int solve_fuse_rows = 64;   // rows below a panel handled inside the panel's workgroup
-    int solve_chunk_rows = 64;  // rows per G task otherwise
 };
 
 struct LevelBatch {            // one launch of the small-front kernel
@@ -42,14 +39,14 @@ struct LargeStep {             // launches of the large-front path for one level
     std::vector<double> upd_flops;            // algorithmic flops of each update launch
 };
 
-// Solve schedule: each front is swept in panels of up to kSolvePanel pivot
-// columns.  A T task solves one panel's triangle in one workgroup; when the
-// rows below the panel are many, G tasks (row chunks) apply the panel to them
-// in parallel.  Per level and panel index j, one T launch and one G launch.
+// Solve schedule: a front with p <= 64 pivots and f <= 128 rows is swept by
+// one wave; every other front in panels of up to 64 pivot columns, each panel
+// split into tasks of up to 64 rows below it (one workgroup each).  Per level
+// and panel index j, one launch of the one-wave fronts (j = 0) and one of the
+// panel tasks.
 struct SolveStep {
     int level = 0, j = 0;
-    int64_t t_first = 0, t_count = 0;   // tasks in Plan::solve_t (5 ints each)
-    int64_t g_first = 0, g_count = 0;   // tasks in Plan::solve_g (5 ints each)
+    int64_t p_first = 0, p_count = 0;   // tasks in Plan::solve_p (kPTaskInts each)
     int64_t s_first = 0, s_count = 0;   // small fronts in Plan::solve_s (one wave each)
     double fwd_bytes = 0.0;             // algorithmic bytes of L read by the step (FP64; padding
                                         // zeros of amalgamated fronts not counted)
@@ -151,10 +148,11 @@ struct Plan {
     int pers_fmax_large = 0, pers_fmax_small = 0, pers_fmax = 0;
     // solve schedule
     std::vector<SolveStep> solve_steps;
-    std::vector<int> solve_t;        // (front, c0, fused, g_first, g_count)
-    std::vector<int> solve_g;        // (front, c0, r0, r1, slot)
+    std::vector<int> solve_pan;      // panels (s, c0, w, slot0, tasks, seg0, nseg)
+    std::vector<int> solve_p;        // tasks (panel, r0, r1, index, seg0, nseg)
+    std::vector<int> solve_seg;      // (child, a0, a1): update-vector entries landing in a task
     std::vector<int> solve_s;        // small fronts (p <= 64, f <= 128) solved by one wave each
-    int64_t solve_max_slots = 0;     // G tasks in the largest step (partial-sum slots)
+    int64_t solve_max_slots = 0;     // tasks in the largest step (partial-sum slots)
 
     // ---- stats ------------------------------------------------------------
     int64_t nnzL = 0;
