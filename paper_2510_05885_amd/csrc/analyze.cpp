@@ -818,7 +818,10 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
         }
         // ---------------- solve schedule -----------------------------------
         {
-            const int PW = 64, GR = 64;   // kPanel, kSolveRows
+            const int PW = 64;   // kPanel
+            // rows per task: the panel's columns are taken 16 at a time by the
+            // four waves, the rest of the workgroup takes more rows
+            auto task_rows = [](int w) { return 64 * (4 / ((w + 15) / 16)); };
             // entries [a0, a1) of child ch's update vector landing in parent rows [lo, hi)
             auto child_range = [&](int ch, int lo, int hi, int& a0, int& a1) {
                 const int* r = P.rel.data() + P.rel_ptr[ch];
@@ -856,6 +859,9 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                             continue;
                         }
                         const int pid = (int)(P.solve_pan.size() / 7);
+                        const int GR = task_rows(w);
+                        if (!P.sn_large[s] && below > 64)
+                            throw AnalyzeError(-4, "internal: LDS-path front with more than 64 rows below a panel");
                         const int ntask = std::max(1, (below + GR - 1) / GR);
                         const int seg0 = (int)(P.solve_seg.size() / 3);
                         if (c0 == 0)

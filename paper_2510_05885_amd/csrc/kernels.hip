@@ -1136,7 +1136,9 @@ __global__ void k_permute_out(DevPlan d, const T* __restrict__ Y, int nrhs, doub
 // w <= kPanel, of front s.  Its triangle is applied through the inverse
 // Z = L_kk^-1 that the factorization published (a GEMV, no dependent chain)
 // for large fronts, by one-wave substitution otherwise.  The rows below the
-// panel are split into tasks of kSolveRows rows, one workgroup each:
+// panel are split into tasks, one workgroup each, of solve_task_rows(w) rows:
+// the panel's columns are taken 16 at a time, so a narrow panel gives each
+// wave more rows instead of leaving waves idle.
 //   forward: every task recomputes y = Z b of its panel (b = the pivots' right-
 //     hand side, plus the children's update vectors at the first panel),
 //     subtracts L[rows, panel] y from its own rows and writes them back; task 0
@@ -1152,6 +1154,8 @@ __global__ void k_permute_out(DevPlan d, const T* __restrict__ Y, int nrhs, doub
 // panel, rows [r0, r1) (r0 == r1 = f for a panel with nothing below), index
 // within the panel, first and count of its rows' segments.  Segment (3 ints):
 // child, entries [a0, a1) of its update vector that land in the rows.
+// NR: columns of the right-hand side the kernel is built for (1, or up to
+// kNrhsMax).
 
 // acc[q] += sum_{k < n} M[row + (col0 + k) * f] v[k + q * ldv], q < nrhs,
 // in chunks of kDotChunk operands loaded before use.
@@ -1206,22 +1210,23 @@ __device__ __forceinline__ void chain_solve64(const T* __restrict__ L, int f, in
     }
     __syncthreads();
     if (tid < 64) {
-        T lrow[64];
-        if (!kBackward) {
-#pragma unroll
-            for (int k = 0; k < 64; ++k) lrow[k] = (k < lane && lane < ws) ? Ld[lane * 65 + k] : T(0);
-        } else {
-#pragma unroll
-            for (int k = 0; k < 64; ++k) lrow[k] = (lane < k && k < ws) ? Ld[k * 65 + lane] : T(0);
-        }
+        // the row (forward) or column (backward) of the triangle is read from
+        // LDS at each step: a register copy would set the register budget of
+        // every kernel that contains this path
         for (int q = 0; q < nrhs; ++q) {
             T val = lane < ws ? v[lane + q * vld] : T(0);
             if (!kBackward) {
-#pragma unroll
-                for (int k = 0; k < 63; ++k) val -= lrow[k] * bcast(val, k);
+#pragma unroll 8
+                for (int k = 0; k < 63; ++k) {
+                    const T l = (k < lane && lane < ws) ? Ld[lane * 65 + k] : T(0);
+                    val -= l * bcast(val, k);
+                }
             } else {
-#pragma unroll
-                for (int k = 63; k > 0; --k) val -= lrow[k] * bcast(val, k);
+#pragma unroll 8
+                for (int k = 63; k > 0; --k) {
+                    const T l = (lane < k && k < ws) ? Ld[k * 65 + lane] : T(0);
+                    val -= l * bcast(val, k);
+                }
             }
             if (lane < ws) v[lane + q * vld] = val;
         }
@@ -1230,30 +1235,53 @@ __device__ __forceinline__ void chain_solve64(const T* __restrict__ L, int f, in
 }
 
 // dst[r - base] += the children's update-vector entries of segments
-// [g0, g0 + gn), one child after the other (two children may add to one row).
-template <typename T>
+// [g0, g0 + gn).  The entries of all segments are loaded at once (256 per
+// round, one per thread, held in registers), then added segment by segment:
+// two children may add to one row, and the order stays the children's.
+template <typename T, int NR>
 __device__ __forceinline__ void add_segments(const DevPlan& d, const T* __restrict__ U, const int* __restrict__ segs,
                                              int g0, int gn, int base, T* dst, int ld, int nrhs) {
-    for (int g = g0; g < g0 + gn; ++g) {
-        const int ch = segs[3 * g], a0 = segs[3 * g + 1], a1 = segs[3 * g + 2];
-        const int cc = (int)(d.sn_rowptr[ch + 1] - d.sn_rowptr[ch]) - (d.sn_first[ch + 1] - d.sn_first[ch]);
-        const T* __restrict__ Uc = U + d.U_off[ch];
-        const int* __restrict__ r = d.rel + d.rel_ptr[ch];
-        for (int q = 0; q < nrhs; ++q)
-            for (int a = a0 + (int)threadIdx.x; a < a1; a += 256) dst[r[a] - base + q * ld] += Uc[a + (int64_t)q * cc];
-        __syncthreads();
+    int total = 0;
+    for (int g = g0; g < g0 + gn; ++g) total += segs[3 * g + 2] - segs[3 * g + 1];
+    for (int e0 = 0; e0 < total; e0 += 256) {
+        const int e = e0 + (int)threadIdx.x;
+        int mine = -1, row = 0;
+        T val[NR];
+        if (e < total) {
+            int g = g0, acc = 0;
+            for (;; ++g) {
+                const int len = segs[3 * g + 2] - segs[3 * g + 1];
+                if (e < acc + len) break;
+                acc += len;
+            }
+            const int ch = segs[3 * g], a = segs[3 * g + 1] + (e - acc);
+            const int cc = (int)(d.sn_rowptr[ch + 1] - d.sn_rowptr[ch]) - (d.sn_first[ch + 1] - d.sn_first[ch]);
+            const T* __restrict__ Uc = U + d.U_off[ch] + a;
+            row = d.rel[d.rel_ptr[ch] + a] - base;
+#pragma unroll
+            for (int q = 0; q < NR; ++q)
+                if (q < nrhs) val[q] = Uc[(int64_t)q * cc];
+            mine = g;
+        }
+        for (int g = g0; g < g0 + gn; ++g) {
+            if (mine == g)
+#pragma unroll
+                for (int q = 0; q < NR; ++q)
+                    if (q < nrhs) dst[row + q * ld] += val[q];
+            __syncthreads();
+        }
     }
 }
 
-template <typename T>
+template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_fwd_P(DevPlan d, const int* __restrict__ ptab, const int* __restrict__ tasks,
                                                const int* __restrict__ segs, const T* __restrict__ F,
                                                const T* __restrict__ Zbuf, T* __restrict__ Y, T* __restrict__ Y2,
                                                T* __restrict__ U, int nrhs) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* v = reinterpret_cast<T*>(smem_raw);        // kPanel x nrhs: b of the pivots, then y
-    T* rw = v + kPanel * nrhs;                    // kSolveRows x nrhs: the task's rows
-    T* part = rw + kSolveRows * nrhs;             // 256 x nrhs
+    T* rw = v + kPanel * nrhs;                    // kSolveRowsMax x nrhs: the task's rows
+    T* part = rw + kSolveRowsMax * nrhs;          // 256 x nrhs
     T* Ld = part + 256 * nrhs;                    // 64 x 65
     const int* tk = tasks + kPTaskInts * blockIdx.x;
     const int* pt = ptab + kPanInts * tk[0];
@@ -1268,40 +1296,41 @@ __global__ __launch_bounds__(256) void k_fwd_P(DevPlan d, const int* __restrict_
     const int tid = threadIdx.x, lane = tid & 63, q4 = tid >> 6;
     const int64_t N = d.N;
     const bool large = d.M_off[s] >= 0;
-    const int k0 = 16 * q4;
+    // wave q4: row group q4 / nwc (64 rows, lane = row), columns 16 (q4 % nwc) + [0, 16)
+    const int nwc = (w + 15) >> 4, ng = 4 / nwc;
+    const int rgrp = q4 / nwc, k0 = 16 * (q4 - rgrp * nwc);
+    const int myrow = 64 * rgrp + lane;           // row of the task (valid if < nr)
     // Operands that depend on nothing computed here are loaded first, so
-    // their latency overlaps the right-hand side's: Z[lane][k0 + j] (large
-    // fronts) and this thread's row of L[rows, panel] (lane = row, wave q4 =
-    // panel columns [k0, k0 + 16)).
+    // their latency overlaps the right-hand side's: Z[lane][16 q4 + j] (large
+    // fronts) and this thread's slice of L[rows, panel].
     T z[16], lv[16];
     if (large) {
         const T* __restrict__ Zb = Zbuf + d.M_off[s] + (int64_t)(c0 / kPanel) * (kPanel * kPanel);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) z[j] = Zb[(k0 + j) * kPanel + lane];
+        for (int j = 0; j < 16; ++j) z[j] = (lane < w && 16 * q4 + j < w) ? Zb[(16 * q4 + j) * kPanel + lane] : T(0);
     }
     {
-        const int64_t row = r0 + min(lane, max(nr - 1, 0));
+        const bool rv = rgrp < ng && myrow < nr;
+        const int64_t row = r0 + (rv ? myrow : 0);
 #pragma unroll
-        for (int j = 0; j < 16; ++j) lv[j] = (nr > 0 && k0 + j < w) ? L[row + (int64_t)(c0 + k0 + j) * f] : T(0);
+        for (int j = 0; j < 16; ++j) lv[j] = (rv && k0 + j < w) ? L[row + (int64_t)(c0 + k0 + j) * f] : T(0);
     }
     for (int q = 0; q < nrhs; ++q) {
         if (tid < kPanel) v[tid + q * kPanel] = tid < w ? Y[first + c0 + tid + q * N] : T(0);
-        else if (tid < kPanel + kSolveRows) {
-            const int i = tid - kPanel, gi = r0 + i;
-            T val = T(0);
-            if (i < nr) val = gi < p ? Y[first + gi + q * N] : (c0 == 0 ? T(0) : Us[(gi - p) + (int64_t)q * c]);
-            rw[i + q * kSolveRows] = val;
-        }
+        const int gi = r0 + tid;
+        T val = T(0);
+        if (tid < nr) val = gi < p ? Y[first + gi + q * N] : (c0 == 0 ? T(0) : Us[(gi - p) + (int64_t)q * c]);
+        rw[tid + q * kSolveRowsMax] = val;
     }
     __syncthreads();
     if (c0 == 0) {
-        add_segments(d, U, segs, pt[5], pt[6], 0, v, kPanel, nrhs);
-        add_segments(d, U, segs, tk[4], tk[5], r0, rw, kSolveRows, nrhs);
+        add_segments<T, NR>(d, U, segs, pt[5], pt[6], 0, v, kPanel, nrhs);
+        add_segments<T, NR>(d, U, segs, tk[4], tk[5], r0, rw, kSolveRowsMax, nrhs);
     }
     if (large) {
         // y = Z b: the 4 waves split the contraction, partial sums meet in part
         for (int q = 0; q < nrhs; ++q) {
-            const T* vq = v + k0 + q * kPanel;
+            const T* vq = v + 16 * q4 + q * kPanel;
             T acc = T(0);
 #pragma unroll
             for (int j = 0; j < 16; ++j) acc += z[j] * vq[j];
@@ -1323,7 +1352,7 @@ __global__ __launch_bounds__(256) void k_fwd_P(DevPlan d, const int* __restrict_
     if (nr == 0) return;
     // rows: y_i -= L[i, panel] y
 #pragma unroll
-    for (int q = 0; q < kNrhsMax; ++q) {
+    for (int q = 0; q < NR; ++q) {
         if (q >= nrhs) continue;
         const T* vq = v + k0 + q * kPanel;
         T acc = T(0);
@@ -1333,24 +1362,26 @@ __global__ __launch_bounds__(256) void k_fwd_P(DevPlan d, const int* __restrict_
     }
     __syncthreads();
     if (tid < nr) {
-        const int gi = r0 + tid;
+        const int gi = r0 + tid, g = tid >> 6, l = tid & 63;
         for (int q = 0; q < nrhs; ++q) {
-            const T* pp = part + tid * nrhs + q;
-            const T val = rw[tid + q * kSolveRows] - ((pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]));
+            const T* pp = part + ((g * nwc) * 64 + l) * nrhs + q;
+            T sum = pp[0];
+            for (int k = 1; k < nwc; ++k) sum += pp[k * 64 * nrhs];
+            const T val = rw[tid + q * kSolveRowsMax] - sum;
             if (gi < p) Y[first + gi + q * N] = val;
             else Us[(gi - p) + (int64_t)q * c] = val;
         }
     }
 }
 
-template <typename T>
+template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_bwd_P(DevPlan d, const int* __restrict__ ptab, const int* __restrict__ tasks,
                                                const T* __restrict__ F, const T* __restrict__ Zbuf,
                                                const T* __restrict__ D, T* __restrict__ Y2, T* __restrict__ partial,
                                                int* __restrict__ pcnt, int nrhs) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
-    T* xs = reinterpret_cast<T*>(smem_raw);       // kSolveRows x nrhs: x of the task's rows
-    T* v = xs + kSolveRows * nrhs;                // kPanel x nrhs
+    T* xs = reinterpret_cast<T*>(smem_raw);       // kSolveRowsMax x nrhs: x of the task's rows
+    T* v = xs + kSolveRowsMax * nrhs;             // kPanel x nrhs
     T* part = v + kPanel * nrhs;                  // 256 x nrhs
     T* Ld = part + 256 * nrhs;                    // 64 x 65
     __shared__ int s_last;
@@ -1368,108 +1399,129 @@ __global__ __launch_bounds__(256) void k_bwd_P(DevPlan d, const int* __restrict_
     const bool large = d.M_off[s] >= 0;
     const int tid = threadIdx.x, lane = tid & 63, q4 = tid >> 6;
     const int64_t N = d.N;
+    // thread = (panel column t, row group rg): columns in slots of 16, the
+    // row groups take rows rg, rg + nrg, ... (at most 16 per thread)
+    const int W16 = 16 * ((w + 15) >> 4), nrg = 256 / W16;
+    const int t = tid % W16, rg = tid / W16;
+    const bool tact = t < w && rg < nrg;
     // Loads that depend on nothing computed here first: this thread's L^T
-    // operands (lane = panel column, wave q4 = rows q4, q4 + 4, ...; L^T is
-    // stored in a large front's upper triangle), Z for the transposed
-    // triangle, and 1 / d of the panel's pivots.
-    T lv[kSolveRows / 4], zv[kPanel * kPanel / 256];
+    // operands (L^T is stored in a large front's upper triangle), Z for the
+    // transposed triangle, and 1 / d of the panel's pivots.
+    T lv[16], zv[kPanel * kPanel / 256];
     if (large) {
-        const T* __restrict__ lt = L + (c0 + min(lane, w - 1)) + (int64_t)r0 * f;
+        const T* __restrict__ lt = L + (c0 + (tact ? t : 0)) + (int64_t)r0 * f;
 #pragma unroll
-        for (int m = 0; m < kSolveRows / 4; ++m) {
-            const int i = q4 + 4 * m;
-            lv[m] = (lane < w && i < nr) ? lt[(int64_t)i * f] : T(0);
+        for (int m = 0; m < 16; ++m) {
+            const int i = rg + nrg * m;
+            lv[m] = (tact && i < nr) ? lt[(int64_t)i * f] : T(0);
         }
         const T* __restrict__ Zb = Zbuf + d.M_off[s] + (int64_t)(c0 / kPanel) * (kPanel * kPanel);
 #pragma unroll
-        for (int it = 0; it < kPanel * kPanel / 256; ++it) zv[it] = Zb[tid + 256 * it];
+        for (int it = 0; it < kPanel * kPanel / 256; ++it) {
+            const int idx = tid + 256 * it;
+            zv[it] = ((idx & 63) < w && (idx >> 6) < w) ? Zb[idx] : T(0);
+        }
     }
     const T dinv = tid < w ? T(1) / D[first + c0 + tid] : T(0);
-    for (int q = 0; q < nrhs; ++q)
-        if (tid < kSolveRows) {
-            const int gi = r0 + tid;
-            xs[tid + q * kSolveRows] = tid >= nr ? T(0) : gi < p ? Y2[first + gi + q * N] : Y2[rows[gi] + q * N];
-        }
+    for (int q = 0; q < nrhs; ++q) {
+        const int gi = r0 + tid;
+        xs[tid + q * kSolveRowsMax] = tid >= nr ? T(0) : gi < p ? Y2[first + gi + q * N] : Y2[rows[gi] + q * N];
+    }
     if (!large && nr > 0) {
-        // column-major L only: stage L[rows, panel] as Ld[i + 65 t] (coalesced reads)
-        for (int idx = tid; idx < kSolveRows * kPanel; idx += 256) {
-            const int i = idx & (kSolveRows - 1), t = idx / kSolveRows;
-            Ld[i + 65 * t] = (i < nr && t < w) ? L[(r0 + i) + (int64_t)(c0 + t) * f] : T(0);
+        // column-major L only: stage L[rows, panel] as Ld[i + 65 t] (coalesced
+        // reads); such fronts have at most 64 rows below a panel (analysis)
+        for (int idx = tid; idx < 64 * kPanel; idx += 256) {
+            const int i = idx & 63, tt = idx >> 6;
+            Ld[i + 65 * tt] = (i < nr && tt < w) ? L[(r0 + i) + (int64_t)(c0 + tt) * f] : T(0);
         }
     }
     __syncthreads();
     // partial sums over the task's rows
 #pragma unroll
-    for (int q = 0; q < kNrhsMax; ++q) {
+    for (int q = 0; q < NR; ++q) {
         if (q >= nrhs) continue;
         T a = T(0);
         if (large) {
 #pragma unroll
-            for (int m = 0; m < kSolveRows / 4; ++m) a += lv[m] * xs[q4 + 4 * m + q * kSolveRows];
-        } else if (lane < w) {
-            for (int m = 0; m < kSolveRows / 4; ++m) a += Ld[q4 + 4 * m + 65 * lane] * xs[q4 + 4 * m + q * kSolveRows];
+            for (int m = 0; m < 16; ++m) {
+                const int i = rg + nrg * m;
+                a += lv[m] * xs[min(i, kSolveRowsMax - 1) + q * kSolveRowsMax];
+            }
+        } else if (tact) {
+            for (int m = 0; m < 16; ++m) {
+                const int i = rg + nrg * m;
+                if (i < 64) a += Ld[i + 65 * t] * xs[i + q * kSolveRowsMax];
+            }
         }
-        part[(q4 * 64 + lane) * nrhs + q] = a;
+        part[tid * nrhs + q] = tact ? a : T(0);
     }
     __syncthreads();
+    // this task's sum per panel column, into v (scratch) until it is combined
+    if (tid < kPanel)
+        for (int q = 0; q < nrhs; ++q) {
+            T sum = T(0);
+            if (tid < w)
+                for (int g = 0; g < nrg; ++g) sum += part[(g * W16 + tid) * nrhs + q];
+            v[tid + q * kPanel] = sum;
+        }
+    __syncthreads();
     if (ntask > 1) {
-        // Publish this task's sums; the last task of the panel goes on.  The
-        // sums are agent-scope atomic stores (coherent across the XCDs' L2
-        // caches) and every wave waits for their completion before the count
-        // is raised -- no whole-L2 write-back, which a release fence would
-        // cost every task.  The last task acquires (invalidating stale lines
-        // in its caches) and reads them with ordinary loads.
+        // Publish this task's sums; the last task of the panel goes on.  Every
+        // access to the partial sums is an agent-scope atomic (coherent across
+        // the XCDs' L2 caches): every wave waits for its stores to complete
+        // before the count is raised, and the last task reads after its count
+        // returned -- no whole-L2 write-back, which a release fence would cost
+        // every task.  (Ordinary loads could hit a line of the same slots that
+        // an earlier solve left in the reading XCD's L2.)
         if (tid < kPanel)
-            for (int q = 0; q < nrhs; ++q) {
-                const T* pp = part + tid * nrhs + q;
+            for (int q = 0; q < nrhs; ++q)
                 __hip_atomic_store(partial + ((int64_t)(slot0 + chunk) * kPanel + tid) * kNrhsMax + q,
-                                   (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]), __ATOMIC_RELAXED,
-                                   __HIP_MEMORY_SCOPE_AGENT);
-            }
+                                   v[tid + q * kPanel], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
         __syncthreads();
         if (tid == 0) {
             const int seen = __hip_atomic_fetch_add(pcnt + pid, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             s_last = seen == ntask - 1;
-            if (s_last) {
-                __hip_atomic_store(pcnt + pid, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            }
+            if (s_last) __hip_atomic_store(pcnt + pid, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         }
         __syncthreads();
         if (!s_last) return;
         // wave q4 adds the tasks g = q4, q4 + 4, ... (eight loads in flight
         // per thread), then the four waves' sums meet in part
-        T acc2[kNrhsMax];
+        T acc2[NR];
 #pragma unroll
-        for (int q = 0; q < kNrhsMax; ++q) acc2[q] = T(0);
+        for (int q = 0; q < NR; ++q) acc2[q] = T(0);
         for (int g0 = q4; g0 < ntask; g0 += 32) {
             T pv[8];
 #pragma unroll
-            for (int q = 0; q < kNrhsMax; ++q) {
+            for (int q = 0; q < NR; ++q) {
                 if (q >= nrhs) continue;
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const int g = g0 + 4 * u;
-                    pv[u] = g < ntask ? partial[((int64_t)(slot0 + g) * kPanel + lane) * kNrhsMax + q] : T(0);
+                    pv[u] = g < ntask ? __hip_atomic_load(partial + ((int64_t)(slot0 + g) * kPanel + lane) * kNrhsMax + q,
+                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                                      : T(0);
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) acc2[q] += pv[u];
             }
         }
-        __syncthreads();
 #pragma unroll
-        for (int q = 0; q < kNrhsMax; ++q)
+        for (int q = 0; q < NR; ++q)
             if (q < nrhs) part[(q4 * 64 + lane) * nrhs + q] = acc2[q];
+        __syncthreads();
+        if (tid < kPanel)
+            for (int q = 0; q < nrhs; ++q) {
+                const T* pp = part + tid * nrhs + q;
+                v[tid + q * kPanel] = (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]);
+            }
         __syncthreads();
     }
     // v = y / d - sums
     if (tid < kPanel)
-        for (int q = 0; q < nrhs; ++q) {
-            const T* pp = part + tid * nrhs + q;
-            const T sum = (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]);
-            v[tid + q * kPanel] = tid < w ? Y2[first + c0 + tid + q * N] * dinv - sum : T(0);
-        }
+        for (int q = 0; q < nrhs; ++q)
+            v[tid + q * kPanel] = tid < w ? Y2[first + c0 + tid + q * N] * dinv - v[tid + q * kPanel] : T(0);
     if (large) {
         // x = Z^T v: Z staged transposed in Ld, wave q4 takes rows 16 q4 .. 16 q4 + 15
 #pragma unroll
@@ -1983,10 +2035,23 @@ __global__ __launch_bounds__(256) void k_persist_solve(DevPlan d, const int* __r
 // ---------------------------------------------------------------------------
 // refinement
 // ---------------------------------------------------------------------------
+// s = a + b rounded, err = its exact rounding error (a + b = s + err, Knuth's
+// two-sum; no reassociation: the build does not allow it).
+__device__ __forceinline__ double two_sum(double a, double b, double& err) {
+    const double s = a + b;
+    const double bb = s - a;
+    err = (a - (s - bb)) + (b - bb);
+    return s;
+}
+
 // Block per chunk of rows (one system); eight lanes share a row.  R = B - K X
 // and, per column, the chunk's kResWidth figures: max |r_i|, max |x_i|,
 // max |b_i|, sum r_i^2, sum b_i^2, and max_i |r_i| / (|K| |x| + |b|)_i (the
-// componentwise backward error; 0/0 counts as 0, r/0 as infinite).
+// componentwise backward error; 0/0 counts as 0, r/0 as infinite).  Each row
+// sum is compensated (products split with fma, sums with two-sum: the Dot2
+// scheme of Ogita, Rump and Oishi, 2005), so r_i is accurate to about one
+// rounding of itself rather than of |K||x|_i.
+
 __global__ __launch_bounds__(256) void k_residual(DevPlan d, const double* __restrict__ K,
                                                   const double* __restrict__ B, int64_t ldb,
                                                   const double* __restrict__ X, int64_t ldx, double* __restrict__ R,
@@ -2000,19 +2065,31 @@ __global__ __launch_bounds__(256) void k_residual(DevPlan d, const double* __res
         double v[kResWidth] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         for (int r = grp; r < chunk_rows[c]; r += 32) {
             const int row = chunk_row0[c] + r;
-            double acc = 0.0, aacc = 0.0;
+            // compensated dot product (sum s + c carries about twice the
+            // working precision): the residual's own rounding stays near one
+            // unit of |b - Kx|, so refinement is not held at the rounding
+            // floor of a plain FP64 row sum
+            double acc = 0.0, cmp = 0.0, aacc = 0.0;
             for (int64_t e = d.Kp[row] + sub; e < d.Kp[row + 1]; e += 8) {
                 const double k = K[e], xv = x[d.Kj[e]];
-                acc += k * xv;
+                const double pr = k * xv;
+                const double pe = fma(k, xv, -pr);
+                double t;
+                acc = two_sum(acc, pr, t);
+                cmp += t + pe;
                 aacc += fabs(k) * fabs(xv);
             }
             for (int o = 4; o > 0; o >>= 1) {
-                acc += __shfl_xor(acc, o, 8);
+                double t;
+                acc = two_sum(acc, __shfl_xor(acc, o, 8), t);
+                cmp += __shfl_xor(cmp, o, 8) + t;
                 aacc += __shfl_xor(aacc, o, 8);
             }
             if (sub == 0) {
                 const double b = B[row + q * ldb];
-                const double rr = b - acc;
+                double t;
+                const double hi = two_sum(b, -acc, t);
+                const double rr = hi + (t - cmp);
                 R[row + q * d.N] = rr;
                 const bool nan = rr != rr;
                 const double den = aacc + fabs(b);
@@ -2295,16 +2372,23 @@ template <typename T>
 void launch_fwd_P(const DevPlan& d, const int* ptab, const int* tasks, int count, const int* segs, const T* F,
                   const T* Z, T* Y, T* Y2, T* U, int nrhs, hipStream_t st) {
     if (count <= 0) return;
-    const size_t lds = (size_t)((kPanel + kSolveRows + 256) * nrhs + 64 * 65) * sizeof(T);
-    launch(k_fwd_P<T>, dim3(count), dim3(256), lds, st, d, ptab, tasks, segs, F, Z, Y, Y2, U, nrhs);
+    const size_t lds = (size_t)((kPanel + kSolveRowsMax + 256) * nrhs + 64 * 65) * sizeof(T);
+    if (nrhs == 1)
+        launch(k_fwd_P<T, 1>, dim3(count), dim3(256), lds, st, d, ptab, tasks, segs, F, Z, Y, Y2, U, nrhs);
+    else
+        launch(k_fwd_P<T, kNrhsMax>, dim3(count), dim3(256), lds, st, d, ptab, tasks, segs, F, Z, Y, Y2, U, nrhs);
 }
 
 template <typename T>
 void launch_bwd_P(const DevPlan& d, const int* ptab, const int* tasks, int count, const T* F, const T* Z,
                   const T* D, T* Y2, T* partial, int* pcnt, int nrhs, hipStream_t st) {
     if (count <= 0) return;
-    const size_t lds = (size_t)((kPanel + kSolveRows + 256) * nrhs + 64 * 65) * sizeof(T);
-    launch(k_bwd_P<T>, dim3(count), dim3(256), lds, st, d, ptab, tasks, F, Z, D, Y2, partial, pcnt, nrhs);
+    const size_t lds = (size_t)((kPanel + kSolveRowsMax + 256) * nrhs + 64 * 65) * sizeof(T);
+    if (nrhs == 1)
+        launch(k_bwd_P<T, 1>, dim3(count), dim3(256), lds, st, d, ptab, tasks, F, Z, D, Y2, partial, pcnt, nrhs);
+    else
+        launch(k_bwd_P<T, kNrhsMax>, dim3(count), dim3(256), lds, st, d, ptab, tasks, F, Z, D, Y2, partial, pcnt,
+               nrhs);
 }
 
 void launch_residual(const DevPlan& d, const double* K, const double* B, int64_t ldb, const double* X, int64_t ldx,
@@ -2366,8 +2450,8 @@ hipError_t configure_kernels(int max_dynamic_lds) {
     hipError_t e = hipSuccess, r;
     const void* fns[] = {(const void*)k_small_fronts<double, true>, (const void*)k_small_fronts<float, true>,
                          (const void*)k_small_fronts<double, false>, (const void*)k_small_fronts<float, false>,
-                         (const void*)k_fwd_P<double>, (const void*)k_fwd_P<float>,
-                         (const void*)k_bwd_P<double>, (const void*)k_bwd_P<float>,
+                         (const void*)k_fwd_P<double, kNrhsMax>, (const void*)k_fwd_P<float, kNrhsMax>,
+                         (const void*)k_bwd_P<double, kNrhsMax>, (const void*)k_bwd_P<float, kNrhsMax>,
                          (const void*)k_fwd_S<double>, (const void*)k_fwd_S<float>,
                          (const void*)k_large_asm<double, true>, (const void*)k_large_asm<float, true>,
                          (const void*)k_bwd_S<double>, (const void*)k_bwd_S<float>,

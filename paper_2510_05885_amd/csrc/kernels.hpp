@@ -11,7 +11,7 @@ constexpr int kNrhsMax = 16;   // columns per solve sweep (wider solves are chun
 constexpr int kPanel = 64;       // pivot block width of the large-front path
 constexpr int kSmallMax = 128;   // largest front order of the LDS-resident path
 constexpr int kTile = 64;        // tile order of the large-front MFMA update
-constexpr int kSolveRows = 64;   // rows below a solve panel per task
+constexpr int kSolveRowsMax = 256;  // rows below a solve panel per task (fewer for wide panels)
 constexpr int kPanInts = 7;      // ints per solve panel: s, c0, w, slot0, tasks, seg0, nseg
 constexpr int kPTaskInts = 6;    // ints per solve task: panel, r0, r1, index, seg0, nseg
 constexpr int kInertiaSlots = 64;  // partial inertia counters per system (spreads the atomics)

@@ -171,12 +171,20 @@ def test_sequence_bitwise_repeatable(opf500k, precision):
     W, J, B = dev(inp.W_val), dev(inp.J_val), dev(b[:, 0])
     seq = [synth.opf_sequence_values(inp, k) for k in range(30)]
     sig = [dev(s) for s, _ in seq]
-    seen = {}
+    seen, first = {}, {}
     for p in range(4):
         for k in range(30):
-            kkt.factor(W, sig[k], J, seq[k][1])
-            X, _ = kkt.solve(B)
-            key = (hashlib.sha1(X.cpu().numpy().tobytes()).hexdigest(), kkt.inertia())
+            rc = kkt.factor(W, sig[k], J, seq[k][1])
+            X, info = kkt.solve(B)
+            x = X.cpu().numpy()
+            key = (hashlib.sha1(x.tobytes()).hexdigest(), kkt.inertia())
+            if k not in first:
+                first[k] = (x, key, rc, info.fell_back_fp64)
+            elif key not in seen[k]:
+                x0, key0, rc0, fb0 = first[k]
+                print(f"[gpu]   pass {p} refactor {k}: rc {rc0}->{rc}, fell back {fb0}->{info.fell_back_fp64}, "
+                      f"inertia {key0[1]}->{key[1]}, max |dx|/|x| {np.abs(x - x0).max() / np.abs(x0).max():.3e}, "
+                      f"entries differing {int((x != x0).sum())}", flush=True)
             seen.setdefault(k, set()).add(key)
     torch.cuda.synchronize()
     varied = {k: len(v) for k, v in seen.items() if len(v) > 1}
