@@ -12,6 +12,9 @@ Paper references (MadNCL, arXiv 2510.05885):
   static pivoting with block-dependent sign ....... Sec. 3.1 ("Sparse LDL^T")
   pivot epsilon, Richardson refinement ............ Sec. 4.3
   inertia (n,0,0) / (n,m,0) ....................... Sec. 3.4, Prop. "inertia"
+  slack elimination K1s, Omega, Delta s ........... Sec. 3.3, Prop. "Condensed KKT system"
+  Delta y, Delta r, Delta z_l, Delta z_u .......... Sec. 3.3 eq. K1-elimination, Sec. 3.2
+                                                    eq. K2-elimination, Sec. 3.1 eq. K3
 """
 from __future__ import annotations
 
@@ -389,3 +392,95 @@ def adjoint_condensed(inp, F: LDL, X, Xbar):
     gJ = -inp.rho * (np.einsum("ec,ec->e", Lam[Jcols], JX[Jrows]) + np.einsum("ec,ec->e", X2[Jcols], JL[Jrows]))
     grho = -float(np.sum(JL * JX))
     return Lam.reshape(np.shape(Xbar)), gW, gS, gJ, grho
+
+
+# ---------------------------------------------------------------------------
+# Slack elimination (K1s) and the recovery of the rest of the Newton step
+# ---------------------------------------------------------------------------
+# Problem NCO (Sec. 3): the rows of J are the equality constraints c_E and the
+# inequality constraints c_I, each inequality row with its slack s_r.  Here
+# every row of J carries a slack barrier value Sigma_s[r]; +inf marks an
+# equality row (the limit of the remark after the proposition: an active
+# inequality, Sigma_s -> inf, is treated as an equality, Omega -> 1).
+# Throughout, `inp.rho` is rho-hat = rho + delta.
+
+def _J(inp) -> sp.csr_matrix:
+    return sp.csr_matrix((inp.J_val, inp.J_colidx, inp.J_rowptr), shape=(inp.m, inp.n))
+
+
+def _W_full(inp) -> sp.csc_matrix:
+    Wl = sp.csc_matrix((inp.W_val, inp.W_rowidx, inp.W_colptr), shape=(inp.n, inp.n))
+    return (Wl + sp.tril(Wl, -1).T).tocsc()
+
+
+def k1s_omega(Sigma_s, rho: float) -> np.ndarray:
+    """Omega_rr = Sigma_s,r / (rho + Sigma_s,r) (Sec. 3.3, Proposition
+    "Condensed KKT system"); 1 on equality rows (Sigma_s = +inf)."""
+    S = np.asarray(Sigma_s, np.float64)
+    om = np.ones_like(S)
+    fin = np.isfinite(S)
+    om[fin] = S[fin] / (rho + S[fin])
+    return om
+
+
+def assemble_k1s(inp, Sigma_s) -> LowerCSC:
+    """K1s = W_t + Sigma_t + rho J_E^T J_E + rho J_I^T Omega J_I (eq. K1s), as
+    W + Sigma + rho J^T diag(omega) J over all rows of J, lower CSC, FP64."""
+    J = _J(inp)
+    K = _W_full(inp) + sp.diags(np.asarray(inp.Sigma, np.float64)) \
+        + inp.rho * (J.T @ sp.diags(k1s_omega(Sigma_s, inp.rho)) @ J)
+    low = sp.tril(K).tocsc()
+    low.sort_indices()
+    return LowerCSC(inp.n, low.indptr.astype(np.int32), low.indices.astype(np.int32), low.data.astype(np.float64))
+
+
+def k1s_rhs(inp, Sigma_s, r_t, r_s) -> np.ndarray:
+    """Right-hand side of eq. K1s as the elimination in the proof produces it:
+    r_t + rho J_I^T (Sigma_s + rho I)^-1 r_s.  (The printed eq. K1s and the
+    proof's intermediate equation omit the factor (Sigma_s + rho I)^-1; the
+    substitution of Delta s into the first block row of K1' gives it.)  r_s
+    is not read on equality rows."""
+    S = np.asarray(Sigma_s, np.float64)
+    ineq = np.isfinite(S)
+    w = np.zeros(inp.m)
+    w[ineq] = np.asarray(r_s, np.float64)[ineq] / (S[ineq] + inp.rho)
+    return np.asarray(r_t, np.float64) + inp.rho * (_J(inp).T @ w)
+
+
+def k1s_recover_ds(inp, Sigma_s, dt, r_s) -> np.ndarray:
+    """Delta s = (Sigma_s + rho I)^-1 (rho J_I Delta t + r_s), the elimination
+    in the proof of the proposition; 0 on equality rows (no slack)."""
+    S = np.asarray(Sigma_s, np.float64)
+    ineq = np.isfinite(S)
+    Jdt = _J(inp) @ np.asarray(dt, np.float64)
+    ds = np.zeros(inp.m)
+    ds[ineq] = (inp.rho * Jdt[ineq] + np.asarray(r_s, np.float64)[ineq]) / (S[ineq] + inp.rho)
+    return ds
+
+
+def barrier_sigma(x, l, u, z_l, z_u) -> np.ndarray:
+    """Sigma = (X - L)^-1 Z_l + (U - X)^-1 Z_u (Sec. 3.1, below eq. K2unreg);
+    an infinite bound gives a zero term."""
+    x, l, u = (np.asarray(a, np.float64) for a in (x, l, u))
+    return z_l / (x - l) + z_u / (u - x)
+
+
+def recover_dy(inp, dx, c, y_k, y) -> np.ndarray:
+    """Delta y = -rho (J Delta x + c) + y_k - y (Sec. 3.3, eq. K1-elimination)."""
+    return -inp.rho * (_J(inp) @ np.asarray(dx, np.float64) + c) + y_k - y
+
+
+def recover_dr(rho: float, dy, y_k, y, r) -> np.ndarray:
+    """Delta r = theta (Delta y - y_k + y) - r with theta = 1 / rho (Sec. 3.2,
+    eq. K2-elimination)."""
+    return (1.0 / rho) * (np.asarray(dy, np.float64) - y_k + y) - r
+
+
+def recover_dz(x, l, u, z_l, z_u, dx, mu: float):
+    """Delta z_l = -(X - L)^-1 (Z_l Delta x - mu e) - z_l and
+    Delta z_u = (U - X)^-1 (Z_u Delta x + mu e) - z_u (Sec. 3.1, the blocks
+    eliminated from eq. K3); with an infinite bound the first term vanishes."""
+    x, l, u, dx = (np.asarray(a, np.float64) for a in (x, l, u, dx))
+    dzl = -(z_l * dx - mu) / (x - l) - z_l
+    dzu = (z_u * dx + mu) / (u - x) - z_u
+    return dzl, dzu
