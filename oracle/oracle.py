@@ -484,3 +484,30 @@ def recover_dz(x, l, u, z_l, z_u, dx, mu: float):
     dzl = -(z_l * dx - mu) / (x - l) - z_l
     dzu = (z_u * dx + mu) / (u - x) - z_u
     return dzl, dzu
+
+
+# ---------------------------------------------------------------------------
+# Inertia correction (Sec. 3.1: delta is raised until the inertia is right)
+# ---------------------------------------------------------------------------
+
+def inertia_correction(inp, form: int, delta_init: float, growth: float, delta_max: float, eps=None,
+                       pivot_scale: str = "global", Sigma_s=None):
+    """Factor with delta = 0, then delta_init, delta_init * growth, ... (the
+    regularization of eq. K2: delta on the primal diagonal and rho-hat =
+    rho + delta) until the inertia is the expected one or delta would exceed
+    delta_max.  Sigma_s given: the K1s form (condensed only).  Returns
+    (delta, attempts, inertia_ok, F, K)."""
+    if eps is None:
+        eps = DEFAULT_EPS[form]
+    delta, attempts = 0.0, 0
+    while True:
+        case = inp.with_values(Sigma=np.asarray(inp.Sigma, np.float64) + delta, rho=inp.rho + delta)
+        K = assemble_k1s(case, Sigma_s) if Sigma_s is not None else assemble(case, form)
+        thr = pivot_thresholds(K, inp.n, inp.m, form, case.rho, eps, pivot_scale)
+        F = LDL(K, signs=block_signs(inp.n, inp.m, form), pivot_thr=thr)
+        attempts += 1
+        ok = F.status == 0 and F.inertia()[:3] == expected_inertia(inp.n, inp.m, form)
+        nxt = delta_init if delta == 0.0 else delta * growth
+        if ok or nxt > delta_max:
+            return delta, attempts, ok, F, K
+        delta = nxt

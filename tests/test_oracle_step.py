@@ -194,3 +194,50 @@ def test_barrier_terms_with_infinite_bounds():
     assert dzl[0] == 0.0 and dzu[1] == 0.0
     far = O.recover_dz(x, np.array([-1e300, -1.0]), np.array([1.0, 1e300]), z_l, z_u, np.array([0.1, 0.2]), 0.01)
     assert np.allclose(far[0], dzl) and np.allclose(far[1], dzu)
+
+
+def _nonconvex(seed, n=40, m=12, rho=3.0):
+    """Small system whose W has clearly negative eigenvalues, so delta = 0
+    gives the wrong inertia; eigenvalue margins keep the PD test unambiguous."""
+    rng = np.random.default_rng(seed)
+    Q, _ = np.linalg.qr(rng.standard_normal((n, n)))
+    ev = np.r_[-rng.uniform(2.0, 30.0, 5), rng.uniform(1.0, 10.0, n - 5)]
+    W = (Q * ev) @ Q.T
+    W[np.abs(W) < 0.2] = 0.0
+    W = (W + W.T) / 2
+    J = np.zeros((m, n))
+    for r in range(m):
+        J[r, rng.choice(n, 3, replace=False)] = rng.standard_normal(3)
+    low = sp.csc_matrix(np.tril(W))
+    Jc = sp.csr_matrix(J)
+    inp = synth.KKTInput(n, m, low.indptr.astype(np.int32), low.indices.astype(np.int32), low.data.copy(),
+                         10.0 ** rng.uniform(-2, 0, n), Jc.indptr.astype(np.int32), Jc.indices.astype(np.int32),
+                         Jc.data.copy(), rho)
+    return inp, W, J
+
+
+@pytest.mark.parametrize("form", [O.CONDENSED, O.STABILIZED])
+def test_inertia_correction_stops_at_first_definite_delta(form):
+    """Brute force with eigvalsh over the same delta sequence: the loop stops
+    at the first delta for which M = W + Sigma + delta I + (rho + delta) J^T J
+    is positive definite -- the condition for inertia (n, 0, 0) of K1 and
+    (n, m, 0) of K2r (Sec. 3.4; eq. ldlk2r)."""
+    inp, W, J = _nonconvex(3)
+    d0, g, dmax = 1e-2, 8.0, 1e6
+    delta, attempts, ok, F, K = O.inertia_correction(inp, form, d0, g, dmax)
+    cands = [0.0] + [d0 * g ** k for k in range(20)]
+    def mineig(dl):
+        M = W + np.diag(inp.Sigma + dl) + (inp.rho + dl) * J.T @ J
+        return np.linalg.eigvalsh(M).min()
+    first = next(k for k, dl in enumerate(cands) if mineig(dl) > 0)
+    assert ok and attempts == first + 1 and delta == cands[first]
+    assert mineig(cands[first]) > 1e-3 and mineig(cands[first - 1]) < -1e-3   # margins: unambiguous
+    ev = np.linalg.eigvalsh(K.dense())
+    expect = O.expected_inertia(inp.n, inp.m, form)
+    assert (int((ev > 0).sum()), int((ev < 0).sum())) == expect[:2]
+
+
+def test_inertia_correction_gives_up_at_delta_max():
+    inp, W, J = _nonconvex(3)
+    delta, attempts, ok, F, K = O.inertia_correction(inp, O.CONDENSED, 1e-6, 2.0, 1e-4)
+    assert not ok and delta <= 1e-4 and delta * 2.0 > 1e-4 and attempts == 1 + 7
