@@ -190,6 +190,85 @@ int ncl_kkt_factor(ncl_kkt_t h, const double *W_val, const double *Sigma,
 int ncl_kkt_factor_batched(ncl_kkt_t h, const double *W_val, const double *Sigma,
                            const double *J_val, const double *rho, void *stream);
 
+/* ---- slack elimination and the rest of the Newton step -------------------
+ * Problem NCO (Sec. 3): the rows of J are equality constraints c_E and
+ * inequality constraints c_I; an inequality row r has a slack s_r whose
+ * barrier diagonal is Sigma_s[r] (Sec. 3.3, the definition of Sigma_s).
+ * Sigma_s is a DEVICE array with one entry per row of J (all systems
+ * concatenated like J's rows): Sigma_s[r] >= 0 for an inequality row, +inf
+ * for an equality row -- the limit in which an active inequality acts as an
+ * equality (the remark after the proposition "Condensed KKT system").
+ * Vectors are device arrays in the caller's (unpermuted) order: length n for
+ * variables, m for rows of J (sums over the systems of a batched handle).
+ * rho below is rho-hat = rho + delta of each system from the last factor
+ * call.  Condensed handles only (NCL_ERR_ARG otherwise); NCL_ERR_STATE before
+ * a factor or on a host-only handle.  Stream-ordered, nothing allocated. */
+
+/* Factors K1s = W_t + Sigma_t + rho J_E^T J_E + rho J_I^T Omega J_I (Sec. 3.3,
+ * eq. K1s) with Omega_rr = Sigma_s,r / (rho + Sigma_s,r): K1's assembly with
+ * the products of row r weighted by Omega_rr (1 on equality rows).  Same
+ * pattern, static pivoting and returns as ncl_kkt_factor; rho is a HOST array
+ * of one penalty per system.  A negative or NaN Sigma_s gives
+ * NCL_ERR_NONFINITE.  ncl_kkt_backward refuses such a factor (NCL_ERR_STATE):
+ * its adjoint is of K1. */
+int ncl_kkt_factor_k1s(ncl_kkt_t h, const double *W_val, const double *Sigma_t,
+                       const double *J_val, const double *Sigma_s, const double *rho,
+                       void *stream);
+
+/* Inertia correction (Sec. 3.1: the regularization delta is raised until
+ * the desired inertia is obtained).  Factors with delta = 0, then delta_init,
+ * delta_init * growth, ... -- delta added to the primal diagonal (Sigma + delta)
+ * and to the penalty (rho-hat = rho + delta, eq. K2) -- and stops at the
+ * first factor with the expected inertia ((n,0,0) condensed, (n,m,0)
+ * stabilized) or when the next delta would exceed delta_max (then the last
+ * factor stays, NCL_WARN_INERTIA).  Sigma_s non-NULL: the K1s form
+ * (condensed only, see ncl_kkt_factor_k1s).  Single-system handles.
+ * delta_init > 0, growth > 1, delta_max >= 0, else NCL_ERR_ARG.  Writes the
+ * delta used and the number of factorizations (host; either may be NULL).
+ * Later solves are of the regularized matrix.  Allocates a Sigma-sized work
+ * array on first use. */
+int ncl_kkt_factor_regularized(ncl_kkt_t h, const double *W_val, const double *Sigma,
+                               const double *J_val, const double *Sigma_s, double rho,
+                               double delta_init, double growth, double delta_max,
+                               double *delta_out, int32_t *attempts_out, void *stream);
+
+/* b = r_t + rho J_I^T (Sigma_s + rho I)^-1 r_s, the right-hand side of K1s
+ * that eliminating Delta s from eq. K1' produces (the proof of the
+ * proposition; the printed eq. K1s omits the factor (Sigma_s + rho I)^-1).
+ * r_t: n, r_s: m (entries of equality rows are not read), b: n. */
+int ncl_kkt_k1s_rhs(ncl_kkt_t h, const double *J_val, const double *r_t, const double *r_s,
+                    const double *Sigma_s, double *b, void *stream);
+
+/* Delta s = (Sigma_s + rho I)^-1 (rho J_I Delta t + r_s) (the proof of the
+ * proposition); ds[r] = 0 on equality rows.  dt: n, r_s and ds: m. */
+int ncl_kkt_k1s_recover(ncl_kkt_t h, const double *J_val, const double *dt, const double *r_s,
+                        const double *Sigma_s, double *ds, void *stream);
+
+/* Delta y = -rho (J Delta x + c) + y_k - y (Sec. 3.3, eq. K1-elimination).
+ * dx: n; c, y_k, y, dy: m. */
+int ncl_kkt_recover_dy(ncl_kkt_t h, const double *J_val, const double *dx, const double *c,
+                       const double *y_k, const double *y, double *dy, void *stream);
+
+/* Delta r = theta (Delta y - y_k + y) - r, theta = 1 / rho (Sec. 3.2,
+ * eq. K2-elimination).  All of length m. */
+int ncl_kkt_recover_dr(ncl_kkt_t h, const double *dy, const double *y_k, const double *y,
+                       const double *r, double *dr, void *stream);
+
+/* Delta z_l = -(X - L)^-1 (Z_l Delta x - mu e) - z_l and
+ * Delta z_u = (U - X)^-1 (Z_u Delta x + mu e) - z_u (Sec. 3.1, the blocks
+ * eliminated from eq. K3).  All of length n; an infinite bound (l = -inf,
+ * u = +inf) makes its quotient 0 (its multiplier should be 0).  Needs an
+ * analyzed device handle, not a factor.  mu must be finite. */
+int ncl_kkt_recover_dz(ncl_kkt_t h, const double *x, const double *l, const double *u,
+                       const double *z_l, const double *z_u, const double *dx, double mu,
+                       double *dz_l, double *dz_u, void *stream);
+
+/* Sigma = (X - L)^-1 Z_l + (U - X)^-1 Z_u, the barrier diagonal (Sec. 3.1,
+ * below eq. K2unreg; Sigma_t and Sigma_s are its t and s parts).  Length n;
+ * infinite bounds give zero terms.  Needs an analyzed device handle. */
+int ncl_kkt_barrier_sigma(ncl_kkt_t h, const double *x, const double *l, const double *u,
+                          const double *z_l, const double *z_u, double *sigma, void *stream);
+
 /* Solve K X = B for nrhs >= 1 columns (device, column-major, leading
  * dimensions >= order), with FP64 iterative refinement against the
  * unperturbed K (Sec. 4.3); refinement runs only when the inertia is the
@@ -220,7 +299,8 @@ int ncl_kkt_inertia_batched(ncl_kkt_t h, int64_t *out);
  *   gRho[s] = -sum_c (J Lambda_c) . (J X_c)   (one value per system).
  * J_val are the Jacobian values of the last factorization (device).  X and
  * Lambda share the leading dimension ld; 1 <= nrhs <= 16.  Any of gW,
- * gSigma, gJ, gRho may be NULL.  Stream-ordered, no synchronization. */
+ * gSigma, gJ, gRho may be NULL.  Stream-ordered, no synchronization.
+ * NCL_ERR_STATE after ncl_kkt_factor_k1s (the factor is then of K1s). */
 int ncl_kkt_backward(ncl_kkt_t h, const double *J_val, const double *X, const double *Lambda, int64_t ld,
                      int32_t nrhs, double *gW, double *gSigma, double *gJ, double *gRho, void *stream);
 

@@ -115,6 +115,13 @@ struct ncl_kkt_s {
     float *F32 = nullptr, *D32 = nullptr, *Y32 = nullptr, *U32 = nullptr, *P32 = nullptr, *M32 = nullptr;
     double *R = nullptr, *DX = nullptr, *Xp = nullptr, *partial_res = nullptr, *res_out = nullptr;
     double *JX = nullptr, *JL = nullptr;
+    // slack elimination: J^T in CSC (row, value index per entry), Omega of the
+    // last factor_k1s call; `weighted` while the factor is of K1s
+    int64_t* Jt_ptr = nullptr;
+    int *Jt_row = nullptr, *Jt_k = nullptr;
+    double* omega = nullptr;
+    bool weighted = false;
+    double* sigma_shift = nullptr;   // Sigma + delta of the inertia correction (allocated on first use)
     int *W_row = nullptr, *W_col = nullptr, *Jj = nullptr, *Jrow_sys = nullptr;
     int64_t *Jp = nullptr, *sys_jrow = nullptr;
     double* host_pinned = nullptr;   // read-back staging
@@ -343,6 +350,28 @@ void setup_device(ncl_kkt_s* h) {
         for (int64_t r = 0; r < P.nJrows; ++r) sj[P.Jrow_sys[r] + 1]++;
         for (int s = 0; s < P.S; ++s) sj[s + 1] += sj[s];
         h->sys_jrow = upload(h, sj);
+        {
+            std::vector<int> jrow(P.nnzJ);
+            for (int64_t r = 0; r < P.nJrows; ++r)
+                for (int64_t k = P.Jp[r]; k < P.Jp[r + 1]; ++k) jrow[k] = (int)r;
+            d.jrow_of = upload(h, jrow);
+            // J^T: entries of each column in increasing row order
+            std::vector<int64_t> tp(P.N + 1, 0);
+            for (int64_t k = 0; k < P.nnzJ; ++k) tp[P.Jj[k] + 1]++;
+            for (int64_t i = 0; i < P.N; ++i) tp[i + 1] += tp[i];
+            std::vector<int> trow(P.nnzJ), tk(P.nnzJ);
+            std::vector<int64_t> fill(tp.begin(), tp.end() - 1);
+            for (int64_t r = 0; r < P.nJrows; ++r)
+                for (int64_t k = P.Jp[r]; k < P.Jp[r + 1]; ++k) {
+                    const int64_t q = fill[P.Jj[k]]++;
+                    trow[q] = (int)r;
+                    tk[q] = (int)k;
+                }
+            h->Jt_ptr = upload(h, tp);
+            h->Jt_row = upload(h, trow);
+            h->Jt_k = upload(h, tk);
+            h->omega = dalloc<double>(h, std::max<int64_t>(P.nJrows, 1));
+        }
         h->JX = dalloc<double>(h, std::max<int64_t>(P.nJrows, 1) * kNrhsMax);
         h->JL = dalloc<double>(h, std::max<int64_t>(P.nJrows, 1) * kNrhsMax);
     }
@@ -685,7 +714,7 @@ int refactor_fp64(ncl_kkt_s* h, hipStream_t st) {
 }
 
 int factor_impl(ncl_kkt_s* h, const double* W, const double* Sigma, const double* J, const double* rho_host,
-                hipStream_t st) {
+                hipStream_t st, const double* Sigma_s = nullptr) {
     if (h->host_only) return NCL_ERR_STATE;
     Plan& P = h->P;
     for (int s = 0; s < P.S; ++s)
@@ -704,7 +733,9 @@ int factor_impl(ncl_kkt_s* h, const double* W, const double* Sigma, const double
             // algorithmic bytes: read W, Sigma, J once, write the lower triangle of K
             const double bytes = 8.0 * ((double)P.nnzW + (double)P.nnzJ + (double)P.N + (double)P.nnz_lower);
             Span sp(h, st, TM_ASM, bytes, 3);
-            launch_assemble(h->d, h->nnzF, W, Sigma, J, h->rho, h->K, st);
+            if (Sigma_s) launch_k1s_omega(P.nJrows, Sigma_s, h->Jrow_sys, h->rho, h->omega, h->nonfinite, st);
+            launch_assemble(h->d, h->nnzF, W, Sigma, J, h->rho, Sigma_s ? h->omega : nullptr, h->K, st);
+            h->weighted = Sigma_s != nullptr;
             launch_chunk_norms(h->d, h->K, h->chunk_row0, h->chunk_rows, h->nchunks, h->partial_norm, st);
             launch_reduce(h->sys_chunk_ptr, P.S, 3, 3, 0u, h->partial_norm, h->norms3, st);
             launch_thresholds(P.S, h->norms3, h->eps, h->pivot_mode, h->rho, h->kmax, h->kinf, h->thr, h->nonfinite,
@@ -952,6 +983,70 @@ Backward solve_refine(ncl_kkt_s* h, const double* B, int64_t ldb, double* X, int
 // ============================================================================
 // C ABI
 // ============================================================================
+namespace {
+
+// Inertia correction: factor with delta = 0, delta_init, delta_init * growth,
+// ... until the inertia is the expected one (or delta would pass delta_max).
+int factor_regularized(ncl_kkt_s* h, const double* W, const double* Sigma, const double* J, const double* Sigma_s,
+                       double rho, double delta_init, double growth, double delta_max, double* delta_out,
+                       int32_t* attempts_out, hipStream_t st) {
+    const int64_t ns = h->P.form == NCL_CONDENSED ? h->P.N : h->P.sys_n[0];   // length of Sigma
+    if (!h->sigma_shift) {
+        try {
+            h->sigma_shift = dalloc<double>(h, ns);
+        } catch (const HipError&) {
+            return NCL_ERR_ALLOC;
+        }
+    }
+    double delta = 0.0;
+    int attempts = 0, rc = NCL_OK;
+    for (;;) {
+        const double rh = rho + delta;
+        const double* sg = Sigma;
+        if (delta > 0.0) {
+            try {
+                HIPCHK(hipSetDevice(h->device));
+                launch_add_scalar(ns, Sigma, delta, h->sigma_shift, st);
+                HIPCHK(hipGetLastError());
+            } catch (const HipError&) {
+                return NCL_ERR_HIP;
+            }
+            sg = h->sigma_shift;
+        }
+        rc = factor_impl(h, W, sg, J, &rh, st, Sigma_s);
+        ++attempts;
+        if (rc < 0) break;
+        const double next = delta == 0.0 ? delta_init : delta * growth;
+        if (h->inertia_ok || !(next <= delta_max)) break;
+        delta = next;
+    }
+    if (delta_out) *delta_out = delta;
+    if (attempts_out) *attempts_out = attempts;
+    return rc;
+}
+
+// The vector kernels below take rho-hat of each system from the last factor.
+int step_ready(ncl_kkt_s* h) {
+    if (!h) return NCL_ERR_ARG;
+    if (h->host_only || !h->factored) return NCL_ERR_STATE;
+    if (h->P.form != NCL_CONDENSED) return NCL_ERR_ARG;
+    return NCL_OK;
+}
+
+template <typename F>
+int run_vec(ncl_kkt_s* h, F&& body) {
+    try {
+        HIPCHK(hipSetDevice(h->device));
+        body();
+        HIPCHK(hipGetLastError());
+    } catch (const HipError&) {
+        return NCL_ERR_HIP;
+    }
+    return NCL_OK;
+}
+
+}  // namespace
+
 extern "C" {
 
 void ncl_kkt_default_options(ncl_kkt_options* o) {
@@ -990,6 +1085,86 @@ int ncl_kkt_factor_batched(ncl_kkt_t h, const double* W_val, const double* Sigma
                            const double* rho, void* stream) {
     if (!h || !rho) return NCL_ERR_ARG;
     return factor_impl(h, W_val, Sigma, J_val, rho, (hipStream_t)stream);
+}
+
+int ncl_kkt_factor_k1s(ncl_kkt_t h, const double* W_val, const double* Sigma_t, const double* J_val,
+                       const double* Sigma_s, const double* rho, void* stream) {
+    if (!h || !rho || !Sigma_s) return NCL_ERR_ARG;
+    if (h->P.form != NCL_CONDENSED) return NCL_ERR_ARG;
+    return factor_impl(h, W_val, Sigma_t, J_val, rho, (hipStream_t)stream, Sigma_s);
+}
+
+int ncl_kkt_factor_regularized(ncl_kkt_t h, const double* W_val, const double* Sigma, const double* J_val,
+                               const double* Sigma_s, double rho, double delta_init, double growth,
+                               double delta_max, double* delta_out, int32_t* attempts_out, void* stream) {
+    if (!h || h->P.S != 1) return NCL_ERR_ARG;
+    if (h->host_only) return NCL_ERR_STATE;
+    if (!(delta_init > 0.0) || !(growth > 1.0) || !(delta_max >= 0.0) || !std::isfinite(delta_init)) return NCL_ERR_ARG;
+    if (Sigma_s && h->P.form != NCL_CONDENSED) return NCL_ERR_ARG;
+    if (!Sigma) return NCL_ERR_ARG;
+    return factor_regularized(h, W_val, Sigma, J_val, Sigma_s, rho, delta_init, growth, delta_max, delta_out,
+                              attempts_out, (hipStream_t)stream);
+}
+
+int ncl_kkt_k1s_rhs(ncl_kkt_t h, const double* J_val, const double* r_t, const double* r_s, const double* Sigma_s,
+                    double* b, void* stream) {
+    int rc = step_ready(h);
+    if (rc) return rc;
+    if ((h->P.nnzJ > 0 && !J_val) || !r_t || !r_s || !Sigma_s || !b) return NCL_ERR_ARG;
+    return run_vec(h, [&] {
+        launch_k1s_rhs(h->P.N, h->Jt_ptr, h->Jt_row, h->Jt_k, J_val, r_t, r_s, Sigma_s, h->Jrow_sys, h->rho,
+                       h->d.row_sys, b, (hipStream_t)stream);
+    });
+}
+
+int ncl_kkt_k1s_recover(ncl_kkt_t h, const double* J_val, const double* dt, const double* r_s,
+                        const double* Sigma_s, double* ds, void* stream) {
+    int rc = step_ready(h);
+    if (rc) return rc;
+    if ((h->P.nnzJ > 0 && !J_val) || !dt || !r_s || !Sigma_s || !ds) return NCL_ERR_ARG;
+    return run_vec(h, [&] {
+        launch_k1s_ds(h->P.nJrows, h->Jp, h->Jj, J_val, dt, r_s, Sigma_s, h->Jrow_sys, h->rho, ds,
+                      (hipStream_t)stream);
+    });
+}
+
+int ncl_kkt_recover_dy(ncl_kkt_t h, const double* J_val, const double* dx, const double* c, const double* y_k,
+                       const double* y, double* dy, void* stream) {
+    int rc = step_ready(h);
+    if (rc) return rc;
+    if ((h->P.nnzJ > 0 && !J_val) || !dx || !c || !y_k || !y || !dy) return NCL_ERR_ARG;
+    return run_vec(h, [&] {
+        launch_recover_dy(h->P.nJrows, h->Jp, h->Jj, J_val, dx, c, y_k, y, h->Jrow_sys, h->rho, dy,
+                          (hipStream_t)stream);
+    });
+}
+
+int ncl_kkt_recover_dr(ncl_kkt_t h, const double* dy, const double* y_k, const double* y, const double* r,
+                       double* dr, void* stream) {
+    int rc = step_ready(h);
+    if (rc) return rc;
+    if (!dy || !y_k || !y || !r || !dr) return NCL_ERR_ARG;
+    return run_vec(h, [&] {
+        launch_recover_dr(h->P.nJrows, dy, y_k, y, r, h->Jrow_sys, h->rho, dr, (hipStream_t)stream);
+    });
+}
+
+int ncl_kkt_recover_dz(ncl_kkt_t h, const double* x, const double* l, const double* u, const double* z_l,
+                       const double* z_u, const double* dx, double mu, double* dz_l, double* dz_u, void* stream) {
+    if (!h) return NCL_ERR_ARG;
+    if (h->host_only) return NCL_ERR_STATE;
+    if (!x || !l || !u || !z_l || !z_u || !dx || !dz_l || !dz_u || !std::isfinite(mu)) return NCL_ERR_ARG;
+    return run_vec(h, [&] {
+        launch_recover_dz(h->P.N, x, l, u, z_l, z_u, dx, mu, dz_l, dz_u, (hipStream_t)stream);
+    });
+}
+
+int ncl_kkt_barrier_sigma(ncl_kkt_t h, const double* x, const double* l, const double* u, const double* z_l,
+                          const double* z_u, double* sigma, void* stream) {
+    if (!h) return NCL_ERR_ARG;
+    if (h->host_only) return NCL_ERR_STATE;
+    if (!x || !l || !u || !z_l || !z_u || !sigma) return NCL_ERR_ARG;
+    return run_vec(h, [&] { launch_barrier_sigma(h->P.N, x, l, u, z_l, z_u, sigma, (hipStream_t)stream); });
 }
 
 int ncl_kkt_solve(ncl_kkt_t h, const double* B, int64_t ldb, double* X, int64_t ldx, int32_t nrhs, void* stream,
@@ -1069,6 +1244,7 @@ int ncl_kkt_backward(ncl_kkt_t h, const double* J_val, const double* X, const do
     if (!h) return NCL_ERR_ARG;
     if (h->host_only || !h->factored) return NCL_ERR_STATE;
     if (h->P.form != NCL_CONDENSED) return NCL_ERR_ARG;
+    if (h->weighted) return NCL_ERR_STATE;   // the adjoint is of K1, not of K1s
     if (!X || !Lambda || nrhs < 1 || nrhs > kNrhsMax || ld < h->P.N) return NCL_ERR_ARG;
     if ((gJ || gRho) && h->P.nnzJ > 0 && !J_val) return NCL_ERR_ARG;
     hipStream_t st = (hipStream_t)stream;
@@ -1088,6 +1264,7 @@ int ncl_kkt_backward_noalloc(ncl_kkt_t h, const double* J_val, const double* X, 
     if (!h) return NCL_ERR_ARG;
     if (h->host_only || !h->factored) return NCL_ERR_STATE;
     if (h->P.form != NCL_CONDENSED) return NCL_ERR_ARG;
+    if (h->weighted) return NCL_ERR_STATE;   // the adjoint is of K1, not of K1s
     if (!X || !Lambda || nrhs < 1 || nrhs > kNrhsMax || ld < h->P.N) return NCL_ERR_ARG;
     if ((gJ || gRho) && h->P.nnzJ > 0 && !J_val) return NCL_ERR_ARG;
     const int64_t need = 2 * h->P.nJrows * (int64_t)nrhs;   // J X and J Lambda, nJrows x nrhs each

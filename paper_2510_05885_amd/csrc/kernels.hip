@@ -458,7 +458,7 @@ inline unsigned int blocks_for(int64_t n, int bs) { return (unsigned int)((n + b
 // ---------------------------------------------------------------------------
 __global__ void k_assemble(DevPlan d, int64_t nnzF, const double* __restrict__ W, const double* __restrict__ Sigma,
                            const double* __restrict__ J, const double* __restrict__ sys_rho,
-                           double* __restrict__ K) {
+                           const double* __restrict__ omega, double* __restrict__ K) {
     const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= nnzF) return;
     const int row = d.Krow[e];
@@ -473,7 +473,17 @@ __global__ void k_assemble(DevPlan d, int64_t nnzF, const double* __restrict__ W
     const int64_t q0 = d.prod_ptr[e], q1 = d.prod_ptr[e + 1];
     if (q1 > q0) {
         double acc = 0.0;
-        for (int64_t q = q0; q < q1; ++q) acc += J[d.prod_a[q]] * J[d.prod_b[q]];
+        // explicit fma in both: with every Omega_rr = 1 the K1s products
+        // round exactly like K1's
+        if (omega) {
+            // K1s: each row r of J weighted by Omega_rr
+            for (int64_t q = q0; q < q1; ++q) {
+                const int a = d.prod_a[q];
+                acc = fma(omega[d.jrow_of[a]] * J[a], J[d.prod_b[q]], acc);
+            }
+        } else {
+            for (int64_t q = q0; q < q1; ++q) acc = fma(J[d.prod_a[q]], J[d.prod_b[q]], acc);
+        }
         v += rho * acc;
     }
     if (fl & 2) v += -1.0 / rho;
@@ -2151,6 +2161,119 @@ __global__ void k_zero_i32(int* p, int64_t n) {
 // ---------------------------------------------------------------------------
 // adjoint (condensed form)
 // ---------------------------------------------------------------------------
+// ---------------------------------------------------------------------------
+// slack elimination (K1s) and the recovery of the rest of the Newton step
+// ---------------------------------------------------------------------------
+// Every row r of J carries Sigma_s[r] >= 0 (its slack's barrier term) or
+// +inf (an equality row: Omega = 1, no slack); rho_r = rho-hat of the row's
+// system.  Sec. 3.3, Proposition "Condensed KKT system" and its proof.
+
+// Omega_rr = Sigma_s / (rho + Sigma_s); a negative or NaN Sigma_s sets
+// kNonfiniteInput.
+__global__ void k_k1s_omega(int64_t nrows, const double* __restrict__ Sigma_s, const int* __restrict__ Jrow_sys,
+                            const double* __restrict__ sys_rho, double* __restrict__ omega, int* nonfinite) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    const double S = Sigma_s[r];
+    if (!(S >= 0.0)) {
+        atomicOr(nonfinite, kNonfiniteInput);
+        omega[r] = 0.0;
+        return;
+    }
+    omega[r] = isinf(S) ? 1.0 : S / (sys_rho[Jrow_sys[r]] + S);
+}
+
+// b = r_t + rho J_I^T (Sigma_s + rho I)^-1 r_s: one thread per variable i,
+// over the rows of column i of J in increasing order (J^T in CSC: Jt_ptr,
+// Jt_row, Jt_k = index of the entry in J's values).
+__global__ void k_k1s_rhs(int64_t n, const int64_t* __restrict__ Jt_ptr, const int* __restrict__ Jt_row,
+                          const int* __restrict__ Jt_k, const double* __restrict__ J, const double* __restrict__ r_t,
+                          const double* __restrict__ r_s, const double* __restrict__ Sigma_s,
+                          const int* __restrict__ Jrow_sys, const double* __restrict__ sys_rho,
+                          const int* __restrict__ row_sys, double* __restrict__ b) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double acc = 0.0;
+    for (int64_t q = Jt_ptr[i]; q < Jt_ptr[i + 1]; ++q) {
+        const int r = Jt_row[q];
+        const double S = Sigma_s[r];
+        if (isinf(S)) continue;
+        acc += J[Jt_k[q]] * (r_s[r] / (S + sys_rho[Jrow_sys[r]]));
+    }
+    b[i] = r_t[i] + sys_rho[row_sys[i]] * acc;
+}
+
+// Delta s_r = (rho (J dt)_r + r_s,r) / (Sigma_s,r + rho) on inequality rows, 0
+// on equality rows.
+__global__ void k_k1s_ds(int64_t nrows, const int64_t* __restrict__ Jp, const int* __restrict__ Jj,
+                         const double* __restrict__ J, const double* __restrict__ dt, const double* __restrict__ r_s,
+                         const double* __restrict__ Sigma_s, const int* __restrict__ Jrow_sys,
+                         const double* __restrict__ sys_rho, double* __restrict__ ds) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    const double S = Sigma_s[r];
+    if (isinf(S)) {
+        ds[r] = 0.0;
+        return;
+    }
+    double a = 0.0;
+    for (int64_t k = Jp[r]; k < Jp[r + 1]; ++k) a += J[k] * dt[Jj[k]];
+    const double rho = sys_rho[Jrow_sys[r]];
+    ds[r] = (rho * a + r_s[r]) / (S + rho);
+}
+
+// Delta y = -rho (J dx + c) + y_k - y (Sec. 3.3, eq. K1-elimination).
+__global__ void k_recover_dy(int64_t nrows, const int64_t* __restrict__ Jp, const int* __restrict__ Jj,
+                             const double* __restrict__ J, const double* __restrict__ dx, const double* __restrict__ c,
+                             const double* __restrict__ y_k, const double* __restrict__ y,
+                             const int* __restrict__ Jrow_sys, const double* __restrict__ sys_rho,
+                             double* __restrict__ dy) {
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= nrows) return;
+    double a = 0.0;
+    for (int64_t k = Jp[r]; k < Jp[r + 1]; ++k) a += J[k] * dx[Jj[k]];
+    dy[r] = -sys_rho[Jrow_sys[r]] * (a + c[r]) + y_k[r] - y[r];
+}
+
+// Delta r = (Delta y - y_k + y) / rho - r (Sec. 3.2, eq. K2-elimination,
+// theta = 1 / rho-hat).
+__global__ void k_recover_dr(int64_t nrows, const double* __restrict__ dy, const double* __restrict__ y_k,
+                             const double* __restrict__ y, const double* __restrict__ r,
+                             const int* __restrict__ Jrow_sys, const double* __restrict__ sys_rho,
+                             double* __restrict__ dr) {
+    const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nrows) return;
+    dr[q] = (1.0 / sys_rho[Jrow_sys[q]]) * (dy[q] - y_k[q] + y[q]) - r[q];
+}
+
+// Delta z_l = -(Z_l dx - mu) / (x - l) - z_l, Delta z_u = (Z_u dx + mu) / (u - x)
+// - z_u (Sec. 3.1, the blocks eliminated from eq. K3); an infinite bound
+// makes the quotient 0.
+__global__ void k_recover_dz(int64_t n, const double* __restrict__ x, const double* __restrict__ l,
+                             const double* __restrict__ u, const double* __restrict__ z_l,
+                             const double* __restrict__ z_u, const double* __restrict__ dx, double mu,
+                             double* __restrict__ dz_l, double* __restrict__ dz_u) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    dz_l[i] = -(z_l[i] * dx[i] - mu) / (x[i] - l[i]) - z_l[i];
+    dz_u[i] = (z_u[i] * dx[i] + mu) / (u[i] - x[i]) - z_u[i];
+}
+
+// out = in + delta (the primal regularization of eq. K2 applied to Sigma).
+__global__ void k_add_scalar(int64_t n, const double* __restrict__ in, double delta, double* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[i] + delta;
+}
+
+// Sigma = Z_l / (x - l) + Z_u / (u - x) (Sec. 3.1, below eq. K2unreg).
+__global__ void k_barrier_sigma(int64_t n, const double* __restrict__ x, const double* __restrict__ l,
+                                const double* __restrict__ u, const double* __restrict__ z_l,
+                                const double* __restrict__ z_u, double* __restrict__ sigma) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    sigma[i] = z_l[i] / (x[i] - l[i]) + z_u[i] / (u[i] - x[i]);
+}
+
 __global__ void k_jmul(int64_t nrows, const int64_t* __restrict__ Jp, const int* __restrict__ Jj,
                        const double* __restrict__ Jv, const double* __restrict__ X, const double* __restrict__ Lam,
                        int64_t ld, int nrhs, double* JX, double* JL) {
@@ -2254,9 +2377,63 @@ LaunchTimer* set_launch_timer(LaunchTimer* t) {
 }
 
 void launch_assemble(const DevPlan& d, int64_t nnzF, const double* W, const double* Sigma, const double* J,
-                     const double* sys_rho, double* K, hipStream_t st) {
+                     const double* sys_rho, const double* omega, double* K, hipStream_t st) {
     if (nnzF <= 0) return;
-    launch(k_assemble, dim3(blocks_for(nnzF, 256)), dim3(256), 0, st, d, nnzF, W, Sigma, J, sys_rho, K);
+    launch(k_assemble, dim3(blocks_for(nnzF, 256)), dim3(256), 0, st, d, nnzF, W, Sigma, J, sys_rho, omega, K);
+}
+
+void launch_k1s_omega(int64_t nrows, const double* Sigma_s, const int* Jrow_sys, const double* sys_rho, double* omega,
+                      int* nonfinite, hipStream_t st) {
+    if (nrows <= 0) return;
+    launch(k_k1s_omega, dim3(blocks_for(nrows, 256)), dim3(256), 0, st, nrows, Sigma_s, Jrow_sys, sys_rho, omega,
+           nonfinite);
+}
+
+void launch_k1s_rhs(int64_t n, const int64_t* Jt_ptr, const int* Jt_row, const int* Jt_k, const double* J,
+                    const double* r_t, const double* r_s, const double* Sigma_s, const int* Jrow_sys,
+                    const double* sys_rho, const int* row_sys, double* b, hipStream_t st) {
+    if (n <= 0) return;
+    launch(k_k1s_rhs, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, Jt_ptr, Jt_row, Jt_k, J, r_t, r_s, Sigma_s,
+           Jrow_sys, sys_rho, row_sys, b);
+}
+
+void launch_k1s_ds(int64_t nrows, const int64_t* Jp, const int* Jj, const double* J, const double* dt,
+                   const double* r_s, const double* Sigma_s, const int* Jrow_sys, const double* sys_rho, double* ds,
+                   hipStream_t st) {
+    if (nrows <= 0) return;
+    launch(k_k1s_ds, dim3(blocks_for(nrows, 256)), dim3(256), 0, st, nrows, Jp, Jj, J, dt, r_s, Sigma_s, Jrow_sys,
+           sys_rho, ds);
+}
+
+void launch_recover_dy(int64_t nrows, const int64_t* Jp, const int* Jj, const double* J, const double* dx,
+                       const double* c, const double* y_k, const double* y, const int* Jrow_sys, const double* sys_rho,
+                       double* dy, hipStream_t st) {
+    if (nrows <= 0) return;
+    launch(k_recover_dy, dim3(blocks_for(nrows, 256)), dim3(256), 0, st, nrows, Jp, Jj, J, dx, c, y_k, y, Jrow_sys,
+           sys_rho, dy);
+}
+
+void launch_recover_dr(int64_t nrows, const double* dy, const double* y_k, const double* y, const double* r,
+                       const int* Jrow_sys, const double* sys_rho, double* dr, hipStream_t st) {
+    if (nrows <= 0) return;
+    launch(k_recover_dr, dim3(blocks_for(nrows, 256)), dim3(256), 0, st, nrows, dy, y_k, y, r, Jrow_sys, sys_rho, dr);
+}
+
+void launch_recover_dz(int64_t n, const double* x, const double* l, const double* u, const double* z_l,
+                       const double* z_u, const double* dx, double mu, double* dz_l, double* dz_u, hipStream_t st) {
+    if (n <= 0) return;
+    launch(k_recover_dz, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, x, l, u, z_l, z_u, dx, mu, dz_l, dz_u);
+}
+
+void launch_add_scalar(int64_t n, const double* in, double delta, double* out, hipStream_t st) {
+    if (n <= 0) return;
+    launch(k_add_scalar, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, in, delta, out);
+}
+
+void launch_barrier_sigma(int64_t n, const double* x, const double* l, const double* u, const double* z_l,
+                          const double* z_u, double* sigma, hipStream_t st) {
+    if (n <= 0) return;
+    launch(k_barrier_sigma, dim3(blocks_for(n, 256)), dim3(256), 0, st, n, x, l, u, z_l, z_u, sigma);
 }
 
 void launch_chunk_norms(const DevPlan& d, const double* K, const int* chunk_row0, const int* chunk_rows, int nchunks,

@@ -49,6 +49,7 @@ struct DevPlan {
     const int* child_list;
     const int* sn_sys;
     const int* sn_parent;      // parent supernode or -1
+    const int* jrow_of;        // row of J of each stored J entry (condensed form)
     const int64_t* kent_ptr;
     const int64_t* kent_csr;
     const int* kent_pos;
@@ -89,8 +90,29 @@ struct LaunchTimer {
 };
 LaunchTimer* set_launch_timer(LaunchTimer* t);   // returns the previous one
 
+// omega: per row of J, the weight of its products (K1s), or nullptr (K1, K2r).
 void launch_assemble(const DevPlan& d, int64_t nnzF, const double* W, const double* Sigma, const double* J,
-                     const double* sys_rho, double* K, hipStream_t st);
+                     const double* sys_rho, const double* omega, double* K, hipStream_t st);
+// ---- slack elimination (K1s) and step recovery (vectors in the caller's
+// order; rows of J of all systems concatenated; rho per system) -------------
+void launch_k1s_omega(int64_t nrows, const double* Sigma_s, const int* Jrow_sys, const double* sys_rho, double* omega,
+                      int* nonfinite, hipStream_t st);
+void launch_k1s_rhs(int64_t n, const int64_t* Jt_ptr, const int* Jt_row, const int* Jt_k, const double* J,
+                    const double* r_t, const double* r_s, const double* Sigma_s, const int* Jrow_sys,
+                    const double* sys_rho, const int* row_sys, double* b, hipStream_t st);
+void launch_k1s_ds(int64_t nrows, const int64_t* Jp, const int* Jj, const double* J, const double* dt,
+                   const double* r_s, const double* Sigma_s, const int* Jrow_sys, const double* sys_rho, double* ds,
+                   hipStream_t st);
+void launch_recover_dy(int64_t nrows, const int64_t* Jp, const int* Jj, const double* J, const double* dx,
+                       const double* c, const double* y_k, const double* y, const int* Jrow_sys, const double* sys_rho,
+                       double* dy, hipStream_t st);
+void launch_recover_dr(int64_t nrows, const double* dy, const double* y_k, const double* y, const double* r,
+                       const int* Jrow_sys, const double* sys_rho, double* dr, hipStream_t st);
+void launch_recover_dz(int64_t n, const double* x, const double* l, const double* u, const double* z_l,
+                       const double* z_u, const double* dx, double mu, double* dz_l, double* dz_u, hipStream_t st);
+void launch_add_scalar(int64_t n, const double* in, double delta, double* out, hipStream_t st);
+void launch_barrier_sigma(int64_t n, const double* x, const double* l, const double* u, const double* z_l,
+                          const double* z_u, double* sigma, hipStream_t st);
 // Block per chunk of rows: partial[3c..3c+2] = max |K_ij|, max row sum of |K|,
 // max |K_ij| over the primal block.
 void launch_chunk_norms(const DevPlan& d, const double* K, const int* chunk_row0, const int* chunk_rows, int nchunks,

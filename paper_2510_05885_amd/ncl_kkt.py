@@ -24,6 +24,7 @@ NCL_FP64, NCL_FP32_IR = 0, 1
 NCL_ORDER_ND, NCL_ORDER_NATURAL, NCL_ORDER_USER = 0, 1, 2
 NCL_PIVOT_GLOBAL, NCL_PIVOT_BLOCK, NCL_PIVOT_ABSOLUTE = 0, 1, 2
 NCL_OK = 0
+NCL_ERR_ARG, NCL_ERR_PATTERN, NCL_ERR_ALLOC, NCL_ERR_HIP, NCL_ERR_STATE, NCL_ERR_NONFINITE = -1, -2, -3, -4, -5, -6
 NCL_ERR_SCRATCH = -7
 NCL_WARN_INERTIA, NCL_WARN_IR_NOT_CONVERGED, NCL_WARN_FELL_BACK_FP64 = 1, 2, 3
 
@@ -32,7 +33,9 @@ EXPORTED = [
     "ncl_kkt_factor", "ncl_kkt_factor_batched", "ncl_kkt_solve", "ncl_kkt_inertia",
     "ncl_kkt_inertia_batched", "ncl_kkt_backward", "ncl_kkt_backward_noalloc", "ncl_kkt_get_stats", "ncl_kkt_get_perm",
     "ncl_kkt_get_supernodes", "ncl_kkt_get_system_times", "ncl_kkt_set_timing", "ncl_kkt_get_timing",
-    "ncl_kkt_destroy", "ncl_kkt_strerror",
+    "ncl_kkt_destroy", "ncl_kkt_strerror", "ncl_kkt_factor_k1s", "ncl_kkt_k1s_rhs", "ncl_kkt_k1s_recover",
+    "ncl_kkt_recover_dy", "ncl_kkt_recover_dr", "ncl_kkt_recover_dz", "ncl_kkt_barrier_sigma",
+    "ncl_kkt_factor_regularized",
 ]
 
 
@@ -105,6 +108,23 @@ def lib():
     L.ncl_kkt_factor.restype = C.c_int
     L.ncl_kkt_factor_batched.argtypes = [vp, vp, vp, vp, C.POINTER(C.c_double), vp]
     L.ncl_kkt_factor_batched.restype = C.c_int
+    L.ncl_kkt_factor_k1s.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_double), vp]
+    L.ncl_kkt_factor_k1s.restype = C.c_int
+    L.ncl_kkt_factor_regularized.argtypes = [vp, vp, vp, vp, vp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                             C.POINTER(C.c_double), C.POINTER(C.c_int32), vp]
+    L.ncl_kkt_factor_regularized.restype = C.c_int
+    L.ncl_kkt_k1s_rhs.argtypes = [vp] * 7
+    L.ncl_kkt_k1s_rhs.restype = C.c_int
+    L.ncl_kkt_k1s_recover.argtypes = [vp] * 7
+    L.ncl_kkt_k1s_recover.restype = C.c_int
+    L.ncl_kkt_recover_dy.argtypes = [vp] * 8
+    L.ncl_kkt_recover_dy.restype = C.c_int
+    L.ncl_kkt_recover_dr.argtypes = [vp] * 7
+    L.ncl_kkt_recover_dr.restype = C.c_int
+    L.ncl_kkt_recover_dz.argtypes = [vp] * 7 + [C.c_double, vp, vp, vp]
+    L.ncl_kkt_recover_dz.restype = C.c_int
+    L.ncl_kkt_barrier_sigma.argtypes = [vp] * 8
+    L.ncl_kkt_barrier_sigma.restype = C.c_int
     L.ncl_kkt_solve.argtypes = [vp, vp, i64, vp, i64, i32, vp, C.POINTER(SolveInfo)]
     L.ncl_kkt_solve.restype = C.c_int
     L.ncl_kkt_inertia.argtypes = [vp] + [C.POINTER(C.c_int64)] * 4
@@ -250,8 +270,9 @@ class Info:
 class KKT:
     """One analyzed KKT pattern (or a batch of independent ones)."""
 
-    def __init__(self, handle, order, S, nnzW, nnzJ, form, n=None):
+    def __init__(self, handle, order, S, nnzW, nnzJ, form, n=None, m=0):
         self._h = handle
+        self.m = m                            # rows of J (all systems)
         self.order = order
         self.S = S
         self.nnzW = nnzW
@@ -270,7 +291,8 @@ class KKT:
         _check(f(C.byref(h), C.byref(o), int(n), int(m), *[a[1] for a in arrs]), "ncl_kkt_analyze")
         del keep
         order = n if o.form == NCL_CONDENSED else n + m
-        return cls(h, order, 1, int(arrs[0][0][-1]), int(arrs[2][0][-1]) if m > 0 else 0, o.form, n=int(n))
+        return cls(h, order, 1, int(arrs[0][0][-1]), int(arrs[2][0][-1]) if m > 0 else 0, o.form, n=int(n),
+                   m=int(m))
 
     @classmethod
     def from_input(cls, inp, host_only=False, **opts):
@@ -298,7 +320,7 @@ class KKT:
                "ncl_kkt_analyze_batched")
         del keep
         return cls(h, int(ns.sum()), cnt, int(sum(int(i.W_colptr[-1]) for i in inputs)),
-                   int(sum(int(i.J_rowptr[-1]) for i in inputs)), o.form)
+                   int(sum(int(i.J_rowptr[-1]) for i in inputs)), o.form, m=int(ms.sum()))
 
     def close(self):
         if self._h:
@@ -329,6 +351,96 @@ class KKT:
                 raise ValueError(f"rho has {r.size} values, expected one per system ({self.S})")
             rc = lib().ncl_kkt_factor_batched(self._h, pw, ps, pj, r.ctypes.data_as(C.POINTER(C.c_double)), st)
         return _check(rc, "ncl_kkt_factor")
+
+    # ------------------------------------------- slack elimination, recovery
+    # Sigma_s: one value per row of J (float64 CUDA), +inf on equality rows.
+    def factor_k1s(self, W_val, Sigma_t, J_val, Sigma_s, rho, stream=None):
+        """Assemble and factor K1s (eq. K1s): K1 with the products of row r of
+        J weighted by Sigma_s,r / (rho + Sigma_s,r)."""
+        pw = _dev(W_val, self.nnzW, "W_val", allow_none=self.nnzW == 0)
+        ps = _dev(Sigma_t, self.n, "Sigma_t")
+        pj = _dev(J_val, self.nnzJ, "J_val", allow_none=self.nnzJ == 0)
+        pss = _dev(Sigma_s, self.m, "Sigma_s")
+        r = np.ascontiguousarray(np.asarray(rho, np.float64).reshape(-1))
+        if r.size != self.S:
+            raise ValueError(f"rho has {r.size} values, expected one per system ({self.S})")
+        self.generation += 1
+        rc = lib().ncl_kkt_factor_k1s(self._h, pw, ps, pj, pss, r.ctypes.data_as(C.POINTER(C.c_double)),
+                                      _stream(stream))
+        return _check(rc, "ncl_kkt_factor_k1s")
+
+    def factor_regularized(self, W_val, Sigma, J_val, rho, delta_init=1e-4, growth=8.0, delta_max=1e40,
+                           Sigma_s=None, stream=None):
+        """Inertia correction: factors with delta = 0, delta_init, delta_init *
+        growth, ... until the inertia is the expected one.  Returns (status,
+        delta, factorizations)."""
+        pw = _dev(W_val, self.nnzW, "W_val", allow_none=self.nnzW == 0)
+        ps = _dev(Sigma, self.n, "Sigma")
+        pj = _dev(J_val, self.nnzJ, "J_val", allow_none=self.nnzJ == 0)
+        pss = _dev(Sigma_s, self.m, "Sigma_s", allow_none=True)
+        d, a = C.c_double(), C.c_int32()
+        self.generation += 1
+        rc = lib().ncl_kkt_factor_regularized(self._h, pw, ps, pj, pss, float(rho), float(delta_init),
+                                              float(growth), float(delta_max), C.byref(d), C.byref(a),
+                                              _stream(stream))
+        return _check(rc, "ncl_kkt_factor_regularized"), d.value, a.value
+
+    def _out(self, t, numel, like):
+        import torch
+        return torch.empty(numel, dtype=torch.float64, device=like.device) if t is None else t
+
+    def k1s_rhs(self, J_val, r_t, r_s, Sigma_s, b=None, stream=None):
+        """b = r_t + rho J_I^T (Sigma_s + rho I)^-1 r_s (length n)."""
+        b = self._out(b, self.n, r_t)
+        _check(lib().ncl_kkt_k1s_rhs(self._h, _dev(J_val, self.nnzJ, "J_val", self.nnzJ == 0),
+                                     _dev(r_t, self.n, "r_t"), _dev(r_s, self.m, "r_s"),
+                                     _dev(Sigma_s, self.m, "Sigma_s"), _dev(b, self.n, "b"), _stream(stream)),
+               "ncl_kkt_k1s_rhs")
+        return b
+
+    def k1s_recover(self, J_val, dt, r_s, Sigma_s, ds=None, stream=None):
+        """Delta s = (Sigma_s + rho I)^-1 (rho J_I dt + r_s); 0 on equality rows."""
+        ds = self._out(ds, self.m, dt)
+        _check(lib().ncl_kkt_k1s_recover(self._h, _dev(J_val, self.nnzJ, "J_val", self.nnzJ == 0),
+                                         _dev(dt, self.n, "dt"), _dev(r_s, self.m, "r_s"),
+                                         _dev(Sigma_s, self.m, "Sigma_s"), _dev(ds, self.m, "ds"), _stream(stream)),
+               "ncl_kkt_k1s_recover")
+        return ds
+
+    def recover_dy(self, J_val, dx, c, y_k, y, dy=None, stream=None):
+        """Delta y = -rho (J dx + c) + y_k - y."""
+        dy = self._out(dy, self.m, dx)
+        _check(lib().ncl_kkt_recover_dy(self._h, _dev(J_val, self.nnzJ, "J_val", self.nnzJ == 0),
+                                        _dev(dx, self.n, "dx"), _dev(c, self.m, "c"), _dev(y_k, self.m, "y_k"),
+                                        _dev(y, self.m, "y"), _dev(dy, self.m, "dy"), _stream(stream)),
+               "ncl_kkt_recover_dy")
+        return dy
+
+    def recover_dr(self, dy, y_k, y, r, dr=None, stream=None):
+        """Delta r = (dy - y_k + y) / rho - r."""
+        dr = self._out(dr, self.m, dy)
+        _check(lib().ncl_kkt_recover_dr(self._h, _dev(dy, self.m, "dy"), _dev(y_k, self.m, "y_k"),
+                                        _dev(y, self.m, "y"), _dev(r, self.m, "r"), _dev(dr, self.m, "dr"),
+                                        _stream(stream)), "ncl_kkt_recover_dr")
+        return dr
+
+    def recover_dz(self, x, l, u, z_l, z_u, dx, mu, dz_l=None, dz_u=None, stream=None):
+        """(Delta z_l, Delta z_u) of the eliminated bound-multiplier blocks."""
+        dz_l = self._out(dz_l, self.n, x)
+        dz_u = self._out(dz_u, self.n, x)
+        ptrs = [_dev(a, self.n, nm) for a, nm in ((x, "x"), (l, "l"), (u, "u"), (z_l, "z_l"), (z_u, "z_u"),
+                                                   (dx, "dx"))]
+        _check(lib().ncl_kkt_recover_dz(self._h, *ptrs, float(mu), _dev(dz_l, self.n, "dz_l"),
+                                        _dev(dz_u, self.n, "dz_u"), _stream(stream)), "ncl_kkt_recover_dz")
+        return dz_l, dz_u
+
+    def barrier_sigma(self, x, l, u, z_l, z_u, sigma=None, stream=None):
+        """Sigma = Z_l / (x - l) + Z_u / (u - x)."""
+        sigma = self._out(sigma, self.n, x)
+        ptrs = [_dev(a, self.n, nm) for a, nm in ((x, "x"), (l, "l"), (u, "u"), (z_l, "z_l"), (z_u, "z_u"))]
+        _check(lib().ncl_kkt_barrier_sigma(self._h, *ptrs, _dev(sigma, self.n, "sigma"), _stream(stream)),
+               "ncl_kkt_barrier_sigma")
+        return sigma
 
     def solve(self, B, X=None, stream=None):
         """Solve K X = B (B: (order,) or (order, nrhs) float64 on the device)."""

@@ -268,3 +268,15 @@ def batched_system(s: int, N_s: int) -> KKTInput:
                       sigma_seed=100000 + s)
     inp.meta["batch_index"] = s
     return inp
+
+
+def slack_sigma(m: int, seed: int = 9, ineq_fraction: float = 1.0 / 3.0, lo: float = -4.0,
+                hi: float = 4.0) -> np.ndarray:
+    """Slack barrier values for the rows of J of a problem with inequality
+    constraints: each row is an inequality with probability `ineq_fraction`,
+    with Sigma_s = 10^U(lo, hi); the other rows are equality rows, marked +inf.
+    Draw order: the row kinds, then the values of all rows."""
+    rng = np.random.default_rng(seed)
+    ineq = rng.uniform(size=m) < ineq_fraction
+    vals = 10.0 ** rng.uniform(lo, hi, size=m)
+    return np.where(ineq, vals, np.inf)
