@@ -425,7 +425,8 @@ def kernel_breakdown(tm, refactors):
     add("large_panel", "k_large_panel<double> (panel solve, v_mfma_f64_16x16x4)", tm["panel_flops"], "mfma",
         "TFLOP/s", PEAK["fp64_mfma_TFs"])
     add("large_assembly", "k_large_asm<double> (front assembly, extend-add)", None, "hbm", "GB/s", PEAK["hbm_GBs"])
-    add("solve_sweeps", "k_fwd_T/G/S + k_bwd_G/T/S<double> (triangular sweeps)", tm["solve_bytes"], "hbm", "GB/s",
+    add("solve_sweeps", "k_fwd_P/S + k_bwd_P/S<double> (triangular sweeps: panel steps, one-wave fronts)",
+        tm["solve_bytes"], "hbm", "GB/s",
         PEAK["hbm_GBs"], tm["solve_bytes"])
     add("assemble", "k_assemble + norms (K = W + Sigma + rho J^T J)", tm["assemble_bytes"], "hbm", "GB/s",
         PEAK["hbm_GBs"], tm["assemble_bytes"])
