@@ -280,3 +280,46 @@ def slack_sigma(m: int, seed: int = 9, ineq_fraction: float = 1.0 / 3.0, lo: flo
     ineq = rng.uniform(size=m) < ineq_fraction
     vals = 10.0 ** rng.uniform(lo, hi, size=m)
     return np.where(ineq, vals, np.inf)
+
+
+def qp_family(n_side: int = 12, m: int = 40, seed: int = 12, bounded: float = 0.5, loose: bool = False):
+    """A convex QP of the problem family NCO with equality rows only:
+    Q = 2-D Laplacian of an n_side x n_side grid + I (SPD), q ~ N(0,1), A with
+    m rows of 4 N(0,1) entries in distinct random columns, b = A x_f for a
+    strictly interior x_f ~ U(-0.5, 0.5); a fraction `bounded` of the
+    variables has bounds [-1 - U, 1 + U] (the others are free), or bounds
+    [-1e3, 1e3] on every variable when `loose` (then none is active).
+    Returns (Q lower CSC parts, q, A CSR parts, b, l, u, x0 = 0).
+    Draw order: q, A columns and values, x_f, the bounded mask, the bounds."""
+    rng = np.random.default_rng(seed)
+    n = n_side * n_side
+    rows, cols, vals = [], [], []
+    for r_ in range(n_side):
+        for c_ in range(n_side):
+            k = r_ * n_side + c_
+            rows.append(k); cols.append(k); vals.append(5.0)
+            if r_ + 1 < n_side:
+                rows.append(k + n_side); cols.append(k); vals.append(-1.0)
+            if c_ + 1 < n_side:
+                rows.append(k + 1); cols.append(k); vals.append(-1.0)
+    Qp, Qi, Qx = _lower_csc(n, rows, cols, vals)
+    q = rng.standard_normal(n)
+    Jr, Jc, Jv = [0], [], []
+    for _ in range(m):
+        cs = np.sort(rng.choice(n, 4, replace=False))
+        Jc.extend(cs.tolist())
+        Jv.extend(rng.standard_normal(4).tolist())
+        Jr.append(len(Jc))
+    x_f = rng.uniform(-0.5, 0.5, n)
+    A_ptr, A_idx, A_val = np.asarray(Jr, np.int32), np.asarray(Jc, np.int32), np.asarray(Jv, np.float64)
+    b = np.zeros(m)
+    for r_ in range(m):
+        b[r_] = float(np.dot(A_val[A_ptr[r_]:A_ptr[r_ + 1]], x_f[A_idx[A_ptr[r_]:A_ptr[r_ + 1]]]))
+    mask = rng.uniform(size=n) < bounded
+    lo, hi = -1.0 - rng.uniform(size=n), 1.0 + rng.uniform(size=n)
+    if loose:
+        l, u = np.full(n, -1e3), np.full(n, 1e3)
+    else:
+        l, u = np.where(mask, lo, -np.inf), np.where(mask, hi, np.inf)
+    return dict(n=n, m=m, Q_colptr=Qp, Q_rowidx=Qi, Q_val=Qx, q=q, A_rowptr=A_ptr, A_colidx=A_idx, A_val=A_val,
+                b=b, l=l, u=u, x0=np.zeros(n))
