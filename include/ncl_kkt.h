@@ -364,6 +364,72 @@ int ncl_kkt_get_system_times(ncl_kkt_t h, double *factor_ms, double *solve_ms);
 void ncl_kkt_destroy(ncl_kkt_t h);
 const char *ncl_kkt_strerror(int code);
 
+/* ---- Algorithm 1 on a convex quadratic program ---------------------------
+ *   min 1/2 x^T Q x + q^T x   s.t.  A x = b,  l <= x <= u
+ * (the problem family NCO of Sec. 3 with equality rows only; entries of l, u
+ * may be -inf / +inf).  Algorithm 1 (MadNCL, Sec. 2.3): outer iterations on
+ * the NCL subproblem with multiplier estimate y_k, penalty rho and barrier mu;
+ * each first tries the extrapolation step (eq. ncl:extrapolation, accepted
+ * when ||F_k(w + alpha d)|| <= theta ||F_k(w)|| + 10 alpha^0.2 mu), else takes
+ * Newton steps until ||F_k||_inf <= omega_k (F_k of eq. kktnclipm); then
+ * y_k += rho r and mu, eta, omega shrink when ||r||_inf <= eta_k, else
+ * rho *= 10 (at most 1e14).  Every Newton direction is one ncl_kkt_factor +
+ * ncl_kkt_solve of K1 = Q + Sigma + rho A^T A (Sec. 3.3, eq. K1) on a
+ * condensed handle analysed once (static pivots by the absolute rule, refinement
+ * to a componentwise backward error of 1e-14: Sigma spans many decades near
+ * the solution), then ncl_kkt_recover_dy, _dr, _dz.
+ * Constants: gamma 0.05, tau 1.99, mu factor 0.2, theta 0.5, rho_0 100,
+ * mu_0 0.1.  Where the paper leaves a choice open the driver takes:
+ *   y_0 = 0, r_0 = -(A x_0 - b), z_0 = mu_0 / (distance to each finite bound);
+ *   eta_0 and omega_0 from Algorithm 1's update formulas at mu_0;
+ *   one step length for all variables, the largest <= 1 keeping x strictly
+ *   inside and z positive, scaled by tau = max(0.99, 1 - mu), then halved (at
+ *   most 30 times) until ||F_k||_inf does not increase;
+ *   optimal when ||r||_inf <= eta_star, ||Q x + q - A^T y - z_l + z_u||_inf
+ *   <= omega_star and max(z_l (x - l), z_u (u - x)) <= omega_star;
+ *   infeasible when rho reached 1e14 and ||r||_inf > eta_star;
+ *   mu >= min(eta_star, omega_star) / 10. */
+typedef struct {
+    double eta_star;      /* primal tolerance (default 1e-8) */
+    double omega_star;    /* dual and complementarity tolerance (default 1e-8) */
+    int32_t max_outer;    /* outer iterations (default 100) */
+    int32_t max_inner;    /* Newton steps per inner loop (default 100) */
+    int32_t precision;    /* of the KKT factor: NCL_FP64 (default) or NCL_FP32_IR */
+    int32_t print_level;  /* 1: one line per outer iteration on stderr (rho, mu after the
+                             update, ||F_k|| before and after the extrapolation step, its
+                             alpha, accepted or not, inner steps, ||r||, dual and
+                             complementarity measures); 0 (default): silent */
+} ncl_qp_options;
+
+typedef struct {
+    int32_t status;       /* 0 optimal, 1 infeasible, 2 outer-iteration limit */
+    int32_t outer;        /* outer iterations done */
+    int32_t inner;        /* Newton steps taken in inner loops */
+    int32_t extrapolated; /* outer iterations whose extrapolation step was accepted */
+    double primal_inf;    /* ||A x - b||_inf at the returned x */
+    double dual_inf;      /* ||Q x + q - A^T y - z_l + z_u||_inf at the returned point */
+} ncl_qp_result;
+
+void ncl_qp_default_options(ncl_qp_options *o);
+
+/* Solves the QP above.  Patterns are host arrays: Q lower-triangular CSC
+ * (Q_colptr[n+1], Q_rowidx sorted, row >= column, the diagonal stored), A CSR
+ * m x n (A_rowptr[m+1], A_colidx sorted); m may be 0.  Values and vectors are
+ * DEVICE arrays: Q_val (nnz of Q's lower part), q (n), A_val (nnz(A)), b (m),
+ * l, u (n).  x (n) holds x_0 on entry, which must lie strictly inside every
+ * finite bound (NCL_ERR_ARG otherwise), and the solution on return; y (m),
+ * z_l, z_u (n) receive the multipliers (z 0 for infinite bounds).  res (host)
+ * receives the status and counts.  Allocates its handle and work vectors on
+ * the current device and frees them before returning; synchronizes the stream
+ * several times per iteration (to read norms and step lengths).  Errors of the
+ * KKT calls are returned as they are (NCL_ERR_NONFINITE for a non-finite
+ * matrix, ...); x, y, z are then unspecified. */
+int ncl_qp_solve(const ncl_qp_options *opt, int32_t n, int32_t m, const int32_t *Q_colptr,
+                 const int32_t *Q_rowidx, const double *Q_val, const double *q,
+                 const int32_t *A_rowptr, const int32_t *A_colidx, const double *A_val,
+                 const double *b, const double *l, const double *u, double *x, double *y,
+                 double *z_l, double *z_u, ncl_qp_result *res, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

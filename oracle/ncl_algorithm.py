@@ -145,8 +145,11 @@ def newton_step(qp: QP, w, yk, rho, mu):
     return _step(w, d, a)
 
 
-def solve(qp: QP, x0, eta_star=1e-8, omega_star=1e-8, max_outer=100, max_inner=100) -> Result:
-    """Algorithm 1 (MadNCL), with the readings listed in the module header."""
+def solve(qp: QP, x0, eta_star=1e-8, omega_star=1e-8, max_outer=100, max_inner=100, log=None) -> Result:
+    """Algorithm 1 (MadNCL), with the readings listed in the module header.
+    With a list as `log`, appends per outer iteration (k, rho, mu after the
+    update, ||F|| before and after the extrapolation step, its alpha, accepted,
+    inner steps, ||r||, dual, complementarity)."""
     n, m = qp.Q.shape[0], qp.A.shape[0]
     x = np.asarray(x0, np.float64).copy()
     fl, fu = np.isfinite(qp.l), np.isfinite(qp.u)
@@ -168,11 +171,13 @@ def solve(qp: QP, x0, eta_star=1e-8, omega_star=1e-8, max_outer=100, max_inner=1
         d = newton_direction(qp, w, yk, rho, mu)
         a = max_step(qp, w, d, mu)
         wp = _step(w, d, a)
-        if fnorm(F(qp, wp, yk, rho, mu)) <= THETA * f0 + 10.0 * a ** 0.2 * mu:
+        fp = fnorm(F(qp, wp, yk, rho, mu))
+        accept = fp <= THETA * f0 + 10.0 * a ** 0.2 * mu
+        steps = 0
+        if accept:
             w = wp
             extrap += 1
         else:
-            steps = 0
             while fnorm(F(qp, w, yk, rho, mu)) > omega and steps < max_inner:
                 w = newton_step(qp, w, yk, rho, mu)
                 steps += 1
@@ -190,6 +195,8 @@ def solve(qp: QP, x0, eta_star=1e-8, omega_star=1e-8, max_outer=100, max_inner=1
         dual = float(np.abs(qp.Q @ x + qp.q - qp.A.T @ y - zl + zu).max())
         comp = max(float(np.max(zl[fl] * (x[fl] - qp.l[fl]), initial=0.0)),
                    float(np.max(zu[fu] * (qp.u[fu] - x[fu]), initial=0.0)))
+        if log is not None:
+            log.append((k, rho, mu, f0, a, fp, accept, steps, rn, dual, comp))
         if rn <= eta_star and dual <= omega_star and comp <= omega_star:
             status = 0
             break
@@ -197,5 +204,5 @@ def solve(qp: QP, x0, eta_star=1e-8, omega_star=1e-8, max_outer=100, max_inner=1
             status = 1
             break
     x, r, y, zl, zu = w
-    return Result(x, y, zl, zu, r, status, k, inner, extrap, float(np.abs(qp.A @ x - qp.b).max()),
+    return Result(x, y, zl, zu, r, status, k, inner, extrap, float(np.abs(qp.A @ x - qp.b).max(initial=0.0)),
                   float(np.abs(qp.Q @ x + qp.q - qp.A.T @ y - zl + zu).max()))

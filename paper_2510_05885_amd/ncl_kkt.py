@@ -35,7 +35,7 @@ EXPORTED = [
     "ncl_kkt_get_supernodes", "ncl_kkt_get_system_times", "ncl_kkt_set_timing", "ncl_kkt_get_timing",
     "ncl_kkt_destroy", "ncl_kkt_strerror", "ncl_kkt_factor_k1s", "ncl_kkt_k1s_rhs", "ncl_kkt_k1s_recover",
     "ncl_kkt_recover_dy", "ncl_kkt_recover_dr", "ncl_kkt_recover_dz", "ncl_kkt_barrier_sigma",
-    "ncl_kkt_factor_regularized",
+    "ncl_kkt_factor_regularized", "ncl_qp_default_options", "ncl_qp_solve",
 ]
 
 
@@ -75,6 +75,16 @@ class Timing(C.Structure):
                 "update_flops": self.update_flops, "small_flops": self.small_flops,
                 "assemble_bytes": self.assemble_bytes, "solve_bytes": self.solve_bytes,
                 "panel_flops": self.panel_flops, "diag_flops": self.diag_flops}
+
+
+class QpOptions(C.Structure):
+    _fields_ = [("eta_star", C.c_double), ("omega_star", C.c_double), ("max_outer", C.c_int32),
+                ("max_inner", C.c_int32), ("precision", C.c_int32), ("print_level", C.c_int32)]
+
+
+class QpResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("outer", C.c_int32), ("inner", C.c_int32),
+                ("extrapolated", C.c_int32), ("primal_inf", C.c_double), ("dual_inf", C.c_double)]
 
 
 _lib = None
@@ -149,6 +159,11 @@ def lib():
     L.ncl_kkt_get_timing.restype = C.c_int
     L.ncl_kkt_destroy.argtypes = [vp]
     L.ncl_kkt_destroy.restype = None
+    L.ncl_qp_default_options.argtypes = [C.POINTER(QpOptions)]
+    L.ncl_qp_default_options.restype = None
+    L.ncl_qp_solve.argtypes = [C.POINTER(QpOptions), i32, i32, pi32, pi32, vp, vp, pi32, pi32, vp, vp, vp, vp,
+                               vp, vp, vp, vp, C.POINTER(QpResult), vp]
+    L.ncl_qp_solve.restype = C.c_int
     L.ncl_kkt_strerror.argtypes = [C.c_int]
     L.ncl_kkt_strerror.restype = C.c_char_p
     _lib = L
@@ -591,3 +606,55 @@ def kkt_solve(kkt, W_val, Sigma, J_val, rho, B):
     if _KKTSolve is None:
         _KKTSolve = _autograd_function()
     return _KKTSolve.apply(kkt, W_val, Sigma, J_val, rho, B)
+
+
+@dataclass
+class QpSolution:
+    x: object               # device tensors
+    y: object
+    z_l: object
+    z_u: object
+    status: int             # 0 optimal, 1 infeasible, 2 outer-iteration limit
+    outer: int
+    inner: int
+    extrapolated: int
+    primal_inf: float
+    dual_inf: float
+
+
+def qp_solve(n, m, Q_colptr, Q_rowidx, Q_val, q, A_rowptr, A_colidx, A_val, b, l, u, x0,
+             eta_star=1e-8, omega_star=1e-8, max_outer=100, max_inner=100, precision="fp64", print_level=0,
+             stream=None):
+    """Algorithm 1 on min 1/2 x^T Q x + q^T x s.t. A x = b, l <= x <= u
+    (ncl_qp_solve).  Patterns are host arrays (Q lower CSC, A CSR); values and
+    vectors float64 CUDA tensors; x0 is copied, not overwritten."""
+    import torch
+    L = lib()
+    o = QpOptions()
+    L.ncl_qp_default_options(C.byref(o))
+    o.eta_star, o.omega_star = float(eta_star), float(omega_star)
+    o.max_outer, o.max_inner = int(max_outer), int(max_inner)
+    o.precision = _PRECS[precision] if isinstance(precision, str) else int(precision)
+    o.print_level = int(print_level)
+    qc, qcp = _i32(Q_colptr)
+    qr, qrp = _i32(Q_rowidx)
+    if len(qc) != n + 1:
+        raise ValueError("Q_colptr must have n + 1 entries")
+    ac, acp = _i32(A_rowptr if m > 0 else [0])
+    ai, aip = _i32(A_colidx if m > 0 else [0])
+    if m > 0 and len(ac) != m + 1:
+        raise ValueError("A_rowptr must have m + 1 entries")
+    nnzQ, nnzA = int(qc[-1]), int(ac[-1]) if m > 0 else 0
+    _dev(x0, n, "x0")
+    x = x0.clone()
+    y = torch.zeros(max(m, 1), dtype=torch.float64, device=x.device)
+    z_l = torch.zeros_like(x)
+    z_u = torch.zeros_like(x)
+    res = QpResult()
+    rc = L.ncl_qp_solve(C.byref(o), int(n), int(m), qcp, qrp, _dev(Q_val, nnzQ, "Q_val"), _dev(q, n, "q"),
+                        acp, aip, _dev(A_val, nnzA, "A_val") if m > 0 else None,
+                        _dev(b, m, "b") if m > 0 else None, _dev(l, n, "l"), _dev(u, n, "u"),
+                        _ptr(x), _ptr(y), _ptr(z_l), _ptr(z_u), C.byref(res), _stream(stream))
+    _check(rc, "ncl_qp_solve")
+    return QpSolution(x, y[:m], z_l, z_u, int(res.status), int(res.outer), int(res.inner),
+                      int(res.extrapolated), float(res.primal_inf), float(res.dual_inf))

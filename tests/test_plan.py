@@ -16,7 +16,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
 def test_library_exports_every_declared_symbol():
     hdr = open(os.path.join(ROOT, "include", "ncl_kkt.h")).read()
-    names = set(re.findall(r"\b(ncl_kkt_[a-z0-9_]+)\s*\(", hdr))
+    names = set(re.findall(r"\b(ncl_(?:kkt|qp)_[a-z0-9_]+)\s*\(", hdr))
     assert len(names) >= 15
     L = nk.lib()
     for n in sorted(names):
