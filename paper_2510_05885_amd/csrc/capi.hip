@@ -101,7 +101,7 @@ struct ncl_kkt_s {
     int64_t nnzF = 0;
     // schedule arrays (device)
     int *small_list = nullptr, *level_list = nullptr, *large_asm = nullptr, *large_panel = nullptr,
-        *large_upd = nullptr, *large_diag = nullptr, *solve_pan = nullptr, *solve_p = nullptr, *solve_seg = nullptr, *solve_s = nullptr,
+        *large_upd = nullptr, *large_diag = nullptr, *solve_p = nullptr, *solve_seg = nullptr, *solve_s = nullptr,
         *solve_cnt = nullptr;
     int *chunk_row0 = nullptr, *chunk_rows = nullptr, *sys_chunk_ptr = nullptr;
     int nchunks = 0;
@@ -282,8 +282,26 @@ void setup_device(ncl_kkt_s* h) {
     h->level_list = upload(h, P.level_list);
     h->large_asm = upload(h, P.large_asm);
     h->large_diag = upload(h, P.large_diag);
-    h->solve_pan = upload(h, P.solve_pan);
-    h->solve_p = upload(h, P.solve_p);
+    {
+        // every sweep task with its panel's and its front's fields (kTaskRec ints)
+        const size_t nt = P.solve_p.size() / kPTaskInts;
+        std::vector<int> rec(std::max<size_t>(nt, 1) * kTaskRec, 0);
+        for (size_t t = 0; t < nt; ++t) {
+            int* r = rec.data() + t * kTaskRec;
+            const int* tk = P.solve_p.data() + t * kPTaskInts;
+            const int* pn = P.solve_pan.data() + (size_t)tk[0] * kPanInts;
+            const int s = pn[0];
+            for (int i = 0; i < kPTaskInts; ++i) r[i] = tk[i];
+            for (int i = 0; i < kPanInts; ++i) r[kPTaskInts + i] = pn[i];
+            r[13] = P.sn_first[s];
+            r[14] = P.sn_first[s + 1] - P.sn_first[s];
+            r[15] = (int)(P.sn_rowptr[s + 1] - P.sn_rowptr[s]);
+            // U_off as on the device: room for kNrhsMax columns per front
+            const int64_t v64[4] = {P.L_off[s], P.U_off[s] * kNrhsMax, P.M_off[s], P.sn_rowptr[s]};
+            std::memcpy(r + kTaskRec64, v64, sizeof(v64));
+        }
+        h->solve_p = upload(h, rec);
+    }
     h->solve_seg = upload(h, P.solve_seg);
     // per-panel arrival counters of the backward sweep: zero here, and every
     // panel's last task sets its counter back to zero
@@ -811,7 +829,6 @@ void sweeps(ncl_kkt_s* h, int nrhs, const T* F, const T* Z, const T* D, T* Y, T*
             if (S[i].p_count > 0) return true;
         return false;
     };
-    const int* pan = h->solve_pan;
     for (size_t i0 = 0; i0 < S.size();) {
         const size_t i1 = level_end(i0);
         const int l = S[i0].level;
@@ -829,7 +846,7 @@ void sweeps(ncl_kkt_s* h, int nrhs, const T* F, const T* Z, const T* D, T* Y, T*
             }
             if (ss_.p_count > 0) {
                 Span sp(h, st, TM_SOLVE, ss_.fwd_bytes * sizeof(T) / 8.0, 4);
-                launch_fwd_P<T>(d, pan, h->solve_p + kPTaskInts * ss_.p_first, (int)ss_.p_count, h->solve_seg, F, Z, Y,
+                launch_fwd_P<T>(d, h->solve_p + kTaskRec * ss_.p_first, (int)ss_.p_count, h->solve_seg, F, Z, Y,
                                 Y2, U, nrhs, st);
             }
         }
@@ -855,7 +872,7 @@ void sweeps(ncl_kkt_s* h, int nrhs, const T* F, const T* Z, const T* D, T* Y, T*
             const SolveStep& ss_ = S[i];
             if (ss_.p_count > 0) {
                 Span sp(h, st, TM_SOLVE, ss_.fwd_bytes * sizeof(T) / 8.0, 4);
-                launch_bwd_P<T>(d, pan, h->solve_p + kPTaskInts * ss_.p_first, (int)ss_.p_count, F, Z, D, Y2, partial,
+                launch_bwd_P<T>(d, h->solve_p + kTaskRec * ss_.p_first, (int)ss_.p_count, F, Z, D, Y2, partial,
                                 h->solve_cnt, nrhs, st);
             }
             if (ss_.s_count > 0) {

@@ -1284,7 +1284,7 @@ __device__ __forceinline__ void add_segments(const DevPlan& d, const T* __restri
 }
 
 template <typename T, int NR>
-__global__ __launch_bounds__(256) void k_fwd_P(DevPlan d, const int* __restrict__ ptab, const int* __restrict__ tasks,
+__global__ __launch_bounds__(256) void k_fwd_P(DevPlan d, const int* __restrict__ tasks,
                                                const int* __restrict__ segs, const T* __restrict__ F,
                                                const T* __restrict__ Zbuf, T* __restrict__ Y, T* __restrict__ Y2,
                                                T* __restrict__ U, int nrhs) {
@@ -1293,19 +1293,18 @@ __global__ __launch_bounds__(256) void k_fwd_P(DevPlan d, const int* __restrict_
     T* rw = v + kPanel * nrhs;                    // kSolveRowsMax x nrhs: the task's rows
     T* part = rw + kSolveRowsMax * nrhs;          // 256 x nrhs
     T* Ld = part + 256 * nrhs;                    // 64 x 65
-    const int* tk = tasks + kPTaskInts * blockIdx.x;
-    const int* pt = ptab + kPanInts * tk[0];
-    const int s = pt[0], c0 = pt[1], w = pt[2];
+    const int* tk = tasks + kTaskRec * blockIdx.x;
+    const int64_t* tk64 = reinterpret_cast<const int64_t*>(tk + kTaskRec64);
+    const int c0 = tk[7], w = tk[8];
     const int r0 = tk[1], nr = tk[2] - tk[1], chunk = tk[3];
-    const int first = d.sn_first[s];
-    const int p = d.sn_first[s + 1] - first;
-    const int f = (int)(d.sn_rowptr[s + 1] - d.sn_rowptr[s]);
+    const int first = tk[13], p = tk[14], f = tk[15];
     const int c = f - p;
-    const T* __restrict__ L = F + d.L_off[s];
-    T* __restrict__ Us = U + d.U_off[s];
+    const T* __restrict__ L = F + tk64[0];
+    T* __restrict__ Us = U + tk64[1];
+    const int64_t moff = tk64[2];
     const int tid = threadIdx.x, lane = tid & 63, q4 = tid >> 6;
     const int64_t N = d.N;
-    const bool large = d.M_off[s] >= 0;
+    const bool large = moff >= 0;
     // wave q4: row group q4 / nwc (64 rows, lane = row), columns 16 (q4 % nwc) + [0, 16)
     const int nwc = (w + 15) >> 4, ng = 4 / nwc;
     const int rgrp = q4 / nwc, k0 = 16 * (q4 - rgrp * nwc);
@@ -1315,7 +1314,7 @@ __global__ __launch_bounds__(256) void k_fwd_P(DevPlan d, const int* __restrict_
     // fronts) and this thread's slice of L[rows, panel].
     T z[16], lv[16];
     if (large) {
-        const T* __restrict__ Zb = Zbuf + d.M_off[s] + (int64_t)(c0 / kPanel) * (kPanel * kPanel);
+        const T* __restrict__ Zb = Zbuf + moff + (int64_t)(c0 / kPanel) * (kPanel * kPanel);
 #pragma unroll
         for (int j = 0; j < 16; ++j) z[j] = (lane < w && 16 * q4 + j < w) ? Zb[(16 * q4 + j) * kPanel + lane] : T(0);
     }
@@ -1334,7 +1333,7 @@ __global__ __launch_bounds__(256) void k_fwd_P(DevPlan d, const int* __restrict_
     }
     __syncthreads();
     if (c0 == 0) {
-        add_segments<T, NR>(d, U, segs, pt[5], pt[6], 0, v, kPanel, nrhs);
+        add_segments<T, NR>(d, U, segs, tk[11], tk[12], 0, v, kPanel, nrhs);
         add_segments<T, NR>(d, U, segs, tk[4], tk[5], r0, rw, kSolveRowsMax, nrhs);
     }
     if (large) {
@@ -1385,7 +1384,7 @@ __global__ __launch_bounds__(256) void k_fwd_P(DevPlan d, const int* __restrict_
 }
 
 template <typename T, int NR>
-__global__ __launch_bounds__(256) void k_bwd_P(DevPlan d, const int* __restrict__ ptab, const int* __restrict__ tasks,
+__global__ __launch_bounds__(256) void k_bwd_P(DevPlan d, const int* __restrict__ tasks,
                                                const T* __restrict__ F, const T* __restrict__ Zbuf,
                                                const T* __restrict__ D, T* __restrict__ Y2, T* __restrict__ partial,
                                                int* __restrict__ pcnt, int nrhs) {
@@ -1395,18 +1394,16 @@ __global__ __launch_bounds__(256) void k_bwd_P(DevPlan d, const int* __restrict_
     T* part = v + kPanel * nrhs;                  // 256 x nrhs
     T* Ld = part + 256 * nrhs;                    // 64 x 65
     __shared__ int s_last;
-    const int* tk = tasks + kPTaskInts * blockIdx.x;
+    const int* tk = tasks + kTaskRec * blockIdx.x;
+    const int64_t* tk64 = reinterpret_cast<const int64_t*>(tk + kTaskRec64);
     const int pid = tk[0];
-    const int* pt = ptab + kPanInts * pid;
-    const int s = pt[0], c0 = pt[1], w = pt[2], slot0 = pt[3], ntask = pt[4];
+    const int c0 = tk[7], w = tk[8], slot0 = tk[9], ntask = tk[10];
     const int r0 = tk[1], nr = tk[2] - tk[1], chunk = tk[3];
-    const int first = d.sn_first[s];
-    const int p = d.sn_first[s + 1] - first;
-    const int64_t rb = d.sn_rowptr[s];
-    const int f = (int)(d.sn_rowptr[s + 1] - rb);
-    const T* __restrict__ L = F + d.L_off[s];
-    const int* __restrict__ rows = d.sn_rows + rb;
-    const bool large = d.M_off[s] >= 0;
+    const int first = tk[13], p = tk[14], f = tk[15];
+    const T* __restrict__ L = F + tk64[0];
+    const int64_t moff = tk64[2];
+    const int* __restrict__ rows = d.sn_rows + tk64[3];
+    const bool large = moff >= 0;
     const int tid = threadIdx.x, lane = tid & 63, q4 = tid >> 6;
     const int64_t N = d.N;
     // thread = (panel column t, row group rg): columns in slots of 16, the
@@ -1425,7 +1422,7 @@ __global__ __launch_bounds__(256) void k_bwd_P(DevPlan d, const int* __restrict_
             const int i = rg + nrg * m;
             lv[m] = (tact && i < nr) ? lt[(int64_t)i * f] : T(0);
         }
-        const T* __restrict__ Zb = Zbuf + d.M_off[s] + (int64_t)(c0 / kPanel) * (kPanel * kPanel);
+        const T* __restrict__ Zb = Zbuf + moff + (int64_t)(c0 / kPanel) * (kPanel * kPanel);
 #pragma unroll
         for (int it = 0; it < kPanel * kPanel / 256; ++it) {
             const int idx = tid + 256 * it;
@@ -2546,25 +2543,25 @@ void launch_bwd_S(const DevPlan& d, const int* fronts, int count, const T* F, co
 }
 
 template <typename T>
-void launch_fwd_P(const DevPlan& d, const int* ptab, const int* tasks, int count, const int* segs, const T* F,
+void launch_fwd_P(const DevPlan& d, const int* tasks, int count, const int* segs, const T* F,
                   const T* Z, T* Y, T* Y2, T* U, int nrhs, hipStream_t st) {
     if (count <= 0) return;
     const size_t lds = (size_t)((kPanel + kSolveRowsMax + 256) * nrhs + 64 * 65) * sizeof(T);
     if (nrhs == 1)
-        launch(k_fwd_P<T, 1>, dim3(count), dim3(256), lds, st, d, ptab, tasks, segs, F, Z, Y, Y2, U, nrhs);
+        launch(k_fwd_P<T, 1>, dim3(count), dim3(256), lds, st, d, tasks, segs, F, Z, Y, Y2, U, nrhs);
     else
-        launch(k_fwd_P<T, kNrhsMax>, dim3(count), dim3(256), lds, st, d, ptab, tasks, segs, F, Z, Y, Y2, U, nrhs);
+        launch(k_fwd_P<T, kNrhsMax>, dim3(count), dim3(256), lds, st, d, tasks, segs, F, Z, Y, Y2, U, nrhs);
 }
 
 template <typename T>
-void launch_bwd_P(const DevPlan& d, const int* ptab, const int* tasks, int count, const T* F, const T* Z,
+void launch_bwd_P(const DevPlan& d, const int* tasks, int count, const T* F, const T* Z,
                   const T* D, T* Y2, T* partial, int* pcnt, int nrhs, hipStream_t st) {
     if (count <= 0) return;
     const size_t lds = (size_t)((kPanel + kSolveRowsMax + 256) * nrhs + 64 * 65) * sizeof(T);
     if (nrhs == 1)
-        launch(k_bwd_P<T, 1>, dim3(count), dim3(256), lds, st, d, ptab, tasks, F, Z, D, Y2, partial, pcnt, nrhs);
+        launch(k_bwd_P<T, 1>, dim3(count), dim3(256), lds, st, d, tasks, F, Z, D, Y2, partial, pcnt, nrhs);
     else
-        launch(k_bwd_P<T, kNrhsMax>, dim3(count), dim3(256), lds, st, d, ptab, tasks, F, Z, D, Y2, partial, pcnt,
+        launch(k_bwd_P<T, kNrhsMax>, dim3(count), dim3(256), lds, st, d, tasks, F, Z, D, Y2, partial, pcnt,
                nrhs);
 }
 
@@ -2661,10 +2658,10 @@ hipError_t configure_kernels(int max_dynamic_lds) {
     template void launch_permute_out<T>(const DevPlan&, const T*, int, double*, int64_t, hipStream_t);             \
     template void launch_fwd_S<T>(const DevPlan&, const int*, int, const T*, const T*, T*, T*, int, hipStream_t);  \
     template void launch_bwd_S<T>(const DevPlan&, const int*, int, const T*, const T*, T*, int, hipStream_t);     \
-    template void launch_fwd_P<T>(const DevPlan&, const int*, const int*, int, const int*, const T*, const T*, T*,  \
-                                  T*, T*, int, hipStream_t);                                                       \
-    template void launch_bwd_P<T>(const DevPlan&, const int*, const int*, int, const T*, const T*, const T*, T*,    \
-                                  T*, int*, int, hipStream_t);
+    template void launch_fwd_P<T>(const DevPlan&, const int*, int, const int*, const T*, const T*, T*, T*, T*,    \
+                                  int, hipStream_t);                                                               \
+    template void launch_bwd_P<T>(const DevPlan&, const int*, int, const T*, const T*, const T*, T*, T*, int*, int, \
+                                  hipStream_t);
 
 NCL_INSTANTIATE(double)
 NCL_INSTANTIATE(float)

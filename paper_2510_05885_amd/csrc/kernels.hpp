@@ -14,6 +14,14 @@ constexpr int kTile = 64;        // tile order of the large-front MFMA update
 constexpr int kSolveRowsMax = 256;  // rows below a solve panel per task (fewer for wide panels)
 constexpr int kPanInts = 7;      // ints per solve panel: s, c0, w, slot0, tasks, seg0, nseg
 constexpr int kPTaskInts = 6;    // ints per solve task: panel, r0, r1, index, seg0, nseg
+// A sweep task as the kernels read it: the task, its panel and its front in
+// one record, so that one round trip brings everything the task needs.
+//   ints  0..5   the task (panel, r0, r1, index, seg0, nseg)
+//   ints  6..12  the panel (s, c0, w, slot0, tasks, seg0, nseg)
+//   ints 13..15  the front (first pivot, pivots p, order f)
+//   int64 at ints 16, 18, 20, 22: L_off, U_off, M_off, first row-list entry
+constexpr int kTaskRec = 24;
+constexpr int kTaskRec64 = 16;
 constexpr int kInertiaSlots = 64;  // partial inertia counters per system (spreads the atomics)
 constexpr int kNonfiniteInput = 1;   // status bit: NaN/Inf in the assembled K (its norms)
 constexpr int kNonfiniteFactor = 4;  // status bit: NaN/Inf pivot met by the factorization
@@ -188,10 +196,10 @@ void launch_bwd_S(const DevPlan& d, const int* fronts, int count, const T* F, co
 // tasks, contribution segments: see the sweep kernels).  partial: slots x
 // kPanel x kNrhsMax; pcnt: one zero counter per panel (left zero).
 template <typename T>
-void launch_fwd_P(const DevPlan& d, const int* ptab, const int* tasks, int count, const int* segs, const T* F,
+void launch_fwd_P(const DevPlan& d, const int* tasks, int count, const int* segs, const T* F,
                   const T* Z, T* Y, T* Y2, T* U, int nrhs, hipStream_t st);
 template <typename T>
-void launch_bwd_P(const DevPlan& d, const int* ptab, const int* tasks, int count, const T* F, const T* Z,
+void launch_bwd_P(const DevPlan& d, const int* tasks, int count, const T* F, const T* Z,
                   const T* D, T* Y2, T* partial, int* pcnt, int nrhs, hipStream_t st);
 
 // ---- refinement -------------------------------------------------------------
