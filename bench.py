@@ -56,15 +56,15 @@ GATE_OMEGA, GATE_CW = 1e-10, 1e-14
 # counter reads for a device copy of known size (--calibrate-copy).  Valid
 # only for the kernel source they were taken on: null once kernels.hip
 # changes.  Source: profiles/pmc_traffic_opf_n500k_fp64.txt.
-TRAFFIC = {"kernels_sha1": "836c5a844f93768a4c7476dabf4d123f0e6c2552", "fetch_scale": 2.00, "write_scale": 1.00,
-           "kib": {"solve_sweeps": (4055.8, 221.8),
-            "large_update_mfma": (13925.1, 19714.7),
-            "large_panel": (4004.3, 6503.8),
-            "large_diag": (1686.9, 6757.1),
-            "large_assembly": (26964.2, 51086.0),
-            "small_fronts": (12876.3, 15669.7),
-            "assemble": (125429.0, 25216.0),
-            "residual": (64276.7, 2234.0)}}
+TRAFFIC = {"kernels_sha1": "95cc476e7cb3ea313545c18e4824abcf01cc7116", "fetch_scale": 2.00, "write_scale": 1.00,
+           "kib": {"solve_sweeps": (4031.5, 221.8),
+            "large_update_mfma": (13924.3, 19714.4),
+            "large_panel": (4004.8, 6503.7),
+            "large_diag": (1685.3, 6757.1),
+            "large_assembly": (26963.4, 51086.1),
+            "small_fronts": (12876.2, 15669.7),
+            "assemble": (125437.3, 25216.0),
+            "residual": (64335.9, 2230.7)}}
 
 
 def kernels_sha1():
