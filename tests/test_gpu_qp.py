@@ -46,9 +46,9 @@ def _close(a, b, tol):
     return float(np.abs(a - b).max(initial=0.0)) <= tol * max(1.0, float(np.abs(b).max(initial=0.0)))
 
 
-def _compare(name, d, q_scale=1.0, x_tol=1e-6, y_tol=1e-5, **kw):
+def _compare(name, d, q_scale=1.0, x_tol=1e-6, y_tol=1e-5, oracle_kw=None, **kw):
     print(f"[gpu] qp {name}: n={d['n']} m={d['m']}", flush=True)
-    ref = NA.solve(_qp(d, q_scale), d["x0"])
+    ref = NA.solve(_qp(d, q_scale), d["x0"], **(oracle_kw or {}))
     got = _gpu(d, q_scale, **kw)
     x, y = got.x.cpu().numpy(), got.y.cpu().numpy()
     print(f"[gpu]   status {got.status}/{ref.status} outer {got.outer}/{ref.outer} inner {got.inner}/{ref.inner} "
@@ -111,6 +111,15 @@ def test_qp_fp32_factor():
 def test_qp_larger_grid():
     d = synth.qp_family(n_side=40, m=400, seed=17, bounded=0.5)
     _compare("grid 40x40", d, q_scale=3.0)
+
+
+def test_qp_outer_iteration_limit():
+    """Stopped after 3 outer iterations: status 2 (limit) with the oracle's
+    iterate at that point."""
+    d = synth.qp_family(seed=14, bounded=0.6)
+    got, ref = _compare("outer limit 3", d, q_scale=6.0, oracle_kw=dict(max_outer=3), max_outer=3)
+    assert got.status == ref.status == 2 and got.outer == 3
+    assert _close(got.x.cpu().numpy(), ref.x, 1e-6)
 
 
 def test_qp_refuses_x0_outside_bounds():
