@@ -598,9 +598,25 @@ __device__ __forceinline__ void small_front_body(const DevPlan& d, int s, int sl
     const int tid = threadIdx.x;
     const int ti = tid & 63, tj = tid >> 6;
 
+    // The front's first K entries (position and value, two per thread) are
+    // loaded before the LDS zero-fill, so their latency overlaps it.
+    const int64_t ke0 = d.kent_ptr[s], ke1 = d.kent_ptr[s + 1];
+    int kpos[2];
+    T kval[2];
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+        const int64_t e = ke0 + tid + 256 * u;
+        if (e < ke1) {
+            kpos[u] = d.kent_pos[e];
+            kval[u] = (T)K[d.kent_csr[e]];
+        }
+    }
     for (int t = tid; t < f * f; t += 256) A[t] = T(0);
     __syncthreads();
-    for (int64_t e = d.kent_ptr[s] + tid; e < d.kent_ptr[s + 1]; e += 256) A[d.kent_pos[e]] = (T)K[d.kent_csr[e]];
+#pragma unroll
+    for (int u = 0; u < 2; ++u)
+        if (ke0 + tid + 256 * u < ke1) A[kpos[u]] = kval[u];
+    for (int64_t e = ke0 + tid + 512; e < ke1; e += 256) A[d.kent_pos[e]] = (T)K[d.kent_csr[e]];
     __syncthreads();
     // extend-add: pull every child's contribution block, children in order.
     // Entry (a, b) of the child's lower CB is element idx = a + 128 b of a
@@ -615,16 +631,26 @@ __device__ __forceinline__ void small_front_body(const DevPlan& d, int s, int sl
         const T* __restrict__ CB = F + d.CB_off[ch];
         const int ld = d.CB_ld[ch];
         const int* __restrict__ r = d.rel + d.rel_ptr[ch];
+        const int n2 = kSmallMax * cc;
+        // the first batch of the child's entries is loaded before the
+        // barrier that publishes its row map, so both round trips overlap
+        T v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int idx = tid + 256 * u;
+            const int a = min(idx & (kSmallMax - 1), cc - 1), b = min(idx >> 7, cc - 1);
+            v[u] = cc > 0 ? CB[a + (int64_t)b * ld] : T(0);
+        }
         if (tid < cc) rl[tid] = r[tid];
         __syncthreads();
-        const int n2 = kSmallMax * cc;
         for (int base = 0; base < n2; base += 256 * 8) {
-            T v[8];
+            if (base > 0) {
 #pragma unroll
-            for (int u = 0; u < 8; ++u) {
-                const int idx = base + tid + 256 * u;
-                const int a = min(idx & (kSmallMax - 1), cc - 1), b = min(idx >> 7, cc - 1);
-                v[u] = CB[a + (int64_t)b * ld];
+                for (int u = 0; u < 8; ++u) {
+                    const int idx = base + tid + 256 * u;
+                    const int a = min(idx & (kSmallMax - 1), cc - 1), b = min(idx >> 7, cc - 1);
+                    v[u] = CB[a + (int64_t)b * ld];
+                }
             }
 #pragma unroll
             for (int u = 0; u < 8; ++u) {
