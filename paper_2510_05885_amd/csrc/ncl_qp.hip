@@ -217,7 +217,7 @@ struct QpSolver {
     int *Qj = nullptr, *Qk = nullptr, *Aj = nullptr, *Tr = nullptr, *Tk = nullptr;
     double *g = nullptr, *c = nullptr, *aty = nullptr, *t = nullptr, *rhs = nullptr, *sigma = nullptr;
     double *yk = nullptr, *partial = nullptr, *scal = nullptr, *host = nullptr;
-    Point w[3]{}, d{};   // w[0] current, w[1] trial, w[2] spare
+    Point w[2]{}, d{};   // w[0] / w[1]: current and trial points (swapped), d: the direction
 
     ~QpSolver() {
         (void)hipStreamSynchronize(st);
@@ -399,8 +399,10 @@ int ncl_qp_solve(const ncl_qp_options* opt, int32_t n, int32_t m, const int32_t*
         if (!(P.reduce(nb, true) > 0.0)) return NCL_ERR_ARG;   // x_0 not strictly inside its bounds
         P.eval(*W);
         if (m > 0) hipLaunchKernelGGL(k_scale, dim3(blocks(m)), dim3(kBlk), 0, P.st, (int64_t)m, -1.0, P.c, W->r);
-        QPCHK(hipMemsetAsync(W->y, 0, sizeof(double) * std::max(m, 1), P.st));
-        QPCHK(hipMemsetAsync(P.yk, 0, sizeof(double) * std::max(m, 1), P.st));
+        if (m > 0) {
+            QPCHK(hipMemsetAsync(W->y, 0, sizeof(double) * m, P.st));
+            QPCHK(hipMemsetAsync(P.yk, 0, sizeof(double) * m, P.st));
+        }
         hipLaunchKernelGGL(k_init_z, dim3(nb), dim3(kBlk), 0, P.st, n, W->x, l, u, mu, W->zl, W->zu);
         double eta = std::min(std::pow(mu, 1.1), 0.1 * mu), omega = 100.0 * std::pow(mu, 1.0 + kGamma);
         int status = 2, k = 0, inner = 0, extrap = 0;
