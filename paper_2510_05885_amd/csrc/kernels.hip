@@ -236,16 +236,18 @@ __device__ void lds_partial_ldlt(T* A, int lda, int f, int p, T* dv, const int8_
             while (rem >= nt - tj) { rem -= nt - tj; ++tj; }
             const int ti = tj + rem;
             const int i0 = r0 + 16 * ti, j0 = r0 + 16 * tj;
-            typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+            T av[4], bv[4];   // operands first: see panel_body
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
                 const int tt = 4 * st + lk;
                 const bool tv = tt < bw;
                 const int t = kb + tt;
-                const T a = (tv && i0 + lr < f) ? A[(i0 + lr) + t * lda] : T(0);
-                const T b = (tv && j0 + lr < f) ? A[(j0 + lr) + t * lda] * dv[tv ? t : 0] : T(0);
-                acc = Mfma<T>::run_chained(a, b, acc);
+                av[st] = (tv && i0 + lr < f) ? A[(i0 + lr) + t * lda] : T(0);
+                bv[st] = (tv && j0 + lr < f) ? A[(j0 + lr) + t * lda] * dv[tv ? t : 0] : T(0);
             }
+            typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+            for (int st = 0; st < 4; ++st) acc = Mfma<T>::run_chained(av[st], bv[st], acc);
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 const int gi = i0 + Mfma<T>::row(lk, r), gj = j0 + lr;
@@ -354,12 +356,16 @@ __device__ __forceinline__ void diag_ldlt64(T* B, T* dv, unsigned long long negm
                 while (rem >= nt - tj) { rem -= nt - tj; ++tj; }
                 const int ti = tj + rem;
                 const int i0 = r0 + 16 * ti, j0 = r0 + 16 * tj;
-                typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+                T av[4], bv[4];   // operands first: see panel_body
 #pragma unroll
                 for (int st = 0; st < 4; ++st) {
                     const int t = kb + 4 * st + lk;
-                    acc = Mfma<T>::run_chained(B[(i0 + lr) + t * LB], B[(j0 + lr) + t * LB] * dv[t], acc);
+                    av[st] = B[(i0 + lr) + t * LB];
+                    bv[st] = B[(j0 + lr) + t * LB] * dv[t];
                 }
+                typename Mfma<T>::acc_t acc = {0, 0, 0, 0};
+#pragma unroll
+                for (int st = 0; st < 4; ++st) acc = Mfma<T>::run_chained(av[st], bv[st], acc);
 #pragma unroll
                 for (int r = 0; r < 4; ++r) {
                     const int gi = i0 + Mfma<T>::row(lk, r), gj = j0 + lr;
@@ -424,17 +430,22 @@ __device__ __forceinline__ void tri_inv64(T* B, int tid) {
         if (i < 4) {
             acc_t S = {0, 0, 0, 0};
             for (int k = q; k < i; ++k) {
+                T la[4], zb[4];   // operands first: see panel_body
 #pragma unroll
                 for (int st = 0; st < 4; ++st) {
                     const int kk = Mfma<T>::row(lk, st);
-                    S = Mfma<T>::run_chained(B[(16 * i + lr) + (16 * k + kk) * LB], zget(B, 16 * k + kk, 16 * q + lr),
-                                             S);
+                    la[st] = B[(16 * i + lr) + (16 * k + kk) * LB];
+                    zb[st] = zget(B, 16 * k + kk, 16 * q + lr);
                 }
+#pragma unroll
+                for (int st = 0; st < 4; ++st) S = Mfma<T>::run_chained(la[st], zb[st], S);
             }
+            T zi[4];
+#pragma unroll
+            for (int st = 0; st < 4; ++st) zi[st] = zget(B, 16 * i + lr, 16 * i + Mfma<T>::row(lk, st));
             acc_t R = {0, 0, 0, 0};
 #pragma unroll
-            for (int st = 0; st < 4; ++st)
-                R = Mfma<T>::run_chained(zget(B, 16 * i + lr, 16 * i + Mfma<T>::row(lk, st)), S[st], R);
+            for (int st = 0; st < 4; ++st) R = Mfma<T>::run_chained(zi[st], S[st], R);
 #pragma unroll
             for (int r = 0; r < 4; ++r) B[(16 * q + lr) + (16 * i + Mfma<T>::row(lk, r)) * LB] = -R[r];
         }
@@ -1067,6 +1078,18 @@ __device__ __forceinline__ void panel_body(const DevPlan& d, int s, int k0, int 
             a[K][st] = (rv && kk < w) ? A[row + (int64_t)(k0 + kk) * f] : T(0);
         }
     typedef typename Mfma<T>::acc_t acc_t;
+    // Z operands of both output blocks, loaded before the padded MFMA chains
+    // (the padding's scheduling barriers would otherwise hold each load next
+    // to its MFMA and serialize the round trips)
+    T zo[2][4][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int J = h ? 3 - (wave >> 1) : (wave >> 1);
+#pragma unroll
+        for (int K = 0; K < 4; ++K)
+#pragma unroll
+            for (int st = 0; st < 4; ++st) zo[h][K][st] = Zt[(16 * K + Mfma<T>::row(lk, st)) * kPanel + 16 * J + lr];
+    }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int J = h ? 3 - (wave >> 1) : (wave >> 1);
@@ -1075,10 +1098,7 @@ __device__ __forceinline__ void panel_body(const DevPlan& d, int s, int k0, int 
         for (int K = 0; K < 4; ++K) {
             if (K > J) continue;   // uniform
 #pragma unroll
-            for (int st = 0; st < 4; ++st) {
-                const int kk = 16 * K + Mfma<T>::row(lk, st);
-                acc = Mfma<T>::run_chained(a[K][st], Zt[kk * kPanel + 16 * J + lr], acc);
-            }
+            for (int st = 0; st < 4; ++st) acc = Mfma<T>::run_chained(a[K][st], zo[h][K][st], acc);
         }
         const int col = 16 * J + lr;
         if (col < w) {
