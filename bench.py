@@ -56,15 +56,15 @@ GATE_OMEGA, GATE_CW = 1e-10, 1e-14
 # counter reads for a device copy of known size (--calibrate-copy).  Valid
 # only for the kernel source they were taken on: null once kernels.hip
 # changes.  Source: profiles/pmc_traffic_opf_n500k_fp64.txt.
-TRAFFIC = {"kernels_sha1": "ab49f3876d93e11d6fa2e535fa0fdc9816591772", "fetch_scale": 2.00, "write_scale": 1.00,
-           "kib": {"solve_sweeps": (4031.1, 221.8),
-            "large_update_mfma": (13928.4, 19714.7),
-            "large_panel": (3999.9, 6503.8),
-            "large_diag": (1681.5, 6757.1),
-            "large_assembly": (26964.1, 51086.1),
-            "small_fronts": (12884.1, 15669.8),
-            "assemble": (125438.5, 25216.0),
-            "residual": (64382.6, 2231.7)}}
+TRAFFIC = {"kernels_sha1": "ee727ef07b52121a39c2588d4dee4cbb7980850e", "fetch_scale": 2.00, "write_scale": 1.00,
+           "kib": {"solve_sweeps": (4031.2, 221.8),
+                   "large_update_mfma": (13927.9, 19714.8),
+                   "large_panel": (4000.1, 6331.0),
+                   "large_diag": (1679.7, 6757.1),
+                   "large_assembly": (26963.9, 51086.1),
+                   "small_fronts": (12885.6, 15669.7),
+                   "assemble": (125433.4, 25216.0),
+                   "residual": (64341.2, 2227.5)}}
 
 
 def kernels_sha1():

@@ -1078,17 +1078,20 @@ __device__ __forceinline__ void panel_body(const DevPlan& d, int s, int k0, int 
             a[K][st] = (rv && kk < w) ? A[row + (int64_t)(k0 + kk) * f] : T(0);
         }
     typedef typename Mfma<T>::acc_t acc_t;
-    // Z operands of both output blocks, loaded before the padded MFMA chains
-    // (the padding's scheduling barriers would otherwise hold each load next
-    // to its MFMA and serialize the round trips)
+    // Z operands of both output blocks (blocks K <= J only: Z is lower
+    // triangular), loaded before the padded MFMA chains (the padding's
+    // scheduling barriers would otherwise hold each load next to its MFMA and
+    // serialize the round trips)
     T zo[2][4][4];
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int J = h ? 3 - (wave >> 1) : (wave >> 1);
 #pragma unroll
-        for (int K = 0; K < 4; ++K)
+        for (int K = 0; K < 4; ++K) {
+            if (K > J) continue;   // uniform
 #pragma unroll
             for (int st = 0; st < 4; ++st) zo[h][K][st] = Zt[(16 * K + Mfma<T>::row(lk, st)) * kPanel + 16 * J + lr];
+        }
     }
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
