@@ -56,15 +56,15 @@ GATE_OMEGA, GATE_CW = 1e-10, 1e-14
 # counter reads for a device copy of known size (--calibrate-copy).  Valid
 # only for the kernel source they were taken on: null once kernels.hip
 # changes.  Source: profiles/pmc_traffic_opf_n500k_fp64.txt.
-TRAFFIC = {"kernels_sha1": "ee727ef07b52121a39c2588d4dee4cbb7980850e", "fetch_scale": 2.00, "write_scale": 1.00,
-           "kib": {"solve_sweeps": (4031.2, 221.8),
-                   "large_update_mfma": (13927.9, 19714.8),
-                   "large_panel": (4000.1, 6331.0),
-                   "large_diag": (1679.7, 6757.1),
-                   "large_assembly": (26963.9, 51086.1),
-                   "small_fronts": (12885.6, 15669.7),
-                   "assemble": (125433.4, 25216.0),
-                   "residual": (64341.2, 2227.5)}}
+TRAFFIC = {"kernels_sha1": "06ef41c35a95b500fb0aa899b1505015e9ff0679", "fetch_scale": 2.00, "write_scale": 1.00,
+           "kib": {"solve_sweeps": (3418.1, 204.4),
+                   "large_update_mfma": (13929.1, 19716.7),
+                   "large_panel": (4005.5, 6330.6),
+                   "large_diag": (1684.9, 6757.1),
+                   "large_assembly": (26964.1, 51086.0),
+                   "small_fronts": (12885.8, 15669.7),
+                   "assemble": (125432.7, 25216.0),
+                   "residual": (64283.3, 2230.3)}}
 
 
 def kernels_sha1():

@@ -832,6 +832,8 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
             for (int s = 0; s < nsn; ++s)
                 for (int64_t q = P.rel_ptr[s] + 1; q < P.rel_ptr[s + 1]; ++q)
                     if (P.rel[q] <= P.rel[q - 1]) throw AnalyzeError(-4, "internal: update-vector map not increasing");
+            std::vector<std::vector<int>> sn_pids(nsn);   // panels of each front, in column order
+            std::vector<int64_t> pan_task0;               // first task of each panel
             for (int l = 0; l < P.nlevels; ++l) {
                 int maxj = 0;
                 for (int k = P.level_ptr[l]; k < P.level_ptr[l + 1]; ++k) {
@@ -859,6 +861,8 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                             continue;
                         }
                         const int pid = (int)(P.solve_pan.size() / 7);
+                        sn_pids[s].push_back(pid);
+                        pan_task0.push_back((int64_t)P.solve_p.size() / 6);
                         const int GR = task_rows(w);
                         if (!P.sn_large[s] && below > 64)
                             throw AnalyzeError(-4, "internal: LDS-path front with more than 64 rows below a panel");
@@ -892,6 +896,44 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                     P.solve_max_slots = std::max<int64_t>(P.solve_max_slots, slot);
                     P.solve_steps.push_back(st);
                 }
+            }
+            // Backward: a panel swept by several tasks is finished (its x from
+            // the tasks' sums) by the first task of the front's previous panel,
+            // whose rows start with it; a front's first panel by a finish-only
+            // record launched after its level's last step.
+            const int64_t nreg = (int64_t)P.solve_p.size() / 6;
+            P.solve_fin.assign(4 * (size_t)nreg, 0);
+            auto fin_fields = [&](int pid, int* out) {
+                const int* pn = P.solve_pan.data() + 7 * (size_t)pid;
+                out[0] = pn[1]; out[1] = pn[2]; out[2] = pn[3]; out[3] = pn[4];
+            };
+            for (int s = 0; s < nsn; ++s) {
+                const std::vector<int>& pids = sn_pids[s];
+                for (size_t j = 0; j + 1 < pids.size(); ++j) {
+                    if (P.solve_pan[7 * (size_t)pids[j + 1] + 4] <= 1) continue;
+                    if (!P.sn_large[s]) throw AnalyzeError(-4, "internal: multi-task panel in an LDS-path front");
+                    const int64_t t0 = pan_task0[pids[j]];
+                    if (P.solve_p[6 * t0 + 3] != 0 || P.solve_p[6 * t0 + 1] != P.solve_pan[7 * (size_t)pids[j + 1] + 1] ||
+                        P.solve_pan[7 * (size_t)pids[j] + 4] <= 1)
+                        throw AnalyzeError(-4, "internal: first task of a panel does not start at the next panel");
+                    fin_fields(pids[j + 1], P.solve_fin.data() + 4 * t0);
+                }
+            }
+            for (SolveStep& st : P.solve_steps) {
+                if (st.j != 0) continue;
+                st.f_first = (int64_t)P.solve_p.size() / 6;
+                for (int k = P.level_ptr[st.level]; k < P.level_ptr[st.level + 1]; ++k) {
+                    const int s = P.level_list[k];
+                    if (sn_pids[s].empty()) continue;
+                    const int pid = sn_pids[s][0];
+                    if (P.solve_pan[7 * (size_t)pid + 4] <= 1) continue;
+                    const int f = (int)(P.sn_rowptr[s + 1] - P.sn_rowptr[s]);
+                    for (int v : {pid, f, f, -1, 0, 0}) P.solve_p.push_back(v);
+                    int fin[4];
+                    fin_fields(pid, fin);
+                    for (int v : fin) P.solve_fin.push_back(v);
+                }
+                st.f_count = (int64_t)P.solve_p.size() / 6 - st.f_first;
             }
         }
     } catch (const AnalyzeError& e) {

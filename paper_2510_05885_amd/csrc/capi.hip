@@ -101,8 +101,7 @@ struct ncl_kkt_s {
     int64_t nnzF = 0;
     // schedule arrays (device)
     int *small_list = nullptr, *level_list = nullptr, *large_asm = nullptr, *large_panel = nullptr,
-        *large_upd = nullptr, *large_diag = nullptr, *solve_p = nullptr, *solve_seg = nullptr, *solve_s = nullptr,
-        *solve_cnt = nullptr;
+        *large_upd = nullptr, *large_diag = nullptr, *solve_p = nullptr, *solve_seg = nullptr, *solve_s = nullptr;
     int *chunk_row0 = nullptr, *chunk_rows = nullptr, *sys_chunk_ptr = nullptr;
     int nchunks = 0;
     // numeric state
@@ -299,14 +298,11 @@ void setup_device(ncl_kkt_s* h) {
             // U_off as on the device: room for kNrhsMax columns per front
             const int64_t v64[4] = {P.L_off[s], P.U_off[s] * kNrhsMax, P.M_off[s], P.sn_rowptr[s]};
             std::memcpy(r + kTaskRec64, v64, sizeof(v64));
+            for (int i = 0; i < 4; ++i) r[kTaskRec64 + 8 + i] = P.solve_fin[4 * t + i];
         }
         h->solve_p = upload(h, rec);
     }
     h->solve_seg = upload(h, P.solve_seg);
-    // per-panel arrival counters of the backward sweep: zero here, and every
-    // panel's last task sets its counter back to zero
-    h->solve_cnt = dalloc<int>(h, std::max<int64_t>((int64_t)P.solve_pan.size() / kPanInts, 1));
-    HIPCHK(hipMemset(h->solve_cnt, 0, sizeof(int) * std::max<size_t>(P.solve_pan.size() / kPanInts, 1)));
     h->solve_s = upload(h, P.solve_s);
     h->large_panel = upload(h, P.large_panel);
     h->large_upd = upload(h, P.large_upd);
@@ -343,14 +339,14 @@ void setup_device(ncl_kkt_s* h) {
     h->M64 = dalloc<double>(h, P.M_elems);
     h->Y64 = dalloc<double>(h, 2 * P.N * kNrhsMax);   // right-hand side, then the pivots' y / x
     h->U64 = dalloc<double>(h, P.U_elems * kNrhsMax);
-    h->P64 = dalloc<double>(h, std::max<int64_t>(P.solve_max_slots, 1) * kPanel * kNrhsMax);
+    h->P64 = dalloc<double>(h, 2 * std::max<int64_t>(P.solve_max_slots, 1) * kPanel * kNrhsMax);
     if (h->opt.precision == NCL_FP32_IR) {
         h->F32 = dalloc<float>(h, P.factor_elems);
         h->D32 = dalloc<float>(h, P.N);
         h->M32 = dalloc<float>(h, P.M_elems);
         h->Y32 = dalloc<float>(h, 2 * P.N * kNrhsMax);
         h->U32 = dalloc<float>(h, P.U_elems * kNrhsMax);
-        h->P32 = dalloc<float>(h, std::max<int64_t>(P.solve_max_slots, 1) * kPanel * kNrhsMax);
+        h->P32 = dalloc<float>(h, 2 * std::max<int64_t>(P.solve_max_slots, 1) * kPanel * kNrhsMax);
     }
     h->R = dalloc<double>(h, P.N * kNrhsMax);
     h->DX = dalloc<double>(h, P.N * kNrhsMax);
@@ -856,7 +852,11 @@ void sweeps(ncl_kkt_s* h, int nrhs, const T* F, const T* Z, const T* D, T* Y, T*
         }
         i0 = i1;
     }
-    // backward: levels from the top down, steps of a level in reverse
+    // backward: levels from the top down, steps of a level in reverse.  The
+    // tasks' sums of panel j go to partial half j & 1 and are read by the
+    // next launch (panel j - 1, or the level's finish-only records).
+    const int64_t half = std::max<int64_t>(P.solve_max_slots, 1) * kPanel * kNrhsMax;
+    T* const pbuf[2] = {partial, partial + half};
     std::vector<size_t> starts;
     for (size_t i0 = 0; i0 < S.size(); i0 = level_end(i0)) starts.push_back(i0);
     for (auto it = starts.rbegin(); it != starts.rend(); ++it) {
@@ -872,13 +872,18 @@ void sweeps(ncl_kkt_s* h, int nrhs, const T* F, const T* Z, const T* D, T* Y, T*
             const SolveStep& ss_ = S[i];
             if (ss_.p_count > 0) {
                 Span sp(h, st, TM_SOLVE, ss_.fwd_bytes * sizeof(T) / 8.0, 4);
-                launch_bwd_P<T>(d, h->solve_p + kTaskRec * ss_.p_first, (int)ss_.p_count, F, Z, D, Y2, partial,
-                                h->solve_cnt, nrhs, st);
+                launch_bwd_P<T>(d, h->solve_p + kTaskRec * ss_.p_first, (int)ss_.p_count, F, Z, D, Y2,
+                                pbuf[ss_.j & 1], pbuf[(ss_.j + 1) & 1], nrhs, st);
             }
             if (ss_.s_count > 0) {
                 Span sp(h, ss, TM_SOLVE, 0.0, 0);
                 launch_bwd_S<T>(d, h->solve_s + ss_.s_first, (int)ss_.s_count, F, D, Y2, nrhs, ss);
             }
+        }
+        if (S[i0].f_count > 0) {
+            Span sp(h, st, TM_SOLVE, 0.0, 0);
+            launch_bwd_P<T>(d, h->solve_p + kTaskRec * S[i0].f_first, (int)S[i0].f_count, F, Z, D, Y2, pbuf[1],
+                            pbuf[0], nrhs, st);
         }
         if (fork) {
             HIPCHK(hipEventRecord(h->lvl_ev[2 * l + 1], ss));

@@ -1205,9 +1205,10 @@ __global__ void k_permute_out(DevPlan d, const T* __restrict__ Y, int nrhs, doub
 //     pivots' results go to a second vector Y2 (y after the forward sweep, x
 //     after the backward one), the right-hand side stays in Y.
 //   backward: every task forms the partial sums L[rows, panel]^T x of its rows
-//     (x of rows below the panel is final) and the last task of the panel to
-//     finish (one agent-scope counter per panel; nothing waits on it) adds the
-//     panel's partial sums in task order, forms v = y / d - sum and x = Z^T v.
+//     (x of rows below the panel is final when it starts).  A one-task panel
+//     forms v = y / d - sum and x = Z^T v itself; otherwise the sums are left
+//     for the next launch, where the task whose rows begin with the panel's
+//     pivots (or a finish-only record) adds them in task order and forms x.
 // Panel table (kPanInts ints): s, c0, w, first partial slot, tasks, first and
 // count of the pivot rows' contribution segments.  Task (kPTaskInts ints):
 // panel, rows [r0, r1) (r0 == r1 = f for a panel with nothing below), index
@@ -1432,37 +1433,91 @@ __global__ __launch_bounds__(256) void k_fwd_P(DevPlan d, const int* __restrict_
     }
 }
 
+// x of a panel's xw pivots from the sums over its rows below (v, kPanel x
+// nrhs in LDS): v = y / d - sums, then x = Z^T v with Z = L_kk^-1 (this
+// thread's share in zv, staged transposed in Ld; wave q4 takes rows
+// 16 q4 .. 16 q4 + 15).  x goes to Y2p (the panel's first pivot) and, when
+// xs is given, to the task's rows from xoff.
+template <typename T, int NR>
+__device__ __forceinline__ void bwd_panel_x(T* v, T* part, T* Ld, const T (&zv)[kPanel * kPanel / 256],
+                                            const T (&yv)[NR], T dinv, int xw, int nrhs, T* __restrict__ Y2p,
+                                            int64_t N, T* xs, int xoff, int tid) {
+    const int lane = tid & 63, q4 = tid >> 6;
+    if (tid < kPanel) {
+#pragma unroll
+        for (int q = 0; q < NR; ++q) {
+            if (q >= nrhs) continue;
+            v[tid + q * kPanel] = tid < xw ? yv[q] * dinv - v[tid + q * kPanel] : T(0);
+        }
+    }
+#pragma unroll
+    for (int it = 0; it < kPanel * kPanel / 256; ++it) {
+        const int idx = tid + 256 * it;
+        Ld[(idx & 63) + (idx >> 6) * 65] = zv[it];
+    }
+    __syncthreads();
+    for (int q = 0; q < nrhs; ++q) {
+        const T* vq = v + 16 * q4 + q * kPanel;
+        T acc = T(0);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc += Ld[(16 * q4 + j) + lane * 65] * vq[j];
+        part[(q4 * 64 + lane) * nrhs + q] = acc;
+    }
+    __syncthreads();
+    if (tid < xw)
+        for (int q = 0; q < nrhs; ++q) {
+            const T* pp = part + tid * nrhs + q;
+            const T x = (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]);
+            Y2p[tid + q * N] = x;
+            if (xs) xs[xoff + tid + q * kSolveRowsMax] = x;
+        }
+}
+
+// Backward sweep step, one workgroup per task (rows r0..r1 below a panel):
+// the task's sums L[rows, panel]^T x[rows] (a large front keeps L^T in its
+// upper triangle).  A panel with one task is finished by it.  A panel with
+// several leaves their sums in pw (slots slot0 + index) and is finished in
+// the next launch -- ordered on the same stream, so plain loads see the sums
+// -- by the first task of the front's previous panel, whose rows start with
+// this panel's pivots and which needs their x first, or, for a front's first
+// panel, by a finish-only record (index -1) after the level's last step.
+// Each panel's sums are added in task order per wave (wave q4: tasks q4,
+// q4 + 4, ...), then the four waves' totals.
 template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_bwd_P(DevPlan d, const int* __restrict__ tasks,
                                                const T* __restrict__ F, const T* __restrict__ Zbuf,
-                                               const T* __restrict__ D, T* __restrict__ Y2, T* __restrict__ partial,
-                                               int* __restrict__ pcnt, int nrhs) {
+                                               const T* __restrict__ D, T* __restrict__ Y2, T* __restrict__ pw,
+                                               const T* __restrict__ pr, int nrhs) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* xs = reinterpret_cast<T*>(smem_raw);       // kSolveRowsMax x nrhs: x of the task's rows
     T* v = xs + kSolveRowsMax * nrhs;             // kPanel x nrhs
     T* part = v + kPanel * nrhs;                  // 256 x nrhs
     T* Ld = part + 256 * nrhs;                    // 64 x 65
-    __shared__ int s_last;
     const int* tk = tasks + kTaskRec * blockIdx.x;
     const int64_t* tk64 = reinterpret_cast<const int64_t*>(tk + kTaskRec64);
-    const int pid = tk[0];
     const int c0 = tk[7], w = tk[8], slot0 = tk[9], ntask = tk[10];
     const int r0 = tk[1], nr = tk[2] - tk[1], chunk = tk[3];
     const int first = tk[13], p = tk[14], f = tk[15];
+    const int fc0 = tk[kTaskRec64 + 8], fw = tk[kTaskRec64 + 9];
+    const int fslot0 = tk[kTaskRec64 + 10], fntask = tk[kTaskRec64 + 11];
     const T* __restrict__ L = F + tk64[0];
     const int64_t moff = tk64[2];
     const int* __restrict__ rows = d.sn_rows + tk64[3];
     const bool large = moff >= 0;
+    const bool own = chunk >= 0;              // else a finish-only record
+    const bool fin = fntask > 0;              // finishes panel fc0 before its own sums
+    const bool self = own && ntask == 1;      // finishes its own panel
+    const int xc0 = fin ? fc0 : c0;           // the panel it finishes (xw pivots, 0: none)
+    const int xw = fin ? fw : (self ? w : 0);
     const int tid = threadIdx.x, lane = tid & 63, q4 = tid >> 6;
     const int64_t N = d.N;
     // thread = (panel column t, row group rg): columns in slots of 16, the
     // row groups take rows rg, rg + nrg, ... (at most 16 per thread)
     const int W16 = 16 * ((w + 15) >> 4), nrg = 256 / W16;
     const int t = tid % W16, rg = tid / W16;
-    const bool tact = t < w && rg < nrg;
+    const bool tact = own && t < w && rg < nrg;
     // Loads that depend on nothing computed here first: this thread's L^T
-    // operands (L^T is stored in a large front's upper triangle), Z for the
-    // transposed triangle, and 1 / d of the panel's pivots.
+    // operands, and Z, 1 / d and y of the panel it finishes.
     T lv[16], zv[kPanel * kPanel / 256];
     if (large) {
         const T* __restrict__ lt = L + (c0 + (tact ? t : 0)) + (int64_t)r0 * f;
@@ -1471,19 +1526,23 @@ __global__ __launch_bounds__(256) void k_bwd_P(DevPlan d, const int* __restrict_
             const int i = rg + nrg * m;
             lv[m] = (tact && i < nr) ? lt[(int64_t)i * f] : T(0);
         }
-        const T* __restrict__ Zb = Zbuf + moff + (int64_t)(c0 / kPanel) * (kPanel * kPanel);
+        const T* __restrict__ Zb = Zbuf + moff + (int64_t)(xc0 / kPanel) * (kPanel * kPanel);
 #pragma unroll
         for (int it = 0; it < kPanel * kPanel / 256; ++it) {
             const int idx = tid + 256 * it;
-            zv[it] = ((idx & 63) < w && (idx >> 6) < w) ? Zb[idx] : T(0);
+            zv[it] = ((idx & 63) < xw && (idx >> 6) < xw) ? Zb[idx] : T(0);
         }
     }
-    const T dinv = tid < w ? T(1) / D[first + c0 + tid] : T(0);
-    for (int q = 0; q < nrhs; ++q) {
-        const int gi = r0 + tid;
-        xs[tid + q * kSolveRowsMax] = tid >= nr ? T(0) : gi < p ? Y2[first + gi + q * N] : Y2[rows[gi] + q * N];
-    }
-    if (!large && nr > 0) {
+    const T dinv = tid < xw ? T(1) / D[first + xc0 + tid] : T(0);
+    T yv[NR];
+#pragma unroll
+    for (int q = 0; q < NR; ++q) yv[q] = (q < nrhs && tid < xw) ? Y2[first + xc0 + tid + q * N] : T(0);
+    if (own)
+        for (int q = 0; q < nrhs; ++q) {
+            const int gi = r0 + tid;
+            xs[tid + q * kSolveRowsMax] = tid >= nr ? T(0) : gi < p ? Y2[first + gi + q * N] : Y2[rows[gi] + q * N];
+        }
+    if (!large && own && nr > 0) {
         // column-major L only: stage L[rows, panel] as Ld[i + 65 t] (coalesced
         // reads); such fronts have at most 64 rows below a panel (analysis)
         for (int idx = tid; idx < 64 * kPanel; idx += 256) {
@@ -1491,6 +1550,38 @@ __global__ __launch_bounds__(256) void k_bwd_P(DevPlan d, const int* __restrict_
             Ld[i + 65 * tt] = (i < nr && tt < w) ? L[(r0 + i) + (int64_t)(c0 + tt) * f] : T(0);
         }
     }
+    if (fin) {
+        T acc2[NR];
+#pragma unroll
+        for (int q = 0; q < NR; ++q) acc2[q] = T(0);
+        for (int g0 = q4; g0 < fntask; g0 += 32) {
+            T pv[8];
+#pragma unroll
+            for (int q = 0; q < NR; ++q) {
+                if (q >= nrhs) continue;
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int g = g0 + 4 * u;
+                    pv[u] = g < fntask ? pr[((int64_t)(fslot0 + g) * kPanel + lane) * kNrhsMax + q] : T(0);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) acc2[q] += pv[u];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NR; ++q)
+            if (q < nrhs) part[(q4 * 64 + lane) * nrhs + q] = acc2[q];
+        __syncthreads();
+        if (tid < kPanel)
+            for (int q = 0; q < nrhs; ++q) {
+                const T* pp = part + tid * nrhs + q;
+                v[tid + q * kPanel] = (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]);
+            }
+        __syncthreads();
+        bwd_panel_x<T, NR>(v, part, Ld, zv, yv, dinv, fw, nrhs, Y2 + first + fc0, N, own ? xs : nullptr,
+                           fc0 - r0, tid);
+    }
+    if (!own) return;
     __syncthreads();
     // partial sums over the task's rows
 #pragma unroll
@@ -1512,7 +1603,7 @@ __global__ __launch_bounds__(256) void k_bwd_P(DevPlan d, const int* __restrict_
         part[tid * nrhs + q] = tact ? a : T(0);
     }
     __syncthreads();
-    // this task's sum per panel column, into v (scratch) until it is combined
+    // this task's sum per panel column
     if (tid < kPanel)
         for (int q = 0; q < nrhs; ++q) {
             T sum = T(0);
@@ -1522,84 +1613,21 @@ __global__ __launch_bounds__(256) void k_bwd_P(DevPlan d, const int* __restrict_
         }
     __syncthreads();
     if (ntask > 1) {
-        // Publish this task's sums; the last task of the panel goes on.  Every
-        // access to the partial sums is an agent-scope atomic (coherent across
-        // the XCDs' L2 caches): every wave waits for its stores to complete
-        // before the count is raised, and the last task reads after its count
-        // returned -- no whole-L2 write-back, which a release fence would cost
-        // every task.  (Ordinary loads could hit a line of the same slots that
-        // an earlier solve left in the reading XCD's L2.)
         if (tid < kPanel)
             for (int q = 0; q < nrhs; ++q)
-                __hip_atomic_store(partial + ((int64_t)(slot0 + chunk) * kPanel + tid) * kNrhsMax + q,
-                                   v[tid + q * kPanel], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
-        __syncthreads();
-        if (tid == 0) {
-            const int seen = __hip_atomic_fetch_add(pcnt + pid, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            s_last = seen == ntask - 1;
-            if (s_last) __hip_atomic_store(pcnt + pid, 0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        }
-        __syncthreads();
-        if (!s_last) return;
-        // wave q4 adds the tasks g = q4, q4 + 4, ... (eight loads in flight
-        // per thread), then the four waves' sums meet in part
-        T acc2[NR];
-#pragma unroll
-        for (int q = 0; q < NR; ++q) acc2[q] = T(0);
-        for (int g0 = q4; g0 < ntask; g0 += 32) {
-            T pv[8];
+                pw[((int64_t)(slot0 + chunk) * kPanel + tid) * kNrhsMax + q] = v[tid + q * kPanel];
+        return;
+    }
+    if (large) {
+        bwd_panel_x<T, NR>(v, part, Ld, zv, yv, dinv, w, nrhs, Y2 + first + c0, N, nullptr, 0, tid);
+    } else {
+        if (tid < kPanel) {
 #pragma unroll
             for (int q = 0; q < NR; ++q) {
                 if (q >= nrhs) continue;
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int g = g0 + 4 * u;
-                    pv[u] = g < ntask ? __hip_atomic_load(partial + ((int64_t)(slot0 + g) * kPanel + lane) * kNrhsMax + q,
-                                                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                                      : T(0);
-                }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) acc2[q] += pv[u];
+                v[tid + q * kPanel] = tid < w ? yv[q] * dinv - v[tid + q * kPanel] : T(0);
             }
         }
-#pragma unroll
-        for (int q = 0; q < NR; ++q)
-            if (q < nrhs) part[(q4 * 64 + lane) * nrhs + q] = acc2[q];
-        __syncthreads();
-        if (tid < kPanel)
-            for (int q = 0; q < nrhs; ++q) {
-                const T* pp = part + tid * nrhs + q;
-                v[tid + q * kPanel] = (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]);
-            }
-        __syncthreads();
-    }
-    // v = y / d - sums
-    if (tid < kPanel)
-        for (int q = 0; q < nrhs; ++q)
-            v[tid + q * kPanel] = tid < w ? Y2[first + c0 + tid + q * N] * dinv - v[tid + q * kPanel] : T(0);
-    if (large) {
-        // x = Z^T v: Z staged transposed in Ld, wave q4 takes rows 16 q4 .. 16 q4 + 15
-#pragma unroll
-        for (int it = 0; it < kPanel * kPanel / 256; ++it) {
-            const int idx = tid + 256 * it;
-            Ld[(idx & 63) + (idx >> 6) * 65] = zv[it];
-        }
-        __syncthreads();
-        for (int q = 0; q < nrhs; ++q) {
-            const T* vq = v + 16 * q4 + q * kPanel;
-            T acc = T(0);
-#pragma unroll
-            for (int j = 0; j < 16; ++j) acc += Ld[(16 * q4 + j) + lane * 65] * vq[j];
-            part[(q4 * 64 + lane) * nrhs + q] = acc;
-        }
-        __syncthreads();
-        if (tid < w)
-            for (int q = 0; q < nrhs; ++q) {
-                const T* pp = part + tid * nrhs + q;
-                Y2[first + c0 + tid + q * N] = (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]);
-            }
-    } else {
         __syncthreads();
         chain_solve64<T, true>(L, f, c0, w, Ld, v, kPanel, nrhs);
         for (int q = 0; q < nrhs; ++q)
@@ -2604,14 +2632,13 @@ void launch_fwd_P(const DevPlan& d, const int* tasks, int count, const int* segs
 
 template <typename T>
 void launch_bwd_P(const DevPlan& d, const int* tasks, int count, const T* F, const T* Z,
-                  const T* D, T* Y2, T* partial, int* pcnt, int nrhs, hipStream_t st) {
+                  const T* D, T* Y2, T* pw, const T* pr, int nrhs, hipStream_t st) {
     if (count <= 0) return;
     const size_t lds = (size_t)((kPanel + kSolveRowsMax + 256) * nrhs + 64 * 65) * sizeof(T);
     if (nrhs == 1)
-        launch(k_bwd_P<T, 1>, dim3(count), dim3(256), lds, st, d, tasks, F, Z, D, Y2, partial, pcnt, nrhs);
+        launch(k_bwd_P<T, 1>, dim3(count), dim3(256), lds, st, d, tasks, F, Z, D, Y2, pw, pr, nrhs);
     else
-        launch(k_bwd_P<T, kNrhsMax>, dim3(count), dim3(256), lds, st, d, tasks, F, Z, D, Y2, partial, pcnt,
-               nrhs);
+        launch(k_bwd_P<T, kNrhsMax>, dim3(count), dim3(256), lds, st, d, tasks, F, Z, D, Y2, pw, pr, nrhs);
 }
 
 void launch_residual(const DevPlan& d, const double* K, const double* B, int64_t ldb, const double* X, int64_t ldx,
@@ -2709,8 +2736,8 @@ hipError_t configure_kernels(int max_dynamic_lds) {
     template void launch_bwd_S<T>(const DevPlan&, const int*, int, const T*, const T*, T*, int, hipStream_t);     \
     template void launch_fwd_P<T>(const DevPlan&, const int*, int, const int*, const T*, const T*, T*, T*, T*,    \
                                   int, hipStream_t);                                                               \
-    template void launch_bwd_P<T>(const DevPlan&, const int*, int, const T*, const T*, const T*, T*, T*, int*, int, \
-                                  hipStream_t);
+    template void launch_bwd_P<T>(const DevPlan&, const int*, int, const T*, const T*, const T*, T*, T*,          \
+                                  const T*, int, hipStream_t);
 
 NCL_INSTANTIATE(double)
 NCL_INSTANTIATE(float)

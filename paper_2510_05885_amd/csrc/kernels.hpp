@@ -20,7 +20,8 @@ constexpr int kPTaskInts = 6;    // ints per solve task: panel, r0, r1, index, s
 //   ints  6..12  the panel (s, c0, w, slot0, tasks, seg0, nseg)
 //   ints 13..15  the front (first pivot, pivots p, order f)
 //   int64 at ints 16, 18, 20, 22: L_off, U_off, M_off, first row-list entry
-constexpr int kTaskRec = 24;
+//   ints 24..27  backward: the panel this task finishes (c0, w, slot0, tasks; tasks 0: none)
+constexpr int kTaskRec = 28;
 constexpr int kTaskRec64 = 16;
 constexpr int kInertiaSlots = 64;  // partial inertia counters per system (spreads the atomics)
 constexpr int kNonfiniteInput = 1;   // status bit: NaN/Inf in the assembled K (its norms)
@@ -192,15 +193,16 @@ void launch_fwd_S(const DevPlan& d, const int* fronts, int count, const T* F, co
 template <typename T>
 void launch_bwd_S(const DevPlan& d, const int* fronts, int count, const T* F, const T* D, T* Y2, int nrhs,
                   hipStream_t st);
-// The other fronts, one launch per panel step of a level (panel table ptab,
-// tasks, contribution segments: see the sweep kernels).  partial: slots x
-// kPanel x kNrhsMax; pcnt: one zero counter per panel (left zero).
+// The other fronts, one launch per panel step of a level (task records of
+// kTaskRec ints, contribution segments: see the sweep kernels).  Backward:
+// the step's task sums go to pw, the previous step's are read from pr (each
+// slots x kPanel x kNrhsMax, two halves used in turn).
 template <typename T>
 void launch_fwd_P(const DevPlan& d, const int* tasks, int count, const int* segs, const T* F,
                   const T* Z, T* Y, T* Y2, T* U, int nrhs, hipStream_t st);
 template <typename T>
 void launch_bwd_P(const DevPlan& d, const int* tasks, int count, const T* F, const T* Z,
-                  const T* D, T* Y2, T* partial, int* pcnt, int nrhs, hipStream_t st);
+                  const T* D, T* Y2, T* pw, const T* pr, int nrhs, hipStream_t st);
 
 // ---- refinement -------------------------------------------------------------
 // R = B - K X; per chunk of rows (all of one system) and column, kResWidth figures:

@@ -48,6 +48,8 @@ struct SolveStep {
     int level = 0, j = 0;
     int64_t p_first = 0, p_count = 0;   // tasks in Plan::solve_p (kPTaskInts each)
     int64_t s_first = 0, s_count = 0;   // small fronts in Plan::solve_s (one wave each)
+    int64_t f_first = 0, f_count = 0;   // j = 0 only: finish-only records in Plan::solve_p, run
+                                        // after the level's backward steps
     double fwd_bytes = 0.0;             // algorithmic bytes of L read by the step (FP64; padding
                                         // zeros of amalgamated fronts not counted)
 };
@@ -149,7 +151,9 @@ struct Plan {
     // solve schedule
     std::vector<SolveStep> solve_steps;
     std::vector<int> solve_pan;      // panels (s, c0, w, slot0, tasks, seg0, nseg)
-    std::vector<int> solve_p;        // tasks (panel, r0, r1, index, seg0, nseg)
+    std::vector<int> solve_p;        // tasks (panel, r0, r1, index, seg0, nseg); index -1: finish only
+    std::vector<int> solve_fin;      // per task: the panel it finishes in the backward sweep
+                                     // (c0, w, slot0, tasks), tasks 0 if none
     std::vector<int> solve_seg;      // (child, a0, a1): update-vector entries landing in a task
     std::vector<int> solve_s;        // small fronts (p <= 64, f <= 128) solved by one wave each
     int64_t solve_max_slots = 0;     // tasks in the largest step (partial-sum slots)
