@@ -935,6 +935,80 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                 }
                 st.f_count = (int64_t)P.solve_p.size() / 6 - st.f_first;
             }
+            // Forward: a large front's panels are taken two at a time (2k and
+            // 2k + 1 in step k of its level): its tasks own the rows below the
+            // second panel, 64 each, and form both panels' y themselves.  Other
+            // fronts keep one panel per step.  Tasks refer to the first
+            // panel's record; solve_fx holds (w of the second panel or 0, its
+            // pivot rows' contribution segments (first, count), 0).
+            {
+                std::vector<int64_t> s_first_of(P.nlevels, 0), s_count_of(P.nlevels, 0);
+                for (const SolveStep& st : P.solve_steps)
+                    if (st.j == 0) { s_first_of[st.level] = st.s_first; s_count_of[st.level] = st.s_count; }
+                for (int l = 0; l < P.nlevels; ++l) {
+                    int maxk = 0;
+                    for (int k = P.level_ptr[l]; k < P.level_ptr[l + 1]; ++k) {
+                        const int s = P.level_list[k];
+                        const int np = (int)sn_pids[s].size();
+                        maxk = std::max(maxk, P.sn_large[s] ? (np + 1) / 2 : np);
+                    }
+                    if (s_count_of[l] > 0) maxk = std::max(maxk, 1);
+                    for (int kk = 0; kk < maxk; ++kk) {
+                        SolveStep st;
+                        st.level = l; st.j = kk;
+                        st.p_first = (int64_t)P.fsolve_p.size() / 6;
+                        if (kk == 0) { st.s_first = s_first_of[l]; st.s_count = s_count_of[l]; }
+                        for (int k = P.level_ptr[l]; k < P.level_ptr[l + 1]; ++k) {
+                            const int s = P.level_list[k];
+                            const std::vector<int>& pids = sn_pids[s];
+                            const bool lg = P.sn_large[s] != 0;
+                            const size_t j = lg ? 2 * (size_t)kk : (size_t)kk;
+                            if (j >= pids.size()) continue;
+                            const int pid = pids[j];
+                            const int* pn = P.solve_pan.data() + 7 * (size_t)pid;
+                            const int c0 = pn[1], w = pn[2];
+                            const int p = P.sn_first[s + 1] - P.sn_first[s];
+                            const int f = (int)(P.sn_rowptr[s + 1] - P.sn_rowptr[s]);
+                            const int w2 = (lg && j + 1 < pids.size()) ? P.solve_pan[7 * (size_t)pids[j + 1] + 2] : 0;
+                            if (w2 > 0 && w != PW) throw AnalyzeError(-4, "internal: paired panel narrower than 64");
+                            auto bytes = [&](int cc, int ww) {
+                                const int below = f - cc - ww;
+                                return 8.0 * ((double)ww * (ww + 1) / 2.0 + (double)below * ww) * P.sn_nnz_ratio[s];
+                            };
+                            st.fwd_bytes += bytes(c0, w) + (w2 > 0 ? bytes(c0 + w, w2) : 0.0);
+                            const int rs = c0 + w + w2;                 // first row below the step's panels
+                            const int below = f - rs;
+                            const int GR = w2 > 0 ? 64 : task_rows(w);
+                            const int ntask = std::max(1, (below + GR - 1) / GR);
+                            int s2seg0 = (int)(P.solve_seg.size() / 3), s2nseg = 0;
+                            if (w2 > 0 && c0 == 0) {
+                                for (int q = P.child_ptr[s]; q < P.child_ptr[s + 1]; ++q) {
+                                    int a0, a1;
+                                    child_range(P.child_list[q], w, w + w2, a0, a1);
+                                    if (a1 > a0) { P.solve_seg.push_back(P.child_list[q]); P.solve_seg.push_back(a0); P.solve_seg.push_back(a1); }
+                                }
+                                s2nseg = (int)(P.solve_seg.size() / 3) - s2seg0;
+                            }
+                            for (int t = 0; t < ntask; ++t) {
+                                const int r0 = below > 0 ? rs + t * GR : f;
+                                const int r1 = below > 0 ? std::min(f, r0 + GR) : f;
+                                const int tseg0 = (int)(P.solve_seg.size() / 3);
+                                if (c0 == 0 && r1 > r0)
+                                    for (int q = P.child_ptr[s]; q < P.child_ptr[s + 1]; ++q) {
+                                        int a0, a1;
+                                        child_range(P.child_list[q], r0, r1, a0, a1);
+                                        if (a1 > a0) { P.solve_seg.push_back(P.child_list[q]); P.solve_seg.push_back(a0); P.solve_seg.push_back(a1); }
+                                    }
+                                const int tnseg = (int)(P.solve_seg.size() / 3) - tseg0;
+                                for (int v : {pid, r0, r1, t, tseg0, tnseg}) P.fsolve_p.push_back(v);
+                                for (int v : {w2, s2seg0, s2nseg, 0}) P.fsolve_x.push_back(v);
+                            }
+                        }
+                        st.p_count = (int64_t)P.fsolve_p.size() / 6 - st.p_first;
+                        P.fsolve_steps.push_back(st);
+                    }
+                }
+            }
         }
     } catch (const AnalyzeError& e) {
         err = e.what();

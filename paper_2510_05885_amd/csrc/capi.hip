@@ -101,7 +101,8 @@ struct ncl_kkt_s {
     int64_t nnzF = 0;
     // schedule arrays (device)
     int *small_list = nullptr, *level_list = nullptr, *large_asm = nullptr, *large_panel = nullptr,
-        *large_upd = nullptr, *large_diag = nullptr, *solve_p = nullptr, *solve_seg = nullptr, *solve_s = nullptr;
+        *large_upd = nullptr, *large_diag = nullptr, *solve_p = nullptr, *solve_seg = nullptr, *solve_s = nullptr,
+        *fsolve_p = nullptr;
     int *chunk_row0 = nullptr, *chunk_rows = nullptr, *sys_chunk_ptr = nullptr;
     int nchunks = 0;
     // numeric state
@@ -282,25 +283,35 @@ void setup_device(ncl_kkt_s* h) {
     h->large_asm = upload(h, P.large_asm);
     h->large_diag = upload(h, P.large_diag);
     {
-        // every sweep task with its panel's and its front's fields (kTaskRec ints)
-        const size_t nt = P.solve_p.size() / kPTaskInts;
-        std::vector<int> rec(std::max<size_t>(nt, 1) * kTaskRec, 0);
-        for (size_t t = 0; t < nt; ++t) {
-            int* r = rec.data() + t * kTaskRec;
-            const int* tk = P.solve_p.data() + t * kPTaskInts;
-            const int* pn = P.solve_pan.data() + (size_t)tk[0] * kPanInts;
-            const int s = pn[0];
-            for (int i = 0; i < kPTaskInts; ++i) r[i] = tk[i];
-            for (int i = 0; i < kPanInts; ++i) r[kPTaskInts + i] = pn[i];
-            r[13] = P.sn_first[s];
-            r[14] = P.sn_first[s + 1] - P.sn_first[s];
-            r[15] = (int)(P.sn_rowptr[s + 1] - P.sn_rowptr[s]);
-            // U_off as on the device: room for kNrhsMax columns per front
-            const int64_t v64[4] = {P.L_off[s], P.U_off[s] * kNrhsMax, P.M_off[s], P.sn_rowptr[s]};
-            std::memcpy(r + kTaskRec64, v64, sizeof(v64));
-            for (int i = 0; i < 4; ++i) r[kTaskRec64 + 8 + i] = P.solve_fin[4 * t + i];
-        }
-        h->solve_p = upload(h, rec);
+        // every sweep task with its panel's and its front's fields (kTaskRec
+        // ints): the backward tasks (with the panel each finishes) and the
+        // forward ones (with their second panel)
+        auto records = [&](const std::vector<int>& tasks, const std::vector<int>* fin,
+                           const std::vector<int>* fx) {
+            const size_t nt = tasks.size() / kPTaskInts;
+            std::vector<int> rec(std::max<size_t>(nt, 1) * kTaskRec, 0);
+            for (size_t t = 0; t < nt; ++t) {
+                int* r = rec.data() + t * kTaskRec;
+                const int* tk = tasks.data() + t * kPTaskInts;
+                const int* pn = P.solve_pan.data() + (size_t)tk[0] * kPanInts;
+                const int s = pn[0];
+                for (int i = 0; i < kPTaskInts; ++i) r[i] = tk[i];
+                for (int i = 0; i < kPanInts; ++i) r[kPTaskInts + i] = pn[i];
+                r[13] = P.sn_first[s];
+                r[14] = P.sn_first[s + 1] - P.sn_first[s];
+                r[15] = (int)(P.sn_rowptr[s + 1] - P.sn_rowptr[s]);
+                // U_off as on the device: room for kNrhsMax columns per front
+                const int64_t v64[4] = {P.L_off[s], P.U_off[s] * kNrhsMax, P.M_off[s], P.sn_rowptr[s]};
+                std::memcpy(r + kTaskRec64, v64, sizeof(v64));
+                for (int i = 0; i < 4; ++i) {
+                    if (fin) r[kTaskRec64 + 8 + i] = (*fin)[4 * t + i];
+                    if (fx) r[kTaskRec64 + 12 + i] = (*fx)[4 * t + i];
+                }
+            }
+            return rec;
+        };
+        h->solve_p = upload(h, records(P.solve_p, &P.solve_fin, nullptr));
+        h->fsolve_p = upload(h, records(P.fsolve_p, nullptr, &P.fsolve_x));
     }
     h->solve_seg = upload(h, P.solve_seg);
     h->solve_s = upload(h, P.solve_s);
@@ -812,37 +823,38 @@ void sweeps(ncl_kkt_s* h, int nrhs, const T* F, const T* Z, const T* D, T* Y, T*
     }
     T* Y2 = Y + P.N * kNrhsMax;
     const std::vector<SolveStep>& S = P.solve_steps;
+    const std::vector<SolveStep>& FS = P.fsolve_steps;
     // Steps of one level are independent between the one-wave fronts and the
     // panel tasks: when a level has both, the one-wave fronts go to the second
     // stream, forked at the level's first step and joined after its last.
-    auto level_end = [&](size_t i) {
+    auto level_end = [&](const std::vector<SolveStep>& V, size_t i) {
         size_t e = i;
-        while (e < S.size() && S[e].level == S[i].level) ++e;
+        while (e < V.size() && V[e].level == V[i].level) ++e;
         return e;
     };
-    auto has_panels = [&](size_t i0, size_t i1) {
+    auto has_panels = [&](const std::vector<SolveStep>& V, size_t i0, size_t i1) {
         for (size_t i = i0; i < i1; ++i)
-            if (S[i].p_count > 0) return true;
+            if (V[i].p_count > 0) return true;
         return false;
     };
-    for (size_t i0 = 0; i0 < S.size();) {
-        const size_t i1 = level_end(i0);
-        const int l = S[i0].level;
-        const bool fork = S[i0].s_count > 0 && has_panels(i0, i1);
+    for (size_t i0 = 0; i0 < FS.size();) {
+        const size_t i1 = level_end(FS, i0);
+        const int l = FS[i0].level;
+        const bool fork = FS[i0].s_count > 0 && has_panels(FS, i0, i1);
         hipStream_t ss = fork ? h->aux_stream : st;
         if (fork) {
             HIPCHK(hipEventRecord(h->lvl_ev[2 * l], st));
             HIPCHK(hipStreamWaitEvent(ss, h->lvl_ev[2 * l], 0));
         }
         for (size_t i = i0; i < i1; ++i) {
-            const SolveStep& ss_ = S[i];
+            const SolveStep& ss_ = FS[i];
             if (ss_.s_count > 0) {
                 Span sp(h, ss, TM_SOLVE, 0.0, 0);
                 launch_fwd_S<T>(d, h->solve_s + ss_.s_first, (int)ss_.s_count, F, Y, Y2, U, nrhs, ss);
             }
             if (ss_.p_count > 0) {
                 Span sp(h, st, TM_SOLVE, ss_.fwd_bytes * sizeof(T) / 8.0, 4);
-                launch_fwd_P<T>(d, h->solve_p + kTaskRec * ss_.p_first, (int)ss_.p_count, h->solve_seg, F, Z, Y,
+                launch_fwd_P<T>(d, h->fsolve_p + kTaskRec * ss_.p_first, (int)ss_.p_count, h->solve_seg, F, Z, Y,
                                 Y2, U, nrhs, st);
             }
         }
@@ -858,11 +870,11 @@ void sweeps(ncl_kkt_s* h, int nrhs, const T* F, const T* Z, const T* D, T* Y, T*
     const int64_t half = std::max<int64_t>(P.solve_max_slots, 1) * kPanel * kNrhsMax;
     T* const pbuf[2] = {partial, partial + half};
     std::vector<size_t> starts;
-    for (size_t i0 = 0; i0 < S.size(); i0 = level_end(i0)) starts.push_back(i0);
+    for (size_t i0 = 0; i0 < S.size(); i0 = level_end(S, i0)) starts.push_back(i0);
     for (auto it = starts.rbegin(); it != starts.rend(); ++it) {
-        const size_t i0 = *it, i1 = level_end(i0);
+        const size_t i0 = *it, i1 = level_end(S, i0);
         const int l = S[i0].level;
-        const bool fork = S[i0].s_count > 0 && has_panels(i0, i1);
+        const bool fork = S[i0].s_count > 0 && has_panels(S, i0, i1);
         hipStream_t ss = fork ? h->aux_stream : st;
         if (fork) {
             HIPCHK(hipEventRecord(h->lvl_ev[2 * l], st));

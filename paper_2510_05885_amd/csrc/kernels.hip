@@ -1333,6 +1333,13 @@ __device__ __forceinline__ void add_segments(const DevPlan& d, const T* __restri
     }
 }
 
+// Forward sweep step, one workgroup per task.  With a second panel (w2 > 0,
+// large fronts, w = 64) the task owns 64 rows below both panels and forms
+// both y itself: y = Z b of the first, the second's b minus L[its pivots,
+// first panel] y, y2 = Z2 b2, then its rows -= L[rows, first] y and
+// -= L[rows, second] y2.  Every product and sum is the one a step per
+// panel would form (the second panel's b as the first panel's task 0
+// would update it), in the same order.
 template <typename T, int NR>
 __global__ __launch_bounds__(256) void k_fwd_P(DevPlan d, const int* __restrict__ tasks,
                                                const int* __restrict__ segs, const T* __restrict__ F,
@@ -1343,11 +1350,14 @@ __global__ __launch_bounds__(256) void k_fwd_P(DevPlan d, const int* __restrict_
     T* rw = v + kPanel * nrhs;                    // kSolveRowsMax x nrhs: the task's rows
     T* part = rw + kSolveRowsMax * nrhs;          // 256 x nrhs
     T* Ld = part + 256 * nrhs;                    // 64 x 65
+    T* v2 = Ld + 64 * 65;                         // kPanel x nrhs: the second panel's b, then y
     const int* tk = tasks + kTaskRec * blockIdx.x;
     const int64_t* tk64 = reinterpret_cast<const int64_t*>(tk + kTaskRec64);
     const int c0 = tk[7], w = tk[8];
     const int r0 = tk[1], nr = tk[2] - tk[1], chunk = tk[3];
     const int first = tk[13], p = tk[14], f = tk[15];
+    const int w2 = tk[kTaskRec64 + 12];
+    const int c02 = c0 + kPanel;
     const int c = f - p;
     const T* __restrict__ L = F + tk64[0];
     T* __restrict__ Us = U + tk64[1];
@@ -1355,14 +1365,18 @@ __global__ __launch_bounds__(256) void k_fwd_P(DevPlan d, const int* __restrict_
     const int tid = threadIdx.x, lane = tid & 63, q4 = tid >> 6;
     const int64_t N = d.N;
     const bool large = moff >= 0;
+    const bool pair = w2 > 0;
     // wave q4: row group q4 / nwc (64 rows, lane = row), columns 16 (q4 % nwc) + [0, 16)
     const int nwc = (w + 15) >> 4, ng = 4 / nwc;
     const int rgrp = q4 / nwc, k0 = 16 * (q4 - rgrp * nwc);
     const int myrow = 64 * rgrp + lane;           // row of the task (valid if < nr)
+    const int nwc2 = (w2 + 15) >> 4;              // second panel: wave q4 takes its columns 16 q4 + [0, 16)
     // Operands that depend on nothing computed here are loaded first, so
     // their latency overlaps the right-hand side's: Z[lane][16 q4 + j] (large
-    // fronts) and this thread's slice of L[rows, panel].
-    T z[16], lv[16];
+    // fronts) and this thread's slice of L[rows, panel]; with a second panel
+    // also its Z, its slice of L[rows, second panel] and of the block
+    // L[second panel's pivots, first panel].
+    T z[16], lv[16], z2[16], lv2[16], lb[16];
     if (large) {
         const T* __restrict__ Zb = Zbuf + moff + (int64_t)(c0 / kPanel) * (kPanel * kPanel);
 #pragma unroll
@@ -1374,8 +1388,23 @@ __global__ __launch_bounds__(256) void k_fwd_P(DevPlan d, const int* __restrict_
 #pragma unroll
         for (int j = 0; j < 16; ++j) lv[j] = (rv && k0 + j < w) ? L[row + (int64_t)(c0 + k0 + j) * f] : T(0);
     }
+    if (pair) {
+        const T* __restrict__ Zb = Zbuf + moff + (int64_t)(c02 / kPanel) * (kPanel * kPanel);
+        const bool rv = lane < nr;
+        const int64_t row = r0 + (rv ? lane : 0);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) {
+            const int kk = 16 * q4 + j;
+            z2[j] = (lane < w2 && kk < w2) ? Zb[kk * kPanel + lane] : T(0);
+            lv2[j] = (rv && kk < w2) ? L[row + (int64_t)(c02 + kk) * f] : T(0);
+            lb[j] = lane < w2 ? L[(c02 + lane) + (int64_t)(c0 + kk) * f] : T(0);
+        }
+    }
     for (int q = 0; q < nrhs; ++q) {
-        if (tid < kPanel) v[tid + q * kPanel] = tid < w ? Y[first + c0 + tid + q * N] : T(0);
+        if (tid < kPanel) {
+            v[tid + q * kPanel] = tid < w ? Y[first + c0 + tid + q * N] : T(0);
+            if (pair) v2[tid + q * kPanel] = tid < w2 ? Y[first + c02 + tid + q * N] : T(0);
+        }
         const int gi = r0 + tid;
         T val = T(0);
         if (tid < nr) val = gi < p ? Y[first + gi + q * N] : (c0 == 0 ? T(0) : Us[(gi - p) + (int64_t)q * c]);
@@ -1384,6 +1413,7 @@ __global__ __launch_bounds__(256) void k_fwd_P(DevPlan d, const int* __restrict_
     __syncthreads();
     if (c0 == 0) {
         add_segments<T, NR>(d, U, segs, tk[11], tk[12], 0, v, kPanel, nrhs);
+        if (pair) add_segments<T, NR>(d, U, segs, tk[kTaskRec64 + 13], tk[kTaskRec64 + 14], c02, v2, kPanel, nrhs);
         add_segments<T, NR>(d, U, segs, tk[4], tk[5], r0, rw, kSolveRowsMax, nrhs);
     }
     if (large) {
@@ -1408,6 +1438,42 @@ __global__ __launch_bounds__(256) void k_fwd_P(DevPlan d, const int* __restrict_
     if (chunk == 0)
         for (int q = 0; q < nrhs; ++q)
             if (tid < w) Y2[first + c0 + tid + q * N] = v[tid + q * kPanel];
+    if (pair) {
+        // the second panel's b -= L[its pivots, first panel] y (wave q4: columns
+        // 16 q4 + [0, 16), lane = pivot), then y2 = Z2 b
+        for (int q = 0; q < nrhs; ++q) {
+            const T* vq = v + 16 * q4 + q * kPanel;
+            T acc = T(0);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc += lb[j] * vq[j];
+            part[(q4 * 64 + lane) * nrhs + q] = acc;
+        }
+        __syncthreads();
+        if (tid < w2)
+            for (int q = 0; q < nrhs; ++q) {
+                const T* pp = part + tid * nrhs + q;
+                T sum = pp[0];
+                for (int k = 1; k < 4; ++k) sum += pp[k * 64 * nrhs];
+                v2[tid + q * kPanel] -= sum;
+            }
+        __syncthreads();
+        for (int q = 0; q < nrhs; ++q) {
+            const T* vq = v2 + 16 * q4 + q * kPanel;
+            T acc = T(0);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) acc += z2[j] * vq[j];
+            part[(q4 * 64 + lane) * nrhs + q] = acc;
+        }
+        __syncthreads();
+        if (tid < w2)
+            for (int q = 0; q < nrhs; ++q) {
+                const T* pp = part + tid * nrhs + q;
+                const T y2 = (pp[0] + pp[64 * nrhs]) + (pp[128 * nrhs] + pp[192 * nrhs]);
+                v2[tid + q * kPanel] = y2;
+                if (chunk == 0) Y2[first + c02 + tid + q * N] = y2;
+            }
+        __syncthreads();
+    }
     if (nr == 0) return;
     // rows: y_i -= L[i, panel] y
 #pragma unroll
@@ -1420,12 +1486,45 @@ __global__ __launch_bounds__(256) void k_fwd_P(DevPlan d, const int* __restrict_
         part[(q4 * 64 + lane) * nrhs + q] = acc;
     }
     __syncthreads();
-    if (tid < nr) {
-        const int gi = r0 + tid, g = tid >> 6, l = tid & 63;
+    if (!pair) {
+        if (tid < nr) {
+            const int gi = r0 + tid, g = tid >> 6, l = tid & 63;
+            for (int q = 0; q < nrhs; ++q) {
+                const T* pp = part + ((g * nwc) * 64 + l) * nrhs + q;
+                T sum = pp[0];
+                for (int k = 1; k < nwc; ++k) sum += pp[k * 64 * nrhs];
+                const T val = rw[tid + q * kSolveRowsMax] - sum;
+                if (gi < p) Y[first + gi + q * N] = val;
+                else Us[(gi - p) + (int64_t)q * c] = val;
+            }
+        }
+        return;
+    }
+    // two panels: the first panel's update of the rows, then the second's
+    if (tid < nr)
         for (int q = 0; q < nrhs; ++q) {
-            const T* pp = part + ((g * nwc) * 64 + l) * nrhs + q;
+            const T* pp = part + tid * nrhs + q;
             T sum = pp[0];
-            for (int k = 1; k < nwc; ++k) sum += pp[k * 64 * nrhs];
+            for (int k = 1; k < 4; ++k) sum += pp[k * 64 * nrhs];
+            rw[tid + q * kSolveRowsMax] -= sum;
+        }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < NR; ++q) {
+        if (q >= nrhs) continue;
+        const T* vq = v2 + 16 * q4 + q * kPanel;
+        T acc = T(0);
+#pragma unroll
+        for (int j = 0; j < 16; ++j) acc += lv2[j] * vq[j];
+        part[(q4 * 64 + lane) * nrhs + q] = acc;
+    }
+    __syncthreads();
+    if (tid < nr) {
+        const int gi = r0 + tid;
+        for (int q = 0; q < nrhs; ++q) {
+            const T* pp = part + tid * nrhs + q;
+            T sum = pp[0];
+            for (int k = 1; k < nwc2; ++k) sum += pp[k * 64 * nrhs];
             const T val = rw[tid + q * kSolveRowsMax] - sum;
             if (gi < p) Y[first + gi + q * N] = val;
             else Us[(gi - p) + (int64_t)q * c] = val;
@@ -2623,7 +2722,7 @@ template <typename T>
 void launch_fwd_P(const DevPlan& d, const int* tasks, int count, const int* segs, const T* F,
                   const T* Z, T* Y, T* Y2, T* U, int nrhs, hipStream_t st) {
     if (count <= 0) return;
-    const size_t lds = (size_t)((kPanel + kSolveRowsMax + 256) * nrhs + 64 * 65) * sizeof(T);
+    const size_t lds = (size_t)((2 * kPanel + kSolveRowsMax + 256) * nrhs + 64 * 65) * sizeof(T);
     if (nrhs == 1)
         launch(k_fwd_P<T, 1>, dim3(count), dim3(256), lds, st, d, tasks, segs, F, Z, Y, Y2, U, nrhs);
     else

@@ -21,7 +21,9 @@ constexpr int kPTaskInts = 6;    // ints per solve task: panel, r0, r1, index, s
 //   ints 13..15  the front (first pivot, pivots p, order f)
 //   int64 at ints 16, 18, 20, 22: L_off, U_off, M_off, first row-list entry
 //   ints 24..27  backward: the panel this task finishes (c0, w, slot0, tasks; tasks 0: none)
-constexpr int kTaskRec = 28;
+//   ints 28..31  forward: the second panel's width (0: one panel), its pivot rows' segments
+//                (first, count), 0
+constexpr int kTaskRec = 32;
 constexpr int kTaskRec64 = 16;
 constexpr int kInertiaSlots = 64;  // partial inertia counters per system (spreads the atomics)
 constexpr int kNonfiniteInput = 1;   // status bit: NaN/Inf in the assembled K (its norms)

@@ -155,6 +155,12 @@ struct Plan {
     std::vector<int> solve_fin;      // per task: the panel it finishes in the backward sweep
                                      // (c0, w, slot0, tasks), tasks 0 if none
     std::vector<int> solve_seg;      // (child, a0, a1): update-vector entries landing in a task
+    // forward sweep: its own steps (j = step index k of the level) and tasks
+    // (as solve_p, panel = the step's first panel), with per task (w2,
+    // seg0, nseg, 0): the second panel's width (0: one panel) and its pivot
+    // rows' contribution segments
+    std::vector<SolveStep> fsolve_steps;
+    std::vector<int> fsolve_p, fsolve_x;
     std::vector<int> solve_s;        // small fronts (p <= 64, f <= 128) solved by one wave each
     int64_t solve_max_slots = 0;     // tasks in the largest step (partial-sum slots)
 
