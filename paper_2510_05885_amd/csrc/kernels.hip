@@ -1093,6 +1093,12 @@ __device__ __forceinline__ void panel_body(const DevPlan& d, int s, int k0, int 
             for (int st = 0; st < 4; ++st) zo[h][K][st] = Zt[(16 * K + Mfma<T>::row(lk, st)) * kPanel + 16 * J + lr];
         }
     }
+    // The results overwrite A[rows, panel] in place, and the two waves that
+    // share a row block each read all of its panel columns but write only
+    // their own output blocks: every wave's loads must have returned before
+    // any wave stores.
+    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+    __syncthreads();
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
         const int J = h ? 3 - (wave >> 1) : (wave >> 1);

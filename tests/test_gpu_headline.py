@@ -160,7 +160,9 @@ def test_sequence_bitwise_repeatable(opf500k, precision):
     (unrefined solves, graph replays): every refactor gives bitwise the same
     solution and inertia in every pass.  Each refactor follows a different
     matrix, so a dependency on stale values -- such as an MFMA accumulator
-    read before it is written -- shows up here, not in repeats of one matrix."""
+    read before it is written, or a wave loading operands that another wave of
+    its workgroup has already overwritten in place -- shows up here, not in
+    repeats of one matrix."""
     import hashlib
 
     import torch
