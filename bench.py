@@ -56,15 +56,15 @@ GATE_OMEGA, GATE_CW = 1e-10, 1e-14
 # counter reads for a device copy of known size (--calibrate-copy).  Valid
 # only for the kernel source they were taken on: null once kernels.hip
 # changes.  Source: profiles/pmc_traffic_opf_n500k_fp64.txt.
-TRAFFIC = {"kernels_sha1": "06ef41c35a95b500fb0aa899b1505015e9ff0679", "fetch_scale": 2.00, "write_scale": 1.00,
-           "kib": {"solve_sweeps": (3418.1, 204.4),
-                   "large_update_mfma": (13929.1, 19716.7),
-                   "large_panel": (4005.5, 6330.6),
-                   "large_diag": (1684.9, 6757.1),
-                   "large_assembly": (26964.1, 51086.0),
-                   "small_fronts": (12885.8, 15669.7),
-                   "assemble": (125432.7, 25216.0),
-                   "residual": (64283.3, 2230.3)}}
+TRAFFIC = {"kernels_sha1": "285e1ff0933adfa82a4a7604290efaa9c075223b", "fetch_scale": 2.00, "write_scale": 1.00,
+           "kib": {"solve_sweeps": (4396.6, 243.8),
+                   "large_update_mfma": (13925.2, 19711.9),
+                   "large_panel": (4004.2, 6316.4),
+                   "large_diag": (1686.2, 6757.1),
+                   "large_assembly": (26963.9, 51086.1),
+                   "small_fronts": (12885.4, 15669.7),
+                   "assemble": (125435.2, 25216.0),
+                   "residual": (64327.6, 2229.9)}}
 
 
 def kernels_sha1():
