@@ -156,7 +156,7 @@ def test_adjoint_config5():
 @pytest.mark.timeout(600)
 @pytest.mark.parametrize("precision", ["fp64", "fp32_ir"])
 def test_sequence_bitwise_repeatable(opf500k, precision):
-    """Four passes over the 30-refactor sequence at n = 500k on one handle
+    """Eight passes over the 30-refactor sequence at n = 500k on one handle
     (unrefined solves, graph replays): every refactor gives bitwise the same
     solution and inertia in every pass.  Each refactor follows a different
     matrix, so a dependency on stale values -- such as an MFMA accumulator
@@ -174,7 +174,7 @@ def test_sequence_bitwise_repeatable(opf500k, precision):
     seq = [synth.opf_sequence_values(inp, k) for k in range(30)]
     sig = [dev(s) for s, _ in seq]
     seen, first = {}, {}
-    for p in range(4):
+    for p in range(8):
         for k in range(30):
             rc = kkt.factor(W, sig[k], J, seq[k][1])
             X, info = kkt.solve(B)
