@@ -967,7 +967,6 @@ int build_plan(Plan& P, int form, const std::vector<SysInput>& sys, int ordering
                             const int pid = pids[j];
                             const int* pn = P.solve_pan.data() + 7 * (size_t)pid;
                             const int c0 = pn[1], w = pn[2];
-                            const int p = P.sn_first[s + 1] - P.sn_first[s];
                             const int f = (int)(P.sn_rowptr[s + 1] - P.sn_rowptr[s]);
                             const int w2 = (lg && j + 1 < pids.size()) ? P.solve_pan[7 * (size_t)pids[j + 1] + 2] : 0;
                             if (w2 > 0 && w != PW) throw AnalyzeError(-4, "internal: paired panel narrower than 64");
