@@ -118,6 +118,29 @@ def test_front_beyond_lds_assembly():
     kkt.close()
 
 
+@pytest.mark.parametrize("n", [950, 1000, 1024])
+def test_dense_front_panel_layouts(n):
+    """One dense front with p = n pivots: 15 panels with the last one 54 wide
+    (n = 950: the forward sweep takes pairs and then the last panel alone), 16
+    panels with the last one 40 wide (n = 1000: the last pair's second panel
+    is narrow) and 16 full panels (n = 1024).  Every backward panel below the
+    last two has several row tasks, so each is finished by the next launch's
+    first task, and the first panel by a finish-only record.  The solution
+    matches the oracle's."""
+    print(f"[gpu] dense front n={n} (sweep panel layouts)", flush=True)
+    inp = synth.random_system(n, 2, seed=21, rho=1.0, w_density=0.0005, j_per_row=n)
+    B = synth.rhs(inp.n, 1, seed=3)
+    kkt = nk.KKT.from_input(inp, ir_cw_tol=1e-14)
+    assert kkt.stats()["max_front"] == n
+    rc, X, info = factor_solve(kkt, inp, B)
+    Xo, io, _, K = O.solve(inp, O.CONDENSED, B, perm=np.arange(inp.n, dtype=np.int32))
+    assert rc == 0 and kkt.inertia()[:3] == io.inertia[:3] == (inp.n, 0, 0)
+    assert float(O.backward_error(K, X, B).max()) <= 1e-12
+    assert info.backward_error_cw <= 1e-14
+    assert np.abs(X - Xo).max() <= 1e-8 * np.abs(Xo).max()
+    kkt.close()
+
+
 def test_fp32_overflow_falls_back_to_fp64():
     """K finite in FP64 but not in FP32 (Sigma_3 = 1e39 > FLT_MAX): the FP32
     factor meets an infinite pivot, the library refactors in FP64 instead of
